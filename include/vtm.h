@@ -1,0 +1,229 @@
+/*
+ * vtm.h -- C ABI of libvtm, a gfx950 (MI355X) implementation of the Virtual
+ * Transmission Method (VTM) over an Electric-Vertex-Split (EVS) SPD system,
+ * after F. Wei and H. Yang, "Virtual Transmission Method, A New Distributed
+ * Algorithm to Solve Sparse Linear System".
+ *
+ * Problem statement (Section 3, eq. (3.1)): solve A x = b with A sparse,
+ * symmetric positive definite.  The library
+ *   1. splits the electric graph of A by EVS (Section 4: boundary, twin
+ *      children, split weights/sources, ports; multilevel splitting, Fig. 7),
+ *   2. agrees on one characteristic impedance Z per virtual transmission line
+ *      (VTL) and factors every port-augmented local matrix of eq. (5.8),
+ *      C_j + Z_j^{-1} on the ports, once (Table 1 step 1; Section 8),
+ *   3. iterates Table 1 steps 3-6: every sweep solves all local systems (5.8)
+ *      with the stored factors and exchanges port waves with the twins under
+ *      the transmission delay equations (5.6), delay = one sweep.
+ * All subdomains live on one GPU; the neighbour-to-neighbour exchange is a
+ * gather of outgoing waves by twin index.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a vtm_status; VTM_OK (0) on success.  No exception
+ *     crosses the ABI.  vtm_last_error() returns a thread-local message for the
+ *     last failing call on the calling thread.
+ *   - Inputs are borrowed for the duration of the call (deep-copied where kept).
+ *     Outputs are caller-allocated.
+ *   - Matrices are CSR with both triangles stored, sorted column indices, an
+ *     explicit positive diagonal: rowptr int64[n+1], col int32[nnz],
+ *     val double[nnz], host memory.
+ *   - Vectors b and x of vtm_solve / vtm_run_sweeps may be host or device
+ *     pointers (detected with hipPointerGetAttributes); column c of an n x nrhs
+ *     block starts at ptr + c * ld.
+ *   - A handle is not thread-safe; distinct handles may be used from distinct
+ *     threads.  All device work of a handle runs on its stream.
+ */
+#ifndef VTM_H
+#define VTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vtm_status;
+
+enum {
+    VTM_OK = 0,
+    VTM_ERR_INVALID = 1,        /* null / size / non-symmetric / non-finite input, tol <= 0, Z <= 0 */
+    VTM_ERR_PARTITION = 2,      /* an edge not inside any subgraph, an empty subgraph, RCB bounds failed */
+    VTM_ERR_NOT_SPD = 3,        /* a local pivot <= 0 during factorisation (subdomain in message) */
+    VTM_ERR_NOT_CONVERGED = 4,  /* max sweeps reached; x, iters, relres are still written */
+    VTM_ERR_DIVERGED = 5,       /* NaN or residual growth > 1e3 x its initial value */
+    VTM_ERR_STATE = 6,          /* call order violated (e.g. solve before setup) */
+    VTM_ERR_HIP = 7,            /* HIP runtime error */
+    VTM_ERR_OOM = 8             /* host or device allocation failed */
+};
+
+enum { VTM_FP64 = 0, VTM_FP32_IR = 1 };
+enum { VTM_PART_GRID = 0, VTM_PART_RCB = 1, VTM_PART_GRAPH = 2, VTM_PART_USER = 3 };
+enum { VTM_SPLIT_BRANCH = 0, VTM_SPLIT_EQUAL = 1 };
+enum { VTM_TOPO_FACE = 0, VTM_TOPO_COMPLETE = 1 };
+enum { VTM_Z_DIAG = 0, VTM_Z_USER = 1, VTM_Z_LEARNED = 2 };
+
+typedef struct vtm_ctx *vtm_handle;
+
+typedef struct {
+    int32_t device;        /* HIP device ordinal; -1 = host-only handle (partition and its analysis only) */
+    void *stream;          /* hipStream_t to run on; NULL = the library creates its own */
+    int32_t precision;     /* VTM_FP64, or VTM_FP32_IR: FP32 factors and sweeps, FP64 refinement */
+    int32_t check_every;   /* sweeps between convergence tests (>= 1; 0 = default 10) */
+    int64_t max_sweeps;    /* cap on sweeps per solve (0 = default 100000) */
+    int32_t rhs_per_block; /* right-hand sides one workgroup carries (0 = tuned: 1, 2, 4 or 8) */
+    int32_t leaf_size;     /* nested-dissection leaf size of the local orderings (0 = tuned) */
+    int32_t reserved[6];
+} vtm_options;
+
+/*
+ * EVS partition scheme (Section 4, steps 1-4; "partition scheme" below
+ * Example 4.1).  Membership S(v) = subgraphs holding a child of vertex v:
+ *   GRID : vertex grid dims (x fastest); parts[a] tiles per axis sharing their
+ *          separator lines: m = dims/parts if exact else (dims-1)/parts, tile I
+ *          covers [I*m, (I+1)*m], the last tile ends at dims-1.  Ids row-major.
+ *   RCB  : seeded random recursive coordinate bisection of the vertex grid into
+ *          2^levels boxes sharing cut planes; longest axis (ties: lowest) cut at
+ *          lo + (len*q + 50)/100, q = 46 + splitmix64(state) mod 9, depth-first
+ *          pre-order; accepted iff every box's owned size sum 1/|S(v)| lies in
+ *          [min_size, max_size].
+ *   GRAPH: per block of vertices (an independent system), point RCB on coords
+ *          into block_parts[b] owners; every cut edge (u,v) with
+ *          owner(u) < owner(v) adds owner(v) to S(u).
+ *   USER : S(v) given as sorted lists s_idx[s_ptr[v] .. s_ptr[v+1]).
+ * Weights (step 3): split_rule BRANCH gives every piece of an edge
+ * a_uv / |S(u) & S(v)| and every child of v the sum of its branch magnitudes
+ * plus an equal share of a_vv - sum_u |a_uv| (weakly diagonally dominant
+ * pieces, hence SNND -- Corollary 4.1 -- for M-matrices); EQUAL gives a_vv/|S(v)|.
+ * Sources are split b_v / |S(v)|.  Multilevel splitting (Fig. 7): topology FACE
+ * joins two children of v by a VTL iff their subgraphs share a vertex of
+ * multiplicity 2 somewhere (all pairs if that leaves S(v) disconnected);
+ * COMPLETE joins all pairs.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t dims[3];
+    int32_t parts[3];
+    int32_t levels;
+    uint64_t seed;
+    double min_size, max_size;
+    const double *coords;        /* n x dim row-major (GRAPH; optional for USER) */
+    int32_t dim;
+    int32_t nblocks;
+    const int64_t *block_start;  /* GRAPH: first vertex of each block */
+    const int64_t *block_count;  /* GRAPH: vertices in each block */
+    const int32_t *block_parts;  /* GRAPH: subgraphs per block */
+    const int64_t *s_ptr;        /* USER */
+    const int32_t *s_idx;        /* USER */
+    int32_t user_nsub;           /* USER */
+    int32_t split_rule;
+    int32_t topology;
+    int32_t nsys;                /* independent systems for per-system convergence (0/1 = one) */
+    const int64_t *sys_ptr;      /* nsys+1 vertex offsets of the systems (NULL if nsys <= 1) */
+} vtm_partition_spec;
+
+typedef struct {
+    int32_t nsub;            /* subgraphs N */
+    int32_t nclass;          /* distinct local sparsity structures (shared symbolic analysis) */
+    int64_t n_split;         /* unknowns after splitting, sum of |M_j| */
+    int64_t nvtl;            /* virtual transmission lines */
+    int64_t nports;          /* ports (2 per VTL) */
+    int32_t max_local;       /* largest |M_j| */
+    int32_t nsys;            /* independent systems */
+    int64_t factor_entries;  /* stored factor entries over all subgraphs */
+} vtm_partition_info;
+
+typedef struct {
+    int64_t sweeps;          /* sweeps of the last solve (all outer steps) */
+    int32_t outer_steps;     /* refinement steps of the last solve (FP32_IR), 1 in FP64 */
+    int32_t checks;          /* convergence tests of the last solve */
+    double setup_ms;         /* last vtm_setup: Z, augmentation and factorisation (device time) */
+    double solve_ms;         /* last solve, wall time on the stream (events) */
+    double sweep_ms;         /* last solve, summed sweep-kernel time (events around sweep launches) */
+    double bytes_per_sweep;  /* algorithmic bytes one sweep must move (factor once + vectors + waves) */
+    double flops_per_sweep;  /* 4 * nrhs * stored lower-factor entries */
+} vtm_stats;
+
+/* Create a handle bound to options->device; NULL options = defaults. */
+vtm_status vtm_create(const vtm_options *options, vtm_handle *out);
+/* Release every host and device resource of the handle. */
+vtm_status vtm_destroy(vtm_handle h);
+/* Message of the last failing call on this thread ("" if none). */
+const char *vtm_last_error(void);
+
+/*
+ * EVS partition of A (host CSR, see conventions) following spec; builds the
+ * local pieces, VTLs, ports and twins, and the per-class symbolic analysis of
+ * the local factors (nested dissection ordering, supernodes).  Replaces any
+ * previous partition of the handle.  No device work besides uploads.
+ * Errors: VTM_ERR_INVALID (bad CSR or spec), VTM_ERR_PARTITION.
+ */
+vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, const int32_t *col,
+                             const double *val, const vtm_partition_spec *spec, vtm_partition_info *info);
+
+/*
+ * Copy the partition out (host arrays sized from vtm_partition_info; any may be
+ * NULL).  Layouts match the description in vtm_evs_partition:
+ *   s_ptr[n+1], s_idx[*]          membership, sorted per vertex
+ *   loc_ptr[nsub+1], loc_vtx[n_split]   vertices of each subgraph, ascending
+ *   lrp[n_split+1], lcol[*], lval[*]    local pieces A~_k as CSR over local indices
+ *   vtl_v, vtl_k, vtl_k2 [nvtl]   VTLs ordered by (v, k, k'), k < k'
+ *   port_ptr[nsub+1], port_v[nports], port_other[nports], port_twin[nports]
+ *                                 ports of each subgraph ordered by (v, other end)
+ *   zdiag[nvtl]                   the diagonal rule Z = 1 / a_vv
+ */
+vtm_status vtm_get_partition(vtm_handle h, int64_t *s_ptr, int32_t *s_idx, int64_t *loc_ptr, int64_t *loc_vtx,
+                             int64_t *lrp, int32_t *lcol, double *lval, int64_t *vtl_v, int32_t *vtl_k,
+                             int32_t *vtl_k2, int64_t *port_ptr, int64_t *port_v, int32_t *port_other,
+                             int64_t *port_twin, double *zdiag);
+
+/*
+ * Table 1 step 1 and eq. (5.8): set one impedance per VTL and factor every
+ * port-augmented local matrix K_k = A~_k + sum_{p in k} Z_p^{-1} e_v(p) e_v(p)^T
+ * on the device (multifrontal Cholesky; diagonal blocks stored inverted).
+ *   z_rule VTM_Z_DIAG   : Z = 1 / a_vv (z_vtl ignored)
+ *          VTM_Z_USER   : z_vtl[nvtl] host array, finite and > 0
+ *          VTM_Z_LEARNED: the loaded impedance model predicts ln(Z a_vv) per VTL
+ *                         (vtm_zmodel_load first); z_vtl ignored
+ * Resets the waves to zero.  Errors: VTM_ERR_STATE (no partition),
+ * VTM_ERR_INVALID (Z), VTM_ERR_NOT_SPD (first failing subgraph in the message).
+ */
+vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl);
+
+/*
+ * Solve A X = B for nrhs right-hand sides: zero initial waves (Example 5.1),
+ * sweeps until every system's relative residual ||b - A xbar||_2 / ||b||_2 is
+ * <= tol for every column, where xbar_v is the mean of the children of v
+ * (tested every check_every sweeps).  FP32_IR runs FP32 sweeps on the
+ * correction equation and refines x in FP64.
+ *   b: n x nrhs (ld >= n), host or device;  x: n x nrhs output (ldx >= n)
+ *   iters[nrhs*nsys]: first passing sweep per (rhs, system), -1 if none
+ *   relres[nrhs*nsys]: last measured relative residual
+ * Returns VTM_ERR_NOT_CONVERGED (with outputs written) if max_sweeps is hit,
+ * VTM_ERR_DIVERGED on NaN or growth.
+ */
+vtm_status vtm_solve(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
+                     int32_t *iters, double *relres);
+
+/*
+ * Run exactly nsweeps FP64-or-FP32 sweeps (handle precision, no refinement)
+ * from the current waves, then write the merged potentials of the last sweep
+ * to x.  The waves persist across calls (checkpoint/resume with
+ * vtm_get_waves / vtm_set_waves).  b, x as in vtm_solve.
+ */
+vtm_status vtm_run_sweeps(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, int64_t nsweeps, double *x,
+                          int64_t ldx);
+
+/* Zero the waves (the state of Example 5.1 before its first iteration). */
+vtm_status vtm_reset_waves(vtm_handle h);
+/* Incoming waves a_p = u_twin - Z w_twin of the next sweep, host array [nrhs][nports]. */
+vtm_status vtm_get_waves(vtm_handle h, double *a, int32_t nrhs);
+vtm_status vtm_set_waves(vtm_handle h, const double *a, int32_t nrhs);
+
+/* Statistics of the last setup / solve. */
+vtm_status vtm_get_stats(vtm_handle h, vtm_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VTM_H */

@@ -1,0 +1,835 @@
+// C ABI of libvtm: handle, EVS partition upload, setup (Z + factorisation) and
+// the VTM solve loop (Table 1 of Wei & Yang) with FP64 or FP32 + FP64
+// iterative refinement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "vtm.h"
+#include "vtm_debug.h"
+#include "vtm_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+vtm_status fail(vtm_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            if (e_ == hipErrorOutOfMemory) return fail(VTM_ERR_OOM, std::string(#expr) + ": out of memory"); \
+            return fail(VTM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                                 \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+}  // namespace
+
+struct vtm_ctx {
+    vtm_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    vtm::Csr A;
+    vtm::Partition P;
+    vtm::Symbolic S;
+    bool partitioned = false, set_up = false;
+    int32_t max_nk = 0, max_front = 0;
+    int64_t nsplit = 0, nports = 0, total_val = 0, total_ws = 0, total_lower = 0;
+    std::vector<DevBuf *> all;
+    // symbolic (class level)
+    DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
+        d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
+    // subgraph level
+    DevBuf d_subcls, d_subval, d_subx, d_subaval, d_subws, d_pgptr, d_pgpos, d_pgbeg, d_pgcnt;
+    // maps, matrix, ports
+    DevBuf d_fvtx, d_fmul, d_cpptr, d_cpidx, d_rp, d_ci, d_v, d_aval, d_twin, d_portvtl, d_chunkrow, d_chunksys,
+        d_syschunk;
+    int32_t nchunks = 0;
+    // setup products
+    DevBuf d_z, d_invz64, d_invz32, d_vals64, d_vals32, d_status;
+    // solve state
+    DevBuf d_o[2], d_bsplit, d_xloc, d_x, d_xt, d_r, d_rt, d_b, d_part, d_relres;
+    int cur = 0;
+    int32_t wave_nrhs = 0, wave_R = 1;
+    bool waves_zero = true;
+    vtm_stats stats{};
+
+    vtm_ctx() {
+        DevBuf *list[] = {&d_cls, &d_lev, &d_colsn, &d_snc0, &d_snnc, &d_snm, &d_snval, &d_snridx, &d_snuoff, &d_ridx,
+                          &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr, &d_scsrc,
+                          &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
+                          &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
+                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
+                          &d_vals64, &d_vals32, &d_status, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_rt, &d_b, &d_part, &d_relres};
+        for (DevBuf *b : list) all.push_back(b);
+    }
+    bool host_only() const { return opt.device < 0; }
+    ~vtm_ctx() {
+        if (host_only()) return;
+        (void)hipSetDevice(opt.device);
+        for (DevBuf *b : all) b->release();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    bool fp32() const { return opt.precision == VTM_FP32_IR; }
+    size_t tsize() const { return fp32() ? sizeof(float) : sizeof(double); }
+};
+
+namespace {
+
+hipError_t ensure(DevBuf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    b.release();
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.bytes = bytes;
+    return e;
+}
+
+template <typename T>
+hipError_t upload(DevBuf &b, const std::vector<T> &v, hipStream_t st) {
+    hipError_t e = ensure(b, sizeof(T) * std::max<size_t>(v.size(), 1));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st);
+}
+
+bool is_device_ptr(const void *p) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+vtm::DevSym dev_sym(vtm_ctx *h) {
+    vtm::DevSym s;
+    s.cls = h->d_cls.as<vtm::ClassDev>();
+    s.lev_c0 = h->d_lev.as<int32_t>();
+    s.col_sn = h->d_colsn.as<int32_t>();
+    s.sn_c0 = h->d_snc0.as<int32_t>();
+    s.sn_nc = h->d_snnc.as<int32_t>();
+    s.sn_m = h->d_snm.as<int32_t>();
+    s.sn_val = h->d_snval.as<int32_t>();
+    s.sn_ridx = h->d_snridx.as<int32_t>();
+    s.sn_uoff = h->d_snuoff.as<int32_t>();
+    s.ridx = h->d_ridx.as<uint16_t>();
+    s.rel = h->d_rel.as<uint16_t>();
+    s.ch_ptr = h->d_chptr.as<int32_t>();
+    s.ch_idx = h->d_chidx.as<int32_t>();
+    s.seg_ptr = h->d_segptr.as<int32_t>();
+    s.seg_off = h->d_segoff.as<int32_t>();
+    s.seg_c0 = h->d_segc0.as<uint16_t>();
+    s.seg_nc = h->d_segnc.as<uint16_t>();
+    s.sc_ptr = h->d_scptr.as<int32_t>();
+    s.sc_src = h->d_scsrc.as<int32_t>();
+    s.sc_dst = h->d_scdst.as<int32_t>();
+    return s;
+}
+
+vtm::DevSub dev_sub(vtm_ctx *h) {
+    vtm::DevSub d;
+    d.cls = h->d_subcls.as<int32_t>();
+    d.val = h->d_subval.as<int64_t>();
+    d.x = h->d_subx.as<int64_t>();
+    d.aval = h->d_subaval.as<int64_t>();
+    d.ws = h->d_subws.as<int64_t>();
+    d.pg_ptr = h->d_pgptr.as<int32_t>();
+    d.pg_pos = h->d_pgpos.as<uint16_t>();
+    d.pg_beg = h->d_pgbeg.as<int32_t>();
+    d.pg_cnt = h->d_pgcnt.as<int32_t>();
+    return d;
+}
+
+vtm::DevMaps dev_maps(vtm_ctx *h) {
+    vtm::DevMaps m;
+    m.fvtx = h->d_fvtx.as<int32_t>();
+    m.fmul = h->d_fmul.as<int32_t>();
+    m.cp_ptr = h->d_cpptr.as<int64_t>();
+    m.cp_idx = h->d_cpidx.as<int32_t>();
+    return m;
+}
+
+void host_sizes(vtm_ctx *h) {
+    h->max_nk = 0;
+    h->max_front = 0;
+    for (const vtm::ClassSym &C : h->S.classes) {
+        h->max_nk = std::max(h->max_nk, C.nk);
+        h->max_front = std::max(h->max_front, C.max_front);
+    }
+    h->total_lower = 0;
+    for (int32_t k = 0; k < h->P.nsub; ++k) h->total_lower += h->S.classes[h->S.sub_class[k]].nlower;
+    h->nsplit = h->P.loc_ptr[h->P.nsub];
+    h->nports = (int64_t)h->P.port_v.size();
+}
+
+vtm_status upload_partition(vtm_ctx *h) {
+    const vtm::Partition &P = h->P;
+    const vtm::Symbolic &S = h->S;
+    hipStream_t st = h->stream;
+    // ---- class arrays
+    std::vector<vtm::ClassDev> cls;
+    std::vector<int32_t> lev, colsn, snc0, snnc, snm, snval, snridx, snuoff, chptr, chidx, segptr, segoff, scptr,
+        scsrc, scdst;
+    std::vector<uint16_t> ridx, rel, segc0, segnc;
+    h->max_nk = 0;
+    h->max_front = 0;
+    for (const vtm::ClassSym &C : S.classes) {
+        vtm::ClassDev d{};
+        d.nk = C.nk;
+        d.nsn = C.nsn;
+        d.nlev = C.nlev;
+        d.max_front = C.max_front;
+        d.o_lev = (int32_t)lev.size();
+        d.o_sn = (int32_t)snc0.size();
+        d.o_snp = (int32_t)chptr.size();
+        d.o_col = (int32_t)colsn.size();
+        d.o_colp = (int32_t)segptr.size();
+        d.o_ridx = (int32_t)ridx.size();
+        d.o_seg = (int32_t)segoff.size();
+        d.o_sc = (int32_t)scsrc.size();
+        d.o_chi = (int32_t)chidx.size();
+        d.nval = C.nval;
+        d.ws_u = C.ws_u;
+        cls.push_back(d);
+        lev.insert(lev.end(), C.lev_c0.begin(), C.lev_c0.end());
+        colsn.insert(colsn.end(), C.col_sn.begin(), C.col_sn.end());
+        snc0.insert(snc0.end(), C.sn_c0.begin(), C.sn_c0.end());
+        snnc.insert(snnc.end(), C.sn_nc.begin(), C.sn_nc.end());
+        snm.insert(snm.end(), C.sn_m.begin(), C.sn_m.end());
+        snval.insert(snval.end(), C.sn_val.begin(), C.sn_val.end());
+        snridx.insert(snridx.end(), C.sn_ridx.begin(), C.sn_ridx.end());
+        snuoff.insert(snuoff.end(), C.sn_uoff.begin(), C.sn_uoff.end());
+        chptr.insert(chptr.end(), C.ch_ptr.begin(), C.ch_ptr.end());
+        scptr.insert(scptr.end(), C.sc_ptr.begin(), C.sc_ptr.end());
+        chidx.insert(chidx.end(), C.ch_idx.begin(), C.ch_idx.end());
+        segptr.insert(segptr.end(), C.seg_ptr.begin(), C.seg_ptr.end());
+        segoff.insert(segoff.end(), C.seg_off.begin(), C.seg_off.end());
+        segc0.insert(segc0.end(), C.seg_c0.begin(), C.seg_c0.end());
+        segnc.insert(segnc.end(), C.seg_nc.begin(), C.seg_nc.end());
+        ridx.insert(ridx.end(), C.ridx.begin(), C.ridx.end());
+        rel.insert(rel.end(), C.rel.begin(), C.rel.end());
+        scsrc.insert(scsrc.end(), C.sc_src.begin(), C.sc_src.end());
+        scdst.insert(scdst.end(), C.sc_dst.begin(), C.sc_dst.end());
+        h->max_nk = std::max(h->max_nk, C.nk);
+        h->max_front = std::max(h->max_front, C.max_front);
+        // ch_ptr/sc_ptr share o_snp: both have nsn + 1 entries per class
+    }
+    // ---- subgraph arrays
+    const int32_t nsub = P.nsub;
+    std::vector<int32_t> subcls(nsub), pgptr(nsub + 1, 0), pgbeg, pgcnt;
+    std::vector<int64_t> subval(nsub), subx(nsub), subaval(nsub), subws(nsub);
+    std::vector<uint16_t> pgpos;
+    int64_t vo = 0, wo = 0;
+    h->total_lower = 0;
+    for (int32_t k = 0; k < nsub; ++k) {
+        const int32_t c = S.sub_class[k];
+        const vtm::ClassSym &C = S.classes[c];
+        subcls[k] = c;
+        subval[k] = vo;
+        vo += C.nval;
+        h->total_lower += C.nlower;
+        subx[k] = P.loc_ptr[k];
+        subaval[k] = P.lrp[P.loc_ptr[k]];
+        subws[k] = wo;
+        wo += C.ws_u + (int64_t)C.max_front * C.max_front;
+        for (int64_t p = P.port_ptr[k]; p < P.port_ptr[k + 1];) {
+            int64_t q = p;
+            while (q < P.port_ptr[k + 1] && P.port_v[q] == P.port_v[p]) ++q;
+            pgpos.push_back((uint16_t)C.ipos[P.port_lidx[p]]);
+            pgbeg.push_back((int32_t)p);
+            pgcnt.push_back((int32_t)(q - p));
+            p = q;
+        }
+        pgptr[k + 1] = (int32_t)pgpos.size();
+    }
+    h->total_val = vo;
+    h->total_ws = wo;
+    h->nsplit = P.loc_ptr[nsub];
+    h->nports = (int64_t)P.port_v.size();
+    // ---- split/merge maps (factor order inside every subgraph)
+    std::vector<int32_t> fvtx(h->nsplit), fmul(h->nsplit), cpidx(P.s_ptr[P.n]);
+    std::vector<int64_t> cpfill(P.s_ptr.begin(), P.s_ptr.end() - 1);
+    for (int32_t k = 0; k < nsub; ++k) {
+        const vtm::ClassSym &C = S.classes[S.sub_class[k]];
+        const int64_t b = P.loc_ptr[k];
+        for (int32_t i = 0; i < C.nk; ++i) {
+            const int64_t v = P.loc_vtx[b + i];
+            const int64_t e = b + C.ipos[i];
+            cpidx[cpfill[v]++] = (int32_t)e;
+        }
+        for (int32_t pos = 0; pos < C.nk; ++pos) {
+            const int64_t v = P.loc_vtx[b + C.perm[pos]];
+            fvtx[b + pos] = (int32_t)v;
+            fmul[b + pos] = (int32_t)(P.s_ptr[v + 1] - P.s_ptr[v]);
+        }
+    }
+    std::vector<int32_t> twin(h->nports), portvtl(h->nports);
+    for (int64_t p = 0; p < h->nports; ++p) {
+        twin[p] = (int32_t)P.port_twin[p];
+        portvtl[p] = (int32_t)P.port_vtl[p];
+    }
+    // residual chunks: contiguous row ranges inside one system
+    std::vector<int64_t> chunkrow;
+    std::vector<int32_t> chunksys, syschunk(P.nsys + 1, 0);
+    const int64_t CH = 4096;
+    for (int32_t s = 0; s < P.nsys; ++s) {
+        for (int64_t r = P.sys_ptr[s]; r < P.sys_ptr[s + 1]; r += CH) {
+            chunkrow.push_back(r);
+            chunksys.push_back(s);
+        }
+        syschunk[s + 1] = (int32_t)chunkrow.size();
+    }
+    chunkrow.push_back(P.n);
+    h->nchunks = (int32_t)chunksys.size();
+
+#define UP(buf, vec) HIP_TRY(upload(h->buf, vec, st))
+    UP(d_cls, cls); UP(d_lev, lev); UP(d_colsn, colsn); UP(d_snc0, snc0); UP(d_snnc, snnc); UP(d_snm, snm);
+    UP(d_snval, snval); UP(d_snridx, snridx); UP(d_snuoff, snuoff); UP(d_ridx, ridx); UP(d_rel, rel);
+    UP(d_chptr, chptr); UP(d_chidx, chidx); UP(d_segptr, segptr); UP(d_segoff, segoff); UP(d_segc0, segc0);
+    UP(d_segnc, segnc); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
+    UP(d_subcls, subcls); UP(d_subval, subval); UP(d_subx, subx); UP(d_subaval, subaval); UP(d_subws, subws);
+    UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt);
+    UP(d_fvtx, fvtx); UP(d_fmul, fmul); UP(d_cpptr, P.s_ptr); UP(d_cpidx, cpidx);
+    UP(d_rp, h->A.rp); UP(d_ci, h->A.ci); UP(d_v, h->A.v); UP(d_aval, P.lval);
+    UP(d_twin, twin); UP(d_portvtl, portvtl); UP(d_chunkrow, chunkrow); UP(d_chunksys, chunksys);
+    UP(d_syschunk, syschunk);
+#undef UP
+    HIP_TRY(hipStreamSynchronize(st));
+    return VTM_OK;
+}
+
+int32_t pick_R(vtm_ctx *h, int32_t nrhs) {
+    if (h->opt.rhs_per_block > 0) return h->opt.rhs_per_block;
+    int32_t want = 1;
+    while (want < nrhs && want < 8) want *= 2;
+    while (want > 1 && 2 * h->tsize() * (size_t)h->max_nk * want > 64 * 1024) want /= 2;
+    return want;
+}
+
+template <typename T>
+vtm_status ensure_waves(vtm_ctx *h, int32_t nrhs) {
+    const int32_t R = pick_R(h, nrhs);
+    const int32_t ng = (nrhs + R - 1) / R;
+    const size_t bytes = sizeof(T) * (size_t)ng * h->nports * R + sizeof(T);
+    if (h->wave_nrhs != nrhs || h->wave_R != R || !h->d_o[0].p) {
+        HIP_TRY(ensure(h->d_o[0], bytes));
+        HIP_TRY(ensure(h->d_o[1], bytes));
+        HIP_TRY(hipMemsetAsync(h->d_o[0].p, 0, bytes, h->stream));
+        HIP_TRY(hipMemsetAsync(h->d_o[1].p, 0, bytes, h->stream));
+        h->wave_nrhs = nrhs;
+        h->wave_R = R;
+        h->cur = 0;
+        h->waves_zero = true;
+    }
+    return VTM_OK;
+}
+
+template <typename T>
+vtm_status zero_waves(vtm_ctx *h) {
+    const int32_t ng = (h->wave_nrhs + h->wave_R - 1) / h->wave_R;
+    const size_t bytes = sizeof(T) * (size_t)ng * h->nports * h->wave_R + sizeof(T);
+    HIP_TRY(hipMemsetAsync(h->d_o[h->cur].p, 0, bytes, h->stream));
+    h->waves_zero = true;
+    return VTM_OK;
+}
+
+// Stage b (host or device) into the handle's FP64 device copy.
+vtm_status stage_b(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb) {
+    const int64_t n = h->P.n;
+    HIP_TRY(ensure(h->d_b, sizeof(double) * (size_t)n * nrhs));
+    if (is_device_ptr(b))
+        HIP_TRY(hipMemcpy2DAsync(h->d_b.p, sizeof(double) * n, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    else
+        HIP_TRY(hipMemcpy2DAsync(h->d_b.p, sizeof(double) * n, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
+                                 hipMemcpyHostToDevice, h->stream));
+    return VTM_OK;
+}
+
+vtm_status write_x(vtm_ctx *h, const double *src, double *x, int32_t nrhs, int64_t ldx) {
+    const int64_t n = h->P.n;
+    hipMemcpyKind kind = is_device_ptr(x) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(hipMemcpy2DAsync(x, sizeof(double) * ldx, src, sizeof(double) * n, sizeof(double) * n, nrhs, kind,
+                             h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return VTM_OK;
+}
+
+template <typename T>
+T *vals_of(vtm_ctx *h) {
+    if constexpr (sizeof(T) == 4) return h->d_vals32.as<T>();
+    else return h->d_vals64.as<T>();
+}
+template <typename T>
+T *invz_of(vtm_ctx *h) {
+    if constexpr (sizeof(T) == 4) return h->d_invz32.as<T>();
+    else return h->d_invz64.as<T>();
+}
+
+// Sweeps on the current waves; the last one stores the local solutions.
+template <typename T>
+void run_sweeps_dev(vtm_ctx *h, int64_t count) {
+    const vtm::DevSym S = dev_sym(h);
+    const vtm::DevSub D = dev_sub(h);
+    const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
+    for (int64_t i = 0; i < count; ++i) {
+        vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, ng, R, h->nsplit, h->nports, vals_of<T>(h),
+                             h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur].as<T>(),
+                             h->d_o[1 - h->cur].as<T>(), h->d_xloc.as<T>(), i == count - 1 ? 1 : 0, h->stream);
+        h->cur ^= 1;
+    }
+    if (count > 0) h->waves_zero = false;
+}
+
+template <typename T>
+vtm_status alloc_solve(vtm_ctx *h, int32_t nrhs) {
+    const int32_t R = h->wave_R, ng = (nrhs + R - 1) / R;
+    const int64_t n = h->P.n;
+    HIP_TRY(ensure(h->d_bsplit, sizeof(T) * (size_t)ng * h->nsplit * R));
+    HIP_TRY(ensure(h->d_xloc, sizeof(T) * (size_t)ng * h->nsplit * R));
+    HIP_TRY(ensure(h->d_x, sizeof(double) * (size_t)n * nrhs));
+    HIP_TRY(ensure(h->d_xt, sizeof(double) * (size_t)n * nrhs));
+    HIP_TRY(ensure(h->d_r, sizeof(double) * (size_t)n * nrhs));
+    HIP_TRY(ensure(h->d_rt, sizeof(double) * (size_t)n * nrhs));
+    HIP_TRY(ensure(h->d_part, sizeof(double) * 2 * (size_t)h->nchunks * nrhs));
+    HIP_TRY(ensure(h->d_relres, sizeof(double) * (size_t)h->P.nsys * nrhs));
+    return VTM_OK;
+}
+
+// FP64 residual of x against the staged b; optional store of r; relres to host.
+vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::vector<double> &rel) {
+    vtm::DevCsr A{h->d_rp.as<int64_t>(), h->d_ci.as<int32_t>(), h->d_v.as<double>()};
+    const int64_t n = h->P.n;
+    vtm::launch_residual(A, n, nrhs, h->d_b.as<double>(), n, x, n, r, n, h->d_chunkrow.as<int64_t>(),
+                         h->d_chunksys.as<int32_t>(), h->nchunks, h->d_syschunk.as<int32_t>(), h->P.nsys,
+                         h->d_part.as<double>(), h->d_relres.as<double>(), h->stream);
+    rel.resize((size_t)h->P.nsys * nrhs);
+    HIP_TRY(hipMemcpyAsync(rel.data(), h->d_relres.p, sizeof(double) * rel.size(), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return VTM_OK;
+}
+
+template <typename T>
+vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
+                      int32_t *iters, double *relres) {
+    vtm_status rc;
+    if ((rc = ensure_waves<T>(h, nrhs))) return rc;
+    if ((rc = alloc_solve<T>(h, nrhs))) return rc;
+    if ((rc = stage_b(h, b, nrhs, ldb))) return rc;
+    const int64_t n = h->P.n;
+    const int32_t nsys = h->P.nsys, R = h->wave_R;
+    const vtm::DevMaps M = dev_maps(h);
+    const int64_t cadence = h->opt.check_every > 0 ? h->opt.check_every : 10;
+    const int64_t maxsw = h->opt.max_sweeps > 0 ? h->opt.max_sweeps : 100000;
+    const bool refine = sizeof(T) == 4;
+    std::vector<double> rel;
+    std::vector<int32_t> it((size_t)nsys * nrhs, -1);
+    std::vector<double> last((size_t)nsys * nrhs, 1.0);
+    hipEvent_t e0, e1, s0, s1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventCreate(&s0));
+    HIP_TRY(hipEventCreate(&s1));
+    HIP_TRY(hipEventRecord(e0, h->stream));
+    double sweep_ms = 0.0;
+    int64_t sweeps = 0;
+    int32_t outer = 1, checks = 0;
+    bool done = false, diverged = false;
+    double first = -1.0;
+    // x = 0, r = b for the refinement; the FP64 path solves b directly
+    double *xcur = h->d_x.as<double>(), *xtr = h->d_xt.as<double>();
+    double *rcur = h->d_r.as<double>(), *rtr = h->d_rt.as<double>();
+    HIP_TRY(hipMemsetAsync(xcur, 0, sizeof(double) * n * nrhs, h->stream));
+    vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
+    if ((rc = zero_waves<T>(h))) return rc;
+    double rel_outer = 1.0, rel_prev = 1e300;
+    const double eta = 2e-6;
+    int inner_checks = 0;
+    double last_worst = 1e300;
+    while (!done && sweeps < maxsw) {
+        const int64_t cnt = std::min(cadence, maxsw - sweeps);
+        HIP_TRY(hipEventRecord(s0, h->stream));
+        run_sweeps_dev<T>(h, cnt);
+        HIP_TRY(hipEventRecord(s1, h->stream));
+        sweeps += cnt;
+        ++checks;
+        ++inner_checks;
+        // merged potentials (plus the refined x in FP32_IR), FP64 residual
+        vtm::launch_merge<T>(M, n, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, h->stream);
+        if ((rc = residual(h, nrhs, xtr, refine ? rtr : nullptr, rel))) return rc;
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, s0, s1));
+        sweep_ms += ms;
+        double worst = 0.0;
+        bool all = true;
+        for (size_t q = 0; q < rel.size(); ++q) {
+            if (!std::isfinite(rel[q])) diverged = true;
+            if (it[q] < 0 && rel[q] <= tol) it[q] = (int32_t)sweeps;
+            all = all && rel[q] <= tol;
+            worst = std::max(worst, rel[q]);
+            last[q] = rel[q];
+        }
+        if (first < 0) first = worst;
+        if (worst > 1e3 * std::max(first, 1.0)) diverged = true;
+        if (diverged) break;
+        if (all) {
+            std::swap(xcur, xtr);
+            done = true;
+            break;
+        }
+        if (!refine) {
+            std::swap(xcur, xtr);
+            continue;
+        }
+        // FP32 inner solve: restart on the new residual once it has gained a factor eta or stalls
+        const bool gained = worst <= eta * rel_outer;
+        const bool stalled = inner_checks >= 2 && worst > 0.9 * rel_prev;
+        rel_prev = worst;
+        if ((gained || stalled) && worst < rel_outer) {
+            std::swap(xcur, xtr);
+            std::swap(rcur, rtr);
+            rel_outer = worst;
+            rel_prev = 1e300;
+            inner_checks = 0;
+            ++outer;
+            vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
+            if ((rc = zero_waves<T>(h))) return rc;
+            last_worst = 1e300;
+            continue;
+        } else if (stalled) {
+            break;  // no further progress possible; keep the last accepted x
+        }
+        last_worst = worst;
+    }
+    if (refine && !done && !diverged && last_worst < rel_outer) std::swap(xcur, xtr);
+    HIP_TRY(hipEventRecord(e1, h->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float total = 0.f;
+    HIP_TRY(hipEventElapsedTime(&total, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(s0);
+    (void)hipEventDestroy(s1);
+    h->stats.sweeps = sweeps;
+    h->stats.outer_steps = outer;
+    h->stats.checks = checks;
+    h->stats.solve_ms = total;
+    h->stats.sweep_ms = sweep_ms;
+    h->stats.bytes_per_sweep =
+        (double)sizeof(T) * ((double)h->total_lower + (double)h->nsplit * nrhs + 2.0 * (double)h->nports * nrhs);
+    h->stats.flops_per_sweep = 4.0 * nrhs * (double)h->total_lower;
+    if ((rc = write_x(h, xcur, x, nrhs, ldx))) return rc;
+    if (iters) std::copy(it.begin(), it.end(), iters);
+    if (relres) std::copy(last.begin(), last.end(), relres);
+    if (diverged) return fail(VTM_ERR_DIVERGED, "VTM diverged (non-finite or growing residual)");
+    if (!done) return fail(VTM_ERR_NOT_CONVERGED, "tolerance not reached within max_sweeps");
+    return VTM_OK;
+}
+
+template <typename T>
+vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int64_t nsweeps, double *x, int64_t ldx) {
+    vtm_status rc;
+    if ((rc = ensure_waves<T>(h, nrhs))) return rc;
+    if ((rc = alloc_solve<T>(h, nrhs))) return rc;
+    if ((rc = stage_b(h, b, nrhs, ldb))) return rc;
+    const int64_t n = h->P.n;
+    const vtm::DevMaps M = dev_maps(h);
+    vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, h->wave_R, h->d_bsplit.as<T>(), h->stream);
+    if (nsweeps > 0) {
+        run_sweeps_dev<T>(h, nsweeps);
+        vtm::launch_merge<T>(M, n, h->nsplit, nrhs, h->wave_R, h->d_xloc.as<T>(), nullptr, n, h->d_x.as<double>(), n,
+                             h->stream);
+    } else {
+        HIP_TRY(hipMemsetAsync(h->d_x.p, 0, sizeof(double) * n * nrhs, h->stream));
+    }
+    return write_x(h, h->d_x.as<double>(), x, nrhs, ldx);
+}
+
+template <typename T>
+vtm_status waves_io(vtm_ctx *h, double *a_out, const double *a_in, int32_t nrhs) {
+    vtm_status rc;
+    if ((rc = ensure_waves<T>(h, nrhs))) return rc;
+    const int32_t R = h->wave_R, ng = (nrhs + R - 1) / R;
+    const int64_t np = h->nports;
+    std::vector<T> o((size_t)ng * np * R);
+    const std::vector<int64_t> &tw = h->P.port_twin;
+    if (a_out) {
+        HIP_TRY(hipMemcpyAsync(o.data(), h->d_o[h->cur].p, sizeof(T) * o.size(), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        for (int32_t c = 0; c < nrhs; ++c) {
+            const int32_t g = c / R, cc = c % R;
+            for (int64_t p = 0; p < np; ++p) a_out[(int64_t)c * np + p] = (double)o[((size_t)g * np + tw[p]) * R + cc];
+        }
+    } else {
+        std::fill(o.begin(), o.end(), (T)0);
+        for (int32_t c = 0; c < nrhs; ++c) {
+            const int32_t g = c / R, cc = c % R;
+            for (int64_t p = 0; p < np; ++p) o[((size_t)g * np + tw[p]) * R + cc] = (T)a_in[(int64_t)c * np + p];
+        }
+        HIP_TRY(hipMemcpyAsync(h->d_o[h->cur].p, o.data(), sizeof(T) * o.size(), hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->waves_zero = false;
+    }
+    return VTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vtm_last_error(void) { return g_err.c_str(); }
+
+vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
+    if (!out) return fail(VTM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    vtm_ctx *h = new (std::nothrow) vtm_ctx();
+    if (!h) return fail(VTM_ERR_OOM, "handle allocation failed");
+    if (options) h->opt = *options;
+    if (h->opt.precision != VTM_FP64 && h->opt.precision != VTM_FP32_IR) {
+        delete h;
+        return fail(VTM_ERR_INVALID, "unknown precision");
+    }
+    if (h->opt.device < 0) {  // host-only handle: partition and symbolic analysis, no device work
+        *out = h;
+        return VTM_OK;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0) {
+        delete h;
+        return fail(VTM_ERR_HIP, "no HIP device available");
+    }
+    if (h->opt.device < 0 || h->opt.device >= ndev) {
+        delete h;
+        return fail(VTM_ERR_INVALID, "device ordinal out of range");
+    }
+    if ((e = hipSetDevice(h->opt.device)) != hipSuccess) {
+        delete h;
+        return fail(VTM_ERR_HIP, hipGetErrorString(e));
+    }
+    if (h->opt.stream) h->stream = (hipStream_t)h->opt.stream;
+    else {
+        if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess) {
+            delete h;
+            return fail(VTM_ERR_HIP, hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    *out = h;
+    return VTM_OK;
+}
+
+vtm_status vtm_destroy(vtm_handle h) {
+    delete h;
+    return VTM_OK;
+}
+
+vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                             const vtm_partition_spec *spec, vtm_partition_info *info) {
+    if (!h || !rowptr || !col || !val || !spec || n < 1) return fail(VTM_ERR_INVALID, "null argument or n < 1");
+    if (rowptr[0] != 0 || rowptr[n] < n) return fail(VTM_ERR_INVALID, "rowptr invalid");
+    if (!h->host_only()) HIP_TRY(hipSetDevice(h->opt.device));
+    h->partitioned = h->set_up = false;
+    h->A.n = n;
+    h->A.rp.assign(rowptr, rowptr + n + 1);
+    h->A.ci.assign(col, col + rowptr[n]);
+    h->A.v.assign(val, val + rowptr[n]);
+    std::string err;
+    int rc = vtm::build_partition(h->A, *spec, h->P, err);
+    if (rc) return fail(rc, err);
+    int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : 8;
+    rc = vtm::build_symbolic(h->P, leaf, h->S, err);
+    if (rc) return fail(rc, err);
+    if (h->host_only()) host_sizes(h);
+    else if ((rc = upload_partition(h))) return rc;
+    h->wave_nrhs = 0;
+    h->partitioned = true;
+    if (info) {
+        info->nsub = h->P.nsub;
+        info->nclass = (int32_t)h->S.classes.size();
+        info->n_split = h->nsplit;
+        info->nvtl = (int64_t)h->P.vtl_v.size();
+        info->nports = h->nports;
+        info->max_local = h->max_nk;
+        info->nsys = h->P.nsys;
+        info->factor_entries = h->total_lower;
+    }
+    return VTM_OK;
+}
+
+vtm_status vtm_get_partition(vtm_handle h, int64_t *s_ptr, int32_t *s_idx, int64_t *loc_ptr, int64_t *loc_vtx,
+                             int64_t *lrp, int32_t *lcol, double *lval, int64_t *vtl_v, int32_t *vtl_k,
+                             int32_t *vtl_k2, int64_t *port_ptr, int64_t *port_v, int32_t *port_other,
+                             int64_t *port_twin, double *zdiag) {
+    if (!h) return fail(VTM_ERR_INVALID, "null handle");
+    if (!h->partitioned) return fail(VTM_ERR_STATE, "no partition");
+    const vtm::Partition &P = h->P;
+    auto cp = [](auto *dst, const auto &src) {
+        if (dst) std::copy(src.begin(), src.end(), dst);
+    };
+    cp(s_ptr, P.s_ptr); cp(s_idx, P.s_idx); cp(loc_ptr, P.loc_ptr); cp(loc_vtx, P.loc_vtx); cp(lrp, P.lrp);
+    cp(lcol, P.lcol); cp(lval, P.lval); cp(vtl_v, P.vtl_v); cp(vtl_k, P.vtl_k); cp(vtl_k2, P.vtl_k2);
+    cp(port_ptr, P.port_ptr); cp(port_v, P.port_v); cp(port_other, P.port_other); cp(port_twin, P.port_twin);
+    cp(zdiag, P.zdiag);
+    return VTM_OK;
+}
+
+vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
+    if (!h) return fail(VTM_ERR_INVALID, "null handle");
+    if (h->host_only()) return fail(VTM_ERR_STATE, "host-only handle (device < 0) cannot set up");
+    if (!h->partitioned) return fail(VTM_ERR_STATE, "vtm_setup before vtm_evs_partition");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    const vtm::Partition &P = h->P;
+    const int64_t nvtl = (int64_t)P.vtl_v.size();
+    std::vector<double> z;
+    if (z_rule == VTM_Z_DIAG) z = P.zdiag;
+    else if (z_rule == VTM_Z_USER) {
+        if (!z_vtl && nvtl) return fail(VTM_ERR_INVALID, "VTM_Z_USER needs z_vtl");
+        z.assign(z_vtl, z_vtl + nvtl);
+        for (int64_t l = 0; l < nvtl; ++l)
+            if (!(z[l] > 0.0) || !std::isfinite(z[l])) return fail(VTM_ERR_INVALID, "Z must be finite and > 0");
+    } else {
+        return fail(VTM_ERR_INVALID, "unsupported z_rule (no impedance model loaded)");
+    }
+    hipStream_t st = h->stream;
+    HIP_TRY(upload(h->d_z, z, st));
+    HIP_TRY(ensure(h->d_invz64, sizeof(double) * (h->nports + 1)));
+    HIP_TRY(ensure(h->d_invz32, sizeof(float) * (h->nports + 1)));
+    HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
+    HIP_TRY(ensure(h->d_status, sizeof(int32_t) * (P.nsub + 1)));
+    DevBuf ws;
+    HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
+                     h->d_invz32.as<float>(), h->nports, st);
+    vtm::launch_factor(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_front, h->d_aval.as<double>(),
+                       h->d_invz64.as<double>(), h->d_vals64.as<double>(), ws.as<double>(), 0,
+                       h->d_status.as<int32_t>(), st);
+    if (h->fp32()) {
+        HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
+        vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> status(P.nsub);
+    HIP_TRY(hipMemcpyAsync(status.data(), h->d_status.p, sizeof(int32_t) * P.nsub, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ws.release();
+    h->stats.setup_ms = ms;
+    for (int32_t k = 0; k < P.nsub; ++k)
+        if (status[k]) {
+            h->set_up = false;
+            return fail(VTM_ERR_NOT_SPD, "non-positive pivot in subgraph " + std::to_string(k) + " (supernode " +
+                                             std::to_string(status[k] - 1) + ")");
+        }
+    h->set_up = true;
+    h->wave_nrhs = 0;  // fresh zero waves on the next solve
+    return VTM_OK;
+}
+
+vtm_status vtm_solve(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
+                     int32_t *iters, double *relres) {
+    if (!h || !b || !x || nrhs < 1) return fail(VTM_ERR_INVALID, "null argument or nrhs < 1");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "vtm_solve before vtm_setup");
+    if (!(tol > 0.0) || ldb < h->P.n || ldx < h->P.n) return fail(VTM_ERR_INVALID, "tol <= 0 or leading dimension < n");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    return h->fp32() ? solve_impl<float>(h, b, nrhs, ldb, tol, x, ldx, iters, relres)
+                     : solve_impl<double>(h, b, nrhs, ldb, tol, x, ldx, iters, relres);
+}
+
+vtm_status vtm_run_sweeps(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, int64_t nsweeps, double *x,
+                          int64_t ldx) {
+    if (!h || !b || !x || nrhs < 1 || nsweeps < 0) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "vtm_run_sweeps before vtm_setup");
+    if (ldb < h->P.n || ldx < h->P.n) return fail(VTM_ERR_INVALID, "leading dimension < n");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    return h->fp32() ? run_impl<float>(h, b, nrhs, ldb, nsweeps, x, ldx)
+                     : run_impl<double>(h, b, nrhs, ldb, nsweeps, x, ldx);
+}
+
+vtm_status vtm_reset_waves(vtm_handle h) {
+    if (!h) return fail(VTM_ERR_INVALID, "null handle");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "no setup");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    if (!h->d_o[0].p) return VTM_OK;
+    vtm_status rc = h->fp32() ? zero_waves<float>(h) : zero_waves<double>(h);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return VTM_OK;
+}
+
+vtm_status vtm_get_waves(vtm_handle h, double *a, int32_t nrhs) {
+    if (!h || !a || nrhs < 1) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "no setup");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    return h->fp32() ? waves_io<float>(h, a, nullptr, nrhs) : waves_io<double>(h, a, nullptr, nrhs);
+}
+
+vtm_status vtm_set_waves(vtm_handle h, const double *a, int32_t nrhs) {
+    if (!h || !a || nrhs < 1) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "no setup");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    return h->fp32() ? waves_io<float>(h, nullptr, a, nrhs) : waves_io<double>(h, nullptr, a, nrhs);
+}
+
+vtm_status vtm_debug_class(vtm_handle h, int32_t k, int64_t *sizes, int32_t *perm, int32_t *sn, int32_t *lev_c0,
+                           uint16_t *ridx, uint16_t *rel, int32_t *sc) {
+    if (!h || !sizes) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->partitioned || k < 0 || k >= h->P.nsub) return fail(VTM_ERR_STATE, "no partition or k out of range");
+    const vtm::ClassSym &C = h->S.classes[h->S.sub_class[k]];
+    sizes[0] = C.nk; sizes[1] = C.nsn; sizes[2] = C.nlev; sizes[3] = (int64_t)C.ridx.size();
+    sizes[4] = (int64_t)C.sc_src.size(); sizes[5] = C.nval; sizes[6] = C.ws_u; sizes[7] = h->S.sub_class[k];
+    if (perm) std::copy(C.perm.begin(), C.perm.end(), perm);
+    if (sn)
+        for (int32_t s = 0; s < C.nsn; ++s) {
+            int32_t *r = sn + 10 * s;
+            r[0] = C.sn_c0[s]; r[1] = C.sn_nc[s]; r[2] = C.sn_m[s]; r[3] = C.sn_val[s];
+            r[4] = C.sn_ridx[s]; r[5] = C.sn_parent[s]; r[6] = C.sn_level[s]; r[7] = C.sn_uoff[s];
+            r[8] = C.sc_ptr[s]; r[9] = C.sc_ptr[s + 1];
+        }
+    if (lev_c0) std::copy(C.lev_c0.begin(), C.lev_c0.end(), lev_c0);
+    if (ridx) std::copy(C.ridx.begin(), C.ridx.end(), ridx);
+    if (rel) std::copy(C.rel.begin(), C.rel.end(), rel);
+    if (sc)
+        for (size_t i = 0; i < C.sc_src.size(); ++i) { sc[2 * i] = C.sc_src[i]; sc[2 * i + 1] = C.sc_dst[i]; }
+    return VTM_OK;
+}
+
+vtm_status vtm_get_stats(vtm_handle h, vtm_stats *out) {
+    if (!h || !out) return fail(VTM_ERR_INVALID, "bad argument");
+    *out = h->stats;
+    return VTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,421 @@
+// HIP kernels of libvtm for gfx950 (CDNA4, 64-wide wavefronts).
+//
+//  k_factor   one workgroup per subgraph: multifrontal Cholesky of the
+//             port-augmented matrix K_k of eq. (5.8), front by front in
+//             level order; the diagonal block of every supernode is stored
+//             inverted so that the sweep has no long sequential chains.
+//  k_sweep    one workgroup per (subgraph, group of right-hand sides): one VTM
+//             sweep (Table 1 steps 3-5).  Gathers the incoming waves from the
+//             twins' outgoing waves of the previous sweep (the delay of (5.6)),
+//             forms the right side of (5.8), runs the level-synchronous forward
+//             and backward substitutions in LDS and writes the outgoing waves
+//             o_p = u_p - Z w_p = 2 u_p - a_p.
+//  k_split / k_merge / k_residual: source split b_v/|S(v)|, merged potentials
+//             (mean over the children) and the FP64 relative residual.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace vtm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_invz(const double *__restrict__ z, const int32_t *__restrict__ port_vtl, double *__restrict__ i64,
+                       float *__restrict__ i32, int64_t np) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    double v = 1.0 / z[port_vtl[p]];
+    i64[p] = v;
+    i32[p] = (float)v;
+}
+
+__global__ void k_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (float)s[i];
+}
+
+// ---------------------------------------------------------------- factorisation
+__global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const double *__restrict__ aval,
+                                                     const double *__restrict__ invz, double *__restrict__ vals,
+                                                     double *__restrict__ ws, int lds_front,
+                                                     int32_t *__restrict__ status) {
+    extern __shared__ double sm[];
+    const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int nk = C.nk;
+    double *dplus = sm;
+    double *Fl = sm + ((nk + 1) & ~1);
+    const double *A = aval + D.aval[k];
+    double *V = vals + D.val[k];
+    double *W = ws + D.ws[k];
+    const int32_t *sn_c0 = S.sn_c0 + C.o_sn, *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn;
+    const int32_t *sn_val = S.sn_val + C.o_sn, *sn_ridx = S.sn_ridx + C.o_sn, *sn_uoff = S.sn_uoff + C.o_sn;
+    const int32_t *ch_ptr = S.ch_ptr + C.o_snp, *ch_idx = S.ch_idx + C.o_chi;
+    const int32_t *sc_ptr = S.sc_ptr + C.o_snp, *sc_src = S.sc_src + C.o_sc, *sc_dst = S.sc_dst + C.o_sc;
+    const uint16_t *rel = S.rel + C.o_ridx;
+
+    // diagonal additions Z^{-1} of the ports, one thread per port vertex (ports in order)
+    for (int i = tid; i < nk; i += nt) dplus[i] = 0.0;
+    __syncthreads();
+    for (int g = D.pg_ptr[k] + tid; g < D.pg_ptr[k + 1]; g += nt) {
+        double s = 0.0;
+        for (int j = 0; j < D.pg_cnt[g]; ++j) s += invz[D.pg_beg[g] + j];
+        dplus[D.pg_pos[g]] = s;
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int s = 0; s < C.nsn; ++s) {
+        const int c0 = sn_c0[s], nc = sn_nc[s], m = sn_m[s], f = nc + m;
+        double *F = lds_front ? Fl : W + C.ws_u;
+        for (int i = tid; i < f * f; i += nt) F[i] = 0.0;
+        __syncthreads();
+        for (int e = sc_ptr[s] + tid; e < sc_ptr[s + 1]; e += nt) F[sc_dst[e]] = A[sc_src[e]];
+        __syncthreads();
+        for (int j = tid; j < nc; j += nt) F[j * f + j] += dplus[c0 + j];
+        // extend-add the children's update matrices, one child at a time
+        for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
+            __syncthreads();
+            const int c = ch_idx[q], mc = sn_m[c];
+            const double *U = W + sn_uoff[c];
+            const uint16_t *rc = rel + sn_ridx[c];
+            for (int idx = tid; idx < mc * mc; idx += nt) {
+                const int a = idx / mc, b = idx - a * mc;
+                if (b <= a) F[rc[a] * f + rc[b]] += U[idx];
+            }
+        }
+        __syncthreads();
+        // partial Cholesky of the nc pivot columns (right-looking)
+        for (int kk = 0; kk < nc; ++kk) {
+            double d = F[kk * f + kk];
+            if (!(d > 0.0) || !isfinite(d)) { bad = bad ? bad : s + 1; d = 1.0; }
+            const double sd = sqrt(d), rs = 1.0 / sd;
+            __syncthreads();
+            for (int i = kk + 1 + tid; i < f; i += nt) F[i * f + kk] *= rs;
+            if (tid == 0) F[kk * f + kk] = sd;
+            __syncthreads();
+            const int T = f - kk - 1;
+            for (int idx = tid; idx < T * T; idx += nt) {
+                const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
+                if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
+            }
+            __syncthreads();
+        }
+        // outputs: inverse of the diagonal block (row-major, upper part zero), L21, update matrix
+        double *Vs = V + sn_val[s];
+        for (int j = tid; j < nc; j += nt) {
+            for (int i = 0; i < j; ++i) Vs[i * nc + j] = 0.0;
+            Vs[j * nc + j] = 1.0 / F[j * f + j];
+            for (int i = j + 1; i < nc; ++i) {
+                double acc = 0.0;
+                for (int t = j; t < i; ++t) acc += F[i * f + t] * Vs[t * nc + j];
+                Vs[i * nc + j] = -acc / F[i * f + i];
+            }
+        }
+        for (int idx = tid; idx < m * nc; idx += nt) {
+            const int i = idx / nc, j = idx - i * nc;
+            Vs[nc * nc + idx] = F[(nc + i) * f + j];
+        }
+        double *Us = W + sn_uoff[s];
+        for (int idx = tid; idx < m * m; idx += nt) {
+            const int i = idx / m, j = idx - i * m;
+            Us[idx] = F[(nc + i) * f + nc + j];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) status[k] = bad;
+}
+
+// ------------------------------------------------------------------------ split
+template <typename T>
+__global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b, int32_t nrhs, int64_t ldb, int32_t R,
+                        T *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nsplit) return;
+    const int32_t v = M.fvtx[e];
+    const double m = (double)M.fmul[e];
+    const int ng = (nrhs + R - 1) / R;
+    for (int g = 0; g < ng; ++g)
+        for (int cc = 0; cc < R; ++cc) {
+            const int c = g * R + cc;
+            out[((int64_t)g * nsplit + e) * R + cc] = c < nrhs ? (T)(b[v + (int64_t)c * ldb] / m) : (T)0;
+        }
+}
+
+// ------------------------------------------------------------------------ sweep
+template <typename T, int R>
+__global__ __launch_bounds__(kThreads) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
+                                                    const T *__restrict__ vals, const T *__restrict__ bsplit,
+                                                    const int32_t *__restrict__ twin, const T *__restrict__ invz,
+                                                    const T *__restrict__ o_prev, T *__restrict__ o_next,
+                                                    T *__restrict__ xloc, int write_x) {
+    extern __shared__ char smraw[];
+    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int nk = C.nk;
+    T *vec = reinterpret_cast<T *>(smraw);
+    T *tmp = vec + (size_t)nk * R;
+    const T *Vk = vals + D.val[k];
+    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
+    const T *bs = bsplit + xo;
+    const int64_t wo = (int64_t)g * nports * R;
+    const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *col_sn = S.col_sn + C.o_col;
+    const int32_t *sn_c0 = S.sn_c0 + C.o_sn, *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn;
+    const int32_t *sn_val = S.sn_val + C.o_sn, *sn_ridx = S.sn_ridx + C.o_sn;
+    const uint16_t *ridx = S.ridx + C.o_ridx;
+    const int32_t *seg_ptr = S.seg_ptr + C.o_colp, *seg_off = S.seg_off + C.o_seg;
+    const uint16_t *seg_c0 = S.seg_c0 + C.o_seg, *seg_nc = S.seg_nc + C.o_seg;
+
+    // right side of (5.8): split source + Z^{-1} * incoming wave at every port
+    for (int i = tid; i < nk * R; i += nt) vec[i] = bs[i];
+    __syncthreads();
+    const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
+    for (int q = pg0 + tid; q < pg1; q += nt) {
+        const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
+        T acc[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] = vec[pos * R + c];
+        for (int j = 0; j < pc; ++j) {
+            const T iz = invz[pb + j];
+            const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) vec[pos * R + c] = acc[c];
+    }
+    __syncthreads();
+    // forward substitution L y = rhs, one level (independent subtrees) at a time
+    for (int lv = 0; lv < C.nlev; ++lv) {
+        const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
+        for (int i = cb + tid; i < ce; i += nt) {
+            T acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = vec[i * R + c];
+            for (int s = seg_ptr[i]; s < seg_ptr[i + 1]; ++s) {
+                const T *l = Vk + seg_off[s];
+                const T *y = vec + seg_c0[s] * R;
+                const int n = seg_nc[s];
+                for (int j = 0; j < n; ++j) {
+                    const T lj = l[j];
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] -= lj * y[j * R + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) tmp[i * R + c] = acc[c];
+        }
+        __syncthreads();
+        for (int i = cb + tid; i < ce; i += nt) {
+            const int s = col_sn[i], c0 = sn_c0[s], nc = sn_nc[s], jj = i - c0;
+            const T *row = Vk + sn_val[s] + jj * nc;
+            const T *t = tmp + c0 * R;
+            T acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = 0;
+            for (int j = 0; j <= jj; ++j) {
+                const T lj = row[j];
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += lj * t[j * R + c];
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) vec[i * R + c] = acc[c];
+        }
+        __syncthreads();
+    }
+    // backward substitution L^T x = y, root level first
+    for (int lv = C.nlev - 1; lv >= 0; --lv) {
+        const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
+        for (int j = cb + tid; j < ce; j += nt) {
+            const int s = col_sn[j], c0 = sn_c0[s], nc = sn_nc[s], m = sn_m[s], jj = j - c0;
+            const T *col = Vk + sn_val[s] + nc * nc + jj;
+            const uint16_t *r = ridx + sn_ridx[s];
+            T acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = vec[j * R + c];
+            for (int q = 0; q < m; ++q) {
+                const T lq = col[q * nc];
+                const T *x = vec + r[q] * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] -= lq * x[c];
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) tmp[j * R + c] = acc[c];
+        }
+        __syncthreads();
+        for (int j = cb + tid; j < ce; j += nt) {
+            const int s = col_sn[j], c0 = sn_c0[s], nc = sn_nc[s], jj = j - c0;
+            const T *colv = Vk + sn_val[s] + jj;
+            const T *t = tmp + c0 * R;
+            T acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = 0;
+            for (int i = jj; i < nc; ++i) {
+                const T li = colv[i * nc];
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += li * t[i * R + c];
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) vec[j * R + c] = acc[c];
+        }
+        __syncthreads();
+    }
+    // outgoing waves o_p = 2 u_p - a_p
+    for (int q = pg0 + tid; q < pg1; q += nt) {
+        const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
+        for (int j = 0; j < pc; ++j) {
+            const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
+            T *o = o_next + wo + (int64_t)(pb + j) * R;
+#pragma unroll
+            for (int c = 0; c < R; ++c) o[c] = (T)2 * vec[pos * R + c] - a[c];
+        }
+    }
+    if (write_x) {
+        T *xo_ = xloc + xo;
+        for (int i = tid; i < nk * R; i += nt) xo_[i] = vec[i];
+    }
+}
+
+// ------------------------------------------------------------------ merge, residual
+template <typename T>
+__global__ void k_merge(DevMaps M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *__restrict__ xloc,
+                        const double *__restrict__ base, int64_t ldbase, double *__restrict__ xout, int64_t ldx) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t p0 = M.cp_ptr[v], p1 = M.cp_ptr[v + 1];
+    const double m = (double)(p1 - p0);
+    for (int c = 0; c < nrhs; ++c) {
+        const int g = c / R, cc = c - g * R;
+        double acc = 0.0;
+        for (int64_t p = p0; p < p1; ++p) acc += (double)xloc[((int64_t)g * nsplit + M.cp_idx[p]) * R + cc];
+        const double xb = acc / m;
+        xout[v + (int64_t)c * ldx] = base ? base[v + (int64_t)c * ldbase] + xb : xb;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
+                                                       const double *__restrict__ x, int64_t ldx, double *__restrict__ r,
+                                                       int64_t ldr, const int64_t *__restrict__ chunk_row,
+                                                       int32_t nchunks, double *__restrict__ part) {
+    __shared__ double red[2][kThreads];
+    const int ch = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const int64_t r0 = chunk_row[ch], r1 = chunk_row[ch + 1];
+    double rr = 0.0, bb = 0.0;
+    for (int64_t v = r0 + tid; v < r1; v += kThreads) {
+        const double bv = b[v + (int64_t)c * ldb];
+        double acc = bv;
+        for (int64_t e = A.rp[v]; e < A.rp[v + 1]; ++e) acc -= A.v[e] * x[A.ci[e] + (int64_t)c * ldx];
+        if (r) r[v + (int64_t)c * ldr] = acc;
+        rr += acc * acc;
+        bb += bv * bv;
+    }
+    red[0][tid] = rr;
+    red[1][tid] = bb;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) { red[0][tid] += red[0][tid + s]; red[1][tid] += red[1][tid + s]; }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        part[((int64_t)c * nchunks + ch) * 2 + 0] = red[0][0];
+        part[((int64_t)c * nchunks + ch) * 2 + 1] = red[1][0];
+    }
+}
+
+__global__ void k_relres(const double *__restrict__ part, int32_t nchunks, const int32_t *__restrict__ sys_chunk_ptr,
+                         int32_t nsys, int32_t nrhs, double *__restrict__ relres) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nsys * nrhs) return;
+    const int c = t / nsys, s = t - c * nsys;
+    double rr = 0.0, bb = 0.0;
+    for (int q = sys_chunk_ptr[s]; q < sys_chunk_ptr[s + 1]; ++q) {
+        rr += part[((int64_t)c * nchunks + q) * 2 + 0];
+        bb += part[((int64_t)c * nchunks + q) * 2 + 1];
+    }
+    relres[c * nsys + s] = bb > 0.0 ? sqrt(rr) / sqrt(bb) : sqrt(rr);
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, float *invz32, int64_t nports,
+                 hipStream_t st) {
+    if (nports == 0) return;
+    hipLaunchKernelGGL(k_invz, dim3(blocks_for(nports, 256)), dim3(256), 0, st, z_vtl, port_vtl, invz64, invz32, nports);
+}
+
+void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_front,
+                   const double *aval, const double *invz, double *vals, double *ws, int64_t, int32_t *status,
+                   hipStream_t st) {
+    size_t base = sizeof(double) * (size_t)((max_nk + 1) & ~1);
+    size_t front = sizeof(double) * (size_t)max_front * max_front;
+    int lds_front = base + front <= 96 * 1024;
+    size_t shm = base + (lds_front ? front : 0);
+    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_front, status);
+}
+
+void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {
+    if (n == 0) return;
+    unsigned nb = blocks_for(n, 256);
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, st, src, dst, n);
+}
+
+template <typename T>
+void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int64_t ldb, int32_t R, T *bsplit,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, ldb, R, bsplit);
+}
+
+template <typename T>
+void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t ngroups, int32_t R,
+                  int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin, const T *invz,
+                  const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st) {
+    size_t shm = 2 * sizeof(T) * (size_t)max_nk * R;
+    dim3 grid(nsub, ngroups);
+    if (shm > 64 * 1024) {
+        const void *fn = R == 1 ? (const void *)k_sweep<T, 1> : R == 2 ? (const void *)k_sweep<T, 2>
+                       : R == 4 ? (const void *)k_sweep<T, 4> : (const void *)k_sweep<T, 8>;
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    }
+    switch (R) {
+        case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        default: hipLaunchKernelGGL((k_sweep<T, 8>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+    }
+}
+
+template <typename T>
+void launch_merge(const DevMaps &M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc,
+                  const double *base, int64_t ldbase, double *xout, int64_t ldx, hipStream_t st) {
+    hipLaunchKernelGGL(k_merge<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, M, n, nsplit, nrhs, R, xloc, base, ldbase,
+                       xout, ldx);
+}
+
+void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, int64_t ldb, const double *x, int64_t ldx,
+                     double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *, int32_t nchunks,
+                     const int32_t *sys_chunk_ptr, int32_t nsys, double *part, double *relres, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual, dim3(nchunks, nrhs), dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr,
+                       chunk_row, nchunks, part);
+    hipLaunchKernelGGL(k_relres, dim3(blocks_for((int64_t)nsys * nrhs, 64)), dim3(64), 0, st, part, nchunks,
+                       sys_chunk_ptr, nsys, nrhs, relres);
+}
+
+template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);
+template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, float *, hipStream_t);
+template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int64_t, int64_t,
+                                   const double *, const double *, const int32_t *, const double *, const double *,
+                                   double *, double *, int, hipStream_t);
+template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int64_t, int64_t,
+                                  const float *, const float *, const int32_t *, const float *, const float *, float *,
+                                  float *, int, hipStream_t);
+template void launch_merge<double>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const double *, const double *,
+                                   int64_t, double *, int64_t, hipStream_t);
+template void launch_merge<float>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const float *, const double *,
+                                  int64_t, double *, int64_t, hipStream_t);
+
+}  // namespace vtm

@@ -1,0 +1,95 @@
+// Device data views and kernel launchers of libvtm (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vtm {
+
+// Per-class symbolic data: offsets into the concatenated class arrays.
+struct ClassDev {
+    int32_t nk, nsn, nlev, max_front;
+    int32_t o_lev;   // lev_c0        (nlev + 1 per class)
+    int32_t o_sn;    // sn_* arrays   (nsn per class)
+    int32_t o_snp;   // ch_ptr, sc_ptr (nsn + 1 per class)
+    int32_t o_col;   // col_sn        (nk per class)
+    int32_t o_colp;  // seg_ptr       (nk + 1 per class)
+    int32_t o_ridx;  // ridx, rel
+    int32_t o_seg;   // seg_off, seg_c0, seg_nc
+    int32_t o_sc;    // sc_src, sc_dst
+    int32_t o_chi;   // ch_idx
+    int32_t pad;
+    int64_t nval, ws_u;
+};
+
+struct DevSym {
+    const ClassDev *cls;
+    const int32_t *lev_c0, *col_sn;
+    const int32_t *sn_c0, *sn_nc, *sn_m, *sn_val, *sn_ridx, *sn_uoff;
+    const uint16_t *ridx, *rel;
+    const int32_t *ch_ptr, *ch_idx;
+    const int32_t *seg_ptr, *seg_off;
+    const uint16_t *seg_c0, *seg_nc;
+    const int32_t *sc_ptr, *sc_src, *sc_dst;
+};
+
+struct DevSub {
+    const int32_t *cls;
+    const int64_t *val;   // factor value offset
+    const int64_t *x;     // offset of the subgraph's entries in split vectors (factor order)
+    const int64_t *aval;  // offset of the local CSR values
+    const int64_t *ws;    // factorisation workspace offset
+    const int32_t *pg_ptr;   // port groups of each subgraph (nsub + 1)
+    const uint16_t *pg_pos;  // factor position of the group's vertex
+    const int32_t *pg_beg;   // first port of the group
+    const int32_t *pg_cnt;   // ports in the group
+};
+
+// Split-vector and merge maps.
+struct DevMaps {
+    const int32_t *fvtx;   // split entry (factor order) -> global vertex
+    const int32_t *fmul;   // |S(v)| of that vertex
+    const int64_t *cp_ptr; // vertex -> its split entries
+    const int32_t *cp_idx;
+};
+
+struct DevCsr {
+    const int64_t *rp;
+    const int32_t *ci;
+    const double *v;
+};
+
+void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, float *invz32, int64_t nports,
+                 hipStream_t st);
+
+// FP64 multifrontal factorisation of every port-augmented local matrix; status[k] = 1 + supernode of the
+// first non-positive pivot (0 if fine).  lds_front selects LDS-resident fronts.
+void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_front,
+                   const double *aval, const double *invz, double *vals, double *ws, int64_t ws_front_off_stride,
+                   int32_t *status, hipStream_t st);
+
+void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+
+template <typename T>
+void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int64_t ldb, int32_t R,
+                  T *bsplit, hipStream_t st);
+
+// One VTM sweep over all subgraphs and right-hand-side groups.
+template <typename T>
+void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t ngroups, int32_t R,
+                  int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin, const T *invz,
+                  const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st);
+
+// xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
+template <typename T>
+void launch_merge(const DevMaps &M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc,
+                  const double *base, int64_t ldbase, double *xout, int64_t ldx, hipStream_t st);
+
+// r = b - A x (optional store), per (rhs, system) relative residual into relres[c * nsys + s].
+void launch_residual(const DevCsr &A, int64_t n, int32_t nrhs, const double *b, int64_t ldb, const double *x,
+                     int64_t ldx, double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *chunk_sys,
+                     int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, double *relres,
+                     hipStream_t st);
+
+}  // namespace vtm

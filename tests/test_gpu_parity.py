@@ -1,0 +1,167 @@
+"""GPU parity: libvtm (HIP, gfx950) against the CPU oracle, through the C ABI.
+
+Tolerances.  Both sides run the same iteration in FP64 from the same split:
+iterates at a fixed sweep count differ only by rounding order (factor
+ordering, inverted diagonal blocks), which grows at most linearly with the
+sweep count for a nonexpansive iteration (Appendix 3), so 1e-10 relative is a
+generous bound for <= a few hundred sweeps.  Converged solutions are compared
+at the same stopping rule; FP32 sweeps with FP64 refinement are compared with
+the FP64 oracle's converged solution.
+"""
+import numpy as np
+import pytest
+
+import gen
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0807_1949_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _setup(B, cfg, precision=0, check_every=1, z_scale=1.0, **kw):
+    h = B.VTM(device=0, precision=precision, check_every=check_every, **kw)
+    h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+    P = O.Partition(cfg["A"], cfg["spec"])
+    z = z_scale * P.zdiag
+    h.setup(B.VTM_Z_USER, z)
+    return h, P, z
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+def test_iterates_match_oracle(B, name):
+    """Merged potentials after 1, 3 and 40 sweeps from zero waves, every config (small sizes)."""
+    cfg = gen.make_config(name, small=True)
+    print(f"[parity] iterates {name}", flush=True)
+    h, P, z = _setup(B, cfg, z_scale=8.0)
+    s = O.Solver(P, z)
+    b = cfg["b"][:2] if name in ("c3", "c5") else cfg["b"][:1]
+    for k in (1, 3, 40):
+        h.reset_waves()
+        xg = h.run_sweeps(b, k)
+        xo = s.run(b, k, 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"]
+        for r in range(b.shape[0]):
+            assert _rel(xg[r], xo[r]) <= 1e-10, (name, k, r, _rel(xg[r], xo[r]))
+
+
+def test_c1_converged_matches_oracle(B):
+    """C1 as specified: diagonal-rule Z, tol 1e-10; same sweep count and x within 1e-8 of the oracle."""
+    cfg = gen.make_config("c1")
+    h = B.VTM(device=0, check_every=1)
+    h.evs_partition(cfg["A"], cfg["spec"])
+    h.setup(B.VTM_Z_DIAG)
+    r = h.solve(cfg["b"], 1e-10)
+    P = O.Partition(cfg["A"], cfg["spec"])
+    ro = O.Solver(P, P.zdiag).run(cfg["b"], 100000, 1, 1e-10)
+    assert r["status"] == 0
+    assert abs(int(r["iters"][0, 0]) - int(ro["iters"][0, 0])) <= 1
+    assert _rel(r["x"][0], ro["x"][0]) <= 1e-8
+    assert r["relres"][0, 0] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_small_converged(B, precision):
+    """Lognormal conductances, 4x4 tiles of 33: FP64 and FP32+IR reach 1e-8 and match the oracle."""
+    cfg = gen.make_config("c2", small=True)
+    h, P, z = _setup(B, cfg, precision=precision, check_every=10, z_scale=32.0)
+    r = h.solve(cfg["b"], 1e-8)
+    assert r["status"] == 0 and r["relres"][0, 0] <= 1e-8
+    ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-12)
+    assert ro["relres"][0, 0] <= 1e-12
+    x_exact = ro["x"][0]
+    # the residual bounds the error by the condition number; measure against a tight oracle solve
+    A = cfg["A"].to_scipy()
+    err = _rel(r["x"][0], x_exact)
+    res = np.linalg.norm(cfg["b"][0] - A @ r["x"][0]) / np.linalg.norm(cfg["b"][0])
+    assert res <= 1e-8
+    assert err <= 1e-5, err
+    if precision == 0:
+        ro8 = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8)
+        assert _rel(r["x"][0], ro8["x"][0]) <= 1e-8
+        assert int(r["iters"][0, 0]) == int(ro8["iters"][0, 0])
+
+
+def test_multi_rhs_and_batch(B):
+    """C5 small: a batch of 4 independent systems x 4 RHS, per-system convergence."""
+    cfg = gen.make_config("c5", small=True)
+    h, P, z = _setup(B, cfg, check_every=10, z_scale=8.0)
+    r = h.solve(cfg["b"], 1e-8)
+    assert r["status"] == 0
+    assert r["iters"].shape == (4, cfg["nsys"]) and (r["iters"] > 0).all()
+    ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8, sys_ptr=cfg["sys_ptr"])
+    assert (r["relres"] <= 1e-8).all()
+    for c in range(4):
+        assert _rel(r["x"][c], ro["x"][c]) <= 1e-7
+
+
+def test_checkpoint_resume_bitwise(B):
+    """k1 sweeps, export the waves, import into a fresh handle, k2 sweeps == k1 + k2 uninterrupted."""
+    cfg = gen.make_config("c2", small=True)
+    h1, P, z = _setup(B, cfg, z_scale=16.0)
+    full = h1.run_sweeps(cfg["b"], 30)
+    h1.reset_waves()
+    h1.run_sweeps(cfg["b"], 12)
+    a = h1.get_waves(1)
+    h2, _, _ = _setup(B, cfg, z_scale=16.0)
+    h2.set_waves(a)
+    resumed = h2.run_sweeps(cfg["b"], 18)
+    assert np.array_equal(resumed, full)
+
+
+def test_device_pointers(B):
+    """b and x as device (torch) tensors give the same result as host arrays."""
+    import torch
+
+    cfg = gen.make_config("c1")
+    h, P, z = _setup(B, cfg, check_every=5, z_scale=16.0)
+    rh = h.solve(cfg["b"], 1e-10)
+    bd = torch.tensor(cfg["b"], dtype=torch.float64, device="cuda")
+    rd = h.solve(bd, 1e-10)
+    assert np.array_equal(rd["x"].cpu().numpy(), rh["x"])
+
+
+def test_not_spd_detected(B):
+    """A non-conformal split (EQUAL rule on lognormal weights) with tiny port terms is rejected."""
+    A = gen.lognormal_conductance_2d(65, seed=2)
+    spec = dict(kind="grid", dims=(65, 65, 1), parts=(2, 2, 1))
+    h = B.VTM(device=0)
+    info = h.evs_partition(A, spec, split="equal")
+    with pytest.raises(B.VTMError) as e:
+        h.setup(B.VTM_Z_USER, np.full(info["nvtl"], 1e12))
+    assert e.value.code == B.VTM_ERR_NOT_SPD
+
+
+def test_invalid_inputs(B):
+    cfg = gen.make_config("c1")
+    h = B.VTM(device=0)
+    with pytest.raises(B.VTMError) as e:
+        h.solve(cfg["b"], 1e-8)  # before partition/setup
+    assert e.value.code == B.VTM_ERR_STATE
+    info = h.evs_partition(cfg["A"], cfg["spec"])
+    with pytest.raises(B.VTMError) as e:
+        h.setup(B.VTM_Z_USER, np.full(info["nvtl"], -1.0))
+    assert e.value.code == B.VTM_ERR_INVALID
+
+
+def test_c2_full_iterates(B):
+    """C2 at full size (1024^2, 32x32 tiles), the benchmark's FP64 launch: 20 sweeps vs the oracle."""
+    cfg = gen.make_config("c2")
+    print("[parity] c2 full", flush=True)
+    h, P, z = _setup(B, cfg, z_scale=64.0)
+    xg = h.run_sweeps(cfg["b"], 20)
+    xo = O.Solver(P, z).run(cfg["b"], 20, 0, 0.0)["x"]
+    assert _rel(xg[0], xo[0]) <= 1e-10

@@ -1,0 +1,163 @@
+"""Host-side checks of libvtm that need no GPU.
+
+* the shared library loads and exports every entry point the headers declare;
+* the library's EVS partition equals the oracle's bit for bit (membership,
+  local vertex lists, split values, VTLs, ports, twins, diagonal-rule Z);
+* the symbolic analysis is a valid multifrontal elimination: re-running it in
+  NumPy from the exported class data reproduces K = L L^T of eq. (5.8)'s local
+  matrix exactly up to rounding.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gen
+from oracle import oracle as O
+
+from paper_0807_1949_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_declared_symbols():
+    L = B.lib()
+    names = set()
+    for h in ("vtm.h", "vtm_debug.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"\b(vtm_[a-z_]+)\s*\(", src))
+    assert names == set(B.EXPORTS)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def _host_handle():
+    return B.VTM(device=-1)
+
+
+def _assert_partition_equal(lp, op):
+    for key in ("s_ptr", "s_idx", "loc_ptr", "loc_vtx", "lrp", "lcol", "vtl_v", "vtl_k", "vtl_k2", "port_ptr",
+                "port_v", "port_other", "port_twin"):
+        a, b = lp[key], getattr(op, key)
+        assert a.shape == b.shape and np.array_equal(a, b.astype(a.dtype)), key
+    for key in ("lval", "zdiag"):
+        assert np.array_equal(lp[key].view(np.uint64), getattr(op, key).view(np.uint64)), key
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+def test_partition_bit_exact_small(name):
+    cfg = gen.make_config(name, small=True)
+    h = _host_handle()
+    h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+    _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"]))
+
+
+@pytest.mark.parametrize("split,topo", [("equal", "face"), ("branch", "complete")])
+def test_partition_bit_exact_rules(split, topo):
+    cfg = gen.make_config("c3", small=True)
+    h = _host_handle()
+    h.evs_partition(cfg["A"], cfg["spec"], split=split, topology=topo)
+    _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"], split=split, topology=topo))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c4"])
+def test_partition_bit_exact_full(name):
+    cfg = gen.make_config(name)
+    h = _host_handle()
+    info = h.evs_partition(cfg["A"], cfg["spec"])
+    _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"]))
+    if name == "c2":
+        assert info["nsub"] == 1024 and info["n_split"] == 1113025 and info["nvtl"] == 65410
+
+
+def test_partition_errors():
+    A = gen.laplace2d_dirichlet(8)
+    h = _host_handle()
+    with pytest.raises(B.VTMError) as e:
+        h.evs_partition(A, dict(kind="grid", dims=(8, 7, 1), parts=(2, 2, 1)))
+    assert e.value.code == B.VTM_ERR_INVALID
+    # an edge whose endpoints share no subgraph
+    s_ptr = np.arange(65, dtype=np.int64)
+    s_idx = (np.arange(64) >= 32).astype(np.int32)
+    with pytest.raises(B.VTMError) as e:
+        h.evs_partition(A, dict(kind="user", s_ptr=s_ptr, s_idx=s_idx, nsub=2))
+    assert e.value.code == B.VTM_ERR_PARTITION
+    # non-symmetric values
+    A2 = gen.laplace2d_dirichlet(8)
+    A2.val = A2.val.copy()
+    A2.val[1] = -0.5
+    with pytest.raises(B.VTMError) as e:
+        h.evs_partition(A2, dict(kind="grid", dims=(8, 8, 1), parts=(2, 2, 1)))
+    assert e.value.code == B.VTM_ERR_INVALID
+    # setup on a host-only handle is a state error
+    h.evs_partition(A, dict(kind="grid", dims=(8, 8, 1), parts=(2, 2, 1)))
+    with pytest.raises(B.VTMError) as e:
+        h.setup()
+    assert e.value.code == B.VTM_ERR_STATE
+
+
+def _emulate_multifrontal(d, lval, dplus):
+    """Re-run the device factorisation in NumPy from the class data: assemble every front from the
+    scatter pairs (local CSR values) and the port diagonal, extend-add the children's update
+    matrices through the relative indices, eliminate the pivot columns.  Returns L (factor order)."""
+    nk, sn = d["nk"], d["sn"]
+    L = np.zeros((nk, nk))
+    U, fronts = {}, {}
+    for s in range(d["nsn"]):
+        c0, nc, m, _, ro, _, _, _, sc0, sc1 = sn[s]
+        f = nc + m
+        idx = np.concatenate([np.arange(c0, c0 + nc), d["ridx"][ro:ro + m].astype(np.int64)])
+        fronts[s] = idx
+        F = np.zeros(f * f)
+        F[d["sc"][sc0:sc1, 1]] = lval[d["sc"][sc0:sc1, 0]]
+        F = F.reshape(f, f)
+        F[np.arange(nc), np.arange(nc)] += dplus[c0:c0 + nc]
+        for c in np.nonzero(sn[:, 5] == s)[0]:
+            mc = sn[c, 2]
+            rel = d["rel"][sn[c, 4]:sn[c, 4] + mc].astype(np.int64)
+            assert np.array_equal(idx[rel], fronts[c][sn[c, 1]:])
+            F[np.ix_(rel, rel)] += np.tril(U[c])
+        for kk in range(nc):
+            F[kk, kk] = np.sqrt(F[kk, kk])
+            F[kk + 1:, kk] /= F[kk, kk]
+            F[kk + 1:, kk + 1:] -= np.tril(np.outer(F[kk + 1:, kk], F[kk + 1:, kk]))
+        L[np.ix_(idx, np.arange(c0, c0 + nc))] = np.tril(F[:, :nc])
+        U[s] = F[nc:, nc:]
+    return L
+
+
+@pytest.mark.parametrize("name,k", [("c1", 5), ("c2", 0), ("c3", 7), ("c4", 3), ("c5", 2)])
+def test_symbolic_analysis_factorises(name, k):
+    cfg = gen.make_config(name, small=True)
+    h = _host_handle()
+    h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+    p = h.get_partition()
+    d = h.debug_class(k)
+    b, e = p["loc_ptr"][k], p["loc_ptr"][k + 1]
+    nk = e - b
+    assert nk == d["nk"]
+    K = np.zeros((nk, nk))
+    for i in range(nk):
+        s, t = p["lrp"][b + i], p["lrp"][b + i + 1]
+        K[i, p["lcol"][s:t]] = p["lval"][s:t]
+    # port augmentation Z^{-1} with some positive impedances
+    zadd = np.random.default_rng(0).uniform(0.5, 2.0, p["port_ptr"][k + 1] - p["port_ptr"][k])
+    perm = d["perm"]
+    ipos = np.argsort(perm)
+    dplus = np.zeros(nk)
+    for q in range(p["port_ptr"][k], p["port_ptr"][k + 1]):
+        li = np.searchsorted(p["loc_vtx"][b:e], p["port_v"][q])
+        dplus[ipos[li]] += zadd[q - p["port_ptr"][k]]
+    L = _emulate_multifrontal(d, p["lval"][p["lrp"][b]:p["lrp"][e]], dplus)
+    Kp = K[np.ix_(perm, perm)] + np.diag(dplus)
+    assert np.allclose(L @ L.T, Kp, rtol=0, atol=1e-12 * np.abs(Kp).max())
+    # levels: contiguous column ranges, children strictly below parents
+    sn = d["sn"]
+    for s in range(d["nsn"]):
+        lev = sn[s, 6]
+        assert d["lev_c0"][lev] <= sn[s, 0] < d["lev_c0"][lev + 1]
+        if sn[s, 5] >= 0:
+            assert sn[sn[s, 5], 6] > lev
+    # assembly scatter covers every lower entry of K exactly once
+    assert d["sc"].shape[0] == (np.count_nonzero(K) + nk) // 2
