@@ -219,6 +219,45 @@ vtm_status vtm_reset_waves(vtm_handle h);
 vtm_status vtm_get_waves(vtm_handle h, double *a, int32_t nrhs);
 vtm_status vtm_set_waves(vtm_handle h, const double *a, int32_t nrhs);
 
+/*
+ * Learned impedance (an addition to the paper's impedance matching, Section
+ * 7.1): an MLP 12 -> 64 -> 64 -> 1 with ReLU predicts delta = ln(Z a_vv) for
+ * every VTL from VTM_NUM_FEATURES scale-free features of its two ends; setup
+ * with VTM_Z_LEARNED uses Z = exp(clamp(delta, ln 1/4, ln 256)) / a_vv.
+ * Inference and training run on the matrix cores with BF16 operands and FP32
+ * accumulation.  Parameter blob (float, VTM_ZMODEL_PARAMS):
+ *   mu[12], sigma[12] (input standardisation), W1[64][12], b1[64],
+ *   W2[64][64], b2[64], w3[64], b3.
+ */
+#define VTM_NUM_FEATURES 12
+#define VTM_ZMODEL_PARAMS 5081
+#define VTM_ZMODEL_TRAIN 5057
+
+/* Features of every VTL (host array [nvtl][VTM_NUM_FEATURES]); works on host-only handles. */
+vtm_status vtm_zfeatures(vtm_handle h, float *out);
+/* Load model parameters (host, copied); enables VTM_Z_LEARNED. */
+vtm_status vtm_zmodel_load(vtm_handle h, const float *params);
+/* Impedance per VTL used by the last vtm_setup (host array [nvtl]). */
+vtm_status vtm_get_z(vtm_handle h, double *z);
+
+/*
+ * Trainer of the impedance model: mean squared error on (features, label)
+ * rows held in device memory; minibatch gradients from the same BF16 kernels,
+ * Adam (beta 0.9 / 0.999, eps 1e-8) on FP32 master weights.
+ */
+typedef struct vtm_trainer_ctx *vtm_trainer;
+vtm_status vtm_trainer_create(int32_t device, const float *params, vtm_trainer *out);
+vtm_status vtm_trainer_destroy(vtm_trainer t);
+/* Copy n rows of features [n][12] and labels [n] (host) to the device. */
+vtm_status vtm_trainer_set_data(vtm_trainer t, const float *feats, const float *labels, int64_t n);
+/* Gradient (host [VTM_ZMODEL_TRAIN], parameter layout without mu/sigma) and loss of rows [row0, row0+nrows). */
+vtm_status vtm_trainer_grad(vtm_trainer t, int64_t row0, int64_t nrows, float *grad, float *loss);
+/* One epoch: splitmix64-seeded shuffle, minibatches of `batch` rows, one Adam step each; mean loss out. */
+vtm_status vtm_trainer_epoch(vtm_trainer t, int64_t batch, float lr, uint64_t seed, float *loss);
+/* Model output for n feature rows (host in, host out). */
+vtm_status vtm_trainer_predict(vtm_trainer t, const float *feats, int64_t n, float *out);
+vtm_status vtm_trainer_get_params(vtm_trainer t, float *params);
+
 /* Statistics of the last setup / solve. */
 vtm_status vtm_get_stats(vtm_handle h, vtm_stats *out);
 

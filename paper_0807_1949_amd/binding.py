@@ -63,7 +63,10 @@ _lib = None
 # exported symbols declared in include/vtm.h and include/vtm_debug.h
 EXPORTS = ("vtm_create", "vtm_destroy", "vtm_last_error", "vtm_evs_partition", "vtm_get_partition", "vtm_setup",
            "vtm_solve", "vtm_run_sweeps", "vtm_reset_waves", "vtm_get_waves", "vtm_set_waves", "vtm_get_stats",
-           "vtm_debug_class")
+           "vtm_debug_class", "vtm_zfeatures", "vtm_zmodel_load", "vtm_get_z", "vtm_trainer_create",
+           "vtm_trainer_destroy", "vtm_trainer_set_data", "vtm_trainer_grad", "vtm_trainer_epoch",
+           "vtm_trainer_predict", "vtm_trainer_get_params")
+NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 12, 5081, 5057
 
 
 def lib():
@@ -86,6 +89,16 @@ def lib():
         L.vtm_set_waves.argtypes = [P, P, C.c_int32]
         L.vtm_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.vtm_debug_class.argtypes = [P, C.c_int32, P, P, P, P, P, P, P]
+        L.vtm_zfeatures.argtypes = [P, P]
+        L.vtm_zmodel_load.argtypes = [P, P]
+        L.vtm_get_z.argtypes = [P, P]
+        L.vtm_trainer_create.argtypes = [C.c_int32, P, C.POINTER(C.c_void_p)]
+        L.vtm_trainer_destroy.argtypes = [P]
+        L.vtm_trainer_set_data.argtypes = [P, P, P, C.c_int64]
+        L.vtm_trainer_grad.argtypes = [P, C.c_int64, C.c_int64, P, P]
+        L.vtm_trainer_epoch.argtypes = [P, C.c_int64, C.c_float, C.c_uint64, P]
+        L.vtm_trainer_predict.argtypes = [P, P, C.c_int64, P]
+        L.vtm_trainer_get_params.argtypes = [P, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int32 if name != "vtm_last_error" else C.c_char_p
         _lib = L
@@ -123,6 +136,7 @@ class VTM:
         _check(lib().vtm_create(C.byref(o), C.byref(self._h)))
         self.precision = precision
         self.info = None
+        self.n = None
         self._keep = []
 
     def close(self):
@@ -232,27 +246,30 @@ class VTM:
 
             if b.dim() == 1:
                 b = b.unsqueeze(0)
-            assert b.dtype == torch.float64 and b.is_contiguous() and b.shape[1] == self.n
+            assert b.dtype == torch.float64 and b.is_contiguous()
+            if self.n is not None and b.shape[1] != self.n:
+                raise ValueError("right-hand side length differs from the partitioned system")
             if b.is_cuda:
                 torch.cuda.synchronize(b.device)
-            return C.c_void_p(b.data_ptr()), b.shape[0], self.n, b
+            return C.c_void_p(b.data_ptr()), b.shape[0], b.shape[1], b
         b = np.ascontiguousarray(np.atleast_2d(b), dtype=np.float64)
-        assert b.shape[1] == self.n
-        return C.c_void_p(b.ctypes.data), b.shape[0], self.n, b
+        if self.n is not None and b.shape[1] != self.n:
+            raise ValueError("right-hand side length differs from the partitioned system")
+        return C.c_void_p(b.ctypes.data), b.shape[0], b.shape[1], b
 
     def _out_like(self, b, nrhs):
         if _is_torch(b):
             import torch
 
-            return torch.empty((nrhs, self.n), dtype=torch.float64, device=b.device)
-        return np.zeros((nrhs, self.n))
+            return torch.empty((nrhs, b.shape[1]), dtype=torch.float64, device=b.device)
+        return np.zeros((nrhs, b.shape[1]))
 
     def solve(self, b, tol: float, x=None, raise_on=(VTM_ERR_DIVERGED,)):
         pb, nrhs, ld, bk = self._vec(b)
         if x is None:
             x = self._out_like(bk, nrhs)
         px, _, ldx, xk = self._vec(x)
-        nsys = self.info["nsys"]
+        nsys = self.info["nsys"] if self.info else 1
         iters = np.zeros(nrhs * nsys, np.int32)
         rel = np.zeros(nrhs * nsys, np.float64)
         code = lib().vtm_solve(self._h, pb, nrhs, ld, tol, px, ldx, _np_ptr(iters), _np_ptr(rel))
@@ -280,7 +297,75 @@ class VTM:
         a = np.ascontiguousarray(np.atleast_2d(a), dtype=np.float64)
         _check(lib().vtm_set_waves(self._h, _np_ptr(a), a.shape[0]))
 
+    # ------------------------------------------------------- learned impedance
+    def zfeatures(self) -> np.ndarray:
+        out = np.zeros((self.info["nvtl"], NUM_FEATURES), np.float32)
+        _check(lib().vtm_zfeatures(self._h, _np_ptr(out)))
+        return out
+
+    def zmodel_load(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (ZMODEL_PARAMS,)
+        _check(lib().vtm_zmodel_load(self._h, _np_ptr(p)))
+
+    def get_z(self) -> np.ndarray:
+        z = np.zeros(self.info["nvtl"])
+        _check(lib().vtm_get_z(self._h, _np_ptr(z)))
+        return z
+
     def get_stats(self) -> dict:
         s = Stats()
         _check(lib().vtm_get_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+class Trainer:
+    """Device trainer of the impedance model (vtm_trainer_*)."""
+
+    def __init__(self, params, device: int = 0):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (ZMODEL_PARAMS,)
+        self._t = C.c_void_p()
+        _check(lib().vtm_trainer_create(device, _np_ptr(p), C.byref(self._t)))
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_t", None) and self._t.value:
+            lib().vtm_trainer_destroy(self._t)
+            self._t = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_data(self, feats, labels):
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        assert f.shape == (y.shape[0], NUM_FEATURES)
+        _check(lib().vtm_trainer_set_data(self._t, _np_ptr(f), _np_ptr(y), y.shape[0]))
+        self.n = y.shape[0]
+
+    def grad(self, row0: int = 0, nrows: int | None = None):
+        nrows = self.n - row0 if nrows is None else nrows
+        g = np.zeros(ZMODEL_TRAIN, np.float32)
+        loss = C.c_float()
+        _check(lib().vtm_trainer_grad(self._t, row0, nrows, _np_ptr(g), C.byref(loss)))
+        return g, loss.value
+
+    def epoch(self, batch: int, lr: float, seed: int) -> float:
+        loss = C.c_float()
+        _check(lib().vtm_trainer_epoch(self._t, batch, lr, seed, C.byref(loss)))
+        return loss.value
+
+    def predict(self, feats) -> np.ndarray:
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        out = np.zeros(f.shape[0], np.float32)
+        _check(lib().vtm_trainer_predict(self._t, _np_ptr(f), f.shape[0], _np_ptr(out)))
+        return out
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(ZMODEL_PARAMS, np.float32)
+        _check(lib().vtm_trainer_get_params(self._t, _np_ptr(p)))
+        return p

@@ -24,8 +24,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-x", "hip"
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", f"-I{INC}", f"-I{CSRC}",
              f"-I{ROCM}/include", "-D__HIP_PLATFORM_AMD__"]
 
-HIP_SRCS = ["kernels.hip", "capi.cpp"]
-CXX_SRCS = ["partition.cpp", "symbolic.cpp"]
+HIP_SRCS = ["kernels.hip", "mlp.hip", "capi.cpp", "zmodel.cpp"]
+CXX_SRCS = ["partition.cpp", "symbolic.cpp", "features.cpp"]
 
 
 def _run(cmd):

@@ -11,16 +11,23 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "vtm.h"
 #include "vtm_debug.h"
 #include "vtm_internal.hpp"
 
+namespace vtm {
+std::string &last_error_ref() {
+    static thread_local std::string err;
+    return err;
+}
+}  // namespace vtm
+
 namespace {
 
-thread_local std::string g_err;
 
 vtm_status fail(vtm_status code, const std::string &msg) {
-    g_err = msg;
+    vtm::last_error_ref() = msg;
     return code;
 }
 
@@ -69,6 +76,10 @@ struct vtm_ctx {
     int32_t nchunks = 0;
     // setup products
     DevBuf d_z, d_invz64, d_invz32, d_vals64, d_vals32, d_status;
+    // learned impedance model
+    DevBuf d_zparams, d_feat, d_avvl, d_pred;
+    bool model_loaded = false, feats_ready = false;
+    std::vector<float> feats;
     // solve state
     DevBuf d_o[2], d_bsplit, d_xloc, d_x, d_xt, d_r, d_rt, d_b, d_part, d_relres;
     int cur = 0;
@@ -82,7 +93,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -597,11 +608,36 @@ vtm_status waves_io(vtm_ctx *h, double *a_out, const double *a_in, int32_t nrhs)
     return VTM_OK;
 }
 
+void ensure_features(vtm_ctx *h) {
+    if (!h->feats_ready) {
+        vtm::compute_features(h->A, h->P, h->feats);
+        h->feats_ready = true;
+    }
+}
+
+// Z = exp(clamp(MLP(features), ln 1/4, ln 256)) / a_vv for every VTL, on the device.
+vtm_status learned_z(vtm_ctx *h) {
+    ensure_features(h);
+    const vtm::Partition &P = h->P;
+    const int64_t nvtl = (int64_t)P.vtl_v.size();
+    std::vector<double> avv(nvtl);
+    for (int64_t l = 0; l < nvtl; ++l) avv[l] = P.adiag[P.vtl_v[l]];
+    HIP_TRY(upload(h->d_feat, h->feats, h->stream));
+    HIP_TRY(upload(h->d_avvl, avv, h->stream));
+    HIP_TRY(ensure(h->d_pred, sizeof(float) * (nvtl + 1)));
+    HIP_TRY(ensure(h->d_z, sizeof(double) * (nvtl + 1)));
+    vtm::launch_mlp_predict(h->d_zparams.as<float>(), h->d_feat.as<float>(), nvtl, h->d_pred.as<float>(), h->stream);
+    vtm::launch_z_from_pred(h->d_pred.as<float>(), h->d_avvl.as<double>(), nvtl, std::log(0.25), std::log(256.0),
+                            h->d_z.as<double>(), h->stream);
+    HIP_TRY(hipGetLastError());
+    return VTM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *vtm_last_error(void) { return g_err.c_str(); }
+const char *vtm_last_error(void) { return vtm::last_error_ref().c_str(); }
 
 vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
     if (!out) return fail(VTM_ERR_INVALID, "out is NULL");
@@ -654,6 +690,7 @@ vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, con
     if (rowptr[0] != 0 || rowptr[n] < n) return fail(VTM_ERR_INVALID, "rowptr invalid");
     if (!h->host_only()) HIP_TRY(hipSetDevice(h->opt.device));
     h->partitioned = h->set_up = false;
+    h->feats_ready = false;
     h->A.n = n;
     h->A.rp.assign(rowptr, rowptr + n + 1);
     h->A.ci.assign(col, col + rowptr[n]);
@@ -712,11 +749,18 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
         z.assign(z_vtl, z_vtl + nvtl);
         for (int64_t l = 0; l < nvtl; ++l)
             if (!(z[l] > 0.0) || !std::isfinite(z[l])) return fail(VTM_ERR_INVALID, "Z must be finite and > 0");
+    } else if (z_rule == VTM_Z_LEARNED) {
+        if (!h->model_loaded) return fail(VTM_ERR_STATE, "VTM_Z_LEARNED before vtm_zmodel_load");
     } else {
-        return fail(VTM_ERR_INVALID, "unsupported z_rule (no impedance model loaded)");
+        return fail(VTM_ERR_INVALID, "unknown z_rule");
     }
     hipStream_t st = h->stream;
-    HIP_TRY(upload(h->d_z, z, st));
+    if (z_rule == VTM_Z_LEARNED) {
+        vtm_status rc = learned_z(h);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(upload(h->d_z, z, st));
+    }
     HIP_TRY(ensure(h->d_invz64, sizeof(double) * (h->nports + 1)));
     HIP_TRY(ensure(h->d_invz32, sizeof(float) * (h->nports + 1)));
     HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
@@ -823,6 +867,37 @@ vtm_status vtm_debug_class(vtm_handle h, int32_t k, int64_t *sizes, int32_t *per
     if (rel) std::copy(C.rel.begin(), C.rel.end(), rel);
     if (sc)
         for (size_t i = 0; i < C.sc_src.size(); ++i) { sc[2 * i] = C.sc_src[i]; sc[2 * i + 1] = C.sc_dst[i]; }
+    return VTM_OK;
+}
+
+vtm_status vtm_zfeatures(vtm_handle h, float *out) {
+    if (!h || !out) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->partitioned) return fail(VTM_ERR_STATE, "no partition");
+    ensure_features(h);
+    std::copy(h->feats.begin(), h->feats.end(), out);
+    return VTM_OK;
+}
+
+vtm_status vtm_zmodel_load(vtm_handle h, const float *params) {
+    if (!h || !params) return fail(VTM_ERR_INVALID, "bad argument");
+    if (h->host_only()) return fail(VTM_ERR_STATE, "host-only handle");
+    for (int i = 0; i < vtm::kParams; ++i)
+        if (!std::isfinite(params[i])) return fail(VTM_ERR_INVALID, "non-finite model parameter");
+    for (int i = 0; i < vtm::kNumFeatures; ++i)
+        if (!(params[vtm::kNumFeatures + i] > 0.f)) return fail(VTM_ERR_INVALID, "feature std must be > 0");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    std::vector<float> p(params, params + vtm::kParams);
+    HIP_TRY(upload(h->d_zparams, p, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->model_loaded = true;
+    return VTM_OK;
+}
+
+vtm_status vtm_get_z(vtm_handle h, double *z) {
+    if (!h || !z) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "no setup");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    HIP_TRY(hipMemcpy(z, h->d_z.p, sizeof(double) * h->P.vtl_v.size(), hipMemcpyDeviceToHost));
     return VTM_OK;
 }
 

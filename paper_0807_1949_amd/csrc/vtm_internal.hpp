@@ -43,6 +43,10 @@ struct Partition {
 
 int build_partition(const Csr &A, const vtm_partition_spec &spec, Partition &P, std::string &err);
 
+constexpr int kNumFeatures = 12;
+// Per-VTL features of the learned impedance model, [nvtl][kNumFeatures].
+void compute_features(const Csr &A, const Partition &P, std::vector<float> &out);
+
 // Symbolic analysis of one local sparsity structure ("class"): nested-dissection
 // ordering, supernodes sorted by assembly-tree level, multifrontal assembly data
 // and the solve layout.  Every subgraph with the same local CSR structure shares it.

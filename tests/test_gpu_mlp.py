@@ -1,0 +1,98 @@
+"""GPU checks of the learned-impedance MLP kernels against the FP64 reference.
+
+Both sides round to BF16 at the same points (oracle/mlp.py); the remaining
+differences are FP32 accumulation order and the rare value that lands on
+opposite sides of a BF16 rounding boundary in FP32 and FP64, hence the
+1e-3-relative tolerances.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0807_1949_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def _problem(n, seed):
+    rng = np.random.default_rng(seed)
+    X = (rng.standard_normal((n, M.NF)) * rng.uniform(0.5, 3, M.NF) + rng.uniform(-2, 2, M.NF)).astype(np.float32)
+    P = M.init_params(X, seed=seed)
+    P[2 * M.NF:] += (rng.standard_normal(M.NTRAIN) * 0.02).astype(np.float32)
+    t = np.sin(X[:, 0]) + 0.3 * X[:, 1] * X[:, 2] / 4 + 0.1 * rng.standard_normal(n)
+    return X, P, t.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000 + 7])
+def test_forward_matches_reference(B, n):
+    X, P, _ = _problem(n, 11)
+    tr = B.Trainer(P)
+    y = tr.predict(X)
+    yo = M.forward(P, X, bf=True)["y"]
+    assert np.abs(y - yo).max() <= 1e-3 * max(1.0, np.abs(yo).max())
+
+
+@pytest.mark.parametrize("n", [16, 999, 4096])
+def test_gradient_matches_reference(B, n):
+    X, P, t = _problem(n, 12)
+    tr = B.Trainer(P)
+    tr.set_data(X, t)
+    g, loss = tr.grad()
+    go, lo = M.grad(P, X, t, bf=True)
+    assert abs(loss - lo) <= 1e-4 * max(lo, 1e-6)
+    blocks = [(0, 768), (768, 832), (832, 4928), (4928, 4992), (4992, 5056), (5056, 5057)]
+    for a, b in blocks:
+        ref = go[a:b]
+        assert np.linalg.norm(g[a:b] - ref) <= 2e-3 * max(np.linalg.norm(ref), 1e-6), (a, b)
+
+
+def test_training_reduces_loss(B):
+    X, P, t = _problem(8192, 13)
+    tr = B.Trainer(P)
+    tr.set_data(X, t)
+    _, l0 = tr.grad()
+    for ep in range(15):
+        tr.epoch(256, 3e-3, ep)
+    _, l1 = tr.grad()
+    assert l1 < 0.2 * l0
+    # the trained parameters still agree with the reference forward pass
+    P1 = tr.get_params()
+    assert np.abs(tr.predict(X[:500]) - M.forward(P1, X[:500])["y"]).max() <= 1e-3 * max(1, np.abs(t).max())
+
+
+def test_learned_z_setup_and_solve(B):
+    """VTM_Z_LEARNED: Z from the model on the device equals exp(clamp(reference output)) / a_vv, and the
+    solve with it matches the oracle run on those exact impedances."""
+    import gen
+    from oracle import oracle as O
+
+    cfg = gen.make_config("c4", small=True)
+    h = B.VTM(device=0, check_every=10)
+    info = h.evs_partition(cfg["A"], cfg["spec"])
+    F = h.zfeatures()
+    P = M.init_params(F, seed=3)
+    P[-1] = np.log(16.0)  # bias the output towards ln 16
+    h.zmodel_load(P)
+    h.setup(B.VTM_Z_LEARNED)
+    z = h.get_z()
+    part = h.get_partition()
+    avv = cfg["A"].to_scipy().diagonal()[part["vtl_v"]]
+    d = np.clip(M.forward(P, F)["y"], np.log(0.25), np.log(256.0))
+    assert np.allclose(z * avv, np.exp(d), rtol=2e-3)
+    r = h.solve(cfg["b"], 1e-8)
+    assert r["status"] == 0
+    Po = O.Partition(cfg["A"], cfg["spec"])
+    ro = O.Solver(Po, z).run(cfg["b"], 100000, 10, 1e-8)
+    assert int(ro["iters"][0, 0]) == int(r["iters"][0, 0])
+    assert np.linalg.norm(r["x"][0] - ro["x"][0]) <= 1e-8 * np.linalg.norm(ro["x"][0])
