@@ -71,8 +71,10 @@ typedef struct {
     int32_t check_every;   /* sweeps between convergence tests (>= 1; 0 = default 10) */
     int64_t max_sweeps;    /* cap on sweeps per solve (0 = default 100000) */
     int32_t rhs_per_block; /* right-hand sides one workgroup carries (0 = tuned: 1, 2, 4 or 8) */
-    int32_t leaf_size;     /* nested-dissection leaf size of the local orderings (0 = tuned) */
-    int32_t reserved[6];
+    int32_t leaf_size;     /* nested-dissection leaf size of the local orderings (0 = 8 in 2D, 16 in 3D) */
+    int32_t sweep_threads; /* threads per sweep workgroup, 64..512 (0 = 256, or vtm_autotune's choice) */
+    int32_t graph_mode;    /* 0: replay sweep batches as captured HIP graphs; 1: plain launches */
+    int32_t reserved[4];
 } vtm_options;
 
 /*
@@ -212,6 +214,15 @@ vtm_status vtm_solve(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, d
  */
 vtm_status vtm_run_sweeps(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, int64_t nsweeps, double *x,
                           int64_t ldx);
+
+/*
+ * Autotuner of the sweep launch: times a few sweeps of every candidate
+ * (right-hand sides per workgroup R in {1,2,4,8} up to nrhs, workgroup size in
+ * {128, 256, 512}) on the current factors with HIP events and keeps the
+ * fastest for solves with nrhs right-hand sides.  chosen[2] = {R, threads}
+ * (may be NULL).  The waves are reset.  Requires vtm_setup.
+ */
+vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen);
 
 /* Zero the waves (the state of Example 5.1 before its first iteration). */
 vtm_status vtm_reset_waves(vtm_handle h);

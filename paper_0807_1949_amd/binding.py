@@ -28,7 +28,7 @@ VTM_Z_DIAG, VTM_Z_USER, VTM_Z_LEARNED = 0, 1, 2
 class Options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("max_sweeps", C.c_int64), ("rhs_per_block", C.c_int32), ("leaf_size", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("sweep_threads", C.c_int32), ("graph_mode", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class PartitionSpec(C.Structure):
@@ -65,7 +65,7 @@ EXPORTS = ("vtm_create", "vtm_destroy", "vtm_last_error", "vtm_evs_partition", "
            "vtm_solve", "vtm_run_sweeps", "vtm_reset_waves", "vtm_get_waves", "vtm_set_waves", "vtm_get_stats",
            "vtm_debug_class", "vtm_zfeatures", "vtm_zmodel_load", "vtm_get_z", "vtm_trainer_create",
            "vtm_trainer_destroy", "vtm_trainer_set_data", "vtm_trainer_grad", "vtm_trainer_epoch",
-           "vtm_trainer_predict", "vtm_trainer_get_params")
+           "vtm_trainer_predict", "vtm_trainer_get_params", "vtm_autotune")
 NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 12, 5081, 5057
 
 
@@ -99,6 +99,7 @@ def lib():
         L.vtm_trainer_epoch.argtypes = [P, C.c_int64, C.c_float, C.c_uint64, P]
         L.vtm_trainer_predict.argtypes = [P, P, C.c_int64, P]
         L.vtm_trainer_get_params.argtypes = [P, P]
+        L.vtm_autotune.argtypes = [P, C.c_int32, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int32 if name != "vtm_last_error" else C.c_char_p
         _lib = L
@@ -123,7 +124,8 @@ class VTM:
     """One libvtm handle.  Method names follow the C entry points."""
 
     def __init__(self, device: int = 0, precision: int = VTM_FP64, check_every: int = 10, max_sweeps: int = 100000,
-                 rhs_per_block: int = 0, leaf_size: int = 0, stream: int | None = None):
+                 rhs_per_block: int = 0, leaf_size: int = 0, stream: int | None = None, sweep_threads: int = 0,
+                 graph_mode: int = 0):
         self._h = C.c_void_p()
         o = Options()
         o.device = device
@@ -133,6 +135,8 @@ class VTM:
         o.max_sweeps = max_sweeps
         o.rhs_per_block = rhs_per_block
         o.leaf_size = leaf_size
+        o.sweep_threads = sweep_threads
+        o.graph_mode = graph_mode
         _check(lib().vtm_create(C.byref(o), C.byref(self._h)))
         self.precision = precision
         self.info = None
@@ -284,6 +288,11 @@ class VTM:
         px, _, ldx, xk = self._vec(x)
         _check(lib().vtm_run_sweeps(self._h, pb, nrhs, ld, int(nsweeps), px, ldx))
         return xk
+
+    def autotune(self, nrhs: int = 1):
+        ch = np.zeros(2, np.int32)
+        _check(lib().vtm_autotune(self._h, nrhs, _np_ptr(ch)))
+        return dict(rhs_per_block=int(ch[0]), sweep_threads=int(ch[1]))
 
     def reset_waves(self):
         _check(lib().vtm_reset_waves(self._h))

@@ -84,6 +84,19 @@ struct vtm_ctx {
     DevBuf d_o[2], d_bsplit, d_xloc, d_x, d_xt, d_r, d_rt, d_b, d_part, d_relres;
     int cur = 0;
     int32_t wave_nrhs = 0, wave_R = 1;
+    // captured sweep batches, one per starting wave buffer
+    struct SweepGraph {
+        hipGraphExec_t exec = nullptr;
+        int64_t count = 0;
+        int32_t R = 0, ng = 0, threads = 0;
+        const void *ptrs[7] = {};
+    } graphs[2];
+    void drop_graphs() {
+        for (auto &g : graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            g = SweepGraph();
+        }
+    }
     bool waves_zero = true;
     vtm_stats stats{};
 
@@ -101,6 +114,7 @@ struct vtm_ctx {
     ~vtm_ctx() {
         if (host_only()) return;
         (void)hipSetDevice(opt.device);
+        drop_graphs();
         for (DevBuf *b : all) b->release();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -401,19 +415,61 @@ T *invz_of(vtm_ctx *h) {
     else return h->d_invz64.as<T>();
 }
 
-// Sweeps on the current waves; the last one stores the local solutions.
+int32_t sweep_threads(vtm_ctx *h) {
+    const int32_t t = h->opt.sweep_threads;
+    return t >= 64 && t <= 512 && t % 64 == 0 ? t : 256;
+}
+
+// Sweeps on the current waves; the last one stores the local solutions.  Batches of two or more
+// sweeps are captured once into a HIP graph per starting wave buffer and replayed.
 template <typename T>
-void run_sweeps_dev(vtm_ctx *h, int64_t count) {
+vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
+    if (count <= 0) return VTM_OK;
     const vtm::DevSym S = dev_sym(h);
     const vtm::DevSub D = dev_sub(h);
-    const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
-    for (int64_t i = 0; i < count; ++i) {
-        vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, ng, R, h->nsplit, h->nports, vals_of<T>(h),
-                             h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur].as<T>(),
-                             h->d_o[1 - h->cur].as<T>(), h->d_xloc.as<T>(), i == count - 1 ? 1 : 0, h->stream);
-        h->cur ^= 1;
+    const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R, nt = sweep_threads(h);
+    HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, R));
+    auto launch = [&](int cur, bool last) {
+        vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, ng, R, nt, h->nsplit, h->nports, vals_of<T>(h),
+                             h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[cur].as<T>(),
+                             h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(), last ? 1 : 0, h->stream);
+    };
+    if (h->opt.graph_mode == 0 && count >= 2) {
+        auto &g = h->graphs[h->cur];
+        const void *ptrs[7] = {vals_of<T>(h), h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p, h->d_o[1].p,
+                               h->d_xloc.p};
+        bool same = g.exec && g.count == count && g.R == R && g.ng == ng && g.threads == nt;
+        for (int i = 0; i < 7 && same; ++i) same = g.ptrs[i] == ptrs[i];
+        if (!same) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            g = vtm_ctx::SweepGraph();
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+            int c = h->cur;
+            for (int64_t i = 0; i < count; ++i) {
+                launch(c, i == count - 1);
+                c ^= 1;
+            }
+            HIP_TRY(hipStreamEndCapture(h->stream, &graph));
+            hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_TRY(e);
+            g.count = count;
+            g.R = R;
+            g.ng = ng;
+            g.threads = nt;
+            for (int i = 0; i < 7; ++i) g.ptrs[i] = ptrs[i];
+        }
+        HIP_TRY(hipGraphLaunch(g.exec, h->stream));
+        h->cur ^= (int)(count & 1);
+    } else {
+        for (int64_t i = 0; i < count; ++i) {
+            launch(h->cur, i == count - 1);
+            h->cur ^= 1;
+        }
     }
-    if (count > 0) h->waves_zero = false;
+    h->waves_zero = false;
+    return VTM_OK;
 }
 
 template <typename T>
@@ -484,7 +540,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     while (!done && sweeps < maxsw) {
         const int64_t cnt = std::min(cadence, maxsw - sweeps);
         HIP_TRY(hipEventRecord(s0, h->stream));
-        run_sweeps_dev<T>(h, cnt);
+        if ((rc = run_sweeps_dev<T>(h, cnt))) return rc;
         HIP_TRY(hipEventRecord(s1, h->stream));
         sweeps += cnt;
         ++checks;
@@ -571,7 +627,7 @@ vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int6
     const vtm::DevMaps M = dev_maps(h);
     vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, h->wave_R, h->d_bsplit.as<T>(), h->stream);
     if (nsweeps > 0) {
-        run_sweeps_dev<T>(h, nsweeps);
+        if ((rc = run_sweeps_dev<T>(h, nsweeps))) return rc;
         vtm::launch_merge<T>(M, n, h->nsplit, nrhs, h->wave_R, h->d_xloc.as<T>(), nullptr, n, h->d_x.as<double>(), n,
                              h->stream);
     } else {
@@ -698,7 +754,7 @@ vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, con
     std::string err;
     int rc = vtm::build_partition(h->A, *spec, h->P, err);
     if (rc) return fail(rc, err);
-    int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : 8;
+    int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : (spec->kind == VTM_PART_RCB || (spec->kind == VTM_PART_GRID && spec->dims[2] > 1) ? 16 : 8);
     rc = vtm::build_symbolic(h->P, leaf, h->S, err);
     if (rc) return fail(rc, err);
     if (h->host_only()) host_sizes(h);
@@ -799,6 +855,7 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
         }
     h->set_up = true;
     h->wave_nrhs = 0;  // fresh zero waves on the next solve
+    h->drop_graphs();
     return VTM_OK;
 }
 
@@ -867,6 +924,51 @@ vtm_status vtm_debug_class(vtm_handle h, int32_t k, int64_t *sizes, int32_t *per
     if (rel) std::copy(C.rel.begin(), C.rel.end(), rel);
     if (sc)
         for (size_t i = 0; i < C.sc_src.size(); ++i) { sc[2 * i] = C.sc_src[i]; sc[2 * i + 1] = C.sc_dst[i]; }
+    return VTM_OK;
+}
+
+vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
+    if (!h || nrhs < 1) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "vtm_autotune before vtm_setup");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    int32_t maxR = 1;
+    while (maxR < nrhs && maxR < 8) maxR *= 2;
+    const vtm_options saved = h->opt;
+    double best = 1e300;
+    int32_t bestR = 1, bestT = 256;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    for (int32_t R = 1; R <= maxR; R *= 2) {
+        if (2 * h->tsize() * (size_t)h->max_nk * R > 160 * 1024) break;
+        for (int32_t nt : {128, 256, 512}) {
+            h->opt.rhs_per_block = R;
+            h->opt.sweep_threads = nt;
+            h->opt.graph_mode = 1;
+            vtm_status rc = h->fp32() ? ensure_waves<float>(h, nrhs) : ensure_waves<double>(h, nrhs);
+            if (!rc) rc = h->fp32() ? alloc_solve<float>(h, nrhs) : alloc_solve<double>(h, nrhs);
+            if (rc) { h->opt = saved; return rc; }
+            const int32_t ng = (nrhs + R - 1) / R;
+            HIP_TRY(hipMemsetAsync(h->d_bsplit.p, 0, h->tsize() * (size_t)ng * h->nsplit * R, h->stream));
+            const int64_t warm = 2, timed = 6;
+            rc = h->fp32() ? run_sweeps_dev<float>(h, warm) : run_sweeps_dev<double>(h, warm);
+            HIP_TRY(hipEventRecord(e0, h->stream));
+            if (!rc) rc = h->fp32() ? run_sweeps_dev<float>(h, timed) : run_sweeps_dev<double>(h, timed);
+            HIP_TRY(hipEventRecord(e1, h->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            if (rc) { h->opt = saved; return rc; }
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; bestR = R; bestT = nt; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->opt = saved;
+    h->opt.rhs_per_block = bestR;
+    h->opt.sweep_threads = bestT;
+    h->wave_nrhs = 0;  // zero waves for the next solve
+    if (chosen) { chosen[0] = bestR; chosen[1] = bestT; }
     return VTM_OK;
 }
 

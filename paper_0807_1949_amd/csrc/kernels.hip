@@ -145,7 +145,7 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
 
 // ------------------------------------------------------------------------ sweep
 template <typename T, int R>
-__global__ __launch_bounds__(kThreads) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
+__global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
                                                     const T *__restrict__ vals, const T *__restrict__ bsplit,
                                                     const int32_t *__restrict__ twin, const T *__restrict__ invz,
                                                     const T *__restrict__ o_prev, T *__restrict__ o_next,
@@ -371,21 +371,32 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
 }
 
 template <typename T>
+static const void *sweep_fn(int32_t R) {
+    return R == 1 ? (const void *)k_sweep<T, 1> : R == 2 ? (const void *)k_sweep<T, 2>
+         : R == 4 ? (const void *)k_sweep<T, 4> : (const void *)k_sweep<T, 8>;
+}
+
+template <typename T>
+size_t sweep_shm(int32_t max_nk, int32_t R) { return 2 * sizeof(T) * (size_t)max_nk * R; }
+
+template <typename T>
+hipError_t prepare_sweep(int32_t max_nk, int32_t R) {
+    const size_t shm = sweep_shm<T>(max_nk, R);
+    if (shm <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(sweep_fn<T>(R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t ngroups, int32_t R,
-                  int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin, const T *invz,
-                  const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st) {
-    size_t shm = 2 * sizeof(T) * (size_t)max_nk * R;
-    dim3 grid(nsub, ngroups);
-    if (shm > 64 * 1024) {
-        const void *fn = R == 1 ? (const void *)k_sweep<T, 1> : R == 2 ? (const void *)k_sweep<T, 2>
-                       : R == 4 ? (const void *)k_sweep<T, 4> : (const void *)k_sweep<T, 8>;
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    }
+                  int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
+                  const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st) {
+    const size_t shm = sweep_shm<T>(max_nk, R);
+    const dim3 grid(nsub, ngroups), block(threads);
     switch (R) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        default: hipLaunchKernelGGL((k_sweep<T, 8>), grid, dim3(kThreads), shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        default: hipLaunchKernelGGL((k_sweep<T, 8>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
     }
 }
 
@@ -407,12 +418,14 @@ void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, in
 
 template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);
 template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, float *, hipStream_t);
-template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int64_t, int64_t,
-                                   const double *, const double *, const int32_t *, const double *, const double *,
-                                   double *, double *, int, hipStream_t);
-template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int64_t, int64_t,
-                                  const float *, const float *, const int32_t *, const float *, const float *, float *,
-                                  float *, int, hipStream_t);
+template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t,
+                                   int64_t, const double *, const double *, const int32_t *, const double *,
+                                   const double *, double *, double *, int, hipStream_t);
+template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t,
+                                  int64_t, const float *, const float *, const int32_t *, const float *, const float *,
+                                  float *, float *, int, hipStream_t);
+template hipError_t prepare_sweep<double>(int32_t, int32_t);
+template hipError_t prepare_sweep<float>(int32_t, int32_t);
 template void launch_merge<double>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const double *, const double *,
                                    int64_t, double *, int64_t, hipStream_t);
 template void launch_merge<float>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const float *, const double *,

@@ -75,11 +75,14 @@ template <typename T>
 void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int64_t ldb, int32_t R,
                   T *bsplit, hipStream_t st);
 
-// One VTM sweep over all subgraphs and right-hand-side groups.
+// One VTM sweep over all subgraphs and right-hand-side groups (grid = subgraphs x RHS groups).
 template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t ngroups, int32_t R,
-                  int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin, const T *invz,
-                  const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st);
+                  int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
+                  const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st);
+// Raise the dynamic-LDS limit of the sweep kernel when needed (call outside stream capture).
+template <typename T>
+hipError_t prepare_sweep(int32_t max_nk, int32_t R);
 
 // xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
 template <typename T>

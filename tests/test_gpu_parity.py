@@ -165,3 +165,32 @@ def test_c2_full_iterates(B):
     xg = h.run_sweeps(cfg["b"], 20)
     xo = O.Solver(P, z).run(cfg["b"], 20, 0, 0.0)["x"]
     assert _rel(xg[0], xo[0]) <= 1e-10
+
+
+def test_graph_replay_matches_eager(B):
+    """Sweep batches replayed from captured HIP graphs (odd batch length, both wave parities, several
+    replays with host synchronisation between them) give bitwise the eager result."""
+    cfg = gen.make_config("c2", small=True)
+    out = []
+    for gm in (0, 1):
+        h, P, z = _setup(B, cfg, check_every=7, z_scale=16.0, graph_mode=gm)
+        r1 = h.solve(cfg["b"], 1e-8)
+        r2 = h.solve(cfg["b"], 1e-8)
+        out.append((r1["x"], r2["x"], r1["iters"].copy()))
+        h.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[0][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_autotune_then_solve(B):
+    """The autotuner picks a launch shape; the solve with it still matches the oracle (3D, 8 RHS)."""
+    cfg = gen.make_config("c3", small=True)
+    h, P, z = _setup(B, cfg, check_every=10, z_scale=8.0)
+    ch = h.autotune(8)
+    assert ch["rhs_per_block"] in (1, 2, 4, 8) and ch["sweep_threads"] in (128, 256, 512)
+    r = h.solve(cfg["b"], 1e-8)
+    assert r["status"] == 0
+    ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8)
+    for c in range(8):
+        assert int(r["iters"][c, 0]) == int(ro["iters"][c, 0])
+        assert _rel(r["x"][c], ro["x"][c]) <= 1e-8
