@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--variants", default="ir_diag,fp64_diag",
                     help="comma list of {ir,fp64}_{diag,a64}; the first is the headline")
     ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="copy this many MiB with a plain device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -92,6 +94,14 @@ def main():
     import gen
     from paper_0807_1949_amd import binding as B
 
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
     cfg = gen.make_config("c2", small=args.small)
     A, spec, tol = cfg["A"], cfg["spec"], cfg["tol"]
     b_dev = torch.tensor(cfg["b"], dtype=torch.float64, device="cuda")

@@ -74,7 +74,9 @@ typedef struct {
     int32_t leaf_size;     /* nested-dissection leaf size of the local orderings (0 = 8 in 2D, 16 in 3D) */
     int32_t sweep_threads; /* threads per sweep workgroup, 64..512 (0 = 256, or vtm_autotune's choice) */
     int32_t graph_mode;    /* 0: replay sweep batches as captured HIP graphs; 1: plain launches */
-    int32_t reserved[4];
+    int32_t sweep_variant; /* forward substitution: 1 = row dot products over descendant L21 rows,
+                              2 = per-level update entries L21*y gathered by the ancestors, 0 = choose */
+    int32_t reserved[3];
 } vtm_options;
 
 /*
@@ -219,8 +221,8 @@ vtm_status vtm_run_sweeps(vtm_handle h, const double *b, int32_t nrhs, int64_t l
  * Autotuner of the sweep launch: times a few sweeps of every candidate
  * (right-hand sides per workgroup R in {1,2,4,8} up to nrhs, workgroup size in
  * {128, 256, 512}) on the current factors with HIP events and keeps the
- * fastest for solves with nrhs right-hand sides.  chosen[2] = {R, threads}
- * (may be NULL).  The waves are reset.  Requires vtm_setup.
+ * fastest for solves with nrhs right-hand sides; also tries both forward
+ * substitution variants.  chosen[3] = {R, threads, variant} (may be NULL).  The waves are reset.  Requires vtm_setup.
  */
 vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen);
 

@@ -66,6 +66,8 @@ struct vtm_ctx {
     int64_t nsplit = 0, nports = 0, total_val = 0, total_ws = 0, total_lower = 0;
     std::vector<DevBuf *> all;
     // symbolic (class level)
+    DevBuf d_segu, d_usn, d_levu;
+    int32_t max_nu = 0;
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
         d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
     // subgraph level
@@ -88,7 +90,7 @@ struct vtm_ctx {
     struct SweepGraph {
         hipGraphExec_t exec = nullptr;
         int64_t count = 0;
-        int32_t R = 0, ng = 0, threads = 0;
+        int32_t R = 0, ng = 0, threads = 0, variant = 0;
         const void *ptrs[7] = {};
     } graphs[2];
     void drop_graphs() {
@@ -106,7 +108,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -169,6 +171,9 @@ vtm::DevSym dev_sym(vtm_ctx *h) {
     s.seg_off = h->d_segoff.as<int32_t>();
     s.seg_c0 = h->d_segc0.as<uint16_t>();
     s.seg_nc = h->d_segnc.as<uint16_t>();
+    s.seg_u = h->d_segu.as<uint16_t>();
+    s.u_sn = h->d_usn.as<uint16_t>();
+    s.lev_u = h->d_levu.as<int32_t>();
     s.sc_ptr = h->d_scptr.as<int32_t>();
     s.sc_src = h->d_scsrc.as<int32_t>();
     s.sc_dst = h->d_scdst.as<int32_t>();
@@ -219,9 +224,11 @@ vtm_status upload_partition(vtm_ctx *h) {
     std::vector<vtm::ClassDev> cls;
     std::vector<int32_t> lev, colsn, snc0, snnc, snm, snval, snridx, snuoff, chptr, chidx, segptr, segoff, scptr,
         scsrc, scdst;
-    std::vector<uint16_t> ridx, rel, segc0, segnc;
+    std::vector<uint16_t> ridx, rel, segc0, segnc, segu, usn;
+    std::vector<int32_t> levu;
     h->max_nk = 0;
     h->max_front = 0;
+    h->max_nu = 0;
     for (const vtm::ClassSym &C : S.classes) {
         vtm::ClassDev d{};
         d.nk = C.nk;
@@ -239,7 +246,12 @@ vtm_status upload_partition(vtm_ctx *h) {
         d.o_chi = (int32_t)chidx.size();
         d.nval = C.nval;
         d.ws_u = C.ws_u;
+        d.nu = (int32_t)C.ridx.size();
+        h->max_nu = std::max(h->max_nu, d.nu);
         cls.push_back(d);
+        levu.insert(levu.end(), C.lev_u.begin(), C.lev_u.end());
+        segu.insert(segu.end(), C.seg_u.begin(), C.seg_u.end());
+        usn.insert(usn.end(), C.u_sn.begin(), C.u_sn.end());
         lev.insert(lev.end(), C.lev_c0.begin(), C.lev_c0.end());
         colsn.insert(colsn.end(), C.col_sn.begin(), C.col_sn.end());
         snc0.insert(snc0.end(), C.sn_c0.begin(), C.sn_c0.end());
@@ -335,7 +347,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     UP(d_cls, cls); UP(d_lev, lev); UP(d_colsn, colsn); UP(d_snc0, snc0); UP(d_snnc, snnc); UP(d_snm, snm);
     UP(d_snval, snval); UP(d_snridx, snridx); UP(d_snuoff, snuoff); UP(d_ridx, ridx); UP(d_rel, rel);
     UP(d_chptr, chptr); UP(d_chidx, chidx); UP(d_segptr, segptr); UP(d_segoff, segoff); UP(d_segc0, segc0);
-    UP(d_segnc, segnc); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
+    UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
     UP(d_subcls, subcls); UP(d_subval, subval); UP(d_subx, subx); UP(d_subaval, subaval); UP(d_subws, subws);
     UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt);
     UP(d_fvtx, fvtx); UP(d_fmul, fmul); UP(d_cpptr, P.s_ptr); UP(d_cpidx, cpidx);
@@ -351,7 +363,7 @@ int32_t pick_R(vtm_ctx *h, int32_t nrhs) {
     if (h->opt.rhs_per_block > 0) return h->opt.rhs_per_block;
     int32_t want = 1;
     while (want < nrhs && want < 8) want *= 2;
-    while (want > 1 && 2 * h->tsize() * (size_t)h->max_nk * want > 64 * 1024) want /= 2;
+    while (want > 1 && 2 * h->tsize() * (size_t)h->max_nk * want > 96 * 1024) want /= 2;
     return want;
 }
 
@@ -415,6 +427,13 @@ T *invz_of(vtm_ctx *h) {
     else return h->d_invz64.as<T>();
 }
 
+int32_t sweep_variant(vtm_ctx *h) {
+    const int32_t v = h->opt.sweep_variant;
+    if (v == 1 || v == 2) return v - 1;
+    // default: gather update entries when they fit in LDS with the vectors
+    return h->tsize() * (size_t)h->wave_R * (2 * (size_t)h->max_nk + h->max_nu) <= 96 * 1024 ? 1 : 0;
+}
+
 int32_t sweep_threads(vtm_ctx *h) {
     const int32_t t = h->opt.sweep_threads;
     return t >= 64 && t <= 512 && t % 64 == 0 ? t : 256;
@@ -428,9 +447,10 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     const vtm::DevSym S = dev_sym(h);
     const vtm::DevSub D = dev_sub(h);
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R, nt = sweep_threads(h);
-    HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, R));
+    HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
     auto launch = [&](int cur, bool last) {
-        vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, ng, R, nt, h->nsplit, h->nports, vals_of<T>(h),
+        vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R, nt, h->nsplit,
+                             h->nports, vals_of<T>(h),
                              h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[cur].as<T>(),
                              h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(), last ? 1 : 0, h->stream);
     };
@@ -438,7 +458,8 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
         auto &g = h->graphs[h->cur];
         const void *ptrs[7] = {vals_of<T>(h), h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p, h->d_o[1].p,
                                h->d_xloc.p};
-        bool same = g.exec && g.count == count && g.R == R && g.ng == ng && g.threads == nt;
+        bool same = g.exec && g.count == count && g.R == R && g.ng == ng && g.threads == nt &&
+                    g.variant == sweep_variant(h);
         for (int i = 0; i < 7 && same; ++i) same = g.ptrs[i] == ptrs[i];
         if (!same) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -458,6 +479,7 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
             g.R = R;
             g.ng = ng;
             g.threads = nt;
+            g.variant = sweep_variant(h);
             for (int i = 0; i < 7; ++i) g.ptrs[i] = ptrs[i];
         }
         HIP_TRY(hipGraphLaunch(g.exec, h->stream));
@@ -939,11 +961,15 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    for (int32_t R = 1; R <= maxR; R *= 2) {
-        if (2 * h->tsize() * (size_t)h->max_nk * R > 160 * 1024) break;
+    int32_t bestV = 0;
+    for (int32_t R = 1; R <= maxR; R *= 2)
+      for (int32_t var = 1; var <= 2; ++var) {
+        const size_t lds = h->tsize() * (size_t)R * (2 * (size_t)h->max_nk + (var == 2 ? h->max_nu : 0));
+        if (lds > 160 * 1024) continue;
         for (int32_t nt : {128, 256, 512}) {
             h->opt.rhs_per_block = R;
             h->opt.sweep_threads = nt;
+            h->opt.sweep_variant = var == 2 ? 2 : 1;
             h->opt.graph_mode = 1;
             vtm_status rc = h->fp32() ? ensure_waves<float>(h, nrhs) : ensure_waves<double>(h, nrhs);
             if (!rc) rc = h->fp32() ? alloc_solve<float>(h, nrhs) : alloc_solve<double>(h, nrhs);
@@ -959,16 +985,17 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
             if (rc) { h->opt = saved; return rc; }
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; bestR = R; bestT = nt; }
+            if (ms < best) { best = ms; bestR = R; bestT = nt; bestV = h->opt.sweep_variant; }
         }
-    }
+      }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->opt = saved;
     h->opt.rhs_per_block = bestR;
     h->opt.sweep_threads = bestT;
+    h->opt.sweep_variant = bestV;
     h->wave_nrhs = 0;  // zero waves for the next solve
-    if (chosen) { chosen[0] = bestR; chosen[1] = bestT; }
+    if (chosen) { chosen[0] = bestR; chosen[1] = bestT; chosen[2] = bestV; }
     return VTM_OK;
 }
 

@@ -144,7 +144,7 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
 }
 
 // ------------------------------------------------------------------------ sweep
-template <typename T, int R>
+template <typename T, int R, int V>
 __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
                                                     const T *__restrict__ vals, const T *__restrict__ bsplit,
                                                     const int32_t *__restrict__ twin, const T *__restrict__ invz,
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
     const int nk = C.nk;
     T *vec = reinterpret_cast<T *>(smraw);
     T *tmp = vec + (size_t)nk * R;
+    T *ubuf = tmp + (size_t)nk * R;  // variant 1: update entries L21_s y_s of every R_s row
     const T *Vk = vals + D.val[k];
     const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
     const T *bs = bsplit + xo;
@@ -187,20 +188,32 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
     }
     __syncthreads();
     // forward substitution L y = rhs, one level (independent subtrees) at a time
+    const uint16_t *seg_u = S.seg_u + C.o_seg, *u_sn = S.u_sn + C.o_ridx;
+    const int32_t *lev_u = S.lev_u + C.o_lev;
     for (int lv = 0; lv < C.nlev; ++lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
         for (int i = cb + tid; i < ce; i += nt) {
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = vec[i * R + c];
-            for (int s = seg_ptr[i]; s < seg_ptr[i + 1]; ++s) {
-                const T *l = Vk + seg_off[s];
-                const T *y = vec + seg_c0[s] * R;
-                const int n = seg_nc[s];
-                for (int j = 0; j < n; ++j) {
-                    const T lj = l[j];
+            if (V == 0) {
+                // pull: L21_d[q, :] . y_d for every descendant row segment of row i
+                for (int s = seg_ptr[i]; s < seg_ptr[i + 1]; ++s) {
+                    const T *l = Vk + seg_off[s];
+                    const T *y = vec + seg_c0[s] * R;
+                    const int n = seg_nc[s];
+                    for (int j = 0; j < n; ++j) {
+                        const T lj = l[j];
 #pragma unroll
-                    for (int c = 0; c < R; ++c) acc[c] -= lj * y[j * R + c];
+                        for (int c = 0; c < R; ++c) acc[c] -= lj * y[j * R + c];
+                    }
+                }
+            } else {
+                // gather the update entries computed by the lower levels
+                for (int s = seg_ptr[i]; s < seg_ptr[i + 1]; ++s) {
+                    const T *u = ubuf + seg_u[s] * R;
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] -= u[c];
                 }
             }
 #pragma unroll
@@ -223,6 +236,25 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
             for (int c = 0; c < R; ++c) vec[i * R + c] = acc[c];
         }
         __syncthreads();
+        if (V == 1 && lev_u[lv + 1] > lev_u[lv]) {
+            // update entries of this level's supernodes: u[e] = L21_s[q, :] . y_s
+            for (int e = lev_u[lv] + tid; e < lev_u[lv + 1]; e += nt) {
+                const int s = u_sn[e], nc = sn_nc[s], q = e - sn_ridx[s];
+                const T *l = Vk + sn_val[s] + nc * nc + q * nc;
+                const T *y = vec + sn_c0[s] * R;
+                T acc[R];
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] = 0;
+                for (int j = 0; j < nc; ++j) {
+                    const T lj = l[j];
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] += lj * y[j * R + c];
+                }
+#pragma unroll
+                for (int c = 0; c < R; ++c) ubuf[e * R + c] = acc[c];
+            }
+            __syncthreads();
+        }
     }
     // backward substitution L^T x = y, root level first
     for (int lv = C.nlev - 1; lv >= 0; --lv) {
@@ -370,34 +402,48 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
     hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, ldb, R, bsplit);
 }
 
-template <typename T>
-static const void *sweep_fn(int32_t R) {
-    return R == 1 ? (const void *)k_sweep<T, 1> : R == 2 ? (const void *)k_sweep<T, 2>
-         : R == 4 ? (const void *)k_sweep<T, 4> : (const void *)k_sweep<T, 8>;
+template <typename T, int V>
+static const void *sweep_fn_v(int32_t R) {
+    return R == 1 ? (const void *)k_sweep<T, 1, V> : R == 2 ? (const void *)k_sweep<T, 2, V>
+         : R == 4 ? (const void *)k_sweep<T, 4, V> : (const void *)k_sweep<T, 8, V>;
 }
 
 template <typename T>
-size_t sweep_shm(int32_t max_nk, int32_t R) { return 2 * sizeof(T) * (size_t)max_nk * R; }
+size_t sweep_shm(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R) {
+    return sizeof(T) * (size_t)R * (2 * (size_t)max_nk + (variant == 1 ? (size_t)max_nu : 0));
+}
 
 template <typename T>
-hipError_t prepare_sweep(int32_t max_nk, int32_t R) {
-    const size_t shm = sweep_shm<T>(max_nk, R);
+hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R) {
+    const size_t shm = sweep_shm<T>(max_nk, max_nu, variant, R);
     if (shm <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(sweep_fn<T>(R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    return hipFuncSetAttribute(variant == 1 ? sweep_fn_v<T, 1>(R) : sweep_fn_v<T, 0>(R),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T, int V>
+static void launch_sweep_v(const DevSym &S, const DevSub &D, dim3 grid, dim3 block, size_t shm, int32_t R,
+                           int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
+                           const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st) {
+    switch (R) {
+        case 1: hipLaunchKernelGGL((k_sweep<T, 1, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, 2, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, 4, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        default: hipLaunchKernelGGL((k_sweep<T, 8, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+    }
 }
 
 template <typename T>
-void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t ngroups, int32_t R,
-                  int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
-                  const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st) {
-    const size_t shm = sweep_shm<T>(max_nk, R);
+void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
+                  int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals,
+                  const T *bsplit, const int32_t *twin, const T *invz, const T *o_prev, T *o_next, T *xloc,
+                  int write_x, hipStream_t st) {
+    const size_t shm = sweep_shm<T>(max_nk, max_nu, variant, R);
     const dim3 grid(nsub, ngroups), block(threads);
-    switch (R) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, 1>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, 2>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, 4>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        default: hipLaunchKernelGGL((k_sweep<T, 8>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-    }
+    if (variant == 1)
+        launch_sweep_v<T, 1>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x, st);
+    else
+        launch_sweep_v<T, 0>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x, st);
 }
 
 template <typename T>
@@ -418,14 +464,14 @@ void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, in
 
 template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);
 template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, float *, hipStream_t);
-template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t,
-                                   int64_t, const double *, const double *, const int32_t *, const double *,
-                                   const double *, double *, double *, int, hipStream_t);
-template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t,
-                                  int64_t, const float *, const float *, const int32_t *, const float *, const float *,
-                                  float *, float *, int, hipStream_t);
-template hipError_t prepare_sweep<double>(int32_t, int32_t);
-template hipError_t prepare_sweep<float>(int32_t, int32_t);
+template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
+                                   int32_t, int64_t, int64_t, const double *, const double *, const int32_t *,
+                                   const double *, const double *, double *, double *, int, hipStream_t);
+template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
+                                  int32_t, int64_t, int64_t, const float *, const float *, const int32_t *,
+                                  const float *, const float *, float *, float *, int, hipStream_t);
+template hipError_t prepare_sweep<double>(int32_t, int32_t, int32_t, int32_t);
+template hipError_t prepare_sweep<float>(int32_t, int32_t, int32_t, int32_t);
 template void launch_merge<double>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const double *, const double *,
                                    int64_t, double *, int64_t, hipStream_t);
 template void launch_merge<float>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const float *, const double *,

@@ -19,7 +19,7 @@ struct ClassDev {
     int32_t o_seg;   // seg_off, seg_c0, seg_nc
     int32_t o_sc;    // sc_src, sc_dst
     int32_t o_chi;   // ch_idx
-    int32_t pad;
+    int32_t nu;      // update entries (sum of m over supernodes)
     int64_t nval, ws_u;
 };
 
@@ -31,6 +31,8 @@ struct DevSym {
     const int32_t *ch_ptr, *ch_idx;
     const int32_t *seg_ptr, *seg_off;
     const uint16_t *seg_c0, *seg_nc;
+    const uint16_t *seg_u, *u_sn;   // update-entry lists (variant 1 of the sweep)
+    const int32_t *lev_u;           // update-entry range per level (lev offsets)
     const int32_t *sc_ptr, *sc_src, *sc_dst;
 };
 
@@ -77,12 +79,12 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
 
 // One VTM sweep over all subgraphs and right-hand-side groups (grid = subgraphs x RHS groups).
 template <typename T>
-void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t ngroups, int32_t R,
-                  int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
+void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
+                  int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
                   const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st);
 // Raise the dynamic-LDS limit of the sweep kernel when needed (call outside stream capture).
 template <typename T>
-hipError_t prepare_sweep(int32_t max_nk, int32_t R);
+hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R);
 
 // xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
 template <typename T>

@@ -298,12 +298,20 @@ int analyse(const Partition &P, int32_t k, int leaf, ClassSym &C, std::string &e
     C.seg_off.resize(C.seg_ptr[nk]);
     C.seg_c0.resize(C.seg_ptr[nk]);
     C.seg_nc.resize(C.seg_ptr[nk]);
+    C.seg_u.resize(C.seg_ptr[nk]);
+    if (ri >= 65535) { err = "too many update entries for 16-bit indices"; return VTM_ERR_PARTITION; }
+    C.u_sn.resize(ri);
+    for (int32_t t = 0; t < nb; ++t)
+        for (int32_t q = 0; q < C.sn_m[t]; ++q) C.u_sn[C.sn_ridx[t] + q] = (uint16_t)t;
+    C.lev_u.assign(C.nlev + 1, (int32_t)ri);
+    for (int32_t t = nb - 1; t >= 0; --t) C.lev_u[C.sn_level[t]] = C.sn_ridx[t];
     {
         std::vector<int32_t> f(C.seg_ptr.begin(), C.seg_ptr.end() - 1);
         for (int32_t t = 0; t < nb; ++t)
             for (int32_t q = 0; q < C.sn_m[t]; ++q) {
                 int32_t i = Rn[t][q], s = f[i]++;
                 C.seg_off[s] = C.sn_val[t] + C.sn_nc[t] * C.sn_nc[t] + q * C.sn_nc[t];
+                C.seg_u[s] = (uint16_t)(C.sn_ridx[t] + q);
                 C.seg_c0[s] = (uint16_t)C.sn_c0[t];
                 C.seg_nc[s] = (uint16_t)C.sn_nc[t];
             }

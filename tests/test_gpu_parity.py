@@ -187,10 +187,23 @@ def test_autotune_then_solve(B):
     cfg = gen.make_config("c3", small=True)
     h, P, z = _setup(B, cfg, check_every=10, z_scale=8.0)
     ch = h.autotune(8)
-    assert ch["rhs_per_block"] in (1, 2, 4, 8) and ch["sweep_threads"] in (128, 256, 512)
+    assert ch["rhs_per_block"] in (1, 2, 4, 8) and ch["sweep_threads"] in (128, 256, 512) and ch["sweep_variant"] in (1, 2)
     r = h.solve(cfg["b"], 1e-8)
     assert r["status"] == 0
     ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8)
     for c in range(8):
         assert int(r["iters"][c, 0]) == int(ro["iters"][c, 0])
         assert _rel(r["x"][c], ro["x"][c]) <= 1e-8
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_sweep_variants_match_oracle(B, variant, name):
+    """Both forward-substitution variants give the oracle's iterates (FP64, 2 RHS)."""
+    cfg = gen.make_config(name, small=True)
+    h, P, z = _setup(B, cfg, z_scale=8.0, sweep_variant=variant)
+    b = cfg["b"][:2] if cfg["b"].shape[0] > 1 else np.vstack([cfg["b"], cfg["b"][:, ::-1]])
+    xg = h.run_sweeps(b, 25)
+    xo = O.Solver(P, z).run(b, 25, 0, 0.0)["x"]
+    for r in range(2):
+        assert _rel(xg[r], xo[r]) <= 1e-10
