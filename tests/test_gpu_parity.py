@@ -104,8 +104,10 @@ def test_multi_rhs_and_batch(B):
     assert r["iters"].shape == (4, cfg["nsys"]) and (r["iters"] > 0).all()
     ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8, sys_ptr=cfg["sys_ptr"])
     assert (r["relres"] <= 1e-8).all()
+    assert np.array_equal(r["iters"], ro["iters"])
+    xo = O.Solver(P, z).run(cfg["b"], int(r["iters"].max()), 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"]
     for c in range(4):
-        assert _rel(r["x"][c], ro["x"][c]) <= 1e-7
+        assert _rel(r["x"][c], xo[c]) <= 1e-10
 
 
 def test_checkpoint_resume_bitwise(B):
@@ -191,9 +193,13 @@ def test_autotune_then_solve(B):
     r = h.solve(cfg["b"], 1e-8)
     assert r["status"] == 0
     ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8)
+    # every RHS passes the test at the oracle's sweep; the solve runs until the last one passes,
+    # so x is compared with the oracle's iterate after that many sweeps
+    last = int(r["iters"].max())
+    xo = O.Solver(P, z).run(cfg["b"], last, 0, 0.0)["x"]
     for c in range(8):
         assert int(r["iters"][c, 0]) == int(ro["iters"][c, 0])
-        assert _rel(r["x"][c], ro["x"][c]) <= 1e-8
+        assert _rel(r["x"][c], xo[c]) <= 1e-10
 
 
 @pytest.mark.parametrize("variant", [1, 2])
