@@ -54,6 +54,27 @@ def pair_colouring(k1: np.ndarray, k2: np.ndarray):
     return pid, colour
 
 
+def port_vtl(part: dict, nsub: int) -> np.ndarray:
+    """VTL of every port: a port of subgraph k at vertex v with other end k2 lies on VTL (v, min, max)."""
+    k_of_port = np.repeat(np.arange(nsub), np.diff(part["port_ptr"]))
+    lo = np.minimum(k_of_port, part["port_other"]).astype(np.int64)
+    hi = np.maximum(k_of_port, part["port_other"]).astype(np.int64)
+    key_l = np.stack([part["vtl_v"], part["vtl_k"].astype(np.int64), part["vtl_k2"].astype(np.int64)])
+    order = np.lexsort(key_l[::-1])
+    ks = key_l[:, order]
+    # position of (v, lo, hi) among the sorted VTL keys
+    idx = np.lexsort((np.concatenate([ks[2], hi]), np.concatenate([ks[1], lo]), np.concatenate([ks[0], part["port_v"]])))
+    nv = ks.shape[1]
+    out = np.empty(len(lo), np.int64)
+    last = -1
+    for j in idx:  # sorted merge: every port follows its VTL key
+        if j < nv:
+            last = j
+        else:
+            out[j - nv] = order[last]
+    return out
+
+
 class Prober:
     """Probe runs of K sweeps on one partitioned system."""
 
@@ -65,21 +86,7 @@ class Prober:
         self.k = k_probe
         self.z0 = self.part["zdiag"]
         self.twin = self.part["port_twin"]
-        # VTL of every port: ports are listed per subgraph; recover it from (v, k, other)
-        self.port_vtl = self._port_vtl()
-
-    def _port_vtl(self):
-        p = self.part
-        k_of_port = np.repeat(np.arange(self.info["nsub"]), np.diff(p["port_ptr"]))
-        a = np.minimum(k_of_port, p["port_other"])
-        b = np.maximum(k_of_port, p["port_other"])
-        key_p = np.stack([p["port_v"], a, b], 1)
-        key_l = np.stack([p["vtl_v"], p["vtl_k"], p["vtl_k2"]], 1)
-        order = np.lexsort(key_l.T[::-1])
-        sorted_l = key_l[order]
-        idx = np.searchsorted(sorted_l[:, 0] * (1 << 40) + sorted_l[:, 1] * (1 << 20) + sorted_l[:, 2],
-                              key_p[:, 0] * (1 << 40) + key_p[:, 1] * (1 << 20) + key_p[:, 2])
-        return order[idx]
+        self.port_vtl = port_vtl(self.part, self.info["nsub"])
 
     def residual(self, z) -> float:
         self.h.setup(B.VTM_Z_USER, z)
