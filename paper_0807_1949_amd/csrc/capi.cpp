@@ -66,7 +66,7 @@ struct vtm_ctx {
     int64_t nsplit = 0, nports = 0, total_val = 0, total_ws = 0, total_lower = 0;
     std::vector<DevBuf *> all;
     // symbolic (class level)
-    DevBuf d_segu, d_usn, d_levu;
+    DevBuf d_segu, d_usn, d_levu, d_colrec, d_urec;
     int32_t max_nu = 0;
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
         d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
@@ -108,7 +108,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -172,6 +172,8 @@ vtm::DevSym dev_sym(vtm_ctx *h) {
     s.seg_c0 = h->d_segc0.as<uint16_t>();
     s.seg_nc = h->d_segnc.as<uint16_t>();
     s.seg_u = h->d_segu.as<uint16_t>();
+    s.colrec = h->d_colrec.as<int32_t>();
+    s.urec = h->d_urec.as<int32_t>();
     s.u_sn = h->d_usn.as<uint16_t>();
     s.lev_u = h->d_levu.as<int32_t>();
     s.sc_ptr = h->d_scptr.as<int32_t>();
@@ -225,7 +227,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     std::vector<int32_t> lev, colsn, snc0, snnc, snm, snval, snridx, snuoff, chptr, chidx, segptr, segoff, scptr,
         scsrc, scdst;
     std::vector<uint16_t> ridx, rel, segc0, segnc, segu, usn;
-    std::vector<int32_t> levu;
+    std::vector<int32_t> levu, colrec, urec;
     h->max_nk = 0;
     h->max_front = 0;
     h->max_nu = 0;
@@ -252,6 +254,8 @@ vtm_status upload_partition(vtm_ctx *h) {
         levu.insert(levu.end(), C.lev_u.begin(), C.lev_u.end());
         segu.insert(segu.end(), C.seg_u.begin(), C.seg_u.end());
         usn.insert(usn.end(), C.u_sn.begin(), C.u_sn.end());
+        colrec.insert(colrec.end(), C.colrec.begin(), C.colrec.end());
+        urec.insert(urec.end(), C.urec.begin(), C.urec.end());
         lev.insert(lev.end(), C.lev_c0.begin(), C.lev_c0.end());
         colsn.insert(colsn.end(), C.col_sn.begin(), C.col_sn.end());
         snc0.insert(snc0.end(), C.sn_c0.begin(), C.sn_c0.end());
@@ -347,7 +351,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     UP(d_cls, cls); UP(d_lev, lev); UP(d_colsn, colsn); UP(d_snc0, snc0); UP(d_snnc, snnc); UP(d_snm, snm);
     UP(d_snval, snval); UP(d_snridx, snridx); UP(d_snuoff, snuoff); UP(d_ridx, ridx); UP(d_rel, rel);
     UP(d_chptr, chptr); UP(d_chidx, chidx); UP(d_segptr, segptr); UP(d_segoff, segoff); UP(d_segc0, segc0);
-    UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
+    UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_colrec, colrec); UP(d_urec, urec); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
     UP(d_subcls, subcls); UP(d_subval, subval); UP(d_subx, subx); UP(d_subaval, subaval); UP(d_subws, subws);
     UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt);
     UP(d_fvtx, fvtx); UP(d_fmul, fmul); UP(d_cpptr, P.s_ptr); UP(d_cpidx, cpidx);

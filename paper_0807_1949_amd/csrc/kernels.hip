@@ -113,9 +113,13 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
                 Vs[i * nc + j] = -acc / F[i * f + i];
             }
         }
+        __syncthreads();  // Linv complete
         for (int idx = tid; idx < m * nc; idx += nt) {
-            const int i = idx / nc, j = idx - i * nc;
-            Vs[nc * nc + idx] = F[(nc + i) * f + j];
+            const int q = idx / nc, j = idx - q * nc;
+            const double *l21 = F + (nc + q) * f;
+            double acc = 0.0;
+            for (int i = j; i < nc; ++i) acc += l21[i] * Vs[i * nc + j];
+            Vs[nc * nc + idx] = acc;  // W = L21 L11^{-1}
         }
         double *Us = W + sn_uoff[s];
         for (int idx = tid; idx < m * m; idx += nt) {
@@ -144,29 +148,46 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
 }
 
 // ------------------------------------------------------------------------ sweep
+//
+// Factor layout per supernode s (nc columns, m off-diagonal rows R_s): Linv_s = L11^{-1}
+// (nc x nc, row-major, upper part zero) followed by W_s = L21 L11^{-1} (m x nc, row-major).
+// With t_s = r_s - (updates from descendants):
+//   forward   y_s = Linv_s t_s,  updates to the rows R_s: u_s = L21 y_s = W_s t_s
+//   backward  x_s = Linv_s^T y_s - W_s^T x_{R_s}
+// so one level costs two phases forward (gather t; then y and u together) and one backward.
+struct ColRec {
+    int32_t off, c0nc, jjm, ridx;
+};
+__device__ inline ColRec load_col(const int32_t *__restrict__ rec, int i) {
+    const int4 v = reinterpret_cast<const int4 *>(rec)[i];
+    return ColRec{v.x, v.y, v.z, v.w};
+}
+__device__ inline int hi16(int32_t w) { return (int)((uint32_t)w >> 16); }
+__device__ inline int lo16(int32_t w) { return (int)((uint32_t)w & 0xFFFFu); }
+
 template <typename T, int R, int V>
 __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
-                                                    const T *__restrict__ vals, const T *__restrict__ bsplit,
-                                                    const int32_t *__restrict__ twin, const T *__restrict__ invz,
-                                                    const T *__restrict__ o_prev, T *__restrict__ o_next,
-                                                    T *__restrict__ xloc, int write_x) {
+                                               const T *__restrict__ vals, const T *__restrict__ bsplit,
+                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
+                                               const T *__restrict__ o_prev, T *__restrict__ o_next,
+                                               T *__restrict__ xloc, int write_x) {
     extern __shared__ char smraw[];
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
-    T *vec = reinterpret_cast<T *>(smraw);
-    T *tmp = vec + (size_t)nk * R;
-    T *ubuf = tmp + (size_t)nk * R;  // variant 1: update entries L21_s y_s of every R_s row
+    T *vec = reinterpret_cast<T *>(smraw);  // right side, then y (forward result)
+    T *tmp = vec + (size_t)nk * R;          // t during the forward pass, x during the backward pass
+    T *ubuf = tmp + (size_t)nk * R;         // variant 1: update entries W_s t_s of every R_s row
     const T *Vk = vals + D.val[k];
     const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
     const T *bs = bsplit + xo;
     const int64_t wo = (int64_t)g * nports * R;
-    const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *col_sn = S.col_sn + C.o_col;
-    const int32_t *sn_c0 = S.sn_c0 + C.o_sn, *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn;
-    const int32_t *sn_val = S.sn_val + C.o_sn, *sn_ridx = S.sn_ridx + C.o_sn;
+    const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *lev_u = S.lev_u + C.o_lev;
+    const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
+    const int32_t *urec = S.urec + 2 * (int64_t)C.o_ridx;
     const uint16_t *ridx = S.ridx + C.o_ridx;
     const int32_t *seg_ptr = S.seg_ptr + C.o_colp, *seg_off = S.seg_off + C.o_seg;
-    const uint16_t *seg_c0 = S.seg_c0 + C.o_seg, *seg_nc = S.seg_nc + C.o_seg;
+    const uint16_t *seg_c0 = S.seg_c0 + C.o_seg, *seg_nc = S.seg_nc + C.o_seg, *seg_u = S.seg_u + C.o_seg;
 
     // right side of (5.8): split source + Z^{-1} * incoming wave at every port
     for (int i = tid; i < nk * R; i += nt) vec[i] = bs[i];
@@ -187,30 +208,28 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
         for (int c = 0; c < R; ++c) vec[pos * R + c] = acc[c];
     }
     __syncthreads();
-    // forward substitution L y = rhs, one level (independent subtrees) at a time
-    const uint16_t *seg_u = S.seg_u + C.o_seg, *u_sn = S.u_sn + C.o_ridx;
-    const int32_t *lev_u = S.lev_u + C.o_lev;
+    // forward substitution, one level (independent subtrees) at a time
     for (int lv = 0; lv < C.nlev; ++lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
         for (int i = cb + tid; i < ce; i += nt) {
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = vec[i * R + c];
+            const int s0 = seg_ptr[i], s1 = seg_ptr[i + 1];
             if (V == 0) {
-                // pull: L21_d[q, :] . y_d for every descendant row segment of row i
-                for (int s = seg_ptr[i]; s < seg_ptr[i + 1]; ++s) {
-                    const T *l = Vk + seg_off[s];
-                    const T *y = vec + seg_c0[s] * R;
+                // pull: W_d[q, :] . t_d of every descendant supernode d with R_d[q] = i
+                for (int s = s0; s < s1; ++s) {
+                    const T *w = Vk + seg_off[s];
+                    const T *t = tmp + seg_c0[s] * R;
                     const int n = seg_nc[s];
                     for (int j = 0; j < n; ++j) {
-                        const T lj = l[j];
+                        const T wj = w[j];
 #pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] -= lj * y[j * R + c];
+                        for (int c = 0; c < R; ++c) acc[c] -= wj * t[j * R + c];
                     }
                 }
             } else {
-                // gather the update entries computed by the lower levels
-                for (int s = seg_ptr[i]; s < seg_ptr[i + 1]; ++s) {
+                for (int s = s0; s < s1; ++s) {
                     const T *u = ubuf + seg_u[s] * R;
 #pragma unroll
                     for (int c = 0; c < R; ++c) acc[c] -= u[c];
@@ -220,76 +239,68 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
             for (int c = 0; c < R; ++c) tmp[i * R + c] = acc[c];
         }
         __syncthreads();
-        for (int i = cb + tid; i < ce; i += nt) {
-            const int s = col_sn[i], c0 = sn_c0[s], nc = sn_nc[s], jj = i - c0;
-            const T *row = Vk + sn_val[s] + jj * nc;
-            const T *t = tmp + c0 * R;
+        // y = Linv t for this level's columns and (variant 1) u = W t for its update entries
+        const int nrow = ce - cb;
+        const int nu = V == 1 ? lev_u[lv + 1] - lev_u[lv] : 0;
+        for (int task = tid; task < nrow + nu; task += nt) {
+            const T *l;
+            const T *t;
+            int n;
+            T *out;
+            if (task < nrow) {
+                const int i = cb + task;
+                const ColRec r = load_col(colrec, i);
+                const int nc = lo16(r.c0nc), jj = hi16(r.jjm);
+                l = Vk + r.off + jj * nc;
+                t = tmp + hi16(r.c0nc) * R;
+                n = jj + 1;
+                out = vec + i * R;
+            } else {
+                const int e = lev_u[lv] + task - nrow;
+                const int2 u = reinterpret_cast<const int2 *>(urec)[e];
+                l = Vk + u.x;
+                t = tmp + hi16(u.y) * R;
+                n = lo16(u.y);
+                out = ubuf + e * R;
+            }
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int j = 0; j <= jj; ++j) {
-                const T lj = row[j];
+            for (int j = 0; j < n; ++j) {
+                const T lj = l[j];
 #pragma unroll
                 for (int c = 0; c < R; ++c) acc[c] += lj * t[j * R + c];
             }
 #pragma unroll
-            for (int c = 0; c < R; ++c) vec[i * R + c] = acc[c];
+            for (int c = 0; c < R; ++c) out[c] = acc[c];
         }
         __syncthreads();
-        if (V == 1 && lev_u[lv + 1] > lev_u[lv]) {
-            // update entries of this level's supernodes: u[e] = L21_s[q, :] . y_s
-            for (int e = lev_u[lv] + tid; e < lev_u[lv + 1]; e += nt) {
-                const int s = u_sn[e], nc = sn_nc[s], q = e - sn_ridx[s];
-                const T *l = Vk + sn_val[s] + nc * nc + q * nc;
-                const T *y = vec + sn_c0[s] * R;
-                T acc[R];
-#pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] = 0;
-                for (int j = 0; j < nc; ++j) {
-                    const T lj = l[j];
-#pragma unroll
-                    for (int c = 0; c < R; ++c) acc[c] += lj * y[j * R + c];
-                }
-#pragma unroll
-                for (int c = 0; c < R; ++c) ubuf[e * R + c] = acc[c];
-            }
-            __syncthreads();
-        }
     }
-    // backward substitution L^T x = y, root level first
+    // backward substitution, root level first: x_s = Linv^T y_s - W^T x_R  (x kept in tmp)
     for (int lv = C.nlev - 1; lv >= 0; --lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
         for (int j = cb + tid; j < ce; j += nt) {
-            const int s = col_sn[j], c0 = sn_c0[s], nc = sn_nc[s], m = sn_m[s], jj = j - c0;
-            const T *col = Vk + sn_val[s] + nc * nc + jj;
-            const uint16_t *r = ridx + sn_ridx[s];
-            T acc[R];
-#pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] = vec[j * R + c];
-            for (int q = 0; q < m; ++q) {
-                const T lq = col[q * nc];
-                const T *x = vec + r[q] * R;
-#pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] -= lq * x[c];
-            }
-#pragma unroll
-            for (int c = 0; c < R; ++c) tmp[j * R + c] = acc[c];
-        }
-        __syncthreads();
-        for (int j = cb + tid; j < ce; j += nt) {
-            const int s = col_sn[j], c0 = sn_c0[s], nc = sn_nc[s], jj = j - c0;
-            const T *colv = Vk + sn_val[s] + jj;
-            const T *t = tmp + c0 * R;
+            const ColRec r = load_col(colrec, j);
+            const int c0 = hi16(r.c0nc), nc = lo16(r.c0nc), jj = hi16(r.jjm), m = lo16(r.jjm);
+            const T *lcol = Vk + r.off + jj;
+            const T *wcol = Vk + r.off + nc * nc + jj;
+            const uint16_t *rr = ridx + r.ridx;
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
             for (int i = jj; i < nc; ++i) {
-                const T li = colv[i * nc];
+                const T li = lcol[i * nc];
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += li * t[i * R + c];
+                for (int c = 0; c < R; ++c) acc[c] += li * vec[(c0 + i) * R + c];
+            }
+            for (int q = 0; q < m; ++q) {
+                const T wq = wcol[q * nc];
+                const T *x = tmp + rr[q] * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] -= wq * x[c];
             }
 #pragma unroll
-            for (int c = 0; c < R; ++c) vec[j * R + c] = acc[c];
+            for (int c = 0; c < R; ++c) tmp[j * R + c] = acc[c];
         }
         __syncthreads();
     }
@@ -300,12 +311,12 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
             const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
             T *o = o_next + wo + (int64_t)(pb + j) * R;
 #pragma unroll
-            for (int c = 0; c < R; ++c) o[c] = (T)2 * vec[pos * R + c] - a[c];
+            for (int c = 0; c < R; ++c) o[c] = (T)2 * tmp[pos * R + c] - a[c];
         }
     }
     if (write_x) {
         T *xo_ = xloc + xo;
-        for (int i = tid; i < nk * R; i += nt) xo_[i] = vec[i];
+        for (int i = tid; i < nk * R; i += nt) xo_[i] = tmp[i];
     }
 }
 

@@ -32,6 +32,7 @@ struct DevSym {
     const int32_t *seg_ptr, *seg_off;
     const uint16_t *seg_c0, *seg_nc;
     const uint16_t *seg_u, *u_sn;   // update-entry lists (variant 1 of the sweep)
+    const int32_t *colrec, *urec;   // packed per-column and per-update-entry records
     const int32_t *lev_u;           // update-entry range per level (lev offsets)
     const int32_t *sc_ptr, *sc_src, *sc_dst;
 };

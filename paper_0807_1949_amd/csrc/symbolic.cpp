@@ -303,6 +303,21 @@ int analyse(const Partition &P, int32_t k, int leaf, ClassSym &C, std::string &e
     C.u_sn.resize(ri);
     for (int32_t t = 0; t < nb; ++t)
         for (int32_t q = 0; q < C.sn_m[t]; ++q) C.u_sn[C.sn_ridx[t] + q] = (uint16_t)t;
+    C.colrec.resize(4 * (size_t)nk);
+    for (int32_t t = 0; t < nb; ++t)
+        for (int32_t q = 0; q < C.sn_nc[t]; ++q) {
+            int32_t *r = &C.colrec[4 * (size_t)(C.sn_c0[t] + q)];
+            r[0] = C.sn_val[t];
+            r[1] = (int32_t)(((uint32_t)C.sn_c0[t] << 16) | (uint32_t)C.sn_nc[t]);
+            r[2] = (int32_t)(((uint32_t)q << 16) | (uint32_t)C.sn_m[t]);
+            r[3] = C.sn_ridx[t];
+        }
+    C.urec.resize(2 * (size_t)ri);
+    for (int32_t t = 0; t < nb; ++t)
+        for (int32_t q = 0; q < C.sn_m[t]; ++q) {
+            C.urec[2 * (size_t)(C.sn_ridx[t] + q)] = C.sn_val[t] + C.sn_nc[t] * C.sn_nc[t] + q * C.sn_nc[t];
+            C.urec[2 * (size_t)(C.sn_ridx[t] + q) + 1] = (int32_t)(((uint32_t)C.sn_c0[t] << 16) | (uint32_t)C.sn_nc[t]);
+        }
     C.lev_u.assign(C.nlev + 1, (int32_t)ri);
     for (int32_t t = nb - 1; t >= 0; --t) C.lev_u[C.sn_level[t]] = C.sn_ridx[t];
     {
