@@ -30,8 +30,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warmup, check_every, max_sweeps):
-    h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps)
+def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warmup, check_every, max_sweeps,
+                mode=0):
+    h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps, sweep_mode=mode)
     t0 = time.perf_counter()
     info = h.evs_partition(A, spec)
     part_s = time.perf_counter() - t0
@@ -78,8 +79,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--small", action="store_true", help="128^2 version of the workload (quick check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="ir_diag,fp64_diag",
-                    help="comma list of {ir,fp64}_{diag,a64}; the first is the headline")
+    ap.add_argument("--variants", default="ir_diag,fp64_diag_sub",
+                    help="comma list of {ir,fp64}_{diag,aNN}[_sub|_port]: precision, impedance rule "
+                         "(diagonal or NN times it), sweep mode (substitution, port-reduced, default chosen "
+                         "by the library); the first is the headline")
     ap.add_argument("--check-every", type=int, default=20)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration)")
@@ -109,7 +112,9 @@ def main():
     variants = args.variants.split(",")
     zinfo = {}
     for v in variants:
-        prec_s, zr = v.split("_")
+        parts = v.split("_")
+        prec_s, zr = parts[0], parts[1]
+        mode = {"sub": 1, "port": 2}.get(parts[2], 0) if len(parts) > 2 else 0
         precision = B.VTM_FP32_IR if prec_s == "ir" else B.VTM_FP64
         if zr == "diag":
             z_rule, z = B.VTM_Z_DIAG, None
@@ -122,7 +127,7 @@ def main():
         zinfo[v] = z
         log(f"variant {v}")
         results[v] = run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, args.steps, args.warmup,
-                                 args.check_every, 200000)
+                                 args.check_every, 200000, mode)
     head = results[variants[0]]
     st = head["stats"]
     sweeps = st["sweeps"]
@@ -143,9 +148,10 @@ def main():
         relres=head["relres"],
         variants={v: dict(time_to_tol_s=r["step_s"], sweeps=r["stats"]["sweeps"], setup_ms=r["stats"]["setup_ms"],
                           sweep_us=r["stats"]["sweep_ms"] * 1e3 / max(r["stats"]["sweeps"], 1),
-                          outer_steps=r["stats"]["outer_steps"], relres=r["relres"], status=r["status"])
+                          outer_steps=r["stats"]["outer_steps"], relres=r["relres"], status=r["status"],
+                          sweep_mode=r["stats"]["sweep_mode"])
                   for v, r in results.items()},
-        roofline=dict(kernel="k_sweep", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+        roofline=dict(kernel="k_schur" if st["sweep_mode"] == 2 else "k_sweep", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=None,
                       bytes_per_launch=st["bytes_per_sweep"], avg_launch_us=sweep_s * 1e6),
     )

@@ -76,7 +76,10 @@ typedef struct {
     int32_t graph_mode;    /* 0: replay sweep batches as captured HIP graphs; 1: plain launches */
     int32_t sweep_variant; /* forward substitution: 1 = row dot products over descendant L21 rows,
                               2 = per-level update entries L21*y gathered by the ancestors, 0 = choose */
-    int32_t reserved[3];
+    int32_t sweep_mode;    /* 1 = substitution sweeps; 2 = port-reduced sweeps u = c + G Z^{-1} a with the
+                              port Green's functions G_k = R_k K_k^{-1} R_k^T (same iterates; the
+                              substitution runs only at convergence tests); 0 = choose by bytes */
+    int32_t reserved[2];
 } vtm_options;
 
 /*
@@ -144,7 +147,9 @@ typedef struct {
     double solve_ms;         /* last solve, wall time on the stream (events) */
     double sweep_ms;         /* last solve, summed sweep-kernel time (events around sweep launches) */
     double bytes_per_sweep;  /* algorithmic bytes one sweep must move (factor once + vectors + waves) */
-    double flops_per_sweep;  /* 4 * nrhs * stored lower-factor entries */
+    double flops_per_sweep;  /* substitution: 4 * nrhs * lower-factor entries; port-reduced: 2 * nrhs * G entries */
+    int32_t sweep_mode;      /* mode of the last solve: 1 substitution, 2 port-reduced */
+    int32_t pad;
 } vtm_stats;
 
 /* Create a handle bound to options->device; NULL options = defaults. */
@@ -222,7 +227,8 @@ vtm_status vtm_run_sweeps(vtm_handle h, const double *b, int32_t nrhs, int64_t l
  * (right-hand sides per workgroup R in {1,2,4,8} up to nrhs, workgroup size in
  * {128, 256, 512}) on the current factors with HIP events and keeps the
  * fastest for solves with nrhs right-hand sides; also tries both forward
- * substitution variants.  chosen[3] = {R, threads, variant} (may be NULL).  The waves are reset.  Requires vtm_setup.
+ * substitution variants and, when the port Green's functions exist, the
+ * port-reduced sweep.  chosen[4] = {R, threads, variant, mode} (may be NULL).  The waves are reset.  Requires vtm_setup.
  */
 vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen);
 

@@ -29,7 +29,7 @@ class Options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("max_sweeps", C.c_int64), ("rhs_per_block", C.c_int32), ("leaf_size", C.c_int32),
                 ("sweep_threads", C.c_int32), ("graph_mode", C.c_int32), ("sweep_variant", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("sweep_mode", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class PartitionSpec(C.Structure):
@@ -50,7 +50,8 @@ class PartitionInfo(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("outer_steps", C.c_int32), ("checks", C.c_int32),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("sweep_ms", C.c_double),
-                ("bytes_per_sweep", C.c_double), ("flops_per_sweep", C.c_double)]
+                ("bytes_per_sweep", C.c_double), ("flops_per_sweep", C.c_double), ("sweep_mode", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class VTMError(RuntimeError):
@@ -126,7 +127,7 @@ class VTM:
 
     def __init__(self, device: int = 0, precision: int = VTM_FP64, check_every: int = 10, max_sweeps: int = 100000,
                  rhs_per_block: int = 0, leaf_size: int = 0, stream: int | None = None, sweep_threads: int = 0,
-                 graph_mode: int = 0, sweep_variant: int = 0):
+                 graph_mode: int = 0, sweep_variant: int = 0, sweep_mode: int = 0):
         self._h = C.c_void_p()
         o = Options()
         o.device = device
@@ -139,6 +140,7 @@ class VTM:
         o.sweep_threads = sweep_threads
         o.graph_mode = graph_mode
         o.sweep_variant = sweep_variant
+        o.sweep_mode = sweep_mode
         _check(lib().vtm_create(C.byref(o), C.byref(self._h)))
         self.precision = precision
         self.info = None
@@ -292,9 +294,10 @@ class VTM:
         return xk
 
     def autotune(self, nrhs: int = 1):
-        ch = np.zeros(3, np.int32)
+        ch = np.zeros(4, np.int32)
         _check(lib().vtm_autotune(self._h, nrhs, _np_ptr(ch)))
-        return dict(rhs_per_block=int(ch[0]), sweep_threads=int(ch[1]), sweep_variant=int(ch[2]))
+        return dict(rhs_per_block=int(ch[0]), sweep_threads=int(ch[1]), sweep_variant=int(ch[2]),
+                    sweep_mode=int(ch[3]))
 
     def reset_waves(self):
         _check(lib().vtm_reset_waves(self._h))

@@ -67,6 +67,11 @@ struct vtm_ctx {
     std::vector<DevBuf *> all;
     // symbolic (class level)
     DevBuf d_segu, d_usn, d_levu, d_colrec, d_urec;
+    // port-reduced sweeps
+    DevBuf d_goff, d_G64, d_G32, d_cport;
+    int32_t max_p = 0, npg = 0;
+    int64_t total_g = 0;
+    bool have_green = false;
     int32_t max_nu = 0;
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
         d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
@@ -108,7 +113,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -309,6 +314,18 @@ vtm_status upload_partition(vtm_ctx *h) {
     }
     h->total_val = vo;
     h->total_ws = wo;
+    {
+        std::vector<int64_t> goff(nsub + 1, 0);
+        h->max_p = 0;
+        for (int32_t k = 0; k < nsub; ++k) {
+            const int64_t p = pgptr[k + 1] - pgptr[k], ldp = (p + 3) & ~3;
+            goff[k + 1] = goff[k] + p * ldp;
+            h->max_p = std::max<int32_t>(h->max_p, (int32_t)p);
+        }
+        h->total_g = goff[nsub];
+        h->npg = pgptr[nsub];
+        HIP_TRY(upload(h->d_goff, goff, st));
+    }
     h->nsplit = P.loc_ptr[nsub];
     h->nports = (int64_t)P.port_v.size();
     // ---- split/merge maps (factor order inside every subgraph)
@@ -426,9 +443,22 @@ T *vals_of(vtm_ctx *h) {
     else return h->d_vals64.as<T>();
 }
 template <typename T>
+T *green_of(vtm_ctx *h) {
+    if constexpr (sizeof(T) == 4) return h->d_G32.as<T>();
+    else return h->d_G64.as<T>();
+}
+template <typename T>
 T *invz_of(vtm_ctx *h) {
     if constexpr (sizeof(T) == 4) return h->d_invz32.as<T>();
     else return h->d_invz64.as<T>();
+}
+
+// Port-reduced sweeps when the Green's functions exist and move no more than twice the factor's bytes.
+bool use_schur(vtm_ctx *h) {
+    if (!h->have_green) return false;
+    if (h->opt.sweep_mode == 2) return true;
+    if (h->opt.sweep_mode == 1) return false;
+    return (double)h->total_g <= 2.0 * (double)h->total_lower;
 }
 
 int32_t sweep_variant(vtm_ctx *h) {
@@ -452,18 +482,26 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     const vtm::DevSub D = dev_sub(h);
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R, nt = sweep_threads(h);
     HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
+    const bool schur = use_schur(h);
+    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, R));
     auto launch = [&](int cur, bool last) {
-        vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R, nt, h->nsplit,
-                             h->nports, vals_of<T>(h),
-                             h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[cur].as<T>(),
-                             h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(), last ? 1 : 0, h->stream);
+        if (schur)
+            vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->max_p, h->npg, h->nports, green_of<T>(h),
+                                 h->d_goff.as<int64_t>(), h->d_cport.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h),
+                                 h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->stream);
+        else
+            vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R, nt, h->nsplit,
+                                 h->nports, vals_of<T>(h), h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(),
+                                 invz_of<T>(h), h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(),
+                                 last ? vtm::kSweepWriteX : 0, h->stream);
     };
     if (h->opt.graph_mode == 0 && count >= 2) {
         auto &g = h->graphs[h->cur];
-        const void *ptrs[7] = {vals_of<T>(h), h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p, h->d_o[1].p,
-                               h->d_xloc.p};
+        const void *ptrs[7] = {schur ? (const void *)green_of<T>(h) : (const void *)vals_of<T>(h),
+                               schur ? h->d_cport.p : h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p,
+                               h->d_o[1].p, h->d_xloc.p};
         bool same = g.exec && g.count == count && g.R == R && g.ng == ng && g.threads == nt &&
-                    g.variant == sweep_variant(h);
+                    g.variant == sweep_variant(h) + (schur ? 10 : 0);
         for (int i = 0; i < 7 && same; ++i) same = g.ptrs[i] == ptrs[i];
         if (!same) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -483,7 +521,7 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
             g.R = R;
             g.ng = ng;
             g.threads = nt;
-            g.variant = sweep_variant(h);
+            g.variant = sweep_variant(h) + (schur ? 10 : 0);
             for (int i = 0; i < 7; ++i) g.ptrs[i] = ptrs[i];
         }
         HIP_TRY(hipGraphLaunch(g.exec, h->stream));
@@ -495,6 +533,31 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
         }
     }
     h->waves_zero = false;
+    return VTM_OK;
+}
+
+// Substitution solve with the incoming waves of the last sweep (or zero waves), local solutions to xloc;
+// the waves are not advanced.
+template <typename T>
+void local_solve(vtm_ctx *h, bool zero_waves) {
+    const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
+    vtm::launch_sweep<T>(dev_sym(h), dev_sub(h), h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R,
+                         sweep_threads(h), h->nsplit, h->nports, vals_of<T>(h), h->d_bsplit.as<T>(),
+                         h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur ^ 1].as<T>(), h->d_o[h->cur].as<T>(),
+                         h->d_xloc.as<T>(),
+                         vtm::kSweepWriteX | vtm::kSweepNoWaves | (zero_waves ? vtm::kSweepZeroWaves : 0), h->stream);
+}
+
+// After a new source split: c = K^{-1} b~ at the port vertices (port-reduced sweeps only).
+template <typename T>
+vtm_status port_constants(vtm_ctx *h) {
+    if (!use_schur(h)) return VTM_OK;
+    const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
+    HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
+    HIP_TRY(ensure(h->d_cport, sizeof(T) * ((size_t)ng * h->npg * R + 1)));
+    local_solve<T>(h, true);
+    vtm::launch_gather_ports<T>(dev_sub(h), h->P.nsub, ng, h->nsplit, h->npg, R, h->d_xloc.as<T>(),
+                                h->d_cport.as<T>(), h->stream);
     return VTM_OK;
 }
 
@@ -559,6 +622,8 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     HIP_TRY(hipMemsetAsync(xcur, 0, sizeof(double) * n * nrhs, h->stream));
     vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
     if ((rc = zero_waves<T>(h))) return rc;
+    if ((rc = port_constants<T>(h))) return rc;
+    const bool schur = use_schur(h);
     double rel_outer = 1.0, rel_prev = 1e300;
     const double eta = 2e-6;
     int inner_checks = 0;
@@ -571,6 +636,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         sweeps += cnt;
         ++checks;
         ++inner_checks;
+        if (schur) local_solve<T>(h, false);  // interior potentials of the last sweep
         // merged potentials (plus the refined x in FP32_IR), FP64 residual
         vtm::launch_merge<T>(M, n, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, h->stream);
         if ((rc = residual(h, nrhs, xtr, refine ? rtr : nullptr, rel))) return rc;
@@ -611,6 +677,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             ++outer;
             vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
             if ((rc = zero_waves<T>(h))) return rc;
+            if ((rc = port_constants<T>(h))) return rc;
             last_worst = 1e300;
             continue;
         } else if (stalled) {
@@ -632,9 +699,16 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     h->stats.checks = checks;
     h->stats.solve_ms = total;
     h->stats.sweep_ms = sweep_ms;
-    h->stats.bytes_per_sweep =
-        (double)sizeof(T) * ((double)h->total_lower + (double)h->nsplit * nrhs + 2.0 * (double)h->nports * nrhs);
-    h->stats.flops_per_sweep = 4.0 * nrhs * (double)h->total_lower;
+    if (schur) {
+        h->stats.bytes_per_sweep =
+            (double)sizeof(T) * ((double)h->total_g + (double)h->npg * nrhs + 2.0 * (double)h->nports * nrhs);
+        h->stats.flops_per_sweep = 2.0 * nrhs * (double)h->total_g;
+    } else {
+        h->stats.bytes_per_sweep =
+            (double)sizeof(T) * ((double)h->total_lower + (double)h->nsplit * nrhs + 2.0 * (double)h->nports * nrhs);
+        h->stats.flops_per_sweep = 4.0 * nrhs * (double)h->total_lower;
+    }
+    h->stats.sweep_mode = schur ? 2 : 1;
     if ((rc = write_x(h, xcur, x, nrhs, ldx))) return rc;
     if (iters) std::copy(it.begin(), it.end(), iters);
     if (relres) std::copy(last.begin(), last.end(), relres);
@@ -653,7 +727,9 @@ vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int6
     const vtm::DevMaps M = dev_maps(h);
     vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, h->wave_R, h->d_bsplit.as<T>(), h->stream);
     if (nsweeps > 0) {
+        if ((rc = port_constants<T>(h))) return rc;
         if ((rc = run_sweeps_dev<T>(h, nsweeps))) return rc;
+        if (use_schur(h)) local_solve<T>(h, false);
         vtm::launch_merge<T>(M, n, h->nsplit, nrhs, h->wave_R, h->d_xloc.as<T>(), nullptr, n, h->d_x.as<double>(), n,
                              h->stream);
     } else {
@@ -862,6 +938,20 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
         HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
         vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
     }
+    // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
+    h->have_green = false;
+    if (h->opt.sweep_mode != 1 && h->max_p > 0 && h->max_p <= 2048 &&
+        (h->opt.sweep_mode == 2 || (double)h->total_g <= 2.0 * (double)h->total_lower)) {
+        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
+        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
+        vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p, h->d_vals64.as<double>(),
+                          h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
+        if (h->fp32()) {
+            HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 4)));
+            vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);
+        }
+        h->have_green = true;
+    }
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipGetLastError());
     std::vector<int32_t> status(P.nsub);
@@ -961,25 +1051,34 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
     while (maxR < nrhs && maxR < 8) maxR *= 2;
     const vtm_options saved = h->opt;
     double best = 1e300;
-    int32_t bestR = 1, bestT = 256;
+    vtm_options bestopt = saved;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    int32_t bestV = 0;
+    struct Cand { int32_t mode, var, nt; };
+    std::vector<Cand> cands;
+    for (int32_t var = 1; var <= 2; ++var)
+        for (int32_t nt : {128, 256, 512}) cands.push_back({1, var, nt});
+    if (h->have_green) cands.push_back({2, 0, 256});
     for (int32_t R = 1; R <= maxR; R *= 2)
-      for (int32_t var = 1; var <= 2; ++var) {
-        const size_t lds = h->tsize() * (size_t)R * (2 * (size_t)h->max_nk + (var == 2 ? h->max_nu : 0));
-        if (lds > 160 * 1024) continue;
-        for (int32_t nt : {128, 256, 512}) {
+        for (const Cand &cd : cands) {
+            const size_t lds = cd.mode == 2 ? 0
+                             : h->tsize() * (size_t)R * (2 * (size_t)h->max_nk + (cd.var == 2 ? h->max_nu : 0));
+            if (lds > 160 * 1024) continue;
             h->opt.rhs_per_block = R;
-            h->opt.sweep_threads = nt;
-            h->opt.sweep_variant = var == 2 ? 2 : 1;
+            h->opt.sweep_threads = cd.nt;
+            h->opt.sweep_variant = cd.mode == 2 ? saved.sweep_variant : cd.var;
+            h->opt.sweep_mode = cd.mode;
             h->opt.graph_mode = 1;
             vtm_status rc = h->fp32() ? ensure_waves<float>(h, nrhs) : ensure_waves<double>(h, nrhs);
             if (!rc) rc = h->fp32() ? alloc_solve<float>(h, nrhs) : alloc_solve<double>(h, nrhs);
             if (rc) { h->opt = saved; return rc; }
             const int32_t ng = (nrhs + R - 1) / R;
             HIP_TRY(hipMemsetAsync(h->d_bsplit.p, 0, h->tsize() * (size_t)ng * h->nsplit * R, h->stream));
+            if (cd.mode == 2) {
+                HIP_TRY(ensure(h->d_cport, h->tsize() * ((size_t)ng * h->npg * R + 1)));
+                HIP_TRY(hipMemsetAsync(h->d_cport.p, 0, h->tsize() * ((size_t)ng * h->npg * R + 1), h->stream));
+            }
             const int64_t warm = 2, timed = 6;
             rc = h->fp32() ? run_sweeps_dev<float>(h, warm) : run_sweeps_dev<double>(h, warm);
             HIP_TRY(hipEventRecord(e0, h->stream));
@@ -989,17 +1088,25 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
             if (rc) { h->opt = saved; return rc; }
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; bestR = R; bestT = nt; bestV = h->opt.sweep_variant; }
+            if (ms < best) {
+                best = ms;
+                bestopt = h->opt;
+            }
         }
-      }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->opt = saved;
-    h->opt.rhs_per_block = bestR;
-    h->opt.sweep_threads = bestT;
-    h->opt.sweep_variant = bestV;
+    h->opt.rhs_per_block = bestopt.rhs_per_block;
+    h->opt.sweep_threads = bestopt.sweep_threads;
+    h->opt.sweep_variant = bestopt.sweep_variant;
+    h->opt.sweep_mode = bestopt.sweep_mode;
     h->wave_nrhs = 0;  // zero waves for the next solve
-    if (chosen) { chosen[0] = bestR; chosen[1] = bestT; chosen[2] = bestV; }
+    if (chosen) {
+        chosen[0] = bestopt.rhs_per_block;
+        chosen[1] = bestopt.sweep_threads;
+        chosen[2] = bestopt.sweep_variant;
+        chosen[3] = bestopt.sweep_mode;
+    }
     return VTM_OK;
 }
 

@@ -21,6 +21,7 @@ namespace vtm {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWriteX = 1, kNoWaves = 2, kZeroWaves = 4;
 
 __global__ void k_invz(const double *__restrict__ z, const int32_t *__restrict__ port_vtl, double *__restrict__ i64,
                        float *__restrict__ i32, int64_t np) {
@@ -165,49 +166,17 @@ __device__ inline ColRec load_col(const int32_t *__restrict__ rec, int i) {
 __device__ inline int hi16(int32_t w) { return (int)((uint32_t)w >> 16); }
 __device__ inline int lo16(int32_t w) { return (int)((uint32_t)w & 0xFFFFu); }
 
+// Forward and backward substitution of one subgraph, R right-hand sides interleaved in LDS.
+// In: vec = right side.  Out: tmp = x, vec = y (forward result).  Ends with a barrier.
 template <typename T, int R, int V>
-__global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
-                                               const T *__restrict__ vals, const T *__restrict__ bsplit,
-                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
-                                               const T *__restrict__ o_prev, T *__restrict__ o_next,
-                                               T *__restrict__ xloc, int write_x) {
-    extern __shared__ char smraw[];
-    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
-    const ClassDev C = S.cls[D.cls[k]];
-    const int nk = C.nk;
-    T *vec = reinterpret_cast<T *>(smraw);  // right side, then y (forward result)
-    T *tmp = vec + (size_t)nk * R;          // t during the forward pass, x during the backward pass
-    T *ubuf = tmp + (size_t)nk * R;         // variant 1: update entries W_s t_s of every R_s row
-    const T *Vk = vals + D.val[k];
-    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
-    const T *bs = bsplit + xo;
-    const int64_t wo = (int64_t)g * nports * R;
+__device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, T *vec, T *tmp, T *ubuf) {
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *lev_u = S.lev_u + C.o_lev;
     const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
     const int32_t *urec = S.urec + 2 * (int64_t)C.o_ridx;
     const uint16_t *ridx = S.ridx + C.o_ridx;
     const int32_t *seg_ptr = S.seg_ptr + C.o_colp, *seg_off = S.seg_off + C.o_seg;
     const uint16_t *seg_c0 = S.seg_c0 + C.o_seg, *seg_nc = S.seg_nc + C.o_seg, *seg_u = S.seg_u + C.o_seg;
-
-    // right side of (5.8): split source + Z^{-1} * incoming wave at every port
-    for (int i = tid; i < nk * R; i += nt) vec[i] = bs[i];
-    __syncthreads();
-    const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
-    for (int q = pg0 + tid; q < pg1; q += nt) {
-        const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
-        T acc[R];
-#pragma unroll
-        for (int c = 0; c < R; ++c) acc[c] = vec[pos * R + c];
-        for (int j = 0; j < pc; ++j) {
-            const T iz = invz[pb + j];
-            const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
-#pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
-        }
-#pragma unroll
-        for (int c = 0; c < R; ++c) vec[pos * R + c] = acc[c];
-    }
-    __syncthreads();
     // forward substitution, one level (independent subtrees) at a time
     for (int lv = 0; lv < C.nlev; ++lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
@@ -304,19 +273,204 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
         }
         __syncthreads();
     }
-    // outgoing waves o_p = 2 u_p - a_p
-    for (int q = pg0 + tid; q < pg1; q += nt) {
-        const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
-        for (int j = 0; j < pc; ++j) {
-            const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
-            T *o = o_next + wo + (int64_t)(pb + j) * R;
+}
+
+// One VTM sweep.  flags: kWriteX stores the local solutions; kNoWaves leaves o_next untouched
+// (a read-only solve with the current incoming waves); kZeroWaves ignores o_prev (a = 0).
+template <typename T, int R, int V>
+__global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
+                                               const T *__restrict__ vals, const T *__restrict__ bsplit,
+                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
+                                               const T *__restrict__ o_prev, T *__restrict__ o_next,
+                                               T *__restrict__ xloc, int flags) {
+    extern __shared__ char smraw[];
+    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int nk = C.nk;
+    T *vec = reinterpret_cast<T *>(smraw);  // right side, then y (forward result)
+    T *tmp = vec + (size_t)nk * R;          // t during the forward pass, x during the backward pass
+    T *ubuf = tmp + (size_t)nk * R;         // variant 1: update entries W_s t_s of every R_s row
+    const T *Vk = vals + D.val[k];
+    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
+    const T *bs = bsplit + xo;
+    const int64_t wo = (int64_t)g * nports * R;
+    const bool zero_waves = flags & kZeroWaves;
+
+    // right side of (5.8): split source + Z^{-1} * incoming wave at every port
+    for (int i = tid; i < nk * R; i += nt) vec[i] = bs[i];
+    __syncthreads();
+    const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
+    if (!zero_waves) {
+        for (int q = pg0 + tid; q < pg1; q += nt) {
+            const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
+            T acc[R];
 #pragma unroll
-            for (int c = 0; c < R; ++c) o[c] = (T)2 * tmp[pos * R + c] - a[c];
+            for (int c = 0; c < R; ++c) acc[c] = vec[pos * R + c];
+            for (int j = 0; j < pc; ++j) {
+                const T iz = invz[pb + j];
+                const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) vec[pos * R + c] = acc[c];
         }
     }
-    if (write_x) {
+    __syncthreads();
+    trisolve<T, R, V>(C, S, Vk, vec, tmp, ubuf);
+    // outgoing waves o_p = 2 u_p - a_p
+    if (!(flags & kNoWaves)) {
+        for (int q = pg0 + tid; q < pg1; q += nt) {
+            const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
+            for (int j = 0; j < pc; ++j) {
+                const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
+                T *o = o_next + wo + (int64_t)(pb + j) * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) o[c] = (T)2 * tmp[pos * R + c] - (zero_waves ? (T)0 : a[c]);
+            }
+        }
+    }
+    if (flags & kWriteX) {
         T *xo_ = xloc + xo;
         for (int i = tid; i < nk * R; i += nt) xo_[i] = tmp[i];
+    }
+}
+
+// Port Green's functions G_k = R_k K_k^{-1} R_k^T (R_k selects the port vertices), FP64:
+// column j of G_k is the port part of K_k^{-1} e_{v(j)}; blockIdx.y picks RHS columns j.
+template <int V>
+__global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double *__restrict__ vals,
+                                               const int64_t *__restrict__ goff, double *__restrict__ G) {
+    constexpr int R = 4;
+    extern __shared__ char smraw[];
+    const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int nk = C.nk;
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
+    const int j0 = blockIdx.y * R;
+    if (j0 >= p) return;  // uniform across the workgroup
+    double *vec = reinterpret_cast<double *>(smraw);
+    double *tmp = vec + (size_t)nk * R;
+    double *ubuf = tmp + (size_t)nk * R;
+    for (int i = tid; i < nk * R; i += nt) vec[i] = 0.0;
+    __syncthreads();
+    if (tid < R && j0 + tid < p) vec[D.pg_pos[pg0 + j0 + tid] * R + tid] = 1.0;
+    __syncthreads();
+    trisolve<double, R, V>(C, S, vals + D.val[k], vec, tmp, ubuf);
+    double *Gk = G + goff[k];
+    const int ldp = (p + 3) & ~3;  // rows padded to a multiple of 4 (padding stays zero)
+    for (int idx = tid; idx < R * p; idx += nt) {
+        const int c = idx / p, q = idx - c * p;
+        if (j0 + c < p) Gk[(int64_t)(j0 + c) * ldp + q] = tmp[D.pg_pos[pg0 + q] * R + c];
+    }
+}
+
+// c[g][q][c] = K^{-1} b~ at the port vertices (local solutions of a zero-wave solve).
+template <typename T>
+__global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
+                               T *__restrict__ cport) {
+    const int k = blockIdx.x, g = blockIdx.y;
+    const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
+    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
+    for (int idx = threadIdx.x; idx < (pg1 - pg0) * R; idx += blockDim.x) {
+        const int q = idx / R, c = idx - q * R;
+        cport[((int64_t)g * npg + pg0 + q) * R + c] = xloc[xo + D.pg_pos[pg0 + q] * R + c];
+    }
+}
+
+// Port-reduced sweep: u = c + G (Z^{-1} a) on the port vertices, then o_p = 2 u - a_p.
+// G_k is symmetric and stored with a leading dimension ldp = p rounded up to 4 (zero padded):
+// a thread owns VW consecutive port vertices and reads G[a * ldp + q .. q + VW) with one 16-byte
+// load per column a; column slices of the workgroup are summed through LDS.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
+template <typename T> __device__ inline T lane(const typename Vec16<T>::type &v, int i);
+template <> __device__ inline float lane<float>(const float4 &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+template <> __device__ inline double lane<double>(const double2 &v, int i) { return i == 0 ? v.x : v.y; }
+
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
+                                               const int64_t *__restrict__ goff, const T *__restrict__ cport,
+                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
+                                               const T *__restrict__ o_prev, T *__restrict__ o_next) {
+    using V4 = typename Vec16<T>::type;
+    constexpr int VW = Vec16<T>::W;
+    extern __shared__ char smraw[];
+    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
+    const int ldp = (p + 3) & ~3;
+    const int64_t wo = (int64_t)g * nports * R;
+    T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a summed per port vertex [ldp][R]
+    T *part = xz + (size_t)ldp * R;        // partial sums [ns][ldp][R]
+    for (int q = tid; q < ldp; q += nt) {
+        T acc[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] = 0;
+        if (q < p) {
+            const int pb = D.pg_beg[pg0 + q], pc = D.pg_cnt[pg0 + q];
+            for (int j = 0; j < pc; ++j) {
+                const T iz = invz[pb + j];
+                const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) xz[q * R + c] = acc[c];
+    }
+    __syncthreads();
+    const T *Gk = G + goff[k];
+    const int nrt = ldp / VW;                     // row threads
+    const int rows_pass = nrt < nt ? nrt : nt;    // row threads per pass
+    const int ns = nrt < nt ? nt / nrt : 1;       // column slices
+    const int slice = (p + ns - 1) / ns;
+    for (int r0 = 0; r0 < nrt; r0 += rows_pass) {
+        const int rt = r0 + tid % rows_pass, sl = tid / rows_pass;
+        if (sl < ns && rt < nrt) {
+            const int q = rt * VW;
+            const int a0 = sl * slice, a1 = min(p, a0 + slice);
+            T acc[VW][R];
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[v][c] = 0;
+            const V4 *gp = reinterpret_cast<const V4 *>(Gk + q);
+            const int ldv = ldp / VW;
+#pragma unroll 8
+            for (int a = a0; a < a1; ++a) {
+                const V4 gv = gp[(int64_t)a * ldv];
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const T gav = lane<T>(gv, v);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[v][c] += gav * xz[a * R + c];
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+#pragma unroll
+                for (int c = 0; c < R; ++c) part[((size_t)sl * ldp + q + v) * R + c] = acc[v][c];
+        }
+        __syncthreads();
+        for (int qq = tid; qq < rows_pass * VW; qq += nt) {
+            const int q = r0 * VW + qq;
+            if (q >= p) continue;
+            T u[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) u[c] = cport[((int64_t)g * npg + pg0 + q) * R + c];
+            for (int sl = 0; sl < ns; ++sl)
+#pragma unroll
+                for (int c = 0; c < R; ++c) u[c] += part[((size_t)sl * ldp + q) * R + c];
+            const int pb = D.pg_beg[pg0 + q], pc = D.pg_cnt[pg0 + q];
+            for (int j = 0; j < pc; ++j) {
+                const T *ai = o_prev + wo + (int64_t)twin[pb + j] * R;
+                T *o = o_next + wo + (int64_t)(pb + j) * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) o[c] = (T)2 * u[c] - ai[c];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -435,12 +589,12 @@ hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_
 template <typename T, int V>
 static void launch_sweep_v(const DevSym &S, const DevSub &D, dim3 grid, dim3 block, size_t shm, int32_t R,
                            int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
-                           const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st) {
+                           const T *invz, const T *o_prev, T *o_next, T *xloc, int flags, hipStream_t st) {
     switch (R) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, 1, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, 2, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, 4, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
-        default: hipLaunchKernelGGL((k_sweep<T, 8, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, 1, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, 2, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, 4, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
+        default: hipLaunchKernelGGL((k_sweep<T, 8, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
     }
 }
 
@@ -448,13 +602,60 @@ template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
                   int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals,
                   const T *bsplit, const int32_t *twin, const T *invz, const T *o_prev, T *o_next, T *xloc,
-                  int write_x, hipStream_t st) {
+                  int flags, hipStream_t st) {
     const size_t shm = sweep_shm<T>(max_nk, max_nu, variant, R);
     const dim3 grid(nsub, ngroups), block(threads);
     if (variant == 1)
-        launch_sweep_v<T, 1>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x, st);
+        launch_sweep_v<T, 1>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags, st);
     else
-        launch_sweep_v<T, 0>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, write_x, st);
+        launch_sweep_v<T, 0>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags, st);
+}
+
+void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
+                  const double *vals, const int64_t *goff, double *G, hipStream_t st) {
+    const int V = 2 * (size_t)max_nk + max_nu <= 96 * 1024 / (8 * 4) ? 1 : 0;
+    const size_t shm = sizeof(double) * 4 * (2 * (size_t)max_nk + (V ? (size_t)max_nu : 0));
+    const void *fn = V ? (const void *)k_green<1> : (const void *)k_green<0>;
+    if (shm > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    const dim3 grid(nsub, (max_p + 3) / 4);
+    if (V) hipLaunchKernelGGL(k_green<1>, grid, dim3(256), shm, st, S, D, vals, goff, G);
+    else hipLaunchKernelGGL(k_green<0>, grid, dim3(256), shm, st, S, D, vals, goff, G);
+}
+
+template <typename T>
+void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,
+                         const T *xloc, T *cport, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_ports<T>, dim3(nsub, ngroups), dim3(128), 0, st, D, nsplit, npg, R, xloc, cport);
+}
+
+template <typename T>
+size_t schur_shm(int32_t max_p, int32_t R, int32_t threads) {
+    // xz [ldp][R] + partial sums: at most (threads / row threads) slices of ldp rows <= ldp + threads * VW
+    const size_t ldp = (size_t)((max_p + 3) & ~3);
+    return sizeof(T) * (size_t)R * (ldp + (size_t)threads * Vec16<T>::W + ldp);
+}
+
+template <typename T>
+hipError_t prepare_schur(int32_t max_p, int32_t R) {
+    const size_t shm = schur_shm<T>(max_p, R, 256);
+    if (shm <= 64 * 1024) return hipSuccess;
+    const void *fn = R == 1 ? (const void *)k_schur<T, 1> : R == 2 ? (const void *)k_schur<T, 2>
+                   : R == 4 ? (const void *)k_schur<T, 4> : (const void *)k_schur<T, 8>;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T>
+void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t npg,
+                  int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
+                  const T *invz, const T *o_prev, T *o_next, hipStream_t st) {
+    const size_t shm = schur_shm<T>(max_p, R, 256);
+    const dim3 grid(nsub, ngroups), block(256);
+    switch (R) {
+        case 1: hipLaunchKernelGGL((k_schur<T, 1>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 2: hipLaunchKernelGGL((k_schur<T, 2>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+    }
 }
 
 template <typename T>
@@ -482,6 +683,18 @@ template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32
                                   int32_t, int64_t, int64_t, const float *, const float *, const int32_t *,
                                   const float *, const float *, float *, float *, int, hipStream_t);
 template hipError_t prepare_sweep<double>(int32_t, int32_t, int32_t, int32_t);
+template void launch_gather_ports<double>(const DevSub &, int32_t, int32_t, int64_t, int32_t, int32_t, const double *,
+                                          double *, hipStream_t);
+template void launch_gather_ports<float>(const DevSub &, int32_t, int32_t, int64_t, int32_t, int32_t, const float *,
+                                         float *, hipStream_t);
+template hipError_t prepare_schur<double>(int32_t, int32_t);
+template hipError_t prepare_schur<float>(int32_t, int32_t);
+template void launch_schur<double>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const double *,
+                                   const int64_t *, const double *, const int32_t *, const double *, const double *,
+                                   double *, hipStream_t);
+template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const float *,
+                                  const int64_t *, const float *, const int32_t *, const float *, const float *,
+                                  float *, hipStream_t);
 template hipError_t prepare_sweep<float>(int32_t, int32_t, int32_t, int32_t);
 template void launch_merge<double>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const double *, const double *,
                                    int64_t, double *, int64_t, hipStream_t);

@@ -82,10 +82,26 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
 template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
                   int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
-                  const T *invz, const T *o_prev, T *o_next, T *xloc, int write_x, hipStream_t st);
+                  const T *invz, const T *o_prev, T *o_next, T *xloc, int flags, hipStream_t st);
+constexpr int kSweepWriteX = 1, kSweepNoWaves = 2, kSweepZeroWaves = 4;  // sweep flags
 // Raise the dynamic-LDS limit of the sweep kernel when needed (call outside stream capture).
 template <typename T>
 hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R);
+
+// Port Green's functions G_k = R K_k^{-1} R^T (FP64, p_k x p_k row-major at goff[k]).
+void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
+                  const double *vals, const int64_t *goff, double *G, hipStream_t st);
+// cport[g][port vertex][R] = local solutions at the port vertices.
+template <typename T>
+void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,
+                         const T *xloc, T *cport, hipStream_t st);
+template <typename T>
+hipError_t prepare_schur(int32_t max_p, int32_t R);
+// Port-reduced sweep: o = 2 (c + G Z^{-1} a) - a at every port.
+template <typename T>
+void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t npg,
+                  int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
+                  const T *invz, const T *o_prev, T *o_next, hipStream_t st);
 
 // xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
 template <typename T>

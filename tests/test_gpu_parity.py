@@ -189,7 +189,7 @@ def test_autotune_then_solve(B):
     cfg = gen.make_config("c3", small=True)
     h, P, z = _setup(B, cfg, check_every=10, z_scale=8.0)
     ch = h.autotune(8)
-    assert ch["rhs_per_block"] in (1, 2, 4, 8) and ch["sweep_threads"] in (128, 256, 512) and ch["sweep_variant"] in (1, 2)
+    assert ch["rhs_per_block"] in (1, 2, 4, 8) and ch["sweep_threads"] in (128, 256, 512) and ch["sweep_mode"] in (1, 2)
     r = h.solve(cfg["b"], 1e-8)
     assert r["status"] == 0
     ro = O.Solver(P, z).run(cfg["b"], 100000, 10, 1e-8)
@@ -213,3 +213,28 @@ def test_sweep_variants_match_oracle(B, variant, name):
     xo = O.Solver(P, z).run(b, 25, 0, 0.0)["x"]
     for r in range(2):
         assert _rel(xg[r], xo[r]) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
+def test_port_reduced_sweeps_match_substitution(B, name, precision):
+    """Port-reduced sweeps (u = c + G Z^-1 a) give the oracle's iterates and the same converged
+    solution and sweep count as substitution sweeps."""
+    cfg = gen.make_config(name, small=True)
+    b = cfg["b"][:2] if cfg["b"].shape[0] > 1 else cfg["b"]
+    hs, P, z = _setup(B, cfg, z_scale=8.0, sweep_mode=2, precision=precision, check_every=10)
+    if precision == 0:
+        xg = hs.run_sweeps(b, 30)
+        xo = O.Solver(P, z).run(b, 30, 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"]
+        for r in range(b.shape[0]):
+            assert _rel(xg[r], xo[r]) <= 1e-10
+    hs.reset_waves()
+    rs = hs.solve(b, 1e-8)
+    assert hs.get_stats()["sweep_mode"] == 2
+    ht, _, _ = _setup(B, cfg, z_scale=8.0, sweep_mode=1, precision=precision, check_every=10)
+    rt = ht.solve(b, 1e-8)
+    assert ht.get_stats()["sweep_mode"] == 1
+    assert rs["status"] == 0 and rt["status"] == 0
+    assert np.array_equal(rs["iters"], rt["iters"]) or precision == 1
+    for r in range(b.shape[0]):
+        assert _rel(rs["x"][r], rt["x"][r]) <= (1e-10 if precision == 0 else 1e-6)
