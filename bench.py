@@ -83,7 +83,7 @@ def main():
                     help="comma list of {ir,fp64}_{diag,aNN}[_sub|_port]: precision, impedance rule "
                          "(diagonal or NN times it), sweep mode (substitution, port-reduced, default chosen "
                          "by the library); the first is the headline")
-    ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--check-every", type=int, default=0, help="0 = adaptive test placement")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration)")
     args = ap.parse_args()

@@ -68,7 +68,8 @@ typedef struct {
     int32_t device;        /* HIP device ordinal; -1 = host-only handle (partition and its analysis only) */
     void *stream;          /* hipStream_t to run on; NULL = the library creates its own */
     int32_t precision;     /* VTM_FP64, or VTM_FP32_IR: FP32 factors and sweeps, FP64 refinement */
-    int32_t check_every;   /* sweeps between convergence tests (>= 1; 0 = default 10) */
+    int32_t check_every;   /* sweeps between convergence tests; 0 = adaptive (placed where the observed
+                              contraction rate predicts the tolerance, 5..200 sweeps apart) */
     int64_t max_sweeps;    /* cap on sweeps per solve (0 = default 100000) */
     int32_t rhs_per_block; /* right-hand sides one workgroup carries (0 = tuned: 1, 2, 4 or 8) */
     int32_t leaf_size;     /* nested-dissection leaf size of the local orderings (0 = 8 in 2D, 16 in 3D) */

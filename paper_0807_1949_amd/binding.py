@@ -125,7 +125,7 @@ def _is_torch(x):
 class VTM:
     """One libvtm handle.  Method names follow the C entry points."""
 
-    def __init__(self, device: int = 0, precision: int = VTM_FP64, check_every: int = 10, max_sweeps: int = 100000,
+    def __init__(self, device: int = 0, precision: int = VTM_FP64, check_every: int = 0, max_sweeps: int = 100000,
                  rhs_per_block: int = 0, leaf_size: int = 0, stream: int | None = None, sweep_threads: int = 0,
                  graph_mode: int = 0, sweep_variant: int = 0, sweep_mode: int = 0):
         self._h = C.c_void_p()

@@ -495,12 +495,16 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
                                  invz_of<T>(h), h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(),
                                  last ? vtm::kSweepWriteX : 0, h->stream);
     };
-    if (h->opt.graph_mode == 0 && count >= 2) {
+    // Batches of kGraphBatch sweeps (even, so the wave buffer returns to its start) are captured once
+    // per starting buffer and replayed; the remaining sweeps, including the last, are launched directly.
+    constexpr int64_t kGraphBatch = 8;
+    const int64_t nrep = h->opt.graph_mode == 0 ? (count - 1) / kGraphBatch : 0;
+    if (nrep > 0) {
         auto &g = h->graphs[h->cur];
         const void *ptrs[7] = {schur ? (const void *)green_of<T>(h) : (const void *)vals_of<T>(h),
                                schur ? h->d_cport.p : h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p,
                                h->d_o[1].p, h->d_xloc.p};
-        bool same = g.exec && g.count == count && g.R == R && g.ng == ng && g.threads == nt &&
+        bool same = g.exec && g.count == kGraphBatch && g.R == R && g.ng == ng && g.threads == nt &&
                     g.variant == sweep_variant(h) + (schur ? 10 : 0);
         for (int i = 0; i < 7 && same; ++i) same = g.ptrs[i] == ptrs[i];
         if (!same) {
@@ -509,28 +513,26 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
             int c = h->cur;
-            for (int64_t i = 0; i < count; ++i) {
-                launch(c, i == count - 1);
+            for (int64_t i = 0; i < kGraphBatch; ++i) {
+                launch(c, false);
                 c ^= 1;
             }
             HIP_TRY(hipStreamEndCapture(h->stream, &graph));
             hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             HIP_TRY(e);
-            g.count = count;
+            g.count = kGraphBatch;
             g.R = R;
             g.ng = ng;
             g.threads = nt;
             g.variant = sweep_variant(h) + (schur ? 10 : 0);
             for (int i = 0; i < 7; ++i) g.ptrs[i] = ptrs[i];
         }
-        HIP_TRY(hipGraphLaunch(g.exec, h->stream));
-        h->cur ^= (int)(count & 1);
-    } else {
-        for (int64_t i = 0; i < count; ++i) {
-            launch(h->cur, i == count - 1);
-            h->cur ^= 1;
-        }
+        for (int64_t r = 0; r < nrep; ++r) HIP_TRY(hipGraphLaunch(g.exec, h->stream));
+    }
+    for (int64_t i = nrep * kGraphBatch; i < count; ++i) {
+        launch(h->cur, i == count - 1);
+        h->cur ^= 1;
     }
     h->waves_zero = false;
     return VTM_OK;
@@ -599,7 +601,10 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     const int64_t n = h->P.n;
     const int32_t nsys = h->P.nsys, R = h->wave_R;
     const vtm::DevMaps M = dev_maps(h);
-    const int64_t cadence = h->opt.check_every > 0 ? h->opt.check_every : 10;
+    // fixed cadence, or (check_every == 0) the next test is placed where the observed contraction
+    // rate predicts the tolerance, between 5 and 200 sweeps
+    const bool adaptive = h->opt.check_every <= 0;
+    int64_t cadence = adaptive ? 10 : h->opt.check_every;
     const int64_t maxsw = h->opt.max_sweeps > 0 ? h->opt.max_sweeps : 100000;
     const bool refine = sizeof(T) == 4;
     std::vector<double> rel;
@@ -625,7 +630,8 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     if ((rc = port_constants<T>(h))) return rc;
     const bool schur = use_schur(h);
     double rel_outer = 1.0, rel_prev = 1e300;
-    const double eta = 2e-6;
+    const double eta = 1e-5;
+    double rate_ref = -1.0;  // worst residual at the previous test of the current inner solve
     int inner_checks = 0;
     double last_worst = 1e300;
     while (!done && sweeps < maxsw) {
@@ -655,6 +661,17 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         if (first < 0) first = worst;
         if (worst > 1e3 * std::max(first, 1.0)) diverged = true;
         if (diverged) break;
+        if (adaptive) {
+            int64_t next = 2 * cnt;
+            if (rate_ref > 0.0 && worst < rate_ref) {
+                const double lr = std::log(worst / rate_ref) / (double)cnt;  // log contraction per sweep
+                const double target = refine ? std::max(tol, eta * rel_outer) : tol;
+                const double need = std::log(target / worst) / lr;
+                next = need > 0 ? (int64_t)std::ceil(0.9 * need) : 5;
+            }
+            cadence = std::max<int64_t>(5, std::min<int64_t>(200, next));
+            rate_ref = worst;
+        }
         if (all) {
             std::swap(xcur, xtr);
             done = true;
@@ -666,7 +683,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         }
         // FP32 inner solve: restart on the new residual once it has gained a factor eta or stalls
         const bool gained = worst <= eta * rel_outer;
-        const bool stalled = inner_checks >= 2 && worst > 0.9 * rel_prev;
+        const bool stalled = inner_checks >= 2 && worst > 0.995 * rel_prev;
         rel_prev = worst;
         if ((gained || stalled) && worst < rel_outer) {
             std::swap(xcur, xtr);
@@ -674,6 +691,8 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             rel_outer = worst;
             rel_prev = 1e300;
             inner_checks = 0;
+            rate_ref = -1.0;
+            if (adaptive) cadence = 10;
             ++outer;
             vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
             if ((rc = zero_waves<T>(h))) return rc;

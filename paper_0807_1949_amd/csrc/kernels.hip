@@ -403,6 +403,23 @@ __global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t np
     const int64_t wo = (int64_t)g * nports * R;
     T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a summed per port vertex [ldp][R]
     T *part = xz + (size_t)ldp * R;        // partial sums [ns][ldp][R]
+    const T *Gk = G + goff[k];
+    const int nrt = ldp / VW;                     // row threads
+    const int rows_pass = nrt < nt ? nrt : nt;    // row threads per pass
+    const int ns = nrt < nt ? nt / nrt : 1;       // column slices
+    const int slice = (p + ns - 1) / ns;
+    const int ldv = ldp / VW;
+    // first pass: start streaming this thread's G columns before the waves arrive
+    constexpr int PF = 16;
+    V4 pre[PF];
+    {
+        const int rt = tid % rows_pass, sl = tid / rows_pass;
+        const bool act = sl < ns && rt < nrt;
+        const int a0 = sl * slice, a1 = act ? min(p, a0 + slice) : a0;
+        const V4 *gp = reinterpret_cast<const V4 *>(Gk + rt * VW);
+#pragma unroll
+        for (int f = 0; f < PF; ++f) pre[f] = a0 + f < a1 ? gp[(int64_t)(a0 + f) * ldv] : V4{};
+    }
     for (int q = tid; q < ldp; q += nt) {
         T acc[R];
 #pragma unroll
@@ -420,11 +437,6 @@ __global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t np
         for (int c = 0; c < R; ++c) xz[q * R + c] = acc[c];
     }
     __syncthreads();
-    const T *Gk = G + goff[k];
-    const int nrt = ldp / VW;                     // row threads
-    const int rows_pass = nrt < nt ? nrt : nt;    // row threads per pass
-    const int ns = nrt < nt ? nt / nrt : 1;       // column slices
-    const int slice = (p + ns - 1) / ns;
     for (int r0 = 0; r0 < nrt; r0 += rows_pass) {
         const int rt = r0 + tid % rows_pass, sl = tid / rows_pass;
         if (sl < ns && rt < nrt) {
@@ -436,9 +448,23 @@ __global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t np
 #pragma unroll
                 for (int c = 0; c < R; ++c) acc[v][c] = 0;
             const V4 *gp = reinterpret_cast<const V4 *>(Gk + q);
-            const int ldv = ldp / VW;
+            int a = a0;
+            if (r0 == 0) {
+#pragma unroll
+                for (int f = 0; f < PF; ++f) {
+                    if (a0 + f < a1) {
+#pragma unroll
+                        for (int v = 0; v < VW; ++v) {
+                            const T gav = lane<T>(pre[f], v);
+#pragma unroll
+                            for (int c = 0; c < R; ++c) acc[v][c] += gav * xz[(a0 + f) * R + c];
+                        }
+                    }
+                }
+                a = min(a1, a0 + PF);
+            }
 #pragma unroll 8
-            for (int a = a0; a < a1; ++a) {
+            for (; a < a1; ++a) {
                 const V4 gv = gp[(int64_t)a * ldv];
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {
@@ -520,17 +546,24 @@ __global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, c
     }
 }
 
-__global__ void k_relres(const double *__restrict__ part, int32_t nchunks, const int32_t *__restrict__ sys_chunk_ptr,
-                         int32_t nsys, int32_t nrhs, double *__restrict__ relres) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nsys * nrhs) return;
-    const int c = t / nsys, s = t - c * nsys;
+__global__ __launch_bounds__(256) void k_relres(const double *__restrict__ part, int32_t nchunks,
+                                                 const int32_t *__restrict__ sys_chunk_ptr, int32_t nsys, int32_t nrhs,
+                                                 double *__restrict__ relres) {
+    __shared__ double red[2][256];
+    const int c = blockIdx.x / nsys, s = blockIdx.x - c * nsys, tid = threadIdx.x;
     double rr = 0.0, bb = 0.0;
-    for (int q = sys_chunk_ptr[s]; q < sys_chunk_ptr[s + 1]; ++q) {
+    for (int q = sys_chunk_ptr[s] + tid; q < sys_chunk_ptr[s + 1]; q += 256) {
         rr += part[((int64_t)c * nchunks + q) * 2 + 0];
         bb += part[((int64_t)c * nchunks + q) * 2 + 1];
     }
-    relres[c * nsys + s] = bb > 0.0 ? sqrt(rr) / sqrt(bb) : sqrt(rr);
+    red[0][tid] = rr;
+    red[1][tid] = bb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+        __syncthreads();
+    }
+    if (tid == 0) relres[c * nsys + s] = red[1][0] > 0.0 ? sqrt(red[0][0]) / sqrt(red[1][0]) : sqrt(red[0][0]);
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -670,8 +703,7 @@ void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, in
                      const int32_t *sys_chunk_ptr, int32_t nsys, double *part, double *relres, hipStream_t st) {
     hipLaunchKernelGGL(k_residual, dim3(nchunks, nrhs), dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr,
                        chunk_row, nchunks, part);
-    hipLaunchKernelGGL(k_relres, dim3(blocks_for((int64_t)nsys * nrhs, 64)), dim3(64), 0, st, part, nchunks,
-                       sys_chunk_ptr, nsys, nrhs, relres);
+    hipLaunchKernelGGL(k_relres, dim3(nsys * nrhs), dim3(256), 0, st, part, nchunks, sys_chunk_ptr, nsys, nrhs, relres);
 }
 
 template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);

@@ -170,12 +170,13 @@ def test_c2_full_iterates(B):
 
 
 def test_graph_replay_matches_eager(B):
-    """Sweep batches replayed from captured HIP graphs (odd batch length, both wave parities, several
-    replays with host synchronisation between them) give bitwise the eager result."""
+    """Sweep batches replayed from captured HIP graphs (19 sweeps per test: two 8-sweep graph replays
+    plus 3 direct launches, so both starting wave buffers are captured; several replays with host
+    synchronisation between them) give bitwise the eager result."""
     cfg = gen.make_config("c2", small=True)
     out = []
     for gm in (0, 1):
-        h, P, z = _setup(B, cfg, check_every=7, z_scale=16.0, graph_mode=gm)
+        h, P, z = _setup(B, cfg, check_every=19, z_scale=16.0, graph_mode=gm)
         r1 = h.solve(cfg["b"], 1e-8)
         r2 = h.solve(cfg["b"], 1e-8)
         out.append((r1["x"], r2["x"], r1["iters"].copy()))
@@ -238,3 +239,18 @@ def test_port_reduced_sweeps_match_substitution(B, name, precision):
     assert np.array_equal(rs["iters"], rt["iters"]) or precision == 1
     for r in range(b.shape[0]):
         assert _rel(rs["x"][r], rt["x"][r]) <= (1e-10 if precision == 0 else 1e-6)
+
+
+def test_adaptive_check_cadence(B):
+    """check_every = 0 places the tests by the observed contraction rate: same solution quality, and the
+    reported sweep count is one where the tolerance holds."""
+    cfg = gen.make_config("c2", small=True)
+    h, P, z = _setup(B, cfg, check_every=0, z_scale=32.0)
+    r = h.solve(cfg["b"], 1e-8)
+    assert r["status"] == 0 and r["relres"][0, 0] <= 1e-8
+    st = h.get_stats()
+    ro = O.Solver(P, z).run(cfg["b"], int(st["sweeps"]), 0, 0.0)
+    assert ro["relres"][0, 0] <= 1e-8
+    assert _rel(r["x"][0], ro["x"][0]) <= 1e-10
+    ro1 = O.Solver(P, z).run(cfg["b"], 100000, 1, 1e-8)
+    assert st["sweeps"] <= 1.25 * int(ro1["iters"][0, 0]) + 10
