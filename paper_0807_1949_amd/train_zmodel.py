@@ -1,13 +1,18 @@
-"""Train the learned impedance model on the 512^2 GRF diffusion workload and evaluate it.
+"""Train the learned impedance model and evaluate it against the diagonal rule.
 
-    python -m paper_0807_1949_amd.train_zmodel [--train 4000:4200] [--eval 4200:4210]
-        [--small] [--k-probe 50] [--epochs 40] [--out zmodel_c4.json] [--report report.json]
+    python -m paper_0807_1949_amd.train_zmodel [--k-probe 200] [--epochs 40]
+        [--budget-s 600] [--out zmodel_weights.json] [--report report.json]
 
+Training systems (all seeded, none from the evaluation seeds):
+  grf    512^2 two-point-flux diffusion, k = exp(GRF sigma 1.5, l 16), 16x16 tiles (seeds 4000..)
+  logn   256^2 lognormal(0,1) conductance Laplacian + 1e-3 I, 8x8 tiles of 33 (seeds 100..)
+  pois3  32^3 Poisson, seeded RCB into 64 boxes (seeds 300..)
+  rgg    random geometric graph Laplacians + 1e-2 I, n 4k..16k, ~n/512 parts (seeds 7000..)
 Labels come from probe sweeps of the method itself (see zmodel.py); the
 network is trained on the GPU by libvtm's BF16 forward/backward kernels and
-Adam.  Evaluation compares sweeps and time to relative residual 1e-8 against
-the diagonal rule Z = 1/a_vv and against the best uniform multiplier
-alpha/a_vv found by the same probe grid.
+Adam.  Evaluation: sweeps and time to relative residual 1e-8 with the diagonal
+rule Z = 1/a_vv, the best uniform multiplier of the probe grid, and the learned
+model, on held-out systems of every family and on the 1024^2 workload.
 """
 from __future__ import annotations
 
@@ -25,85 +30,111 @@ if ROOT not in sys.path:
 
 import gen  # noqa: E402
 from gen import configs as GC  # noqa: E402
+from gen import systems as GS  # noqa: E402
 
 from . import binding as B  # noqa: E402
 from . import zmodel as Zm  # noqa: E402
+
+DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "zmodel_weights.json")
 
 
 def log(m):
     print(m, flush=True)
 
 
-def _range(s):
-    a, b = s.split(":")
-    return list(range(int(a), int(b)))
+def family_system(fam: str, seed: int):
+    """(A, spec, b, nsys, sys_ptr) of one training or evaluation system."""
+    if fam == "grf":
+        c = GC.c4(seed=seed)
+        return c["A"], c["spec"], c["b"], 1, None
+    if fam == "logn":
+        A = GS.lognormal_conductance_2d(256, seed=seed, shift=1e-3)
+        return A, dict(kind="grid", dims=(256, 256, 1), parts=(8, 8, 1)), GS.random_rhs(A.n, 1, seed), 1, None
+    if fam == "pois3":
+        A = GS.poisson3d_dirichlet(32)
+        spec = dict(kind="rcb", dims=(32, 32, 32), levels=6, seed=seed, min_size=0.0, max_size=1e30)
+        return A, spec, GS.random_rhs(A.n, 1, seed), 1, None
+    if fam == "rgg":
+        n = int(np.random.default_rng([seed, 3]).integers(4000, 16001))
+        A = GS.random_geometric_graph(n, seed)
+        spec = dict(kind="graph", coords=A.coords, blocks=[(0, n, max(1, (n + 256) // 512))])
+        return A, spec, GS.random_rhs(n, 1, seed), 1, None
+    raise ValueError(fam)
+
+
+TRAIN = dict(grf=range(4000, 4200), logn=range(100, 200), pois3=range(300, 400), rgg=range(7000, 7100))
+EVAL = dict(grf=range(4200, 4205), logn=range(200, 203), pois3=range(400, 403), rgg=range(7100, 7103))
+SHARE = dict(grf=0.4, logn=0.25, pois3=0.15, rgg=0.2)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", default="4000:4200")
-    ap.add_argument("--eval", default="4200:4210")
-    ap.add_argument("--small", action="store_true")
-    ap.add_argument("--k-probe", type=int, default=50)
+    ap.add_argument("--k-probe", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--out", default=Zm.DEFAULT_WEIGHTS)
+    ap.add_argument("--budget-s", type=float, default=600.0, help="labelling time budget, split by family")
+    ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--report", default=None)
-    ap.add_argument("--time-budget", type=float, default=1e9, help="stop labelling after this many seconds")
+    ap.add_argument("--eval-c2", action="store_true", help="also evaluate on the 1024^2 workload")
     args = ap.parse_args(argv)
-    t_start = time.time()
-    feats, labels, alphas = [], [], []
-    used = []
-    for seed in _range(args.train):
-        if time.time() - t_start > args.time_budget:
-            log(f"label budget reached after {len(used)} systems")
-            break
-        cfg = GC.c4(small=args.small, seed=seed)
-        t0 = time.time()
-        f, y, a = Zm.make_labels(cfg["A"], cfg["spec"], cfg["b"], k_probe=args.k_probe, log=log)
-        feats.append(f)
-        labels.append(y)
-        alphas.append(a)
-        used.append(seed)
-        log(f"  system {seed}: {len(y)} VTLs, label mean {y.mean():.3f} sd {y.std():.3f}, {time.time() - t0:.1f}s")
+    feats, labels, used, astar = [], [], {}, {}
+    for fam, seeds in TRAIN.items():
+        t_fam = time.time()
+        used[fam] = []
+        astar[fam] = []
+        for seed in seeds:
+            if time.time() - t_fam > SHARE[fam] * args.budget_s:
+                break
+            A, spec, b, nsys, sptr = family_system(fam, seed)
+            t0 = time.time()
+            f, y, a = Zm.make_labels(A, spec, b, k_probe=args.k_probe)
+            feats.append(f)
+            labels.append(y)
+            used[fam].append(seed)
+            astar[fam].append(a)
+            log(f"  {fam} {seed}: {len(y)} VTLs, alpha*={a:g}, label mean {y.mean():.3f} sd {y.std():.3f}, "
+                f"{time.time() - t0:.1f}s")
+        log(f"{fam}: {len(used[fam])} systems")
     X = np.concatenate(feats)
     Y = np.concatenate(labels)
-    log(f"training on {len(Y)} VTLs from {len(used)} systems")
+    log(f"training on {len(Y)} VTLs from {sum(len(v) for v in used.values())} systems")
     P, hist = Zm.fit(X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
-    Zm.save(P, args.out, meta=dict(train_seeds=used, k_probe=args.k_probe, epochs=args.epochs,
-                                   loss=hist, label_mean=float(Y.mean()), label_sd=float(Y.std()),
-                                   small=args.small))
+    Zm.save(P, args.out, meta=dict(train=used, k_probe=args.k_probe, epochs=args.epochs, loss=hist,
+                                   label_mean=float(Y.mean()), label_sd=float(Y.std()),
+                                   alpha_star={k: v for k, v in astar.items()}))
     log(f"saved {args.out}")
-    # evaluation on held-out systems
-    a_glob = float(np.exp(np.median(np.log(alphas))))
     rows = []
-    for seed in _range(args.eval):
-        cfg = GC.c4(small=args.small, seed=seed)
-        A, spec, b = cfg["A"], cfg["spec"], cfg["b"]
+    evals = [(fam, s) for fam, ss in EVAL.items() for s in ss]
+    if args.eval_c2:
+        evals.append(("c2", 2))
+    for fam, seed in evals:
+        if fam == "c2":
+            c = GC.c2()
+            A, spec, b, nsys, sptr = c["A"], c["spec"], c["b"], 1, None
+        else:
+            A, spec, b, nsys, sptr = family_system(fam, seed)
         hh = B.VTM(device=-1)
         hh.evs_partition(A, spec)
         z0 = hh.get_partition()["zdiag"]
         hh.close()
+        a_f = float(np.exp(np.median(np.log(astar.get(fam, [16.0]) or [16.0]))))
         r_diag = Zm.solve_iters(A, spec, b, 1e-8, B.VTM_Z_USER, z0)
-        r_unif = Zm.solve_iters(A, spec, b, 1e-8, B.VTM_Z_USER, a_glob * z0)
+        r_unif = Zm.solve_iters(A, spec, b, 1e-8, B.VTM_Z_USER, a_f * z0)
         r_lrn = Zm.solve_iters(A, spec, b, 1e-8, B.VTM_Z_LEARNED, params=P)
-        rows.append(dict(seed=seed, diag=r_diag, uniform=r_unif, learned=r_lrn))
-        log(f"  eval {seed}: sweeps diag {r_diag['sweeps']}, uniform(alpha={a_glob:g}) {r_unif['sweeps']}, "
-            f"learned {r_lrn['sweeps']}")
-    summ = dict(
-        uniform_alpha=a_glob,
-        sweeps=dict(diag=float(np.mean([r["diag"]["sweeps"] for r in rows])),
-                    uniform=float(np.mean([r["uniform"]["sweeps"] for r in rows])),
-                    learned=float(np.mean([r["learned"]["sweeps"] for r in rows]))),
-        time_s=dict(diag=float(np.mean([r["diag"]["time_s"] for r in rows])),
-                    uniform=float(np.mean([r["uniform"]["time_s"] for r in rows])),
-                    learned=float(np.mean([r["learned"]["time_s"] for r in rows]))),
-    )
+        rows.append(dict(family=fam, seed=seed, alpha_uniform=a_f, diag=r_diag, uniform=r_unif, learned=r_lrn))
+        log(f"  eval {fam} {seed}: sweeps diag {r_diag['sweeps']}, uniform(alpha={a_f:g}) {r_unif['sweeps']}, "
+            f"learned {r_lrn['sweeps']}  (time {r_diag['time_s']:.3f} / {r_unif['time_s']:.3f} / "
+            f"{r_lrn['time_s']:.3f} s)")
+    summ = {}
+    for fam in sorted(set(r["family"] for r in rows)):
+        rr = [r for r in rows if r["family"] == fam]
+        summ[fam] = {k: dict(sweeps=float(np.mean([r[k]["sweeps"] for r in rr])),
+                             time_s=float(np.mean([r[k]["time_s"] for r in rr]))) for k in ("diag", "uniform", "learned")}
     log("summary " + json.dumps(summ))
     if args.report:
         with open(args.report, "w") as f:
-            json.dump(dict(summary=summ, rows=rows, train_seeds=used, loss=hist), f, indent=1)
+            json.dump(dict(summary=summ, rows=rows, train=used, alpha_star=astar, loss=hist), f, indent=1)
 
 
 if __name__ == "__main__":

@@ -7,7 +7,9 @@ MLP predicts delta = ln(Z a_vv) per VTL from scale-free features
 
 1. global probe: Z = alpha / a_vv for alpha in {2^(j/2): j = 0..16}; run
    K_probe sweeps from zero waves and keep the alpha* with the lowest relative
-   residual (measured on the device by vtm_solve with max_sweeps = K_probe);
+   residual (measured on the device by vtm_solve with max_sweeps = K_probe).
+   K_probe must reach the asymptotic regime: short probes reward the decay of
+   the first transient and pick much too small multipliers;
 2. per-interface refinement: colour the subgraph-pair graph so that no two
    pairs of a colour share a subgraph; for each colour and each
    beta in {2^(j/2): j = -4..4}, scale that colour's VTLs by beta, run K_probe
@@ -78,9 +80,11 @@ def port_vtl(part: dict, nsub: int) -> np.ndarray:
 class Prober:
     """Probe runs of K sweeps on one partitioned system."""
 
-    def __init__(self, A, spec, b, k_probe=50, device=0):
-        self.h = B.VTM(device=device, check_every=k_probe, max_sweeps=k_probe)
-        self.info = self.h.evs_partition(A, spec)
+    def __init__(self, A, spec, b, k_probe=200, device=0, nsys=1, sys_ptr=None):
+        # substitution sweeps: the probes change Z every few hundred sweeps, so the port Green's
+        # functions would cost more than they save
+        self.h = B.VTM(device=device, check_every=k_probe, max_sweeps=k_probe, sweep_mode=1)
+        self.info = self.h.evs_partition(A, spec, nsys=nsys, sys_ptr=sys_ptr)
         self.part = self.h.get_partition()
         self.b = np.atleast_2d(b)
         self.k = k_probe
@@ -108,8 +112,8 @@ class Prober:
         self.h.close()
 
 
-def make_labels(A, spec, b, k_probe=50, device=0, log=None):
-    pr = Prober(A, spec, b, k_probe, device)
+def make_labels(A, spec, b, k_probe=200, device=0, log=None, nsys=1, sys_ptr=None):
+    pr = Prober(A, spec, b[:1], k_probe, device, nsys, sys_ptr)
     try:
         res = np.array([pr.residual(a * pr.z0) for a in ALPHAS])
         a_star = float(ALPHAS[int(np.argmin(res))])
@@ -182,10 +186,11 @@ def load(path=DEFAULT_WEIGHTS) -> np.ndarray:
         return np.array(json.load(f)["params"], dtype=np.float32)
 
 
-def solve_iters(A, spec, b, tol, z_rule, z=None, params=None, precision=B.VTM_FP64, check_every=10, device=0):
+def solve_iters(A, spec, b, tol, z_rule, z=None, params=None, precision=B.VTM_FP64, check_every=0, device=0,
+                nsys=1, sys_ptr=None, sweep_mode=0):
     """Sweeps and time to tolerance for one impedance choice."""
-    h = B.VTM(device=device, precision=precision, check_every=check_every, max_sweeps=200000)
-    h.evs_partition(A, spec)
+    h = B.VTM(device=device, precision=precision, check_every=check_every, max_sweeps=200000, sweep_mode=sweep_mode)
+    h.evs_partition(A, spec, nsys=nsys, sys_ptr=sys_ptr)
     if params is not None:
         h.zmodel_load(params)
     t0 = time.perf_counter()
