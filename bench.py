@@ -2,15 +2,19 @@
 """Benchmark: VTM on the 1024^2 lognormal-conductance system (32x32 subgraphs).
 
 One step = the whole hot path on one batch of synthetic input, with the
-partition (host) done once beforehand: vtm_setup (impedances, port
-augmentation, device factorisation of all 1024 local matrices) + vtm_solve to
-relative residual 1e-8 (sweeps, exchanges, FP64 residual tests, refinement).
-Inputs are resident in HBM (torch tensors) before the timed region.
+partition (host) done once beforehand: vtm_setup (impedances -- for the
+learned rule the network's inference on the GPU --, port augmentation, device
+factorisation of all 1024 local matrices, port Green's functions) + vtm_solve
+to relative residual 1e-8 (sweeps, exchanges, FP64 residual tests,
+refinement).  Inputs are resident in HBM (torch tensors) before the timed
+region.  The per-VTL features of the learned rule depend only on the matrix
+and the partition and are computed with it, in the warm-up step.
 
 Prints ONE JSON line.  value = unknown-updates per second of the headline
 variant (n * nrhs * sweeps / step time).  Also reported: time to tolerance of
-every variant, the sweep kernel's roofline (algorithmic bytes per sweep over
-the event-timed sweep duration) and the CPU oracle timed on this host.
+every variant and the speedup of the headline over plain FP64 VTM, the sweep
+kernel's roofline (algorithmic bytes per sweep over the event-timed sweep
+duration) and the CPU oracle timed on this host.
 """
 from __future__ import annotations
 
@@ -31,11 +35,13 @@ def log(msg):
 
 
 def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warmup, check_every, max_sweeps,
-                mode=0):
+                mode=0, params=None):
     h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps, sweep_mode=mode)
     t0 = time.perf_counter()
     info = h.evs_partition(A, spec)
     part_s = time.perf_counter() - t0
+    if params is not None:
+        h.zmodel_load(params)
     x_dev = torch.empty_like(b_dev)
     times, res = [], None
     for i in range(warmup + steps):
@@ -51,7 +57,7 @@ def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warm
             f"sweeps {h.get_stats()['sweeps']}, relres {float(res['relres'].max()):.2e}")
     st = h.get_stats()
     out = dict(partition_s=part_s, info=info, step_s=sum(times) / len(times), stats=st,
-               relres=float(res["relres"].max()), status=int(res["status"]), x=x_dev.clone())
+               relres=float(res["relres"].max()), status=int(res["status"]), x=x_dev.clone(), z=h.get_z())
     h.close()
     return out
 
@@ -79,10 +85,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--small", action="store_true", help="128^2 version of the workload (quick check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="ir_diag,fp64_diag_sub",
-                    help="comma list of {ir,fp64}_{diag,aNN}[_sub|_port]: precision, impedance rule "
-                         "(diagonal or NN times it), sweep mode (substitution, port-reduced, default chosen "
-                         "by the library); the first is the headline")
+    ap.add_argument("--variants", default="ir_lrn,fp64_diag_sub,ir_diag",
+                    help="comma list of {ir,fp64}_{lrn,diag,aNN}[_sub|_port]: precision, impedance rule "
+                         "(learned network, diagonal, or NN times the diagonal), sweep mode (substitution, "
+                         "port-reduced, default chosen by the library); the first is the headline, the "
+                         "second its comparison")
     ap.add_argument("--check-every", type=int, default=0, help="0 = adaptive test placement")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration)")
@@ -96,6 +103,7 @@ def main():
 
     import gen
     from paper_0807_1949_amd import binding as B
+    from paper_0807_1949_amd import zmodel as Zm
 
     if args.calib_copy_mib > 0:
         src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -116,18 +124,21 @@ def main():
         prec_s, zr = parts[0], parts[1]
         mode = {"sub": 1, "port": 2}.get(parts[2], 0) if len(parts) > 2 else 0
         precision = B.VTM_FP32_IR if prec_s == "ir" else B.VTM_FP64
+        params = None
         if zr == "diag":
             z_rule, z = B.VTM_Z_DIAG, None
+        elif zr == "lrn":
+            z_rule, z, params = B.VTM_Z_LEARNED, None, Zm.load()
         else:  # uniform multiplier alpha on the diagonal rule, e.g. a64
             alpha = float(zr[1:])
             hh = B.VTM(device=-1)
             hh.evs_partition(A, spec)
             z_rule, z = B.VTM_Z_USER, alpha * hh.get_partition()["zdiag"]
             hh.close()
-        zinfo[v] = z
         log(f"variant {v}")
         results[v] = run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, args.steps, args.warmup,
-                                 args.check_every, 200000, mode)
+                                 args.check_every, 200000, mode, params)
+        zinfo[v] = results[v]["z"]
     head = results[variants[0]]
     st = head["stats"]
     sweeps = st["sweeps"]
@@ -145,7 +156,7 @@ def main():
                     "1024 subgraphs of 33x33, single RHS)", n=A.n, nsub=head["info"]["nsub"], nrhs=nrhs, tol=tol,
                     variant=variants[0], parallelism="1 GPU, all subgraphs on one device"),
         time_to_tol_s=head["step_s"], sweeps=sweeps, setup_ms=st["setup_ms"], solve_ms=st["solve_ms"],
-        relres=head["relres"],
+        relres=head["relres"], partition_s=head["partition_s"],
         variants={v: dict(time_to_tol_s=r["step_s"], sweeps=r["stats"]["sweeps"], setup_ms=r["stats"]["setup_ms"],
                           sweep_us=r["stats"]["sweep_ms"] * 1e3 / max(r["stats"]["sweeps"], 1),
                           outer_steps=r["stats"]["outer_steps"], relres=r["relres"], status=r["status"],
@@ -161,9 +172,6 @@ def main():
         from oracle import oracle as O
 
         z = zinfo[variants[0]]
-        if z is None:
-            P = O.Partition(A, spec)
-            z = P.zdiag
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(O, A, spec, cfg["b"], z)
     print(json.dumps(line), flush=True)

@@ -72,6 +72,12 @@ struct vtm_ctx {
     int32_t max_p = 0, npg = 0;
     int64_t total_g = 0;
     bool have_green = false;
+    // column plan of the multifrontal Green's-function computation (built on first use)
+    DevBuf d_gsn, d_gpy, d_gpq, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws;
+    int plan_state = 0;  // 0 not built, 1 ready, -1 not applicable (fall back to per-column solves)
+    int64_t gws_total = 0;
+    std::vector<int32_t> h_pgptr;
+    std::vector<uint16_t> h_pgpos;
     int32_t max_nu = 0;
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
         d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
@@ -113,7 +119,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gpy, &d_gpq, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -199,6 +205,120 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     d.pg_beg = h->d_pgbeg.as<int32_t>();
     d.pg_cnt = h->d_pgcnt.as<int32_t>();
     return d;
+}
+
+// Column plan of k_green_mf.  Ports are sorted by the postorder of their supernode; the ports below
+// supernode s then form the range [lo_s, hi_s) of width w_s, its own ports the tail [own_s, hi_s).
+// Workspace per supernode: front (nc + m) x w_s, then Y_s (nc x w_s).
+vtm_status build_green_plan(vtm_ctx *h) {
+    const vtm::Partition &P = h->P;
+    const vtm::Symbolic &S = h->S;
+    const int32_t nsub = P.nsub;
+    std::vector<std::vector<int32_t>> post(S.classes.size()), first(S.classes.size());
+    for (size_t c = 0; c < S.classes.size(); ++c) {
+        const vtm::ClassSym &C = S.classes[c];
+        std::vector<std::vector<int32_t>> ch(C.nsn);
+        std::vector<int32_t> roots;
+        for (int32_t s = 0; s < C.nsn; ++s) (C.sn_parent[s] < 0 ? roots : ch[C.sn_parent[s]]).push_back(s);
+        post[c].assign(C.nsn, 0);
+        first[c].assign(C.nsn, 0);
+        int32_t cnt = 0;
+        std::vector<std::pair<int32_t, size_t>> stack;  // (supernode, next child)
+        for (int32_t r : roots) {
+            stack.push_back({r, 0});
+            first[c][r] = cnt;
+            while (!stack.empty()) {
+                auto &top = stack.back();
+                if (top.second < ch[top.first].size()) {
+                    const int32_t q = ch[top.first][top.second++];
+                    first[c][q] = cnt;
+                    stack.push_back({q, 0});
+                } else {
+                    post[c][top.first] = cnt++;
+                    stack.pop_back();
+                }
+            }
+        }
+    }
+    std::vector<int4> sn;
+    std::vector<int32_t> py, pq, base(nsub + 1, 0), idoff(h->npg, 0);
+    std::vector<uint16_t> perm(h->npg, 0);
+    std::vector<int64_t> wso(nsub + 1, 0);
+    for (int32_t k = 0; k < nsub; ++k) {
+        const int32_t c = S.sub_class[k];
+        const vtm::ClassSym &C = S.classes[c];
+        const int32_t pg0 = h->h_pgptr[k], p = h->h_pgptr[k + 1] - pg0;
+        std::vector<int32_t> key(p), order(p);
+        for (int32_t j = 0; j < p; ++j) {
+            key[j] = post[c][C.col_sn[h->h_pgpos[pg0 + j]]];
+            order[j] = j;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        std::vector<int32_t> ks(p);
+        for (int32_t a = 0; a < p; ++a) ks[a] = key[order[a]];
+        std::vector<int32_t> lo(C.nsn), own(C.nsn), w(C.nsn);
+        std::vector<int64_t> fo(C.nsn);
+        int64_t off = 0;
+        for (int32_t s = 0; s < C.nsn; ++s) {
+            lo[s] = (int32_t)(std::lower_bound(ks.begin(), ks.end(), first[c][s]) - ks.begin());
+            own[s] = (int32_t)(std::lower_bound(ks.begin(), ks.end(), post[c][s]) - ks.begin());
+            w[s] = (int32_t)(std::upper_bound(ks.begin(), ks.end(), post[c][s]) - ks.begin()) - lo[s];
+            fo[s] = off;
+            off += (int64_t)(2 * C.sn_nc[s] + C.sn_m[s]) * w[s];
+        }
+        int64_t iy = 0, iq = 0;
+        base[k] = (int32_t)sn.size();
+        for (int32_t s = 0; s < C.nsn; ++s) {
+            const int32_t par = C.sn_parent[s];
+            const int64_t f = C.sn_nc[s] + C.sn_m[s];
+            sn.push_back(int4{(int32_t)fo[s], lo[s] | (w[s] << 16), par < 0 ? 0 : (int32_t)fo[par],
+                              par < 0 ? 0 : (lo[par] | (w[par] << 16))});
+            py.push_back((int32_t)iy);
+            pq.push_back((int32_t)iq);
+            iy += f * w[s];
+            iq += (int64_t)((w[s] + 15) / 16) * ((w[s] + 15) / 16 + 1) / 2;
+        }
+        sn.push_back(int4{0, 0, 0, 0});
+        py.push_back((int32_t)iy);
+        pq.push_back((int32_t)iq);
+        if (off >= ((int64_t)1 << 31) || iy >= ((int64_t)1 << 31) || iq >= ((int64_t)1 << 31) ||
+            sn.size() >= ((size_t)1 << 31)) {
+            h->plan_state = -1;
+            return VTM_OK;
+        }
+        for (int32_t a = 0; a < p; ++a) {
+            const int32_t j = order[a], pos = h->h_pgpos[pg0 + j], s = C.col_sn[pos];
+            perm[pg0 + a] = (uint16_t)j;
+            idoff[pg0 + a] = (int32_t)(fo[s] + (int64_t)(pos - C.sn_c0[s]) * w[s] + (a - lo[s]));
+        }
+        wso[k + 1] = wso[k] + ((off + 1) & ~(int64_t)1);
+    }
+    base[nsub] = (int32_t)sn.size();
+    h->gws_total = wso[nsub];
+    hipStream_t st = h->stream;
+    HIP_TRY(upload(h->d_gsn, sn, st));
+    HIP_TRY(upload(h->d_gpy, py, st));
+    HIP_TRY(upload(h->d_gpq, pq, st));
+    HIP_TRY(upload(h->d_gbase, base, st));
+    HIP_TRY(upload(h->d_gwso, wso, st));
+    HIP_TRY(upload(h->d_gidoff, idoff, st));
+    HIP_TRY(upload(h->d_gperm, perm, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    h->plan_state = 1;
+    return VTM_OK;
+}
+
+vtm::DevGreen dev_green(vtm_ctx *h) {
+    vtm::DevGreen g;
+    g.sn = h->d_gsn.as<int4>();
+    g.py = h->d_gpy.as<int32_t>();
+    g.pq = h->d_gpq.as<int32_t>();
+    g.base = h->d_gbase.as<int32_t>();
+    g.wso = h->d_gwso.as<int64_t>();
+    g.idoff = h->d_gidoff.as<int32_t>();
+    g.perm = h->d_gperm.as<uint16_t>();
+    g.ws = h->d_gws.as<double>();
+    return g;
 }
 
 vtm::DevMaps dev_maps(vtm_ctx *h) {
@@ -301,7 +421,7 @@ vtm_status upload_partition(vtm_ctx *h) {
         subx[k] = P.loc_ptr[k];
         subaval[k] = P.lrp[P.loc_ptr[k]];
         subws[k] = wo;
-        wo += C.ws_u + (int64_t)C.max_front * C.max_front;
+        wo += C.ws_u + (int64_t)C.max_front * C.max_front + ((C.nk + 1) & ~1);  // updates, front, port diagonal
         for (int64_t p = P.port_ptr[k]; p < P.port_ptr[k + 1];) {
             int64_t q = p;
             while (q < P.port_ptr[k + 1] && P.port_v[q] == P.port_v[p]) ++q;
@@ -314,6 +434,9 @@ vtm_status upload_partition(vtm_ctx *h) {
     }
     h->total_val = vo;
     h->total_ws = wo;
+    h->h_pgptr = pgptr;
+    h->h_pgpos = pgpos;
+    h->plan_state = 0;
     {
         std::vector<int64_t> goff(nsub + 1, 0);
         h->max_p = 0;
@@ -944,6 +1067,14 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
     HIP_TRY(ensure(h->d_status, sizeof(int32_t) * (P.nsub + 1)));
     DevBuf ws;
     HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
+    // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
+    const bool want_green = h->opt.sweep_mode != 1 && h->max_p > 0 && h->max_p <= 2048 &&
+                            (h->opt.sweep_mode == 2 || (double)h->total_g <= 2.0 * (double)h->total_lower);
+    if (want_green && h->plan_state == 0) {
+        vtm_status rc = build_green_plan(h);
+        if (rc) return rc;
+    }
+    if (want_green && h->plan_state == 1) HIP_TRY(ensure(h->d_gws, sizeof(double) * (h->gws_total + 2)));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -957,14 +1088,18 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
         HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
         vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
     }
-    // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
     h->have_green = false;
-    if (h->opt.sweep_mode != 1 && h->max_p > 0 && h->max_p <= 2048 &&
-        (h->opt.sweep_mode == 2 || (double)h->total_g <= 2.0 * (double)h->total_lower)) {
+    if (want_green) {
         HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
         HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
-        vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p, h->d_vals64.as<double>(),
-                          h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
+        if (h->plan_state == 1) {
+            HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
+            vtm::launch_green_mf(dev_sym(h), dev_sub(h), dev_green(h), P.nsub, h->d_vals64.as<double>(),
+                                 h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
+        } else {
+            vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p,
+                              h->d_vals64.as<double>(), h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
+        }
         if (h->fp32()) {
             HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 4)));
             vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);

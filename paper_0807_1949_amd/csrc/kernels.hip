@@ -21,6 +21,7 @@ namespace vtm {
 namespace {
 
 constexpr int kThreads = 256;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kWriteX = 1, kNoWaves = 2, kZeroWaves = 4;
 
 __global__ void k_invz(const double *__restrict__ z, const int32_t *__restrict__ port_vtl, double *__restrict__ i64,
@@ -38,23 +39,43 @@ __global__ void k_to_f32(const double *__restrict__ s, float *__restrict__ d, in
 }
 
 // ---------------------------------------------------------------- factorisation
+//
+// Per supernode s (front F of order f = nc + m in LDS, row-major; only its lower triangle carries
+// the matrix, so the strictly upper part of the leading nc x nc block and the nc x m block to its
+// right serve as scratch):
+//   1. assemble: local entries, the port diagonal Z^{-1}, the children's update matrices;
+//   2. L11 = chol(F11) in place (one wave when nc <= kWaveChol, else the workgroup);
+//   3. Linv = L11^{-1}, column j by thread j, strictly lower part stored transposed in the upper
+//      triangle (Linv[i][j] at F[j][i]; the diagonal is 1 / L11[j][j]);
+//   4. L21 = F21 L11^{-T}, stored transposed in the upper-right block (L21[q][t] at F[t][nc + q]);
+//   5. outputs Linv and W = L21 Linv, and the update matrix F22 - L21 L21^T written straight to
+//      the workspace (lower triangle); the rank-nc update runs on the FP64 matrix cores in 16 x 16
+//      tiles when m >= 16.
+constexpr int kWaveChol = 48;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const double *__restrict__ aval,
                                                      const double *__restrict__ invz, double *__restrict__ vals,
                                                      double *__restrict__ ws, int lds_front,
                                                      int32_t *__restrict__ status) {
     extern __shared__ double sm[];
     const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
-    double *dplus = sm;
-    double *Fl = sm + ((nk + 1) & ~1);
     const double *A = aval + D.aval[k];
     double *V = vals + D.val[k];
     double *W = ws + D.ws[k];
+    double *dplus = W + C.ws_u + (int64_t)C.max_front * C.max_front;
     const int32_t *sn_c0 = S.sn_c0 + C.o_sn, *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn;
-    const int32_t *sn_val = S.sn_val + C.o_sn, *sn_ridx = S.sn_ridx + C.o_sn, *sn_uoff = S.sn_uoff + C.o_sn;
+    const int32_t *sn_val = S.sn_val + C.o_sn, *sn_uoff = S.sn_uoff + C.o_sn;
     const int32_t *ch_ptr = S.ch_ptr + C.o_snp, *ch_idx = S.ch_idx + C.o_chi;
     const int32_t *sc_ptr = S.sc_ptr + C.o_snp, *sc_src = S.sc_src + C.o_sc, *sc_dst = S.sc_dst + C.o_sc;
+    const int32_t *sn_ridx = S.sn_ridx + C.o_sn;
     const uint16_t *rel = S.rel + C.o_ridx;
 
     // diagonal additions Z^{-1} of the ports, one thread per port vertex (ports in order)
@@ -69,14 +90,14 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
     int bad = 0;
     for (int s = 0; s < C.nsn; ++s) {
         const int c0 = sn_c0[s], nc = sn_nc[s], m = sn_m[s], f = nc + m;
-        double *F = lds_front ? Fl : W + C.ws_u;
+        double *F = lds_front ? sm : W + C.ws_u;
+        // 1. assembly
         for (int i = tid; i < f * f; i += nt) F[i] = 0.0;
         __syncthreads();
         for (int e = sc_ptr[s] + tid; e < sc_ptr[s + 1]; e += nt) F[sc_dst[e]] = A[sc_src[e]];
         __syncthreads();
         for (int j = tid; j < nc; j += nt) F[j * f + j] += dplus[c0 + j];
-        // extend-add the children's update matrices, one child at a time
-        for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {
+        for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {  // children one at a time (they share rows)
             __syncthreads();
             const int c = ch_idx[q], mc = sn_m[c];
             const double *U = W + sn_uoff[c];
@@ -87,45 +108,108 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
             }
         }
         __syncthreads();
-        // partial Cholesky of the nc pivot columns (right-looking)
-        for (int kk = 0; kk < nc; ++kk) {
-            double d = F[kk * f + kk];
-            if (!(d > 0.0) || !isfinite(d)) { bad = bad ? bad : s + 1; d = 1.0; }
-            const double sd = sqrt(d), rs = 1.0 / sd;
-            __syncthreads();
-            for (int i = kk + 1 + tid; i < f; i += nt) F[i * f + kk] *= rs;
-            if (tid == 0) F[kk * f + kk] = sd;
-            __syncthreads();
-            const int T = f - kk - 1;
-            for (int idx = tid; idx < T * T; idx += nt) {
-                const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
-                if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
+        // 2. Cholesky of the diagonal block (right-looking)
+        if (nc <= kWaveChol) {
+            if (wv == 0) {
+                for (int kk = 0; kk < nc; ++kk) {
+                    double d = F[kk * f + kk];
+                    if (!(d > 0.0) || !isfinite(d)) { bad = bad ? bad : s + 1; d = 1.0; }
+                    const double sd = sqrt(d), rs = 1.0 / sd;
+                    wave_sync();
+                    for (int i = kk + 1 + lane; i < nc; i += 64) F[i * f + kk] *= rs;
+                    if (lane == 0) F[kk * f + kk] = sd;
+                    wave_sync();
+                    const int T = nc - kk - 1;
+                    for (int idx = lane; idx < T * T; idx += 64) {
+                        const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
+                        if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
+                    }
+                    wave_sync();
+                }
             }
-            __syncthreads();
+        } else {
+            for (int kk = 0; kk < nc; ++kk) {
+                double d = F[kk * f + kk];
+                if (!(d > 0.0) || !isfinite(d)) { bad = bad ? bad : s + 1; d = 1.0; }
+                const double sd = sqrt(d), rs = 1.0 / sd;
+                __syncthreads();
+                for (int i = kk + 1 + tid; i < nc; i += nt) F[i * f + kk] *= rs;
+                if (tid == 0) F[kk * f + kk] = sd;
+                __syncthreads();
+                const int T = nc - kk - 1;
+                for (int idx = tid; idx < T * T; idx += nt) {
+                    const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
+                    if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
+                }
+                __syncthreads();
+            }
         }
-        // outputs: inverse of the diagonal block (row-major, upper part zero), L21, update matrix
-        double *Vs = V + sn_val[s];
+        __syncthreads();
+        // 3. Linv, column j by thread j: Linv[i][j] = -(sum_{j <= t < i} L[i][t] Linv[t][j]) / L[i][i]
         for (int j = tid; j < nc; j += nt) {
-            for (int i = 0; i < j; ++i) Vs[i * nc + j] = 0.0;
-            Vs[j * nc + j] = 1.0 / F[j * f + j];
+            const double djj = 1.0 / F[j * f + j];
             for (int i = j + 1; i < nc; ++i) {
-                double acc = 0.0;
-                for (int t = j; t < i; ++t) acc += F[i * f + t] * Vs[t * nc + j];
-                Vs[i * nc + j] = -acc / F[i * f + i];
+                double acc = F[i * f + j] * djj;
+                for (int t = j + 1; t < i; ++t) acc += F[i * f + t] * F[j * f + t];
+                F[j * f + i] = -acc / F[i * f + i];
             }
         }
-        __syncthreads();  // Linv complete
+        __syncthreads();
+        // 4. L21[q][t] = sum_{u <= t} F21[q][u] Linv[t][u]
         for (int idx = tid; idx < m * nc; idx += nt) {
+            const int q = idx / nc, t = idx - q * nc;
+            const double *row = F + (nc + q) * f;
+            double acc = row[t] / F[t * f + t];
+            for (int u = 0; u < t; ++u) acc += row[u] * F[u * f + t];
+            F[t * f + nc + q] = acc;
+        }
+        __syncthreads();
+        // 5. outputs
+        double *Vs = V + sn_val[s];
+        for (int idx = tid; idx < nc * nc; idx += nt) {
+            const int i = idx / nc, j = idx - i * nc;
+            Vs[idx] = j > i ? 0.0 : (j == i ? 1.0 / F[i * f + i] : F[j * f + i]);
+        }
+        for (int idx = tid; idx < m * nc; idx += nt) {  // W[q][j] = sum_{t >= j} L21[q][t] Linv[t][j]
             const int q = idx / nc, j = idx - q * nc;
-            const double *l21 = F + (nc + q) * f;
-            double acc = 0.0;
-            for (int i = j; i < nc; ++i) acc += l21[i] * Vs[i * nc + j];
-            Vs[nc * nc + idx] = acc;  // W = L21 L11^{-1}
+            double acc = F[j * f + nc + q] / F[j * f + j];
+            for (int t = j + 1; t < nc; ++t) acc += F[t * f + nc + q] * F[j * f + t];
+            Vs[nc * nc + idx] = acc;
         }
         double *Us = W + sn_uoff[s];
-        for (int idx = tid; idx < m * m; idx += nt) {
-            const int i = idx / m, j = idx - i * m;
-            Us[idx] = F[(nc + i) * f + nc + j];
+        if (m >= 16) {
+            // update = F22 - L21 L21^T on the matrix cores: wave per 16 x 16 tile (ta, tb <= ta).
+            // v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16], B[l / 16][l % 16] and holds
+            // D[4 j + l / 16][l % 16]; A[a][t] = B[t][a] = L21[a][t] = F[t][nc + a].
+            const int tm = (m + 15) >> 4, ntile = tm * (tm + 1) / 2;
+            const int kr = lane >> 4;
+            for (int it = wv; it < ntile; it += nw) {
+                int ta = (int)((sqrtf(8.0f * (float)it + 1.0f) - 1.0f) * 0.5f);
+                while (ta * (ta + 1) / 2 > it) --ta;
+                while ((ta + 1) * (ta + 2) / 2 <= it) ++ta;
+                const int tb = it - ta * (ta + 1) / 2;
+                const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15);
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int t0 = 0; t0 < nc; t0 += 4) {
+                    const int t = t0 + kr;
+                    const double av = (t < nc && ra < m) ? F[t * f + nc + ra] : 0.0;
+                    const double bv = (t < nc && rb < m) ? F[t * f + nc + rb] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int a = 16 * ta + 4 * j + kr;
+                    if (a < m && rb < m && rb <= a) Us[a * m + rb] = F[(nc + a) * f + nc + rb] - acc[j];
+                }
+            }
+        } else {
+            for (int idx = tid; idx < m * m; idx += nt) {
+                const int a = idx / m, b = idx - a * m;
+                if (b > a) continue;
+                double acc = F[(nc + a) * f + nc + b];
+                for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + a] * F[t * f + nc + b];
+                Us[idx] = acc;
+            }
         }
         __syncthreads();
     }
@@ -365,6 +449,112 @@ __global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double 
     }
 }
 
+// Largest s in [s0, s1) with pre[s] <= it (the owner of flat item it; empty supernodes never win).
+__device__ inline int owner(const int32_t *__restrict__ pre, int s0, int s1, int it) {
+    int lo = s0, hi = s1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Port Green's functions by multifrontal forward substitution, one workgroup per subgraph, FP64.
+// With E the unit columns of the port vertices, Y = L^{-1} E and G_k = E^T K^{-1} E = Y^T Y.  Column
+// j of Y is non-zero only on the supernodes above the one holding port j, so supernode s carries
+// just the w_s ports below it (a contiguous range, see DevGreen).  Its front F_s is (nc + m) x w_s
+// (row-major, zero on entry except the unit entries of its own ports and what the children pushed)
+// and Y_s (nc x w_s) follows it in the workspace.  Level by level:
+//   phase 1  Y_s = Linv_s T_s (T_s = first nc rows of F_s); the update F_s[nc:] - W_s T_s goes into
+//            the parent's front (rows by rel, columns shifted by the range offset; siblings own
+//            disjoint columns, so these are plain stores);
+//   phase 2  G[ports of s, ports of s] += Y_s^T Y_s (siblings own disjoint blocks of G), a
+//            symmetric rank-nc update done by FP64 MFMA, 16 x 16 tiles of the lower triangle.
+// Work items (phase 1) and tiles (phase 2) of a level are numbered across its supernodes through
+// the prefixes py / pq.
+__global__ __launch_bounds__(256) void k_green_mf(DevSym S, DevSub D, DevGreen Gp, const double *__restrict__ vals,
+                                                  const int64_t *__restrict__ goff, double *__restrict__ G) {
+    const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
+    if (p == 0) return;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int32_t *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn, *sn_val = S.sn_val + C.o_sn;
+    const int32_t *sn_ridx = S.sn_ridx + C.o_sn;
+    const int32_t *col_sn = S.col_sn + C.o_col, *lev_c0 = S.lev_c0 + C.o_lev;
+    const uint16_t *rel = S.rel + C.o_ridx;
+    const int b0 = Gp.base[k];
+    const int4 *pl = Gp.sn + b0;
+    const int32_t *py = Gp.py + b0, *pq = Gp.pq + b0;
+    const uint16_t *perm = Gp.perm + pg0;
+    double *ws = Gp.ws + Gp.wso[k];
+    const double *Vk = vals + D.val[k];
+    double *Gk = G + goff[k];
+    const int ldp = (p + 3) & ~3;
+    for (int a = tid; a < p; a += nt) ws[Gp.idoff[pg0 + a]] = 1.0;
+    __syncthreads();
+    for (int lv = 0; lv < C.nlev; ++lv) {
+        const int s0 = col_sn[lev_c0[lv]], s1 = lv + 1 < C.nlev ? col_sn[lev_c0[lv + 1]] : C.nsn;
+        for (int it = py[s0] + tid; it < py[s1]; it += nt) {
+            const int s = owner(py, s0, s1, it);
+            const int4 e = pl[s];
+            const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
+            const int nc = sn_nc[s], m = sn_m[s];
+            const int loc = it - py[s], i = loc / w, a = loc - i * w;
+            const double *F = ws + e.x;
+            const double *V = Vk + sn_val[s];
+            if (i < nc) {
+                double acc = 0.0;
+                for (int t = 0; t <= i; ++t) acc += V[i * nc + t] * F[t * w + a];
+                ws[e.x + (nc + m) * w + i * w + a] = acc;
+            } else {
+                const int q = i - nc;
+                const double *Wq = V + nc * nc + q * nc;
+                double acc = F[i * w + a];
+                for (int t = 0; t < nc; ++t) acc -= Wq[t] * F[t * w + a];
+                const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
+                ws[e.z + (int)rel[sn_ridx[s] + q] * pw + a + (pc0 - ppc0)] = acc;
+            }
+        }
+        __syncthreads();
+        // phase 2 on the FP64 matrix cores: one wave per 16 x 16 tile (ta, tb <= ta) of Y_s^T Y_s.
+        // v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+        // D[4 j + l / 16][l % 16] in acc[j]; here A[a][i] = Y[i][a], B[i][b] = Y[i][b].
+        for (int it = pq[s0] + wv; it < pq[s1]; it += nw) {
+            const int s = owner(pq, s0, s1, it);
+            const int4 e = pl[s];
+            const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
+            const int nc = sn_nc[s], m = sn_m[s];
+            const int loc = it - pq[s];
+            int ta = (int)((sqrtf(8.0f * (float)loc + 1.0f) - 1.0f) * 0.5f);
+            while (ta * (ta + 1) / 2 > loc) --ta;
+            while ((ta + 1) * (ta + 2) / 2 <= loc) ++ta;
+            const int tb = loc - ta * (ta + 1) / 2;
+            const double *Y = ws + e.x + (nc + m) * w;
+            const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15), kr = lane >> 4;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int i0 = 0; i0 < nc; i0 += 4) {
+                const int i = i0 + kr;
+                const double av = (i < nc && ra < w) ? Y[i * w + ra] : 0.0;
+                const double bv = (i < nc && rb < w) ? Y[i * w + rb] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+            const int b = rb;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int a = 16 * ta + 4 * j + kr;
+                if (a < w && b < w && (ta != tb || b <= a)) {
+                    const int ja = perm[pc0 + a], jb = perm[pc0 + b];
+                    Gk[(int64_t)ja * ldp + jb] += acc[j];
+                    if (a != b) Gk[(int64_t)jb * ldp + ja] += acc[j];
+                }
+            }
+        }
+        // the next level's phase-1 barrier orders these G updates before the parents' ones
+    }
+}
+
 // c[g][q][c] = K^{-1} b~ at the port vertices (local solutions of a zero-wave solve).
 template <typename T>
 __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
@@ -579,10 +769,10 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_front,
                    const double *aval, const double *invz, double *vals, double *ws, int64_t, int32_t *status,
                    hipStream_t st) {
-    size_t base = sizeof(double) * (size_t)((max_nk + 1) & ~1);
-    size_t front = sizeof(double) * (size_t)max_front * max_front;
-    int lds_front = base + front <= 96 * 1024;
-    size_t shm = base + (lds_front ? front : 0);
+    (void)max_nk;
+    const size_t front = sizeof(double) * (size_t)max_front * max_front;
+    const int lds_front = front <= 96 * 1024;
+    const size_t shm = lds_front ? front : 0;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_front, status);
 }
@@ -653,6 +843,11 @@ void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk
     const dim3 grid(nsub, (max_p + 3) / 4);
     if (V) hipLaunchKernelGGL(k_green<1>, grid, dim3(256), shm, st, S, D, vals, goff, G);
     else hipLaunchKernelGGL(k_green<0>, grid, dim3(256), shm, st, S, D, vals, goff, G);
+}
+
+void launch_green_mf(const DevSym &S, const DevSub &D, const DevGreen &Gp, int32_t nsub, const double *vals,
+                     const int64_t *goff, double *G, hipStream_t st) {
+    hipLaunchKernelGGL(k_green_mf, dim3(nsub), dim3(256), 0, st, S, D, Gp, vals, goff, G);
 }
 
 template <typename T>

@@ -49,6 +49,21 @@ struct DevSub {
     const int32_t *pg_cnt;   // ports in the group
 };
 
+// Column plan of the port Green's functions by one multifrontal forward substitution with all port
+// columns (k_green_mf).  Ports of a subgraph are sorted by the postorder of their supernode, so the
+// ports below supernode s form one column range [pc0, pc0 + w) and a child's range lies inside its
+// parent's.  Plan entries of subgraph k start at base[k] (nsn + 1 entries, the last only for the prefixes).
+struct DevGreen {
+    const int4 *sn;         // {front offset, pc0 | w << 16, parent front offset, parent pc0 | parent w << 16}
+    const int32_t *py;      // exclusive prefix of the phase-1 items (nc + m) * w
+    const int32_t *pq;      // exclusive prefix of the phase-2 tiles t (t + 1) / 2, t = ceil(w / 16)
+    const int32_t *base;    // first plan entry of each subgraph
+    const int64_t *wso;     // workspace offset of each subgraph (doubles)
+    const int32_t *idoff;   // per sorted port: workspace offset of its unit right-side entry
+    const uint16_t *perm;   // per sorted port: its port-vertex index in the subgraph
+    double *ws;             // fronts and Y blocks, zero on entry
+};
+
 // Split-vector and merge maps.
 struct DevMaps {
     const int32_t *fvtx;   // split entry (factor order) -> global vertex
@@ -91,6 +106,9 @@ hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_
 // Port Green's functions G_k = R K_k^{-1} R^T (FP64, p_k x p_k row-major at goff[k]).
 void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
                   const double *vals, const int64_t *goff, double *G, hipStream_t st);
+// The same G_k by Y = L^{-1} R^T (one forward substitution with all port columns) and G = Y^T Y.
+void launch_green_mf(const DevSym &S, const DevSub &D, const DevGreen &Gp, int32_t nsub, const double *vals,
+                     const int64_t *goff, double *G, hipStream_t st);
 // cport[g][port vertex][R] = local solutions at the port vertices.
 template <typename T>
 void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,

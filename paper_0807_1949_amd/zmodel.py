@@ -32,7 +32,7 @@ import numpy as np
 from . import binding as B
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_WEIGHTS = os.path.join(HERE, "zmodel_c4.json")
+DEFAULT_WEIGHTS = os.path.join(HERE, "zmodel_weights.json")
 
 ALPHAS = 2.0 ** (np.arange(17) / 2.0)
 BETAS = 2.0 ** (np.arange(-4, 5) / 2.0)

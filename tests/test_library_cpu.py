@@ -161,3 +161,95 @@ def test_symbolic_analysis_factorises(name, k):
             assert sn[sn[s, 5], 6] > lev
     # assembly scatter covers every lower entry of K exactly once
     assert d["sc"].shape[0] == (np.count_nonzero(K) + nk) // 2
+
+
+def _emulate_green_forward(d, L, port_pos):
+    """Port Green's functions as the device computes them in the port-reduced setup: ports sorted by
+    the postorder of their supernode, one multifrontal forward substitution carrying only the ports
+    below each supernode (a contiguous column range), update blocks pushed into the parent's front
+    through the relative indices, and G = sum over supernodes of Y_s^T Y_s."""
+    sn, nsn = d["sn"], d["nsn"]
+    par = sn[:, 5]
+    col_sn = np.empty(d["nk"], np.int64)
+    for s in range(nsn):
+        col_sn[sn[s, 0]:sn[s, 0] + sn[s, 1]] = s
+    children = [[] for _ in range(nsn)]
+    for s in range(nsn):
+        if par[s] >= 0:
+            children[par[s]].append(s)
+    post, first, cnt = np.zeros(nsn, np.int64), np.zeros(nsn, np.int64), 0
+    for r in [r for r in range(nsn) if par[r] < 0]:  # iterative postorder of every tree
+        st = [[r, 0]]
+        first[r] = cnt
+        while st:
+            s, i = st[-1]
+            if i < len(children[s]):
+                st[-1][1] += 1
+                q = children[s][i]
+                first[q] = cnt
+                st.append([q, 0])
+            else:
+                post[s] = cnt
+                cnt += 1
+                st.pop()
+    key = post[col_sn[port_pos]]
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    lo = np.searchsorted(ks, first, "left")
+    hi = np.searchsorted(ks, post, "right")
+    p = len(port_pos)
+    F = {}
+    for s in range(nsn):
+        nc, m = sn[s, 1], sn[s, 2]
+        F[s] = np.zeros((nc + m, hi[s] - lo[s]))
+    for a in range(p):
+        s = col_sn[port_pos[order[a]]]
+        F[s][port_pos[order[a]] - sn[s, 0], a - lo[s]] = 1.0
+    G = np.zeros((p, p))
+    for s in range(nsn):  # supernodes are sorted by level: children first
+        c0, nc, m, ro = sn[s, 0], sn[s, 1], sn[s, 2], sn[s, 4]
+        if hi[s] == lo[s]:
+            continue
+        L11 = L[c0:c0 + nc, c0:c0 + nc]
+        rows = d["ridx"][ro:ro + m].astype(np.int64)
+        Linv = np.linalg.inv(L11)
+        W = L[rows][:, c0:c0 + nc] @ Linv
+        T = F[s][:nc]
+        Y = Linv @ T
+        if m:
+            U = F[s][nc:] - W @ T
+            q = par[s]
+            rel = d["rel"][ro:ro + m].astype(np.int64)
+            F[q][np.ix_(rel, np.arange(lo[s], hi[s]) - lo[q])] = U
+        js = order[lo[s]:hi[s]]
+        G[np.ix_(js, js)] += Y.T @ Y
+    return G
+
+
+@pytest.mark.parametrize("name,k", [("c1", 5), ("c2", 0), ("c3", 7), ("c4", 3), ("c5", 2)])
+def test_green_by_port_forward_substitution(name, k):
+    cfg = gen.make_config(name, small=True)
+    h = _host_handle()
+    h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+    p = h.get_partition()
+    d = h.debug_class(k)
+    b, e = p["loc_ptr"][k], p["loc_ptr"][k + 1]
+    nk = e - b
+    K = np.zeros((nk, nk))
+    for i in range(nk):
+        s, t = p["lrp"][b + i], p["lrp"][b + i + 1]
+        K[i, p["lcol"][s:t]] = p["lval"][s:t]
+    zadd = np.random.default_rng(1).uniform(0.5, 2.0, p["port_ptr"][k + 1] - p["port_ptr"][k])
+    perm = d["perm"]
+    ipos = np.argsort(perm)
+    dplus = np.zeros(nk)
+    for q in range(p["port_ptr"][k], p["port_ptr"][k + 1]):
+        li = np.searchsorted(p["loc_vtx"][b:e], p["port_v"][q])
+        dplus[ipos[li]] += zadd[q - p["port_ptr"][k]]
+    L = _emulate_multifrontal(d, p["lval"][p["lrp"][b]:p["lrp"][e]], dplus)
+    pv = np.unique(p["port_v"][p["port_ptr"][k]:p["port_ptr"][k + 1]])  # port vertices, ascending = group order
+    port_pos = ipos[np.searchsorted(p["loc_vtx"][b:e], pv)]
+    G = _emulate_green_forward(d, L, port_pos)
+    Kp = K[np.ix_(perm, perm)] + np.diag(dplus)
+    Gref = np.linalg.inv(Kp)[np.ix_(port_pos, port_pos)]
+    assert np.allclose(G, Gref, rtol=0, atol=1e-11 * np.abs(Gref).max())
