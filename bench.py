@@ -159,7 +159,8 @@ def main():
         relres=head["relres"], partition_s=head["partition_s"],
         variants={v: dict(time_to_tol_s=r["step_s"], sweeps=r["stats"]["sweeps"], setup_ms=r["stats"]["setup_ms"],
                           sweep_us=r["stats"]["sweep_ms"] * 1e3 / max(r["stats"]["sweeps"], 1),
-                          outer_steps=r["stats"]["outer_steps"], relres=r["relres"], status=r["status"],
+                          outer_steps=r["stats"]["outer_steps"], checks=r["stats"]["checks"],
+                          relres=r["relres"], status=r["status"],
                           sweep_mode=r["stats"]["sweep_mode"])
                   for v, r in results.items()},
         roofline=dict(kernel="k_schur" if st["sweep_mode"] == 2 else "k_sweep", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",

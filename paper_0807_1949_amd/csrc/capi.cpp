@@ -73,7 +73,7 @@ struct vtm_ctx {
     int64_t total_g = 0;
     bool have_green = false;
     // column plan of the multifrontal Green's-function computation (built on first use)
-    DevBuf d_gsn, d_gpy, d_gpq, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws;
+    DevBuf d_gsn, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws, d_levmaxf;
     int plan_state = 0;  // 0 not built, 1 ready, -1 not applicable (fall back to per-column solves)
     int64_t gws_total = 0;
     std::vector<int32_t> h_pgptr;
@@ -119,7 +119,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gpy, &d_gpq, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -168,6 +168,7 @@ vtm::DevSym dev_sym(vtm_ctx *h) {
     s.cls = h->d_cls.as<vtm::ClassDev>();
     s.lev_c0 = h->d_lev.as<int32_t>();
     s.col_sn = h->d_colsn.as<int32_t>();
+    s.lev_maxf = h->d_levmaxf.as<int32_t>();
     s.sn_c0 = h->d_snc0.as<int32_t>();
     s.sn_nc = h->d_snnc.as<int32_t>();
     s.sn_m = h->d_snm.as<int32_t>();
@@ -207,9 +208,9 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     return d;
 }
 
-// Column plan of k_green_mf.  Ports are sorted by the postorder of their supernode; the ports below
-// supernode s then form the range [lo_s, hi_s) of width w_s, its own ports the tail [own_s, hi_s).
-// Workspace per supernode: front (nc + m) x w_s, then Y_s (nc x w_s).
+// Column plan of the port Green's functions (computed inside k_factor).  Ports are sorted by the
+// postorder of their supernode; the ports below supernode s then form the range [lo_s, lo_s + w_s),
+// its own ports the tail of it.  Workspace per supernode: port front (nc + m) x w_s, then Y_s (nc x w_s).
 vtm_status build_green_plan(vtm_ctx *h) {
     const vtm::Partition &P = h->P;
     const vtm::Symbolic &S = h->S;
@@ -241,7 +242,7 @@ vtm_status build_green_plan(vtm_ctx *h) {
         }
     }
     std::vector<int4> sn;
-    std::vector<int32_t> py, pq, base(nsub + 1, 0), idoff(h->npg, 0);
+    std::vector<int32_t> base(nsub + 1, 0), idoff(h->npg, 0);
     std::vector<uint16_t> perm(h->npg, 0);
     std::vector<int64_t> wso(nsub + 1, 0);
     for (int32_t k = 0; k < nsub; ++k) {
@@ -256,35 +257,24 @@ vtm_status build_green_plan(vtm_ctx *h) {
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
         std::vector<int32_t> ks(p);
         for (int32_t a = 0; a < p; ++a) ks[a] = key[order[a]];
-        std::vector<int32_t> lo(C.nsn), own(C.nsn), w(C.nsn);
+        std::vector<int32_t> lo(C.nsn), w(C.nsn);
         std::vector<int64_t> fo(C.nsn);
         int64_t off = 0;
         for (int32_t s = 0; s < C.nsn; ++s) {
             lo[s] = (int32_t)(std::lower_bound(ks.begin(), ks.end(), first[c][s]) - ks.begin());
-            own[s] = (int32_t)(std::lower_bound(ks.begin(), ks.end(), post[c][s]) - ks.begin());
             w[s] = (int32_t)(std::upper_bound(ks.begin(), ks.end(), post[c][s]) - ks.begin()) - lo[s];
             fo[s] = off;
             off += (int64_t)(2 * C.sn_nc[s] + C.sn_m[s]) * w[s];
         }
-        int64_t iy = 0, iq = 0;
+        if (off >= ((int64_t)1 << 31)) {
+            h->plan_state = -1;
+            return VTM_OK;
+        }
         base[k] = (int32_t)sn.size();
         for (int32_t s = 0; s < C.nsn; ++s) {
             const int32_t par = C.sn_parent[s];
-            const int64_t f = C.sn_nc[s] + C.sn_m[s];
             sn.push_back(int4{(int32_t)fo[s], lo[s] | (w[s] << 16), par < 0 ? 0 : (int32_t)fo[par],
                               par < 0 ? 0 : (lo[par] | (w[par] << 16))});
-            py.push_back((int32_t)iy);
-            pq.push_back((int32_t)iq);
-            iy += f * w[s];
-            iq += (int64_t)((w[s] + 15) / 16) * ((w[s] + 15) / 16 + 1) / 2;
-        }
-        sn.push_back(int4{0, 0, 0, 0});
-        py.push_back((int32_t)iy);
-        pq.push_back((int32_t)iq);
-        if (off >= ((int64_t)1 << 31) || iy >= ((int64_t)1 << 31) || iq >= ((int64_t)1 << 31) ||
-            sn.size() >= ((size_t)1 << 31)) {
-            h->plan_state = -1;
-            return VTM_OK;
         }
         for (int32_t a = 0; a < p; ++a) {
             const int32_t j = order[a], pos = h->h_pgpos[pg0 + j], s = C.col_sn[pos];
@@ -297,8 +287,6 @@ vtm_status build_green_plan(vtm_ctx *h) {
     h->gws_total = wso[nsub];
     hipStream_t st = h->stream;
     HIP_TRY(upload(h->d_gsn, sn, st));
-    HIP_TRY(upload(h->d_gpy, py, st));
-    HIP_TRY(upload(h->d_gpq, pq, st));
     HIP_TRY(upload(h->d_gbase, base, st));
     HIP_TRY(upload(h->d_gwso, wso, st));
     HIP_TRY(upload(h->d_gidoff, idoff, st));
@@ -308,11 +296,10 @@ vtm_status build_green_plan(vtm_ctx *h) {
     return VTM_OK;
 }
 
-vtm::DevGreen dev_green(vtm_ctx *h) {
-    vtm::DevGreen g;
+vtm::DevGreen dev_green(vtm_ctx *h, bool on) {
+    vtm::DevGreen g{};
+    if (!on) return g;
     g.sn = h->d_gsn.as<int4>();
-    g.py = h->d_gpy.as<int32_t>();
-    g.pq = h->d_gpq.as<int32_t>();
     g.base = h->d_gbase.as<int32_t>();
     g.wso = h->d_gwso.as<int64_t>();
     g.idoff = h->d_gidoff.as<int32_t>();
@@ -352,7 +339,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     std::vector<int32_t> lev, colsn, snc0, snnc, snm, snval, snridx, snuoff, chptr, chidx, segptr, segoff, scptr,
         scsrc, scdst;
     std::vector<uint16_t> ridx, rel, segc0, segnc, segu, usn;
-    std::vector<int32_t> levu, colrec, urec;
+    std::vector<int32_t> levu, colrec, urec, levmaxf;
     h->max_nk = 0;
     h->max_front = 0;
     h->max_nu = 0;
@@ -382,6 +369,7 @@ vtm_status upload_partition(vtm_ctx *h) {
         colrec.insert(colrec.end(), C.colrec.begin(), C.colrec.end());
         urec.insert(urec.end(), C.urec.begin(), C.urec.end());
         lev.insert(lev.end(), C.lev_c0.begin(), C.lev_c0.end());
+        levmaxf.insert(levmaxf.end(), C.lev_maxf.begin(), C.lev_maxf.end());
         colsn.insert(colsn.end(), C.col_sn.begin(), C.col_sn.end());
         snc0.insert(snc0.end(), C.sn_c0.begin(), C.sn_c0.end());
         snnc.insert(snnc.end(), C.sn_nc.begin(), C.sn_nc.end());
@@ -488,7 +476,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     h->nchunks = (int32_t)chunksys.size();
 
 #define UP(buf, vec) HIP_TRY(upload(h->buf, vec, st))
-    UP(d_cls, cls); UP(d_lev, lev); UP(d_colsn, colsn); UP(d_snc0, snc0); UP(d_snnc, snnc); UP(d_snm, snm);
+    UP(d_cls, cls); UP(d_lev, lev); UP(d_levmaxf, levmaxf); UP(d_colsn, colsn); UP(d_snc0, snc0); UP(d_snnc, snnc); UP(d_snm, snm);
     UP(d_snval, snval); UP(d_snridx, snridx); UP(d_snuoff, snuoff); UP(d_ridx, ridx); UP(d_rel, rel);
     UP(d_chptr, chptr); UP(d_chidx, chidx); UP(d_segptr, segptr); UP(d_segoff, segoff); UP(d_segc0, segc0);
     UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_colrec, colrec); UP(d_urec, urec); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
@@ -725,7 +713,9 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     const int32_t nsys = h->P.nsys, R = h->wave_R;
     const vtm::DevMaps M = dev_maps(h);
     // fixed cadence, or (check_every == 0) the next test is placed where the observed contraction
-    // rate predicts the tolerance, between 5 and 200 sweeps
+    // rate predicts the tolerance (between 5 and 200 sweeps later), a little past it when a test
+    // costs more than a sweep: the margin is at most the test's measured cost in sweeps and 15 %
+    // of the prediction.  A refinement restart keeps the rate: the operator is the same.
     const bool adaptive = h->opt.check_every <= 0;
     int64_t cadence = adaptive ? 10 : h->opt.check_every;
     const int64_t maxsw = h->opt.max_sweeps > 0 ? h->opt.max_sweeps : 100000;
@@ -733,11 +723,12 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     std::vector<double> rel;
     std::vector<int32_t> it((size_t)nsys * nrhs, -1);
     std::vector<double> last((size_t)nsys * nrhs, 1.0);
-    hipEvent_t e0, e1, s0, s1;
+    hipEvent_t e0, e1, s0, s1, c1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventCreate(&s0));
     HIP_TRY(hipEventCreate(&s1));
+    HIP_TRY(hipEventCreate(&c1));
     HIP_TRY(hipEventRecord(e0, h->stream));
     double sweep_ms = 0.0;
     int64_t sweeps = 0;
@@ -755,6 +746,8 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     double rel_outer = 1.0, rel_prev = 1e300;
     const double eta = 1e-5;
     double rate_ref = -1.0;  // worst residual at the previous test of the current inner solve
+    double lr_known = 0.0;   // last measured log contraction per sweep (< 0 when known)
+    double test_sweeps = 0.0;  // cost of one test in sweeps (measured)
     int inner_checks = 0;
     double last_worst = 1e300;
     while (!done && sweeps < maxsw) {
@@ -768,10 +761,13 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         if (schur) local_solve<T>(h, false);  // interior potentials of the last sweep
         // merged potentials (plus the refined x in FP32_IR), FP64 residual
         vtm::launch_merge<T>(M, n, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, h->stream);
+        HIP_TRY(hipEventRecord(c1, h->stream));
         if ((rc = residual(h, nrhs, xtr, refine ? rtr : nullptr, rel))) return rc;
-        float ms = 0.f;
+        float ms = 0.f, cms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, s0, s1));
+        HIP_TRY(hipEventElapsedTime(&cms, s1, c1));
         sweep_ms += ms;
+        if (ms > 0.f) test_sweeps = (double)cms / ((double)ms / (double)cnt);
         double worst = 0.0;
         bool all = true;
         for (size_t q = 0; q < rel.size(); ++q) {
@@ -786,11 +782,12 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         if (diverged) break;
         if (adaptive) {
             int64_t next = 2 * cnt;
-            if (rate_ref > 0.0 && worst < rate_ref) {
-                const double lr = std::log(worst / rate_ref) / (double)cnt;  // log contraction per sweep
+            if (rate_ref > 0.0 && worst < rate_ref) lr_known = std::log(worst / rate_ref) / (double)cnt;
+            if (lr_known < 0.0) {
                 const double target = refine ? std::max(tol, eta * rel_outer) : tol;
-                const double need = std::log(target / worst) / lr;
-                next = need > 0 ? (int64_t)std::ceil(0.9 * need) : 5;
+                const double need = std::log(target / worst) / lr_known;
+                const double margin = std::min(0.15 * need, test_sweeps);
+                next = need > 0 ? (int64_t)std::ceil(need + std::max(0.0, margin)) : 5;
             }
             cadence = std::max<int64_t>(5, std::min<int64_t>(200, next));
             rate_ref = worst;
@@ -815,7 +812,11 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             rel_prev = 1e300;
             inner_checks = 0;
             rate_ref = -1.0;
-            if (adaptive) cadence = 10;
+            if (adaptive) {  // first test of the new inner solve from the known rate
+                const double target = std::max(tol, eta * rel_outer);
+                const double need = lr_known < 0.0 ? std::log(target / rel_outer) / lr_known : 10.0;
+                cadence = std::max<int64_t>(5, std::min<int64_t>(200, (int64_t)std::ceil(need)));
+            }
             ++outer;
             vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
             if ((rc = zero_waves<T>(h))) return rc;
@@ -836,6 +837,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(s0);
     (void)hipEventDestroy(s1);
+    (void)hipEventDestroy(c1);
     h->stats.sweeps = sweeps;
     h->stats.outer_steps = outer;
     h->stats.checks = checks;
@@ -1081,25 +1083,25 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
     HIP_TRY(hipEventRecord(e0, st));
     vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
                      h->d_invz32.as<float>(), h->nports, st);
-    vtm::launch_factor(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_front, h->d_aval.as<double>(),
-                       h->d_invz64.as<double>(), h->d_vals64.as<double>(), ws.as<double>(), 0,
-                       h->d_status.as<int32_t>(), st);
+    const bool fused = want_green && h->plan_state == 1;
+    if (want_green) {
+        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
+        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
+        if (fused) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
+    }
+    vtm::launch_factor(dev_sym(h), dev_sub(h), P.nsub, h->max_front, h->d_aval.as<double>(),
+                       h->d_invz64.as<double>(), h->d_vals64.as<double>(), ws.as<double>(),
+                       h->d_status.as<int32_t>(), dev_green(h, fused), h->d_goff.as<int64_t>(),
+                       want_green ? h->d_G64.as<double>() : nullptr, st);
     if (h->fp32()) {
         HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
         vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
     }
     h->have_green = false;
     if (want_green) {
-        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
-        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
-        if (h->plan_state == 1) {
-            HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
-            vtm::launch_green_mf(dev_sym(h), dev_sub(h), dev_green(h), P.nsub, h->d_vals64.as<double>(),
-                                 h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
-        } else {
+        if (!fused)
             vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p,
                               h->d_vals64.as<double>(), h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
-        }
         if (h->fp32()) {
             HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 4)));
             vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);

@@ -1,9 +1,10 @@
 // HIP kernels of libvtm for gfx950 (CDNA4, 64-wide wavefronts).
 //
 //  k_factor   one workgroup per subgraph: multifrontal Cholesky of the
-//             port-augmented matrix K_k of eq. (5.8), front by front in
-//             level order; the diagonal block of every supernode is stored
-//             inverted so that the sweep has no long sequential chains.
+//             port-augmented matrix K_k of eq. (5.8), level by level; the
+//             diagonal block of every supernode is stored inverted so that the
+//             sweep has no long sequential chains.  Optionally also the port
+//             Green's functions G_k used by the port-reduced sweep (k_schur).
 //  k_sweep    one workgroup per (subgraph, group of right-hand sides): one VTM
 //             sweep (Table 1 steps 3-5).  Gathers the incoming waves from the
 //             twins' outgoing waves of the previous sweep (the delay of (5.6)),
@@ -13,6 +14,8 @@
 //  k_split / k_merge / k_residual: source split b_v/|S(v)|, merged potentials
 //             (mean over the children) and the FP64 relative residual.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernels.hpp"
 
@@ -40,17 +43,27 @@ __global__ void k_to_f32(const double *__restrict__ s, float *__restrict__ d, in
 
 // ---------------------------------------------------------------- factorisation
 //
-// Per supernode s (front F of order f = nc + m in LDS, row-major; only its lower triangle carries
-// the matrix, so the strictly upper part of the leading nc x nc block and the nc x m block to its
-// right serve as scratch):
+// One workgroup per subgraph walks the assembly tree level by level.  A level whose fronts are
+// small is spread over the waves (one supernode per wave at a time, wave-level synchronisation
+// only); otherwise the whole workgroup takes its supernodes one after the other.  Per supernode s
+// (front F of order f = nc + m in LDS, row-major; only its lower triangle carries the matrix, so the
+// strictly upper part of the leading nc x nc block and the nc x m block to its right are scratch):
 //   1. assemble: local entries, the port diagonal Z^{-1}, the children's update matrices;
 //   2. L11 = chol(F11) in place (one wave when nc <= kWaveChol, else the workgroup);
-//   3. Linv = L11^{-1}, column j by thread j, strictly lower part stored transposed in the upper
-//      triangle (Linv[i][j] at F[j][i]; the diagonal is 1 / L11[j][j]);
+//   3. Linv = L11^{-1}, column j by one thread: strictly lower part stored transposed in the upper
+//      triangle (Linv[i][j] at F[j][i]); the diagonal is 1 / L11[j][j];
 //   4. L21 = F21 L11^{-T}, stored transposed in the upper-right block (L21[q][t] at F[t][nc + q]);
 //   5. outputs Linv and W = L21 Linv, and the update matrix F22 - L21 L21^T written straight to
 //      the workspace (lower triangle); the rank-nc update runs on the FP64 matrix cores in 16 x 16
-//      tiles when m >= 16.
+//      tiles when m >= 16;
+//   6. (port Green's functions) the forward substitution of all port columns through s, while
+//      Linv and L21 are still in LDS: with E the unit columns of the port vertices, Y = L^{-1} E
+//      and G_k = E^T K_k^{-1} E = Y^T Y.  Column j of Y is non-zero only on the supernodes above
+//      the one holding port j, so s carries just the w_s ports below it (a contiguous range, see
+//      DevGreen).  Its port front T_s ((nc + m) x w_s, workspace) holds the unit entries of its
+//      own ports and what the children pushed; Y_s = Linv T_s, the update T_s[nc:] - L21 Y_s goes
+//      into the parent's port front (siblings own disjoint columns: plain stores), and
+//      G[ports of s, ports of s] += Y_s^T Y_s on the matrix cores (siblings own disjoint blocks).
 constexpr int kWaveChol = 48;
 
 __device__ inline void wave_sync() {
@@ -58,28 +71,257 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+template <bool BLK>
+__device__ inline void team_sync() {
+    if (BLK) __syncthreads();
+    else wave_sync();
+}
+
+// Lower-triangle tile (ta, tb <= ta) of tile number it in row-major triangular order.
+__device__ inline void tri_tile(int it, int &ta, int &tb) {
+    ta = (int)((sqrtf(8.0f * (float)it + 1.0f) - 1.0f) * 0.5f);
+    while (ta * (ta + 1) / 2 > it) --ta;
+    while ((ta + 1) * (ta + 2) / 2 <= it) ++ta;
+    tb = it - ta * (ta + 1) / 2;
+}
+
+// 16 x 16 tile (ta, tb) of P^T P for P (K x n) read through ld(t, col): v_mfma_f64_16x16x4, where
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 j + l / 16][l % 16].
+template <typename LD>
+__device__ inline f64x4 gram_tile(int ta, int tb, int K, int n, int lane, LD ld) {
+    const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15), kr = lane >> 4;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < K; t0 += 4) {
+        const int t = t0 + kr;
+        const double av = (t < K && ra < n) ? ld(t, ra) : 0.0;
+        const double bv = (t < K && rb < n) ? ld(t, rb) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+struct FactorArgs {
+    const double *A;       // local CSR values of the subgraph
+    double *V;             // factor values of the subgraph
+    double *W;             // update-matrix workspace of the subgraph
+    const double *dplus;   // port diagonal per factor position
+    const int32_t *sn_c0, *sn_nc, *sn_m, *sn_val, *sn_uoff, *sn_ridx;
+    const int32_t *ch_ptr, *ch_idx, *sc_ptr, *sc_src, *sc_dst;
+    const uint16_t *rel;
+    // port Green's functions (gpl == nullptr: not computed)
+    const int4 *gpl;
+    double *gws;
+    const uint16_t *perm;
+    double *Gk;
+    int ldp;
+};
+
+// Supernode s by a team of n threads (this thread has rank r; wv / nw: its wave in the team and
+// the team's waves); F is the team's LDS front.
+template <bool BLK>
+__device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n, int wv, int nw, int *sbad) {
+    const int lane = threadIdx.x & 63;
+    const int c0 = X.sn_c0[s], nc = X.sn_nc[s], m = X.sn_m[s], f = nc + m;
+    // 1. assembly
+    for (int i = r; i < f * f; i += n) F[i] = 0.0;
+    team_sync<BLK>();
+    for (int e = X.sc_ptr[s] + r; e < X.sc_ptr[s + 1]; e += n) F[X.sc_dst[e]] = X.A[X.sc_src[e]];
+    team_sync<BLK>();
+    for (int j = r; j < nc; j += n) F[j * f + j] += X.dplus[c0 + j];
+    for (int q = X.ch_ptr[s]; q < X.ch_ptr[s + 1]; ++q) {  // children one at a time (they share rows)
+        team_sync<BLK>();
+        const int c = X.ch_idx[q], mc = X.sn_m[c];
+        const double *U = X.W + X.sn_uoff[c];
+        const uint16_t *rc = X.rel + X.sn_ridx[c];
+        for (int idx = r; idx < mc * mc; idx += n) {
+            const int a = idx / mc, b = idx - a * mc;
+            if (b <= a) F[rc[a] * f + rc[b]] += U[idx];
+        }
+    }
+    team_sync<BLK>();
+    // 2. Cholesky of the diagonal block (right-looking)
+    if (!BLK || nc <= kWaveChol) {
+        if (!BLK || wv == 0) {
+            for (int kk = 0; kk < nc; ++kk) {
+                double d = F[kk * f + kk];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    if (lane == 0) atomicMin(sbad, s + 1);
+                    d = 1.0;
+                }
+                const double sd = sqrt(d), rs = 1.0 / sd;
+                wave_sync();
+                for (int i = kk + 1 + lane; i < nc; i += 64) F[i * f + kk] *= rs;
+                if (lane == 0) F[kk * f + kk] = sd;
+                wave_sync();
+                const int T = nc - kk - 1;
+                for (int idx = lane; idx < T * T; idx += 64) {
+                    const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
+                    if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
+                }
+                wave_sync();
+            }
+        }
+    } else {
+        for (int kk = 0; kk < nc; ++kk) {
+            double d = F[kk * f + kk];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (r == 0) atomicMin(sbad, s + 1);
+                d = 1.0;
+            }
+            const double sd = sqrt(d), rs = 1.0 / sd;
+            __syncthreads();
+            for (int i = kk + 1 + r; i < nc; i += n) F[i * f + kk] *= rs;
+            if (r == 0) F[kk * f + kk] = sd;
+            __syncthreads();
+            const int T = nc - kk - 1;
+            for (int idx = r; idx < T * T; idx += n) {
+                const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
+                if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
+            }
+            __syncthreads();
+        }
+    }
+    team_sync<BLK>();
+    // 3. Linv[i][j] = -(sum_{j <= t < i} L[i][t] Linv[t][j]) / L[i][i]
+    for (int j = r; j < nc; j += n) {
+        const double djj = 1.0 / F[j * f + j];
+        for (int i = j + 1; i < nc; ++i) {
+            double acc = F[i * f + j] * djj;
+            for (int t = j + 1; t < i; ++t) acc += F[i * f + t] * F[j * f + t];
+            F[j * f + i] = -acc / F[i * f + i];
+        }
+    }
+    team_sync<BLK>();
+    // 4. L21[q][t] = sum_{u <= t} F21[q][u] Linv[t][u]
+    for (int idx = r; idx < m * nc; idx += n) {
+        const int q = idx / nc, t = idx - q * nc;
+        const double *row = F + (nc + q) * f;
+        double acc = row[t] / F[t * f + t];
+        for (int u = 0; u < t; ++u) acc += row[u] * F[u * f + t];
+        F[t * f + nc + q] = acc;
+    }
+    team_sync<BLK>();
+    // 5. outputs
+    double *Vs = X.V + X.sn_val[s];
+    for (int idx = r; idx < nc * nc; idx += n) {
+        const int i = idx / nc, j = idx - i * nc;
+        Vs[idx] = j > i ? 0.0 : (j == i ? 1.0 / F[i * f + i] : F[j * f + i]);
+    }
+    for (int idx = r; idx < m * nc; idx += n) {  // W[q][j] = sum_{t >= j} L21[q][t] Linv[t][j]
+        const int q = idx / nc, j = idx - q * nc;
+        double acc = F[j * f + nc + q] / F[j * f + j];
+        for (int t = j + 1; t < nc; ++t) acc += F[t * f + nc + q] * F[j * f + t];
+        Vs[nc * nc + idx] = acc;
+    }
+    double *Us = X.W + X.sn_uoff[s];
+    if (m >= 16) {  // update = F22 - L21 L21^T, L21^T read from the upper-right block
+        const int tm = (m + 15) >> 4, kr = lane >> 4;
+        for (int it = wv; it < tm * (tm + 1) / 2; it += nw) {
+            int ta, tb;
+            tri_tile(it, ta, tb);
+            const f64x4 acc = gram_tile(ta, tb, nc, m, lane, [&](int t, int a) { return F[t * f + nc + a]; });
+            const int b = 16 * tb + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int a = 16 * ta + 4 * j + kr;
+                if (a < m && b < m && b <= a) Us[a * m + b] = F[(nc + a) * f + nc + b] - acc[j];
+            }
+        }
+    } else {
+        for (int idx = r; idx < m * m; idx += n) {
+            const int a = idx / m, b = idx - a * m;
+            if (b > a) continue;
+            double acc = F[(nc + a) * f + nc + b];
+            for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + a] * F[t * f + nc + b];
+            Us[idx] = acc;
+        }
+    }
+    // 6. port Green's functions through s
+    if (X.gpl) {
+        const int4 e = X.gpl[s];
+        const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
+        if (w > 0) {
+            const double *T = X.gws + e.x;
+            double *Y = X.gws + e.x + (int64_t)f * w;
+            for (int idx = r; idx < nc * w; idx += n) {  // Y = Linv T
+                const int i = idx / w, a = idx - i * w;
+                double acc = T[i * w + a] / F[i * f + i];
+                for (int t = 0; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
+                Y[idx] = acc;
+            }
+            team_sync<BLK>();
+            const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
+            const uint16_t *rs_ = X.rel + X.sn_ridx[s];
+            for (int idx = r; idx < m * w; idx += n) {  // T[nc:] - L21 Y into the parent's port front
+                const int q = idx / w, a = idx - q * w;
+                double acc = T[(nc + q) * w + a];
+                for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + q] * Y[t * w + a];
+                X.gws[e.z + (int64_t)rs_[q] * pw + a + (pc0 - ppc0)] = acc;
+            }
+            const int tw = (w + 15) >> 4, kr = lane >> 4;
+            for (int it = wv; it < tw * (tw + 1) / 2; it += nw) {  // G += Y^T Y
+                int ta, tb;
+                tri_tile(it, ta, tb);
+                const f64x4 acc = gram_tile(ta, tb, nc, w, lane, [&](int t, int a) { return Y[t * w + a]; });
+                const int b = 16 * tb + (lane & 15);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int a = 16 * ta + 4 * j + kr;
+                    if (a < w && b < w && b <= a) {
+                        const int ja = X.perm[pc0 + a], jb = X.perm[pc0 + b];
+                        X.Gk[(int64_t)ja * X.ldp + jb] += acc[j];
+                        if (a != b) X.Gk[(int64_t)jb * X.ldp + ja] += acc[j];
+                    }
+                }
+            }
+        }
+    }
+    team_sync<BLK>();
+}
+
 __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const double *__restrict__ aval,
                                                      const double *__restrict__ invz, double *__restrict__ vals,
-                                                     double *__restrict__ ws, int lds_front,
-                                                     int32_t *__restrict__ status) {
+                                                     double *__restrict__ ws, int lds_front, int lds_doubles,
+                                                     int32_t *__restrict__ status, DevGreen Gp,
+                                                     const int64_t *__restrict__ goff, double *__restrict__ G) {
     extern __shared__ double sm[];
+    __shared__ int sbad;
     const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
-    const double *A = aval + D.aval[k];
-    double *V = vals + D.val[k];
-    double *W = ws + D.ws[k];
-    double *dplus = W + C.ws_u + (int64_t)C.max_front * C.max_front;
-    const int32_t *sn_c0 = S.sn_c0 + C.o_sn, *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn;
-    const int32_t *sn_val = S.sn_val + C.o_sn, *sn_uoff = S.sn_uoff + C.o_sn;
-    const int32_t *ch_ptr = S.ch_ptr + C.o_snp, *ch_idx = S.ch_idx + C.o_chi;
-    const int32_t *sc_ptr = S.sc_ptr + C.o_snp, *sc_src = S.sc_src + C.o_sc, *sc_dst = S.sc_dst + C.o_sc;
-    const int32_t *sn_ridx = S.sn_ridx + C.o_sn;
-    const uint16_t *rel = S.rel + C.o_ridx;
-
+    FactorArgs X;
+    X.A = aval + D.aval[k];
+    X.V = vals + D.val[k];
+    X.W = ws + D.ws[k];
+    double *dplus = X.W + C.ws_u + (int64_t)C.max_front * C.max_front;
+    X.dplus = dplus;
+    X.sn_c0 = S.sn_c0 + C.o_sn;
+    X.sn_nc = S.sn_nc + C.o_sn;
+    X.sn_m = S.sn_m + C.o_sn;
+    X.sn_val = S.sn_val + C.o_sn;
+    X.sn_uoff = S.sn_uoff + C.o_sn;
+    X.sn_ridx = S.sn_ridx + C.o_sn;
+    X.ch_ptr = S.ch_ptr + C.o_snp;
+    X.ch_idx = S.ch_idx + C.o_chi;
+    X.sc_ptr = S.sc_ptr + C.o_snp;
+    X.sc_src = S.sc_src + C.o_sc;
+    X.sc_dst = S.sc_dst + C.o_sc;
+    X.rel = S.rel + C.o_ridx;
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
+    X.gpl = nullptr;
+    if (Gp.sn && p > 0) {
+        X.gpl = Gp.sn + Gp.base[k];
+        X.gws = Gp.ws + Gp.wso[k];
+        X.perm = Gp.perm + pg0;
+        X.Gk = G + goff[k];
+        X.ldp = (p + 3) & ~3;
+        for (int a = tid; a < p; a += nt) X.gws[Gp.idoff[pg0 + a]] = 1.0;
+    }
+    const int32_t *col_sn = S.col_sn + C.o_col, *lev_c0 = S.lev_c0 + C.o_lev, *lev_maxf = S.lev_maxf + C.o_lev;
     // diagonal additions Z^{-1} of the ports, one thread per port vertex (ports in order)
     for (int i = tid; i < nk; i += nt) dplus[i] = 0.0;
+    if (tid == 0) sbad = 0x7FFFFFFF;
     __syncthreads();
     for (int g = D.pg_ptr[k] + tid; g < D.pg_ptr[k + 1]; g += nt) {
         double s = 0.0;
@@ -87,133 +329,19 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
         dplus[D.pg_pos[g]] = s;
     }
     __syncthreads();
-    int bad = 0;
-    for (int s = 0; s < C.nsn; ++s) {
-        const int c0 = sn_c0[s], nc = sn_nc[s], m = sn_m[s], f = nc + m;
-        double *F = lds_front ? sm : W + C.ws_u;
-        // 1. assembly
-        for (int i = tid; i < f * f; i += nt) F[i] = 0.0;
-        __syncthreads();
-        for (int e = sc_ptr[s] + tid; e < sc_ptr[s + 1]; e += nt) F[sc_dst[e]] = A[sc_src[e]];
-        __syncthreads();
-        for (int j = tid; j < nc; j += nt) F[j * f + j] += dplus[c0 + j];
-        for (int q = ch_ptr[s]; q < ch_ptr[s + 1]; ++q) {  // children one at a time (they share rows)
+    for (int lv = 0; lv < C.nlev; ++lv) {
+        const int s0 = col_sn[lev_c0[lv]], s1 = lv + 1 < C.nlev ? col_sn[lev_c0[lv + 1]] : C.nsn;
+        const int mf = lev_maxf[lv];
+        if (s1 - s0 > 1 && nw * mf * mf <= lds_doubles) {
+            double *F = sm + wv * mf * mf;
+            for (int s = s0 + wv; s < s1; s += nw) factor_node<false>(X, s, F, lane, 64, 0, 1, &sbad);
             __syncthreads();
-            const int c = ch_idx[q], mc = sn_m[c];
-            const double *U = W + sn_uoff[c];
-            const uint16_t *rc = rel + sn_ridx[c];
-            for (int idx = tid; idx < mc * mc; idx += nt) {
-                const int a = idx / mc, b = idx - a * mc;
-                if (b <= a) F[rc[a] * f + rc[b]] += U[idx];
-            }
-        }
-        __syncthreads();
-        // 2. Cholesky of the diagonal block (right-looking)
-        if (nc <= kWaveChol) {
-            if (wv == 0) {
-                for (int kk = 0; kk < nc; ++kk) {
-                    double d = F[kk * f + kk];
-                    if (!(d > 0.0) || !isfinite(d)) { bad = bad ? bad : s + 1; d = 1.0; }
-                    const double sd = sqrt(d), rs = 1.0 / sd;
-                    wave_sync();
-                    for (int i = kk + 1 + lane; i < nc; i += 64) F[i * f + kk] *= rs;
-                    if (lane == 0) F[kk * f + kk] = sd;
-                    wave_sync();
-                    const int T = nc - kk - 1;
-                    for (int idx = lane; idx < T * T; idx += 64) {
-                        const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
-                        if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
-                    }
-                    wave_sync();
-                }
-            }
         } else {
-            for (int kk = 0; kk < nc; ++kk) {
-                double d = F[kk * f + kk];
-                if (!(d > 0.0) || !isfinite(d)) { bad = bad ? bad : s + 1; d = 1.0; }
-                const double sd = sqrt(d), rs = 1.0 / sd;
-                __syncthreads();
-                for (int i = kk + 1 + tid; i < nc; i += nt) F[i * f + kk] *= rs;
-                if (tid == 0) F[kk * f + kk] = sd;
-                __syncthreads();
-                const int T = nc - kk - 1;
-                for (int idx = tid; idx < T * T; idx += nt) {
-                    const int i = kk + 1 + idx / T, j = kk + 1 + idx % T;
-                    if (j <= i) F[i * f + j] -= F[i * f + kk] * F[j * f + kk];
-                }
-                __syncthreads();
-            }
+            double *F = lds_front ? sm : X.W + C.ws_u;
+            for (int s = s0; s < s1; ++s) factor_node<true>(X, s, F, tid, nt, wv, nw, &sbad);
         }
-        __syncthreads();
-        // 3. Linv, column j by thread j: Linv[i][j] = -(sum_{j <= t < i} L[i][t] Linv[t][j]) / L[i][i]
-        for (int j = tid; j < nc; j += nt) {
-            const double djj = 1.0 / F[j * f + j];
-            for (int i = j + 1; i < nc; ++i) {
-                double acc = F[i * f + j] * djj;
-                for (int t = j + 1; t < i; ++t) acc += F[i * f + t] * F[j * f + t];
-                F[j * f + i] = -acc / F[i * f + i];
-            }
-        }
-        __syncthreads();
-        // 4. L21[q][t] = sum_{u <= t} F21[q][u] Linv[t][u]
-        for (int idx = tid; idx < m * nc; idx += nt) {
-            const int q = idx / nc, t = idx - q * nc;
-            const double *row = F + (nc + q) * f;
-            double acc = row[t] / F[t * f + t];
-            for (int u = 0; u < t; ++u) acc += row[u] * F[u * f + t];
-            F[t * f + nc + q] = acc;
-        }
-        __syncthreads();
-        // 5. outputs
-        double *Vs = V + sn_val[s];
-        for (int idx = tid; idx < nc * nc; idx += nt) {
-            const int i = idx / nc, j = idx - i * nc;
-            Vs[idx] = j > i ? 0.0 : (j == i ? 1.0 / F[i * f + i] : F[j * f + i]);
-        }
-        for (int idx = tid; idx < m * nc; idx += nt) {  // W[q][j] = sum_{t >= j} L21[q][t] Linv[t][j]
-            const int q = idx / nc, j = idx - q * nc;
-            double acc = F[j * f + nc + q] / F[j * f + j];
-            for (int t = j + 1; t < nc; ++t) acc += F[t * f + nc + q] * F[j * f + t];
-            Vs[nc * nc + idx] = acc;
-        }
-        double *Us = W + sn_uoff[s];
-        if (m >= 16) {
-            // update = F22 - L21 L21^T on the matrix cores: wave per 16 x 16 tile (ta, tb <= ta).
-            // v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16], B[l / 16][l % 16] and holds
-            // D[4 j + l / 16][l % 16]; A[a][t] = B[t][a] = L21[a][t] = F[t][nc + a].
-            const int tm = (m + 15) >> 4, ntile = tm * (tm + 1) / 2;
-            const int kr = lane >> 4;
-            for (int it = wv; it < ntile; it += nw) {
-                int ta = (int)((sqrtf(8.0f * (float)it + 1.0f) - 1.0f) * 0.5f);
-                while (ta * (ta + 1) / 2 > it) --ta;
-                while ((ta + 1) * (ta + 2) / 2 <= it) ++ta;
-                const int tb = it - ta * (ta + 1) / 2;
-                const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15);
-                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-                for (int t0 = 0; t0 < nc; t0 += 4) {
-                    const int t = t0 + kr;
-                    const double av = (t < nc && ra < m) ? F[t * f + nc + ra] : 0.0;
-                    const double bv = (t < nc && rb < m) ? F[t * f + nc + rb] : 0.0;
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int a = 16 * ta + 4 * j + kr;
-                    if (a < m && rb < m && rb <= a) Us[a * m + rb] = F[(nc + a) * f + nc + rb] - acc[j];
-                }
-            }
-        } else {
-            for (int idx = tid; idx < m * m; idx += nt) {
-                const int a = idx / m, b = idx - a * m;
-                if (b > a) continue;
-                double acc = F[(nc + a) * f + nc + b];
-                for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + a] * F[t * f + nc + b];
-                Us[idx] = acc;
-            }
-        }
-        __syncthreads();
     }
-    if (tid == 0) status[k] = bad;
+    if (tid == 0) status[k] = sbad == 0x7FFFFFFF ? 0 : sbad;
 }
 
 // ------------------------------------------------------------------------ split
@@ -449,112 +577,6 @@ __global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double 
     }
 }
 
-// Largest s in [s0, s1) with pre[s] <= it (the owner of flat item it; empty supernodes never win).
-__device__ inline int owner(const int32_t *__restrict__ pre, int s0, int s1, int it) {
-    int lo = s0, hi = s1 - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= it) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Port Green's functions by multifrontal forward substitution, one workgroup per subgraph, FP64.
-// With E the unit columns of the port vertices, Y = L^{-1} E and G_k = E^T K^{-1} E = Y^T Y.  Column
-// j of Y is non-zero only on the supernodes above the one holding port j, so supernode s carries
-// just the w_s ports below it (a contiguous range, see DevGreen).  Its front F_s is (nc + m) x w_s
-// (row-major, zero on entry except the unit entries of its own ports and what the children pushed)
-// and Y_s (nc x w_s) follows it in the workspace.  Level by level:
-//   phase 1  Y_s = Linv_s T_s (T_s = first nc rows of F_s); the update F_s[nc:] - W_s T_s goes into
-//            the parent's front (rows by rel, columns shifted by the range offset; siblings own
-//            disjoint columns, so these are plain stores);
-//   phase 2  G[ports of s, ports of s] += Y_s^T Y_s (siblings own disjoint blocks of G), a
-//            symmetric rank-nc update done by FP64 MFMA, 16 x 16 tiles of the lower triangle.
-// Work items (phase 1) and tiles (phase 2) of a level are numbered across its supernodes through
-// the prefixes py / pq.
-__global__ __launch_bounds__(256) void k_green_mf(DevSym S, DevSub D, DevGreen Gp, const double *__restrict__ vals,
-                                                  const int64_t *__restrict__ goff, double *__restrict__ G) {
-    const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
-    if (p == 0) return;
-    const ClassDev C = S.cls[D.cls[k]];
-    const int32_t *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn, *sn_val = S.sn_val + C.o_sn;
-    const int32_t *sn_ridx = S.sn_ridx + C.o_sn;
-    const int32_t *col_sn = S.col_sn + C.o_col, *lev_c0 = S.lev_c0 + C.o_lev;
-    const uint16_t *rel = S.rel + C.o_ridx;
-    const int b0 = Gp.base[k];
-    const int4 *pl = Gp.sn + b0;
-    const int32_t *py = Gp.py + b0, *pq = Gp.pq + b0;
-    const uint16_t *perm = Gp.perm + pg0;
-    double *ws = Gp.ws + Gp.wso[k];
-    const double *Vk = vals + D.val[k];
-    double *Gk = G + goff[k];
-    const int ldp = (p + 3) & ~3;
-    for (int a = tid; a < p; a += nt) ws[Gp.idoff[pg0 + a]] = 1.0;
-    __syncthreads();
-    for (int lv = 0; lv < C.nlev; ++lv) {
-        const int s0 = col_sn[lev_c0[lv]], s1 = lv + 1 < C.nlev ? col_sn[lev_c0[lv + 1]] : C.nsn;
-        for (int it = py[s0] + tid; it < py[s1]; it += nt) {
-            const int s = owner(py, s0, s1, it);
-            const int4 e = pl[s];
-            const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
-            const int nc = sn_nc[s], m = sn_m[s];
-            const int loc = it - py[s], i = loc / w, a = loc - i * w;
-            const double *F = ws + e.x;
-            const double *V = Vk + sn_val[s];
-            if (i < nc) {
-                double acc = 0.0;
-                for (int t = 0; t <= i; ++t) acc += V[i * nc + t] * F[t * w + a];
-                ws[e.x + (nc + m) * w + i * w + a] = acc;
-            } else {
-                const int q = i - nc;
-                const double *Wq = V + nc * nc + q * nc;
-                double acc = F[i * w + a];
-                for (int t = 0; t < nc; ++t) acc -= Wq[t] * F[t * w + a];
-                const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
-                ws[e.z + (int)rel[sn_ridx[s] + q] * pw + a + (pc0 - ppc0)] = acc;
-            }
-        }
-        __syncthreads();
-        // phase 2 on the FP64 matrix cores: one wave per 16 x 16 tile (ta, tb <= ta) of Y_s^T Y_s.
-        // v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
-        // D[4 j + l / 16][l % 16] in acc[j]; here A[a][i] = Y[i][a], B[i][b] = Y[i][b].
-        for (int it = pq[s0] + wv; it < pq[s1]; it += nw) {
-            const int s = owner(pq, s0, s1, it);
-            const int4 e = pl[s];
-            const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
-            const int nc = sn_nc[s], m = sn_m[s];
-            const int loc = it - pq[s];
-            int ta = (int)((sqrtf(8.0f * (float)loc + 1.0f) - 1.0f) * 0.5f);
-            while (ta * (ta + 1) / 2 > loc) --ta;
-            while ((ta + 1) * (ta + 2) / 2 <= loc) ++ta;
-            const int tb = loc - ta * (ta + 1) / 2;
-            const double *Y = ws + e.x + (nc + m) * w;
-            const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15), kr = lane >> 4;
-            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int i0 = 0; i0 < nc; i0 += 4) {
-                const int i = i0 + kr;
-                const double av = (i < nc && ra < w) ? Y[i * w + ra] : 0.0;
-                const double bv = (i < nc && rb < w) ? Y[i * w + rb] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-            }
-            const int b = rb;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int a = 16 * ta + 4 * j + kr;
-                if (a < w && b < w && (ta != tb || b <= a)) {
-                    const int ja = perm[pc0 + a], jb = perm[pc0 + b];
-                    Gk[(int64_t)ja * ldp + jb] += acc[j];
-                    if (a != b) Gk[(int64_t)jb * ldp + ja] += acc[j];
-                }
-            }
-        }
-        // the next level's phase-1 barrier orders these G updates before the parents' ones
-    }
-}
-
 // c[g][q][c] = K^{-1} b~ at the port vertices (local solutions of a zero-wave solve).
 template <typename T>
 __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
@@ -766,15 +788,17 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
     hipLaunchKernelGGL(k_invz, dim3(blocks_for(nports, 256)), dim3(256), 0, st, z_vtl, port_vtl, invz64, invz32, nports);
 }
 
-void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_front,
-                   const double *aval, const double *invz, double *vals, double *ws, int64_t, int32_t *status,
-                   hipStream_t st) {
-    (void)max_nk;
-    const size_t front = sizeof(double) * (size_t)max_front * max_front;
-    const int lds_front = front <= 96 * 1024;
-    const size_t shm = lds_front ? front : 0;
+void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
+                   const double *invz, double *vals, double *ws, int32_t *status, const DevGreen &Gp,
+                   const int64_t *goff, double *G, hipStream_t st) {
+    // the workgroup's front (in the workspace when larger than 96 KiB), or four per-wave fronts of
+    // order <= 24 on the lower levels
+    const int lds_front = max_front * max_front <= 96 * 1024 / 8;
+    const int lds_doubles = std::max(lds_front ? max_front * max_front : 0, 4 * 24 * 24);
+    const size_t shm = sizeof(double) * (size_t)lds_doubles;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_front, status);
+    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_front, lds_doubles,
+                       status, Gp, goff, G);
 }
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {
@@ -843,11 +867,6 @@ void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk
     const dim3 grid(nsub, (max_p + 3) / 4);
     if (V) hipLaunchKernelGGL(k_green<1>, grid, dim3(256), shm, st, S, D, vals, goff, G);
     else hipLaunchKernelGGL(k_green<0>, grid, dim3(256), shm, st, S, D, vals, goff, G);
-}
-
-void launch_green_mf(const DevSym &S, const DevSub &D, const DevGreen &Gp, int32_t nsub, const double *vals,
-                     const int64_t *goff, double *G, hipStream_t st) {
-    hipLaunchKernelGGL(k_green_mf, dim3(nsub), dim3(256), 0, st, S, D, Gp, vals, goff, G);
 }
 
 template <typename T>

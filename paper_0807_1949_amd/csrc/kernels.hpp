@@ -26,6 +26,7 @@ struct ClassDev {
 struct DevSym {
     const ClassDev *cls;
     const int32_t *lev_c0, *col_sn;
+    const int32_t *lev_maxf;        // largest front of each level (lev offsets)
     const int32_t *sn_c0, *sn_nc, *sn_m, *sn_val, *sn_ridx, *sn_uoff;
     const uint16_t *ridx, *rel;
     const int32_t *ch_ptr, *ch_idx;
@@ -49,19 +50,17 @@ struct DevSub {
     const int32_t *pg_cnt;   // ports in the group
 };
 
-// Column plan of the port Green's functions by one multifrontal forward substitution with all port
-// columns (k_green_mf).  Ports of a subgraph are sorted by the postorder of their supernode, so the
-// ports below supernode s form one column range [pc0, pc0 + w) and a child's range lies inside its
-// parent's.  Plan entries of subgraph k start at base[k] (nsn + 1 entries, the last only for the prefixes).
+// Column plan of the port Green's functions computed inside the factorisation.  Ports of a subgraph
+// are sorted by the postorder of their supernode, so the ports below supernode s form one column
+// range [pc0, pc0 + w) and a child's range lies inside its parent's.  Plan entries of subgraph k
+// start at base[k] (one per supernode).  sn == nullptr: no Green's functions.
 struct DevGreen {
-    const int4 *sn;         // {front offset, pc0 | w << 16, parent front offset, parent pc0 | parent w << 16}
-    const int32_t *py;      // exclusive prefix of the phase-1 items (nc + m) * w
-    const int32_t *pq;      // exclusive prefix of the phase-2 tiles t (t + 1) / 2, t = ceil(w / 16)
+    const int4 *sn;         // {port-front offset, pc0 | w << 16, parent's port-front offset, parent pc0 | parent w << 16}
     const int32_t *base;    // first plan entry of each subgraph
     const int64_t *wso;     // workspace offset of each subgraph (doubles)
     const int32_t *idoff;   // per sorted port: workspace offset of its unit right-side entry
     const uint16_t *perm;   // per sorted port: its port-vertex index in the subgraph
-    double *ws;             // fronts and Y blocks, zero on entry
+    double *ws;             // port fronts (nc + m) x w followed by Y blocks nc x w; zero on entry
 };
 
 // Split-vector and merge maps.
@@ -82,10 +81,11 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
                  hipStream_t st);
 
 // FP64 multifrontal factorisation of every port-augmented local matrix; status[k] = 1 + supernode of the
-// first non-positive pivot (0 if fine).  lds_front selects LDS-resident fronts.
-void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_front,
-                   const double *aval, const double *invz, double *vals, double *ws, int64_t ws_front_off_stride,
-                   int32_t *status, hipStream_t st);
+// first non-positive pivot (0 if fine).  With Gp.sn set it also accumulates the port Green's functions
+// G_k = R K_k^{-1} R^T (FP64, p_k x ldp_k row-major at goff[k], zero on entry).
+void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
+                   const double *invz, double *vals, double *ws, int32_t *status, const DevGreen &Gp,
+                   const int64_t *goff, double *G, hipStream_t st);
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 
@@ -103,12 +103,10 @@ constexpr int kSweepWriteX = 1, kSweepNoWaves = 2, kSweepZeroWaves = 4;  // swee
 template <typename T>
 hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R);
 
-// Port Green's functions G_k = R K_k^{-1} R^T (FP64, p_k x p_k row-major at goff[k]).
+// Port Green's functions G_k = R K_k^{-1} R^T by one substitution per group of four port columns
+// (FP64, p_k x ldp_k row-major at goff[k]); used when the column plan does not apply.
 void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
                   const double *vals, const int64_t *goff, double *G, hipStream_t st);
-// The same G_k by Y = L^{-1} R^T (one forward substitution with all port columns) and G = Y^T Y.
-void launch_green_mf(const DevSym &S, const DevSub &D, const DevGreen &Gp, int32_t nsub, const double *vals,
-                     const int64_t *goff, double *G, hipStream_t st);
 // cport[g][port vertex][R] = local solutions at the port vertices.
 template <typename T>
 void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,

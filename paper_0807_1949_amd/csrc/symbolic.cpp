@@ -261,6 +261,9 @@ int analyse(const Partition &P, int32_t k, int leaf, ClassSym &C, std::string &e
         C.max_front = std::max<int32_t>(C.max_front, (int32_t)(nc + m));
         for (int32_t i : Rn[t]) C.ridx.push_back((uint16_t)i);
     }
+    C.lev_maxf.assign(C.nlev + 1, 0);
+    for (int32_t t = 0; t < nb; ++t)
+        C.lev_maxf[C.sn_level[t]] = std::max<int32_t>(C.lev_maxf[C.sn_level[t]], C.sn_nc[t] + C.sn_m[t]);
     if (val > INT32_MAX || uo > INT32_MAX) { err = "local factor too large"; return VTM_ERR_PARTITION; }
     C.nval = val;
     C.ws_u = uo;

@@ -57,6 +57,7 @@ struct ClassSym {
     int32_t nsn = 0, nlev = 0;
     std::vector<int32_t> sn_c0, sn_nc, sn_m, sn_val, sn_ridx, sn_parent, sn_level, sn_uoff;
     std::vector<int32_t> lev_c0;     // column range of each level (nlev + 1)
+    std::vector<int32_t> lev_maxf;   // largest front order nc + m of each level (nlev + 1, last 0)
     std::vector<int32_t> col_sn;     // supernode of each factor column
     std::vector<uint16_t> ridx;      // R_s rows (factor positions), concatenated
     std::vector<uint16_t> rel;       // position of each R_s row inside the parent's front
