@@ -62,6 +62,25 @@ def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warm
     return out
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of the sweep kernel from the committed counter summary, or None when the
+    kernels' source has changed since the counters were taken (or the kernel is another one)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_schur_traffic_c2_lognormal_1024.md")
+    if kernel != "k_schur" or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0].strip() in ("kernels-source-sha256", "k_schur-traffic-bytes-per-launch"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_0807_1949_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernels-source-sha256"):
+        return None
+    return float(fields["k_schur-traffic-bytes-per-launch"])
+
+
 def cpu_baseline(O, A, spec, b, z):
     """Oracle (plain FP64 C, OpenMP) on a bounded sample: a few sweeps of the same system."""
     P = O.Partition(A, spec)
@@ -147,6 +166,7 @@ def main():
     value = A.n * nrhs * sweeps / head["step_s"]
     sweep_s = st["sweep_ms"] / 1e3 / max(sweeps, 1)
     achieved = st["bytes_per_sweep"] / sweep_s / 1e9
+    kernel = "k_schur" if st["sweep_mode"] == 2 else "k_sweep"
     line = dict(
         metric="time to rel. residual 1e-8 (s) & unknown-updates/s; learned-Z vs plain VTM",
         value=value, unit="unknown-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -163,8 +183,8 @@ def main():
                           relres=r["relres"], status=r["status"],
                           sweep_mode=r["stats"]["sweep_mode"])
                   for v, r in results.items()},
-        roofline=dict(kernel="k_schur" if st["sweep_mode"] == 2 else "k_sweep", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=None,
+        roofline=dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(kernel),
                       bytes_per_launch=st["bytes_per_sweep"], avg_launch_us=sweep_s * 1e6),
     )
     if len(variants) > 1:

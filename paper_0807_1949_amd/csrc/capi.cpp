@@ -69,8 +69,9 @@ struct vtm_ctx {
     DevBuf d_segu, d_usn, d_levu, d_colrec, d_urec;
     // port-reduced sweeps
     DevBuf d_goff, d_G64, d_G32, d_cport;
-    int32_t max_p = 0, npg = 0;
-    int64_t total_g = 0;
+    int32_t max_p = 0, npg = 0, max_np = 0;
+    int64_t total_g = 0;   // stored entries of all packed G_k
+    double total_pp = 0;   // sum of p_k^2 (entries of the full G_k)
     bool have_green = false;
     // column plan of the multifrontal Green's-function computation (built on first use)
     DevBuf d_gsn, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws, d_levmaxf;
@@ -82,7 +83,7 @@ struct vtm_ctx {
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
         d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
     // subgraph level
-    DevBuf d_subcls, d_subval, d_subx, d_subaval, d_subws, d_pgptr, d_pgpos, d_pgbeg, d_pgcnt;
+    DevBuf d_subcls, d_subval, d_subx, d_subaval, d_subws, d_pgptr, d_pgpos, d_pgbeg, d_pgcnt, d_portptr;
     // maps, matrix, ports
     DevBuf d_fvtx, d_fmul, d_cpptr, d_cpidx, d_rp, d_ci, d_v, d_aval, d_twin, d_portvtl, d_chunkrow, d_chunksys,
         d_syschunk;
@@ -117,7 +118,7 @@ struct vtm_ctx {
         DevBuf *list[] = {&d_cls, &d_lev, &d_colsn, &d_snc0, &d_snnc, &d_snm, &d_snval, &d_snridx, &d_snuoff, &d_ridx,
                           &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr, &d_scsrc,
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
-                          &d_pgbeg, &d_pgcnt, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
+                          &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
                           &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
@@ -205,6 +206,7 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     d.pg_pos = h->d_pgpos.as<uint16_t>();
     d.pg_beg = h->d_pgbeg.as<int32_t>();
     d.pg_cnt = h->d_pgcnt.as<int32_t>();
+    d.port_ptr = h->d_portptr.as<int32_t>();
     return d;
 }
 
@@ -428,9 +430,12 @@ vtm_status upload_partition(vtm_ctx *h) {
     {
         std::vector<int64_t> goff(nsub + 1, 0);
         h->max_p = 0;
+        h->total_pp = 0;
         for (int32_t k = 0; k < nsub; ++k) {
-            const int64_t p = pgptr[k + 1] - pgptr[k], ldp = (p + 3) & ~3;
-            goff[k + 1] = goff[k] + p * ldp;
+            // packed symmetric G_k: lower block triangle of 16 x 16 blocks
+            const int64_t p = pgptr[k + 1] - pgptr[k], nb = (p + 15) / 16;
+            goff[k + 1] = goff[k] + nb * (nb + 1) / 2 * 256;
+            h->total_pp += (double)p * (double)p;
             h->max_p = std::max<int32_t>(h->max_p, (int32_t)p);
         }
         h->total_g = goff[nsub];
@@ -482,6 +487,13 @@ vtm_status upload_partition(vtm_ctx *h) {
     UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_colrec, colrec); UP(d_urec, urec); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
     UP(d_subcls, subcls); UP(d_subval, subval); UP(d_subx, subx); UP(d_subaval, subaval); UP(d_subws, subws);
     UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt);
+    {
+        std::vector<int32_t> portptr(nsub + 1);
+        h->max_np = 0;
+        for (int32_t k = 0; k <= nsub; ++k) portptr[k] = (int32_t)P.port_ptr[k];
+        for (int32_t k = 0; k < nsub; ++k) h->max_np = std::max(h->max_np, portptr[k + 1] - portptr[k]);
+        UP(d_portptr, portptr);
+    }
     UP(d_fvtx, fvtx); UP(d_fmul, fmul); UP(d_cpptr, P.s_ptr); UP(d_cpidx, cpidx);
     UP(d_rp, h->A.rp); UP(d_ci, h->A.ci); UP(d_v, h->A.v); UP(d_aval, P.lval);
     UP(d_twin, twin); UP(d_portvtl, portvtl); UP(d_chunkrow, chunkrow); UP(d_chunksys, chunksys);
@@ -567,6 +579,8 @@ T *invz_of(vtm_ctx *h) {
 // Port-reduced sweeps when the Green's functions exist and move no more than twice the factor's bytes.
 bool use_schur(vtm_ctx *h) {
     if (!h->have_green) return false;
+    // the port vectors of a workgroup (R right-hand sides) must fit in LDS
+    if (vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, std::max(1, h->wave_R)) > vtm::kMaxLds) return false;
     if (h->opt.sweep_mode == 2) return true;
     if (h->opt.sweep_mode == 1) return false;
     return (double)h->total_g <= 2.0 * (double)h->total_lower;
@@ -594,10 +608,10 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R, nt = sweep_threads(h);
     HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
     const bool schur = use_schur(h);
-    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, R));
+    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, h->max_np, R));
     auto launch = [&](int cur, bool last) {
         if (schur)
-            vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->max_p, h->npg, h->nports, green_of<T>(h),
+            vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
                                  h->d_goff.as<int64_t>(), h->d_cport.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h),
                                  h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->stream);
         else
@@ -846,7 +860,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     if (schur) {
         h->stats.bytes_per_sweep =
             (double)sizeof(T) * ((double)h->total_g + (double)h->npg * nrhs + 2.0 * (double)h->nports * nrhs);
-        h->stats.flops_per_sweep = 2.0 * nrhs * (double)h->total_g;
+        h->stats.flops_per_sweep = 2.0 * nrhs * h->total_pp;
     } else {
         h->stats.bytes_per_sweep =
             (double)sizeof(T) * ((double)h->total_lower + (double)h->nsplit * nrhs + 2.0 * (double)h->nports * nrhs);
@@ -1218,7 +1232,7 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
     if (h->have_green) cands.push_back({2, 0, 256});
     for (int32_t R = 1; R <= maxR; R *= 2)
         for (const Cand &cd : cands) {
-            const size_t lds = cd.mode == 2 ? 0
+            const size_t lds = cd.mode == 2 ? vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, R)
                              : h->tsize() * (size_t)R * (2 * (size_t)h->max_nk + (cd.var == 2 ? h->max_nu : 0));
             if (lds > 160 * 1024) continue;
             h->opt.rhs_per_block = R;

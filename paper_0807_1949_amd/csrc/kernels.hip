@@ -100,6 +100,15 @@ __device__ inline f64x4 gram_tile(int ta, int tb, int K, int n, int lane, LD ld)
     return acc;
 }
 
+// Position of G[i][j] in the packed symmetric layout of the port-reduced sweep (lower block
+// triangle of 16 x 16 blocks, block column by block column, each block row-major), or -1 for an
+// entry of the strictly upper block triangle (not stored).
+__device__ inline int64_t gpack_index(int nb, int i, int j) {
+    const int I = i >> 4, J = j >> 4;
+    if (I < J) return -1;
+    return ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + (i & 15) * 16 + (j & 15);
+}
+
 struct FactorArgs {
     const double *A;       // local CSR values of the subgraph
     double *V;             // factor values of the subgraph
@@ -113,7 +122,7 @@ struct FactorArgs {
     double *gws;
     const uint16_t *perm;
     double *Gk;
-    int ldp;
+    int nb;  // 16 x 16 blocks per row of the packed G_k
 };
 
 // Supernode s by a team of n threads (this thread has rank r; wv / nw: its wave in the team and
@@ -269,8 +278,9 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
                     const int a = 16 * ta + 4 * j + kr;
                     if (a < w && b < w && b <= a) {
                         const int ja = X.perm[pc0 + a], jb = X.perm[pc0 + b];
-                        X.Gk[(int64_t)ja * X.ldp + jb] += acc[j];
-                        if (a != b) X.Gk[(int64_t)jb * X.ldp + ja] += acc[j];
+                        const int64_t e1 = gpack_index(X.nb, ja, jb), e2 = gpack_index(X.nb, jb, ja);
+                        if (e1 >= 0) X.Gk[e1] += acc[j];
+                        if (a != b && e2 >= 0) X.Gk[e2] += acc[j];
                     }
                 }
             }
@@ -315,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
         X.gws = Gp.ws + Gp.wso[k];
         X.perm = Gp.perm + pg0;
         X.Gk = G + goff[k];
-        X.ldp = (p + 3) & ~3;
+        X.nb = (p + 15) >> 4;
         for (int a = tid; a < p; a += nt) X.gws[Gp.idoff[pg0 + a]] = 1.0;
     }
     const int32_t *col_sn = S.col_sn + C.o_col, *lev_c0 = S.lev_c0 + C.o_lev, *lev_maxf = S.lev_maxf + C.o_lev;
@@ -570,10 +580,13 @@ __global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double 
     __syncthreads();
     trisolve<double, R, V>(C, S, vals + D.val[k], vec, tmp, ubuf);
     double *Gk = G + goff[k];
-    const int ldp = (p + 3) & ~3;  // rows padded to a multiple of 4 (padding stays zero)
+    const int nb = (p + 15) >> 4;
     for (int idx = tid; idx < R * p; idx += nt) {
         const int c = idx / p, q = idx - c * p;
-        if (j0 + c < p) Gk[(int64_t)(j0 + c) * ldp + q] = tmp[D.pg_pos[pg0 + q] * R + c];
+        if (j0 + c < p) {
+            const int64_t e = gpack_index(nb, j0 + c, q);
+            if (e >= 0) Gk[e] = tmp[D.pg_pos[pg0 + q] * R + c];
+        }
     }
 }
 
@@ -591,124 +604,207 @@ __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R,
 }
 
 // Port-reduced sweep: u = c + G (Z^{-1} a) on the port vertices, then o_p = 2 u - a_p.
-// G_k is symmetric and stored with a leading dimension ldp = p rounded up to 4 (zero padded):
-// a thread owns VW consecutive port vertices and reads G[a * ldp + q .. q + VW) with one 16-byte
-// load per column a; column slices of the workgroup are summed through LDS.
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
-template <typename T> __device__ inline T lane(const typename Vec16<T>::type &v, int i);
-template <> __device__ inline float lane<float>(const float4 &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
-template <> __device__ inline double lane<double>(const double2 &v, int i) { return i == 0 ? v.x : v.y; }
+// G_k is symmetric; it is stored as its lower block triangle of 16 x 16 blocks (diagonal blocks in
+// full, rows and columns padded with zeros to nb = ceil(p / 16) blocks), block column by block
+// column (see gpack_index).  Wave w of the workgroup owns the block columns J = 8 m + w and
+// 8 m + 7 - w (equal work for the four waves when nb is a multiple of 8).  For an off-diagonal
+// block B = G[I][J]: y_I += B x_J (summed over the 4 lanes of a block row by DPP, added to the
+// wave's LDS copy of y) and y_J += B^T x_I (kept in registers for the whole column, summed over
+// its 16 lanes once per column).  Each y entry of a wave has one writing lane per instruction, so
+// the LDS adds are atomics only to avoid waiting on a read-modify-write.  Lane l holds B[l / 4][4 (l % 4) .. + 4) with one or two 16-byte loads.
+template <typename T> struct Quad;
+template <> struct Quad<float> {
+    float4 v;
+    __device__ void load(const float *p) { v = *reinterpret_cast<const float4 *>(p); }
+    __device__ float operator[](int i) const { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+};
+template <> struct Quad<double> {
+    double2 a, b;
+    __device__ void load(const double *p) {
+        a = reinterpret_cast<const double2 *>(p)[0];
+        b = reinterpret_cast<const double2 *>(p)[1];
+    }
+    __device__ double operator[](int i) const { return i == 0 ? a.x : i == 1 ? a.y : i == 2 ? b.x : b.y; }
+};
+
+// Sum over the 4 lanes of a quad (DPP quad permutations: xor 1, then xor 2).
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <typename T>
+__device__ inline T quad_sum(T v) {
+    v += dpp_mov<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    return v;
+}
+
+// Block columns of wave w (of 4) in increasing order: the i-th one, or -1.
+__device__ inline int wave_col(int w, int i, int nb) {
+    const int J = 8 * (i >> 1) + ((i & 1) ? 7 - w : w);
+    return J < nb ? J : -1;
+}
 
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
+__global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t nports, int32_t max_np,
+                                               const T *__restrict__ G,
                                                const int64_t *__restrict__ goff, const T *__restrict__ cport,
                                                const int32_t *__restrict__ twin, const T *__restrict__ invz,
                                                const T *__restrict__ o_prev, T *__restrict__ o_next) {
-    using V4 = typename Vec16<T>::type;
-    constexpr int VW = Vec16<T>::W;
     extern __shared__ char smraw[];
+    constexpr int PF = sizeof(T) == 4 ? 8 : 4;  // blocks in flight per wave
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
-    const int ldp = (p + 3) & ~3;
+    const int nb = (p + 15) >> 4, pp = nb * 16;
     const int64_t wo = (int64_t)g * nports * R;
-    T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a summed per port vertex [ldp][R]
-    T *part = xz + (size_t)ldp * R;        // partial sums [ns][ldp][R]
+    T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a per port vertex [pp][R]
+    T *yw = xz + (size_t)pp * R;           // per-wave partial y [4][pp][R]
     const T *Gk = G + goff[k];
-    const int nrt = ldp / VW;                     // row threads
-    const int rows_pass = nrt < nt ? nrt : nt;    // row threads per pass
-    const int ns = nrt < nt ? nt / nrt : 1;       // column slices
-    const int slice = (p + ns - 1) / ns;
-    const int ldv = ldp / VW;
-    // first pass: start streaming this thread's G columns before the waves arrive
-    constexpr int PF = 16;
-    V4 pre[PF];
-    {
-        const int rt = tid % rows_pass, sl = tid / rows_pass;
-        const bool act = sl < ns && rt < nrt;
-        const int a0 = sl * slice, a1 = act ? min(p, a0 + slice) : a0;
-        const V4 *gp = reinterpret_cast<const V4 *>(Gk + rt * VW);
+    const int r = lane >> 2, c0 = 4 * (lane & 3);
+    // cursor over this wave's blocks: column index ci (J = wave_col(wv, ci)), row block I >= J
+    int ci = 0, J = wave_col(wv, 0, nb), I = J;
+    Quad<T> pre[PF];
+    int pI[PF], pJ[PF];
 #pragma unroll
-        for (int f = 0; f < PF; ++f) pre[f] = a0 + f < a1 ? gp[(int64_t)(a0 + f) * ldv] : V4{};
+    for (int f = 0; f < PF; ++f) {
+        pJ[f] = J;
+        pI[f] = I;
+        if (J >= 0) {
+            pre[f].load(Gk + ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + r * 16 + c0);
+            if (++I == nb) { ++ci; J = wave_col(wv, ci, nb); I = J; }
+        }
     }
-    for (int q = tid; q < ldp; q += nt) {
+    // incoming waves a_p = o_twin(p) and Z^{-1}, one thread per port, kept in LDS for the output
+    const int port0 = D.port_ptr[k], np_k = D.port_ptr[k + 1] - port0;
+    T *al = yw + (size_t)4 * pp * R;       // a per local port [np_k][R]
+    T *izl = al + (size_t)max_np * R;      // Z^{-1} per local port
+    int qb = 0, qc = 0;                    // this thread's port group (q = tid): first local port, count
+    T cq[R];
+    if (tid < p) {
+        qb = D.pg_beg[pg0 + tid] - port0;
+        qc = D.pg_cnt[pg0 + tid];
+#pragma unroll
+        for (int c = 0; c < R; ++c) cq[c] = cport[((int64_t)g * npg + pg0 + tid) * R + c];
+    }
+    for (int t = tid; t < np_k; t += nt) {
+        const int tw = twin[port0 + t];
+        izl[t] = invz[port0 + t];
+#pragma unroll
+        for (int c = 0; c < R; ++c) al[t * R + c] = o_prev[wo + (int64_t)tw * R + c];
+    }
+    __syncthreads();
+    for (int q = tid; q < pp; q += nt) {  // xz = sum over the group's ports of Z^{-1} a (fixed order)
+        int b0 = qb, cnt = qc;
+        if (q != tid) {
+            b0 = q < p ? D.pg_beg[pg0 + q] - port0 : 0;
+            cnt = q < p ? D.pg_cnt[pg0 + q] : 0;
+        } else if (q >= p) {
+            cnt = 0;
+        }
         T acc[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[c] = 0;
-        if (q < p) {
-            const int pb = D.pg_beg[pg0 + q], pc = D.pg_cnt[pg0 + q];
-            for (int j = 0; j < pc; ++j) {
-                const T iz = invz[pb + j];
-                const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
+        for (int j = 0; j < cnt; ++j)
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
-            }
+            for (int c = 0; c < R; ++c) acc[c] += al[(b0 + j) * R + c] * izl[b0 + j];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            xz[q * R + c] = acc[c];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) yw[((size_t)w * pp + q) * R + c] = 0;
         }
-#pragma unroll
-        for (int c = 0; c < R; ++c) xz[q * R + c] = acc[c];
     }
     __syncthreads();
-    for (int r0 = 0; r0 < nrt; r0 += rows_pass) {
-        const int rt = r0 + tid % rows_pass, sl = tid / rows_pass;
-        if (sl < ns && rt < nrt) {
-            const int q = rt * VW;
-            const int a0 = sl * slice, a1 = min(p, a0 + slice);
-            T acc[VW][R];
+    T *y = yw + (size_t)wv * pp * R;
+    int cur = -1;   // block column being accumulated
+    T xj[4][R], t[4][R];
+    auto flush = [&]() {  // y_J += column sums of B^T x_I over the 16 lanes of each column quad
 #pragma unroll
-            for (int v = 0; v < VW; ++v)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[v][c] = 0;
-            const V4 *gp = reinterpret_cast<const V4 *>(Gk + q);
-            int a = a0;
-            if (r0 == 0) {
+            for (int c = 0; c < R; ++c) {
+                T v = t[j][c];
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 8);
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                t[j][c] = v;
+            }
+        if (lane < 4)
 #pragma unroll
-                for (int f = 0; f < PF; ++f) {
-                    if (a0 + f < a1) {
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int v = 0; v < VW; ++v) {
-                            const T gav = lane<T>(pre[f], v);
+                for (int c = 0; c < R; ++c) atomicAdd(&y[(cur * 16 + c0 + j) * R + c], t[j][c]);
+    };
+    while (pJ[0] >= 0) {
 #pragma unroll
-                            for (int c = 0; c < R; ++c) acc[v][c] += gav * xz[(a0 + f) * R + c];
+        for (int f = 0; f < PF; ++f) {
+            const int bJ = pJ[f], bI = pI[f];
+            if (bJ >= 0) {
+                if (bJ != cur) {
+                    if (cur >= 0) flush();
+                    cur = bJ;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int c = 0; c < R; ++c) {
+                            xj[j][c] = xz[(bJ * 16 + c0 + j) * R + c];
+                            t[j][c] = 0;
                         }
+                }
+                const Quad<T> v = pre[f];
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const T sr = quad_sum(v[0] * xj[0][c] + v[1] * xj[1][c] + v[2] * xj[2][c] + v[3] * xj[3][c]);
+                    // one lane per row adds (no-return LDS atomic: no read-after-write wait)
+                    if ((lane & 3) == 0) atomicAdd(&y[(bI * 16 + r) * R + c], sr);
+                    if (bI != bJ) {
+                        const T xi = xz[(bI * 16 + r) * R + c];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) t[j][c] += v[j] * xi;
                     }
                 }
-                a = min(a1, a0 + PF);
             }
-#pragma unroll 8
-            for (; a < a1; ++a) {
-                const V4 gv = gp[(int64_t)a * ldv];
-#pragma unroll
-                for (int v = 0; v < VW; ++v) {
-                    const T gav = lane<T>(gv, v);
-#pragma unroll
-                    for (int c = 0; c < R; ++c) acc[v][c] += gav * xz[a * R + c];
-                }
+            // refill this slot with the block PF positions ahead
+            pJ[f] = J;
+            pI[f] = I;
+            if (J >= 0) {
+                pre[f].load(Gk + ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + r * 16 + c0);
+                if (++I == nb) { ++ci; J = wave_col(wv, ci, nb); I = J; }
             }
-#pragma unroll
-            for (int v = 0; v < VW; ++v)
-#pragma unroll
-                for (int c = 0; c < R; ++c) part[((size_t)sl * ldp + q + v) * R + c] = acc[v][c];
         }
-        __syncthreads();
-        for (int qq = tid; qq < rows_pass * VW; qq += nt) {
-            const int q = r0 * VW + qq;
-            if (q >= p) continue;
-            T u[R];
+    }
+    if (cur >= 0) flush();
+    __syncthreads();
+    for (int q = tid; q < p; q += nt) {  // u = c + y, o_p = 2 u - a_p
+        int b0 = qb, cnt = qc;
+        T u[R];
+        if (q != tid) {
+            b0 = D.pg_beg[pg0 + q] - port0;
+            cnt = D.pg_cnt[pg0 + q];
 #pragma unroll
             for (int c = 0; c < R; ++c) u[c] = cport[((int64_t)g * npg + pg0 + q) * R + c];
-            for (int sl = 0; sl < ns; ++sl)
+        } else {
 #pragma unroll
-                for (int c = 0; c < R; ++c) u[c] += part[((size_t)sl * ldp + q) * R + c];
-            const int pb = D.pg_beg[pg0 + q], pc = D.pg_cnt[pg0 + q];
-            for (int j = 0; j < pc; ++j) {
-                const T *ai = o_prev + wo + (int64_t)twin[pb + j] * R;
-                T *o = o_next + wo + (int64_t)(pb + j) * R;
-#pragma unroll
-                for (int c = 0; c < R; ++c) o[c] = (T)2 * u[c] - ai[c];
-            }
+            for (int c = 0; c < R; ++c) u[c] = cq[c];
         }
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+            u[c] += yw[(size_t)q * R + c] + yw[((size_t)pp + q) * R + c] + yw[((size_t)2 * pp + q) * R + c] +
+                    yw[((size_t)3 * pp + q) * R + c];
+        for (int j = 0; j < cnt; ++j) {
+            T *o = o_next + wo + (int64_t)(port0 + b0 + j) * R;
+#pragma unroll
+            for (int c = 0; c < R; ++c) o[c] = (T)2 * u[c] - al[(b0 + j) * R + c];
+        }
     }
 }
 
@@ -875,16 +971,19 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
     hipLaunchKernelGGL(k_gather_ports<T>, dim3(nsub, ngroups), dim3(128), 0, st, D, nsplit, npg, R, xloc, cport);
 }
 
-template <typename T>
-size_t schur_shm(int32_t max_p, int32_t R, int32_t threads) {
-    // xz [ldp][R] + partial sums: at most (threads / row threads) slices of ldp rows <= ldp + threads * VW
-    const size_t ldp = (size_t)((max_p + 3) & ~3);
-    return sizeof(T) * (size_t)R * (ldp + (size_t)threads * Vec16<T>::W + ldp);
+size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R) {
+    const size_t pp = (size_t)((max_p + 15) & ~15);
+    return tsize * ((size_t)R * (5 * pp + (size_t)max_np) + (size_t)max_np);  // xz, 4 x y, a, Z^{-1}
 }
 
 template <typename T>
-hipError_t prepare_schur(int32_t max_p, int32_t R) {
-    const size_t shm = schur_shm<T>(max_p, R, 256);
+size_t schur_shm(int32_t max_p, int32_t max_np, int32_t R) {
+    return schur_lds_bytes(sizeof(T), max_p, max_np, R);
+}
+
+template <typename T>
+hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R) {
+    const size_t shm = schur_shm<T>(max_p, max_np, R);
     if (shm <= 64 * 1024) return hipSuccess;
     const void *fn = R == 1 ? (const void *)k_schur<T, 1> : R == 2 ? (const void *)k_schur<T, 2>
                    : R == 4 ? (const void *)k_schur<T, 4> : (const void *)k_schur<T, 8>;
@@ -892,16 +991,16 @@ hipError_t prepare_schur(int32_t max_p, int32_t R) {
 }
 
 template <typename T>
-void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t npg,
-                  int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
+void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t max_np,
+                  int32_t npg, int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
                   const T *invz, const T *o_prev, T *o_next, hipStream_t st) {
-    const size_t shm = schur_shm<T>(max_p, R, 256);
+    const size_t shm = schur_shm<T>(max_p, max_np, R);
     const dim3 grid(nsub, ngroups), block(256);
     switch (R) {
-        case 1: hipLaunchKernelGGL((k_schur<T, 1>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 2: hipLaunchKernelGGL((k_schur<T, 2>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 1: hipLaunchKernelGGL((k_schur<T, 1>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 2: hipLaunchKernelGGL((k_schur<T, 2>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
+        default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
     }
 }
 
@@ -933,12 +1032,12 @@ template void launch_gather_ports<double>(const DevSub &, int32_t, int32_t, int6
                                           double *, hipStream_t);
 template void launch_gather_ports<float>(const DevSub &, int32_t, int32_t, int64_t, int32_t, int32_t, const float *,
                                          float *, hipStream_t);
-template hipError_t prepare_schur<double>(int32_t, int32_t);
-template hipError_t prepare_schur<float>(int32_t, int32_t);
-template void launch_schur<double>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const double *,
+template hipError_t prepare_schur<double>(int32_t, int32_t, int32_t);
+template hipError_t prepare_schur<float>(int32_t, int32_t, int32_t);
+template void launch_schur<double>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const double *,
                                    const int64_t *, const double *, const int32_t *, const double *, const double *,
                                    double *, hipStream_t);
-template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const float *,
+template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const float *,
                                   const int64_t *, const float *, const int32_t *, const float *, const float *,
                                   float *, hipStream_t);
 template hipError_t prepare_sweep<float>(int32_t, int32_t, int32_t, int32_t);

@@ -48,6 +48,7 @@ struct DevSub {
     const uint16_t *pg_pos;  // factor position of the group's vertex
     const int32_t *pg_beg;   // first port of the group
     const int32_t *pg_cnt;   // ports in the group
+    const int32_t *port_ptr; // first port of each subgraph (nsub + 1)
 };
 
 // Column plan of the port Green's functions computed inside the factorisation.  Ports of a subgraph
@@ -82,7 +83,7 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
 
 // FP64 multifrontal factorisation of every port-augmented local matrix; status[k] = 1 + supernode of the
 // first non-positive pivot (0 if fine).  With Gp.sn set it also accumulates the port Green's functions
-// G_k = R K_k^{-1} R^T (FP64, p_k x ldp_k row-major at goff[k], zero on entry).
+// G_k = R K_k^{-1} R^T (FP64, packed lower block triangle at goff[k], see k_schur; zero on entry).
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
                    const double *invz, double *vals, double *ws, int32_t *status, const DevGreen &Gp,
                    const int64_t *goff, double *G, hipStream_t st);
@@ -104,7 +105,7 @@ template <typename T>
 hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R);
 
 // Port Green's functions G_k = R K_k^{-1} R^T by one substitution per group of four port columns
-// (FP64, p_k x ldp_k row-major at goff[k]); used when the column plan does not apply.
+// (FP64, packed like above); used when the column plan does not apply.
 void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
                   const double *vals, const int64_t *goff, double *G, hipStream_t st);
 // cport[g][port vertex][R] = local solutions at the port vertices.
@@ -112,11 +113,14 @@ template <typename T>
 void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,
                          const T *xloc, T *cport, hipStream_t st);
 template <typename T>
-hipError_t prepare_schur(int32_t max_p, int32_t R);
+hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R);
+// LDS of the port-reduced sweep kernel; it runs only when this fits the 160 KiB of a CU.
+size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R);
+constexpr size_t kMaxLds = 160 * 1024;
 // Port-reduced sweep: o = 2 (c + G Z^{-1} a) - a at every port.
 template <typename T>
-void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t npg,
-                  int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
+void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t max_np,
+                  int32_t npg, int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
                   const T *invz, const T *o_prev, T *o_next, hipStream_t st);
 
 // xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
