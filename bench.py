@@ -67,18 +67,19 @@ def measured_traffic(kernel):
     kernels' source has changed since the counters were taken (or the kernel is another one)."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_schur_traffic_c2_lognormal_1024.md")
-    if kernel != "k_schur" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", "sweep_traffic_c2_lognormal_1024.md")
+    key = kernel + "-traffic-bytes-per-launch"
+    if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0].strip() in ("kernels-source-sha256", "k_schur-traffic-bytes-per-launch"):
+        if ":" in line and line.split(":", 1)[0].strip() in ("kernels-source-sha256", key):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_0807_1949_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernels-source-sha256"):
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernels-source-sha256") or key not in fields:
         return None
-    return float(fields["k_schur-traffic-bytes-per-launch"])
+    return float(fields[key])
 
 
 def cpu_baseline(O, A, spec, b, z):
@@ -166,7 +167,7 @@ def main():
     value = A.n * nrhs * sweeps / head["step_s"]
     sweep_s = st["sweep_ms"] / 1e3 / max(sweeps, 1)
     achieved = st["bytes_per_sweep"] / sweep_s / 1e9
-    kernel = "k_schur" if st["sweep_mode"] == 2 else "k_sweep"
+    kernel = ("k_schur_persist" if st["persistent"] else "k_schur") if st["sweep_mode"] == 2 else "k_sweep"
     line = dict(
         metric="time to rel. residual 1e-8 (s) & unknown-updates/s; learned-Z vs plain VTM",
         value=value, unit="unknown-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -180,7 +181,7 @@ def main():
         variants={v: dict(time_to_tol_s=r["step_s"], sweeps=r["stats"]["sweeps"], setup_ms=r["stats"]["setup_ms"],
                           sweep_us=r["stats"]["sweep_ms"] * 1e3 / max(r["stats"]["sweeps"], 1),
                           outer_steps=r["stats"]["outer_steps"], checks=r["stats"]["checks"],
-                          relres=r["relres"], status=r["status"],
+                          relres=r["relres"], status=r["status"], persistent=r["stats"]["persistent"],
                           sweep_mode=r["stats"]["sweep_mode"])
                   for v, r in results.items()},
         roofline=dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",

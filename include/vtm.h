@@ -83,7 +83,12 @@ typedef struct {
                               Port-reduced sweeps need one workgroup's port vectors in LDS
                               (about 5 p_k rhs_per_block values); when they do not fit, or
                               G_k was not built (p_k > 2048), substitution sweeps run. */
-    int32_t reserved[2];
+    int32_t persistent;    /* port-reduced FP32 sweeps: 0 = one persistent cooperative launch per batch of
+                              sweeps between tests when every workgroup fits on the device at once, each
+                              wave's G_k blocks fit in registers and rhs_per_block <= 2 (G_k held on chip,
+                              waves exchanged as tagged words), else per-sweep launches;
+                              1 = per-sweep launches only */
+    int32_t reserved;
 } vtm_options;
 
 /*
@@ -150,10 +155,12 @@ typedef struct {
     double setup_ms;         /* last vtm_setup: Z, augmentation and factorisation (device time) */
     double solve_ms;         /* last solve, wall time on the stream (events) */
     double sweep_ms;         /* last solve, summed sweep-kernel time (events around sweep launches) */
-    double bytes_per_sweep;  /* algorithmic bytes one sweep must move (factor once + vectors + waves) */
+    double bytes_per_sweep;  /* algorithmic bytes per sweep: factor (substitution) or G (port-reduced; in
+                                persistent launches read once per launch, so averaged over its sweeps)
+                                + vectors + waves */
     double flops_per_sweep;  /* substitution: 4 * nrhs * lower-factor entries; port-reduced: 2 * nrhs * G entries */
     int32_t sweep_mode;      /* mode of the last solve: 1 substitution, 2 port-reduced */
-    int32_t pad;
+    int32_t persistent;      /* 1 if the last solve or run ran its sweeps in persistent launches */
 } vtm_stats;
 
 /* Create a handle bound to options->device; NULL options = defaults. */

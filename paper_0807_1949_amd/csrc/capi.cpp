@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -70,6 +71,8 @@ struct vtm_ctx {
     // port-reduced sweeps
     DevBuf d_goff, d_G64, d_G32, d_cport;
     int32_t max_p = 0, npg = 0, max_np = 0;
+    int32_t persist_R = -1, persist_ng = -1;
+    bool persist_fits = false;
     int64_t total_g = 0;   // stored entries of all packed G_k
     double total_pp = 0;   // sum of p_k^2 (entries of the full G_k)
     bool have_green = false;
@@ -112,6 +115,10 @@ struct vtm_ctx {
         }
     }
     bool waves_zero = true;
+    // persistent port-reduced sweeps: tagged wave words, abort flag, next sweep tag
+    DevBuf d_tw, d_abort;
+    int32_t tag = 1;
+    int64_t persist_launches = 0;  // persistent launches of the current solve or run
     vtm_stats stats{};
 
     vtm_ctx() {
@@ -120,7 +127,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -431,6 +438,7 @@ vtm_status upload_partition(vtm_ctx *h) {
         std::vector<int64_t> goff(nsub + 1, 0);
         h->max_p = 0;
         h->total_pp = 0;
+        h->persist_R = h->persist_ng = -1;
         for (int32_t k = 0; k < nsub; ++k) {
             // packed symmetric G_k: lower block triangle of 16 x 16 blocks
             const int64_t p = pgptr[k + 1] - pgptr[k], nb = (p + 15) / 16;
@@ -600,6 +608,28 @@ int32_t sweep_threads(vtm_ctx *h) {
 
 // Sweeps on the current waves; the last one stores the local solutions.  Batches of two or more
 // sweeps are captured once into a HIP graph per starting wave buffer and replayed.
+// Persistent port-reduced sweeps need FP32, every workgroup resident at once and each wave's G
+// blocks in registers.
+bool persistent_ok(vtm_ctx *h, int32_t R, int32_t ng) {
+    if (!h->fp32() || h->opt.persistent == 1 || !use_schur(h)) return false;
+    if (R != 1 && R != 2) return false;  // wider groups spill the on-chip G blocks to scratch
+    if (h->max_p > vtm::persist_max_p()) return false;  // G_k rows held in registers
+    if (vtm::persist_lds_bytes(h->max_p, h->max_np, R) > vtm::kMaxLds) return false;
+    if (h->persist_R != R || h->persist_ng != ng) {
+        int64_t resident = 0;
+        if (vtm::persist_capacity(h->max_p, h->max_np, R, &resident) != hipSuccess) {
+            (void)hipGetLastError();
+            resident = 0;
+        }
+        h->persist_R = R;
+        h->persist_ng = ng;
+        h->persist_fits = (int64_t)h->P.nsub * ng <= resident;
+    }
+    return h->persist_fits;
+}
+
+constexpr int32_t kSpinLimit = 1 << 20;  // polls of one wave word before a persistent launch gives up
+
 template <typename T>
 vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     if (count <= 0) return VTM_OK;
@@ -609,6 +639,46 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
     const bool schur = use_schur(h);
     if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, h->max_np, R));
+    if constexpr (std::is_same<T, float>::value) {
+        if (schur && persistent_ok(h, R, ng)) {
+            const int64_t nw = (int64_t)ng * h->nports * R;
+            HIP_TRY(ensure(h->d_tw, sizeof(unsigned long long) * (2 * nw + 2)));
+            HIP_TRY(ensure(h->d_abort, sizeof(int32_t) * 2));
+            HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
+            bool refused = false;
+            for (int64_t left = count; left > 0;) {
+                const int32_t nsw = (int32_t)std::min<int64_t>(left, 1 << 20);
+                if (h->tag > (1 << 29)) h->tag = 1;
+                vtm::launch_tag_waves(h->d_o[h->cur].as<float>(), h->d_tw.as<unsigned long long>(), nw, h->tag,
+                                      h->stream);
+                const hipError_t e = vtm::launch_schur_persist(
+                    D, h->P.nsub, ng, R, h->max_p, h->max_np, h->npg, h->nports, green_of<float>(h),
+                    h->d_goff.as<int64_t>(), h->d_cport.as<float>(), h->d_twin.as<int32_t>(), invz_of<float>(h),
+                    h->d_tw.as<unsigned long long>(), h->d_o[0].as<float>(), h->d_o[1].as<float>(), h->tag, nsw,
+                    h->cur, kSpinLimit, h->d_abort.as<int32_t>(), h->stream);
+                if (e != hipSuccess && left == count) {  // not co-resident after all: per-sweep launches
+                    (void)hipGetLastError();
+                    h->persist_fits = false;
+                    refused = true;
+                    break;
+                }
+                HIP_TRY(e);
+                h->tag += nsw + 2;
+                h->cur ^= (int)(nsw & 1);
+                ++h->persist_launches;
+                left -= nsw;
+            }
+            int32_t aborted = 0;
+            if (refused) goto per_sweep;
+            HIP_TRY(hipMemcpyAsync(&aborted, h->d_abort.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            if (aborted) return fail(VTM_ERR_HIP, "persistent sweep: a wave exchange wait timed out");
+            h->waves_zero = false;
+            h->stats.persistent = 1;
+            return VTM_OK;
+        }
+    }
+per_sweep:
     auto launch = [&](int cur, bool last) {
         if (schur)
             vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
@@ -720,6 +790,8 @@ template <typename T>
 vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
                       int32_t *iters, double *relres) {
     vtm_status rc;
+    h->stats.persistent = 0;
+    h->persist_launches = 0;
     if ((rc = ensure_waves<T>(h, nrhs))) return rc;
     if ((rc = alloc_solve<T>(h, nrhs))) return rc;
     if ((rc = stage_b(h, b, nrhs, ldb))) return rc;
@@ -858,8 +930,10 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     h->stats.solve_ms = total;
     h->stats.sweep_ms = sweep_ms;
     if (schur) {
+        // G_k is read once per launch: every sweep in per-sweep launches, once per batch in persistent ones
+        const double g_reads = h->stats.persistent ? (double)h->persist_launches / (double)std::max<int64_t>(1, sweeps) : 1.0;
         h->stats.bytes_per_sweep =
-            (double)sizeof(T) * ((double)h->total_g + (double)h->npg * nrhs + 2.0 * (double)h->nports * nrhs);
+            (double)sizeof(T) * ((double)h->total_g * g_reads + (double)h->npg * nrhs + 2.0 * (double)h->nports * nrhs);
         h->stats.flops_per_sweep = 2.0 * nrhs * h->total_pp;
     } else {
         h->stats.bytes_per_sweep =
@@ -878,6 +952,8 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
 template <typename T>
 vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int64_t nsweeps, double *x, int64_t ldx) {
     vtm_status rc;
+    h->stats.persistent = 0;
+    h->persist_launches = 0;
     if ((rc = ensure_waves<T>(h, nrhs))) return rc;
     if ((rc = alloc_solve<T>(h, nrhs))) return rc;
     if ((rc = stage_b(h, b, nrhs, ldb))) return rc;

@@ -808,6 +808,199 @@ __global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t np
     }
 }
 
+// ------------------------------------------------------------ persistent port-reduced sweeps
+//
+// One launch runs nsw sweeps of the port-reduced map (k_schur's arithmetic, FP32).  Workgroup (k, g)
+// keeps its blocks of G_k in registers for the whole launch, so a sweep moves only the waves.
+// Sweeps are ordered by the waves themselves: every outgoing wave is published as one 64-bit word
+// {sweep tag, FP32 value} by a relaxed agent-scope atomic store into the buffer of its sweep's
+// parity, and a workgroup starts sweep s once each of its incoming words carries tag s - 1 (a
+// single-copy-atomic word needs no separate flag or fence).  Two buffers suffice: the word of sweep
+// s overwrites the one of sweep s - 2, which the twin's owner read during its sweep s - 1, before
+// it published the sweep s - 1 word this workgroup waited for.  Neighbours thus stay within one
+// sweep of each other.  All workgroups must be resident at once (cooperative launch).  Every wait
+// is bounded: a wait that exceeds spin_limit polls raises *abort, every other wait then gives up
+// too, and the launch runs to its end with the host reporting the error.
+
+__device__ inline unsigned long long load_word(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_word(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long tag_word(int tag, float v) {
+    return ((unsigned long long)(unsigned)tag << 32) | (unsigned long long)__float_as_uint(v);
+}
+
+// Wait until the word at w carries tag want (re-reading it), bounded by spin_limit polls or an abort.
+__device__ inline unsigned long long await_word(const unsigned long long *w, unsigned long long v, int want,
+                                                int spin_limit, int32_t *abort_flag) {
+    int spins = 0;
+    while ((int)(v >> 32) != want) {
+        if ((++spins & 63) == 0 &&
+            (spins > spin_limit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = load_word(w);
+    }
+    return v;
+}
+
+// Workgroup (k, g), 256 threads: thread t owns a 4 x 16 tile of G_k (rows 4 (t / 8) .. + 4,
+// columns 16 (t % 8) .. + 16; zero beyond p_k), expanded once per launch from the packed blocks into
+// 64 registers; p_k <= 128.  Per sweep: (A) one thread per port awaits its incoming word; (A2) one
+// thread per port vertex forms Z^{-1} a; (B) each thread multiplies its tile by its 16 entries of
+// Z^{-1} a (four 16-byte LDS reads), the 8 threads of a row group add their partial sums (DPP quad
+// permutations, then a swizzle), and thread 4 (t / 8) + j writes the outgoing waves of row 4 (t / 8)
+// + j's port vertex.
+template <int R>
+__global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg, int64_t nports, int32_t max_np,
+                                                          const float *__restrict__ G,
+                                                          const int64_t *__restrict__ goff,
+                                                          const float *__restrict__ cport,
+                                                          const int32_t *__restrict__ twin,
+                                                          const float *__restrict__ invz, unsigned long long *tw,
+                                                          float *plain0, float *plain1, int32_t t0, int32_t nsw,
+                                                          int32_t cur0, int32_t spin_limit, int32_t *abort_flag) {
+    extern __shared__ __attribute__((aligned(16))) char smraw[];
+    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
+    const int nb = (p + 15) >> 4;
+    const int64_t wo = (int64_t)g * nports * R, bstride = (int64_t)gridDim.y * nports * R;
+    // LDS, double-buffered by sweep parity: xz [2][128][R], a [2][max_np][R]; Z^{-1} and twin per port
+    float *xz2 = reinterpret_cast<float *>(smraw);
+    float *al2 = xz2 + (size_t)2 * 128 * R;
+    float *izl = al2 + (size_t)2 * max_np * R;
+    int *twl = reinterpret_cast<int *>(izl + max_np);
+    __shared__ int stop[2];
+    const int port0 = D.port_ptr[k], np_k = D.port_ptr[k + 1] - port0;
+    const float *Gk = G + goff[k];
+    const int rg = tid >> 3, cg = tid & 7;   // rows 4 rg .. + 4, columns 16 cg .. + 16
+    float gr[4][16];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) {
+            const int i = 4 * rg + rr, j = 16 * cg + cc;
+            float v = 0.f;
+            if (i < p && j < p) {
+                const int I = i >> 4, J = j >> 4;
+                v = I >= J ? Gk[((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + (i & 15) * 16 + (j & 15)]
+                           : Gk[((int64_t)I * nb - (int64_t)I * (I - 1) / 2 + (J - I)) * 256 + (j & 15) * 16 + (i & 15)];
+            }
+            gr[rr][cc] = v;
+        }
+    // this thread's port vertex for Z^{-1} a (q = tid), and for the output (row 4 rg + cg, cg < 4)
+    const int orow = 4 * rg + cg;
+    const bool outer = cg < 4 && orow < p;
+    int qb = 0, qc = 0, rb = 0, rc = 0;
+    float cq[R];
+    if (tid < p) {
+        qb = D.pg_beg[pg0 + tid] - port0;
+        qc = D.pg_cnt[pg0 + tid];
+    }
+    if (outer) {
+        rb = D.pg_beg[pg0 + orow] - port0;
+        rc = D.pg_cnt[pg0 + orow];
+#pragma unroll
+        for (int c = 0; c < R; ++c) cq[c] = cport[((int64_t)g * npg + pg0 + orow) * R + c];
+    }
+    for (int t = tid; t < np_k; t += nt) {
+        twl[t] = twin[port0 + t];
+        izl[t] = invz[port0 + t];
+    }
+    for (int e = tid; e < 2 * 128 * R; e += nt) xz2[e] = 0.f;  // rows >= p stay zero
+    __syncthreads();
+    for (int i = 1; i <= nsw; ++i) {
+        const int s = t0 + i, par = i & 1;
+        float *xz = xz2 + (size_t)par * 128 * R, *al = al2 + (size_t)par * max_np * R;
+        // A: incoming words of sweep s - 1, one thread per port (all loads issued before any wait)
+        const unsigned long long *src = tw + (int64_t)((s - 1) & 1) * bstride + wo;
+        if (tid == 0) stop[par] = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int t = tid; t < np_k; t += nt) {
+            const unsigned long long *w = src + (int64_t)twl[t] * R;
+            unsigned long long v[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) v[c] = load_word(w + c);
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                const unsigned long long x = await_word(w + c, v[c], s - 1, spin_limit, abort_flag);
+                al[t * R + c] = __uint_as_float((unsigned)(x & 0xFFFFFFFFull));
+            }
+        }
+        __syncthreads();
+        if (stop[par]) return;  // uniform: the whole workgroup leaves
+        // A2: xz = sum over the port vertex's ports of Z^{-1} a (fixed order)
+        if (tid < p) {
+            float acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = 0.f;
+            for (int j = 0; j < qc; ++j)
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += al[(qb + j) * R + c] * izl[qb + j];
+#pragma unroll
+            for (int c = 0; c < R; ++c) xz[tid * R + c] = acc[c];
+        }
+        __syncthreads();
+        // B: tile times its 16 entries of xz, row-group sums over the 8 threads, outgoing waves
+        float acc[4][R];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[rr][c] = 0.f;
+        const float4 *x4 = reinterpret_cast<const float4 *>(xz + (size_t)16 * cg * R);  // 16-byte LDS reads
+#pragma unroll
+        for (int q4 = 0; q4 < 4 * R; ++q4) {
+            const float4 xv = x4[q4];
+            const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int cc = (4 * q4 + e) / R, c = (4 * q4 + e) % R;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) acc[rr][c] += gr[rr][cc] * xs[e];
+            }
+        }
+        // reduce-scatter over the 8 threads of the row group: thread cg ends with row (cg & 3)'s sum
+        float y[R];
+        const bool b1 = cg & 2, b0 = cg & 1;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            // lanes xor 2 swap row pairs: keep rows {0,1} (b1 = 0) or {2,3} (b1 = 1)
+            const float k0 = b1 ? acc[2][c] : acc[0][c], k1 = b1 ? acc[3][c] : acc[1][c];
+            const float s0 = b1 ? acc[0][c] : acc[2][c], s1 = b1 ? acc[1][c] : acc[3][c];
+            const float q0 = k0 + dpp_mov<0x4E>(s0), q1 = k1 + dpp_mov<0x4E>(s1);
+            // lanes xor 1 swap single rows: keep row 2 b1 + b0
+            float v = (b0 ? q1 : q0) + dpp_mov<0xB1>(b0 ? q0 : q1);
+            v += __shfl_xor(v, 4);  // the other quad of the row group
+            y[c] = v;
+        }
+        if (outer) {
+            unsigned long long *dst = tw + (int64_t)(s & 1) * bstride + wo;
+            float *pl = i >= nsw - 1 ? (((cur0 ^ (i & 1)) == 0) ? plain0 : plain1) : nullptr;
+            for (int j = 0; j < rc; ++j) {
+                const int64_t o = (int64_t)(port0 + rb + j) * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const float ov = 2.f * (cq[c] + y[c]) - al[(rb + j) * R + c];
+                    store_word(dst + o + c, tag_word(s, ov));
+                    if (pl) pl[wo + o + c] = ov;
+                }
+            }
+        }
+    }
+}
+
+// Tagged wave buffers for a persistent launch starting at sweep tag t0: buffer t0 & 1 holds the
+// current waves with tag t0, the other buffer tag t0 - 1 (never the tag a reader waits for).
+__global__ void k_tag_waves(const float *__restrict__ o, unsigned long long *tw, int64_t n, int32_t t0) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        tw[(int64_t)(t0 & 1) * n + i] = tag_word(t0, o[i]);
+        tw[(int64_t)((t0 + 1) & 1) * n + i] = tag_word(t0 - 1, 0.f);
+    }
+}
+
 // ------------------------------------------------------------------ merge, residual
 template <typename T>
 __global__ void k_merge(DevMaps M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *__restrict__ xloc,
@@ -1002,6 +1195,52 @@ void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int
         case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
         default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
     }
+}
+
+static const void *persist_fn(int32_t R) {
+    return R == 1 ? (const void *)k_schur_persist<1> : R == 2 ? (const void *)k_schur_persist<2>
+         : R == 4 ? (const void *)k_schur_persist<4> : (const void *)k_schur_persist<8>;
+}
+
+size_t persist_lds_bytes(int32_t, int32_t max_np, int32_t R) {
+    return sizeof(float) * ((size_t)R * (2 * 128 + 2 * (size_t)max_np) + 2 * (size_t)max_np);
+}
+
+int persist_max_p() { return 128; }
+
+hipError_t persist_capacity(int32_t max_p, int32_t max_np, int32_t R, int64_t *resident) {
+    const size_t shm = persist_lds_bytes(max_p, max_np, R);
+    const void *fn = persist_fn(R);
+    if (shm > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0, dev = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, shm);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    *resident = (int64_t)per_cu * ncu;
+    return hipSuccess;
+}
+
+hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p,
+                                int32_t max_np, int32_t npg, int64_t nports, const float *G, const int64_t *goff,
+                                const float *cport, const int32_t *twin, const float *invz, unsigned long long *tw,
+                                float *plain0, float *plain1, int32_t t0, int32_t nsw, int32_t cur0,
+                                int32_t spin_limit, int32_t *abort_flag, hipStream_t st) {
+    const size_t shm = persist_lds_bytes(max_p, max_np, R);
+    DevSub d = D;
+    void *args[] = {&d, &npg, &nports, &max_np, &G, &goff, &cport, &twin, &invz, &tw, &plain0, &plain1,
+                    &t0, &nsw, &cur0, &spin_limit, &abort_flag};
+    return hipLaunchCooperativeKernel(persist_fn(R), dim3(nsub, ngroups), dim3(256), args, (unsigned)shm, st);
+}
+
+void launch_tag_waves(const float *o, unsigned long long *tw, int64_t n, int32_t t0, hipStream_t st) {
+    unsigned nb = blocks_for(n, 256);
+    if (nb > 4096) nb = 4096;
+    if (nb == 0) nb = 1;
+    hipLaunchKernelGGL(k_tag_waves, dim3(nb), dim3(256), 0, st, o, tw, n, t0);
 }
 
 template <typename T>

@@ -254,3 +254,38 @@ def test_adaptive_check_cadence(B):
     assert _rel(r["x"][0], ro["x"][0]) <= 1e-10
     ro1 = O.Solver(P, z).run(cfg["b"], 100000, 1, 1e-8)
     assert st["sweeps"] <= 1.25 * int(ro1["iters"][0, 0]) + 10
+
+
+@pytest.mark.parametrize("name,nrhs", [("c2", 1), ("c2", 2), ("c5", 1)])
+def test_persistent_sweeps_match_per_sweep_launches(B, name, nrhs):
+    """FP32 port-reduced sweeps in one persistent launch (G_k rows on chip, tagged wave words) give
+    the oracle's iterates to FP32 accuracy, the per-sweep kernel's waves to rounding, and the same
+    converged solve."""
+    cfg = gen.make_config(name, small=True)
+    b = np.vstack([cfg["b"][:1]] * nrhs) if nrhs > 1 else cfg["b"][:1].copy()
+    if nrhs > 1:
+        b[1] = b[1][::-1]
+    print(f"[parity] persistent {name} nrhs={nrhs}", flush=True)
+    out = {}
+    for pers in (0, 1):
+        # fixed test cadence: the adaptive one depends on measured timings
+        h, P, z = _setup(B, cfg, precision=1, z_scale=8.0, sweep_mode=2, persistent=pers, check_every=10)
+        x = h.run_sweeps(b, 37)
+        ran_persistent = h.get_stats()["persistent"]
+        w = h.get_waves(nrhs)
+        h.reset_waves()
+        r = h.solve(b, 1e-8)
+        out[pers] = (x, w, r, h.get_stats())
+        h.close()
+        assert ran_persistent == (1 if pers == 0 else 0)
+    (x0, w0, r0, s0), (x1, w1, r1, s1) = out[0], out[1]
+    assert s0["sweep_mode"] == 2 and s1["sweep_mode"] == 2 and s0["persistent"] == 1 and s1["persistent"] == 0
+    xo = O.Solver(P, z).run(b, 37, 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"]
+    for c in range(nrhs):
+        assert _rel(x0[c], xo[c]) <= 2e-5, (c, _rel(x0[c], xo[c]))
+        assert _rel(x0[c], x1[c]) <= 2e-5
+        assert _rel(w0[c], w1[c]) <= 2e-5
+    assert r0["status"] == 0 and r1["status"] == 0
+    assert np.all(np.abs(r0["iters"] - r1["iters"]) <= 10)
+    for c in range(nrhs):
+        assert _rel(r0["x"][c], r1["x"][c]) <= 1e-6
