@@ -35,8 +35,9 @@ def log(msg):
 
 
 def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warmup, check_every, max_sweeps,
-                mode=0, params=None):
-    h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps, sweep_mode=mode)
+                mode=0, params=None, leaf_size=0):
+    h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps, sweep_mode=mode,
+              leaf_size=leaf_size)
     t0 = time.perf_counter()
     info = h.evs_partition(A, spec)
     part_s = time.perf_counter() - t0
@@ -98,6 +99,73 @@ def cpu_baseline(O, A, spec, b, z):
                        f"{dt:.1f} s", time_per_sweep_s=dt / nsw)
 
 
+def run_configs(names, B, Zm, torch, out_path=None, sweep_mode=0):
+    """Every named workload at full size: learned-Z FP32+IR VTM on the GPU to its tolerance (timed:
+    setup + solve after one warm-up), its relative residual re-checked on the host in FP64, and its
+    error against the FP64 oracle with the same impedances, both solved to 1e-12 (at 1e-8 the error
+    is bounded only by the condition number times the residual)."""
+    import numpy as np
+
+    import gen
+    from oracle import oracle as O
+
+    rows = []
+    for name in names:
+        cfg = gen.make_config(name)
+        A, spec, b, tol = cfg["A"], cfg["spec"], cfg["b"], cfg["tol"]
+        oracle_rhs = 1 if A.n > 1_500_000 else b.shape[0]  # the FP64 oracle runs one RHS at a time
+        As = A.to_scipy()
+        log(f"config {cfg['name']}: n {A.n}, nrhs {b.shape[0]}, systems {cfg['nsys']}")
+        h = B.VTM(device=0, precision=B.VTM_FP32_IR, check_every=0, sweep_mode=sweep_mode)
+        info = h.evs_partition(A, spec, nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+        h.zmodel_load(Zm.load())
+        b_dev = torch.tensor(b, dtype=torch.float64, device="cuda")
+        x_dev = torch.empty_like(b_dev)
+        times = []
+        for i in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.setup(B.VTM_Z_LEARNED)
+            res = h.solve(b_dev, tol, x_dev)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        st = h.get_stats()
+        log(f"  GPU: {times[-1] * 1e3:.2f} ms to {tol:g}, {st['sweeps']} sweeps, {st['checks']} tests, "
+            f"mode {st['sweep_mode']}, persistent {st['persistent']}")
+        x = x_dev.cpu().numpy()
+        sp = cfg["sys_ptr"]
+        host_rel = 0.0
+        for c in range(b.shape[0]):
+            r = b[c] - As @ x[c]
+            for k in range(cfg["nsys"]):
+                lo, hi = sp[k], sp[k + 1]
+                host_rel = max(host_rel, float(np.linalg.norm(r[lo:hi]) / np.linalg.norm(b[c, lo:hi])))
+        log(f"  host residual {host_rel:.3e}")
+        z = h.get_z()
+        h.reset_waves()
+        tight = h.solve(b_dev, 1e-12, x_dev)
+        xt = x_dev.cpu().numpy()
+        log(f"  GPU at 1e-12: {int(np.max(tight['iters']))} sweeps; oracle on {oracle_rhs} right-hand side(s)")
+        P = O.Partition(A, spec)
+        t0 = time.perf_counter()
+        ro = O.Solver(P, z).run(b[:oracle_rhs], 10 ** 6, 10, 1e-12, sys_ptr=sp)
+        t_oracle = time.perf_counter() - t0
+        err = max(float(np.linalg.norm(xt[c] - ro["x"][c]) / np.linalg.norm(ro["x"][c])) for c in range(oracle_rhs))
+        row = dict(config=cfg["name"], n=int(A.n), nsub=int(info["nsub"]), nrhs=int(b.shape[0]), systems=int(cfg["nsys"]),
+                   tol=tol, time_to_tol_s=times[-1], setup_ms=st["setup_ms"], sweeps=int(st["sweeps"]),
+                   outer_steps=int(st["outer_steps"]), tests=int(st["checks"]), sweep_mode=int(st["sweep_mode"]),
+                   persistent=int(st["persistent"]), relres_lib=float(np.max(res["relres"])), relres_host=host_rel,
+                   err_vs_oracle_at_1e12=err, oracle_rhs=oracle_rhs, sweeps_1e12=int(np.max(tight["iters"])),
+                   oracle_sweeps_1e12=int(np.max(ro["iters"])), oracle_s_1e12=t_oracle, oracle_threads=O.num_threads())
+        log("  " + json.dumps(row))
+        rows.append(row)
+        h.close()
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(rows, f, indent=1)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +179,11 @@ def main():
                          "port-reduced, default chosen by the library); the first is the headline, the "
                          "second its comparison")
     ap.add_argument("--check-every", type=int, default=0, help="0 = adaptive test placement")
+    ap.add_argument("--leaf-size", type=int, default=0, help="nested-dissection leaf size (0 = library default)")
+    ap.add_argument("--configs", default="", help="instead of the benchmark line: check these workloads at full "
+                    "size (comma list of c1..c5) against the oracle")
+    ap.add_argument("--configs-out", default="", help="write the --configs results as JSON to this path")
+    ap.add_argument("--configs-mode", type=int, default=0, help="sweep mode for --configs (0 library choice, 1, 2)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration)")
     args = ap.parse_args()
@@ -125,6 +198,9 @@ def main():
     from paper_0807_1949_amd import binding as B
     from paper_0807_1949_amd import zmodel as Zm
 
+    if args.configs:
+        run_configs(args.configs.split(","), B, Zm, torch, args.configs_out or None, args.configs_mode)
+        return
     if args.calib_copy_mib > 0:
         src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -157,7 +233,7 @@ def main():
             hh.close()
         log(f"variant {v}")
         results[v] = run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, args.steps, args.warmup,
-                                 args.check_every, 200000, mode, params)
+                                 args.check_every, 200000, mode, params, args.leaf_size)
         zinfo[v] = results[v]["z"]
     head = results[variants[0]]
     st = head["stats"]

@@ -79,7 +79,8 @@ typedef struct {
                               2 = per-level update entries L21*y gathered by the ancestors, 0 = choose */
     int32_t sweep_mode;    /* 1 = substitution sweeps; 2 = port-reduced sweeps u = c + G Z^{-1} a with the
                               port Green's functions G_k = R_k K_k^{-1} R_k^T (same iterates; the
-                              substitution runs only at convergence tests); 0 = choose by bytes.
+                              substitution runs only at convergence tests); 0 = port-reduced when the packed
+                              G_k hold at most 8 times the stored factor entries.
                               Port-reduced sweeps need one workgroup's port vectors in LDS
                               (about 5 p_k rhs_per_block values); when they do not fit, or
                               G_k was not built (p_k > 2048), substitution sweeps run. */

@@ -585,13 +585,18 @@ T *invz_of(vtm_ctx *h) {
 }
 
 // Port-reduced sweeps when the Green's functions exist and move no more than twice the factor's bytes.
+// Port-reduced sweeps by default when the packed G_k hold at most this many times the stored factor
+// entries: the G stream runs near HBM bandwidth while the substitution is bound by its level chain
+// (3D Poisson, 4096 boxes, 8 RHS: G 4.1x the factor and still 2x faster per sweep).
+constexpr double kGreenRatio = 8.0;
+
 bool use_schur(vtm_ctx *h) {
     if (!h->have_green) return false;
     // the port vectors of a workgroup (R right-hand sides) must fit in LDS
     if (vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, std::max(1, h->wave_R)) > vtm::kMaxLds) return false;
     if (h->opt.sweep_mode == 2) return true;
     if (h->opt.sweep_mode == 1) return false;
-    return (double)h->total_g <= 2.0 * (double)h->total_lower;
+    return (double)h->total_g <= kGreenRatio * (double)h->total_lower;
 }
 
 int32_t sweep_variant(vtm_ctx *h) {
@@ -1161,7 +1166,7 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
     HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
     // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
     const bool want_green = h->opt.sweep_mode != 1 && h->max_p > 0 && h->max_p <= 2048 &&
-                            (h->opt.sweep_mode == 2 || (double)h->total_g <= 2.0 * (double)h->total_lower);
+                            (h->opt.sweep_mode == 2 || (double)h->total_g <= kGreenRatio * (double)h->total_lower);
     if (want_green && h->plan_state == 0) {
         vtm_status rc = build_green_plan(h);
         if (rc) return rc;

@@ -109,6 +109,25 @@ __device__ inline int64_t gpack_index(int nb, int i, int j) {
     return ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + (i & 15) * 16 + (j & 15);
 }
 
+// The same tile with the k loop unrolled to KMAX (K <= KMAX): all operand loads are independent and
+// issued together, which matters when they come from global memory.
+template <int KMAX, typename LD>
+__device__ inline f64x4 gram_tile_unrolled(int ta, int tb, int K, int n, int lane, LD ld) {
+    const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15), kr = lane >> 4;
+    double av[KMAX / 4], bv[KMAX / 4];
+#pragma unroll
+    for (int q = 0; q < KMAX / 4; ++q) {
+        const int t = 4 * q + kr;
+        av[q] = (t < K && ra < n) ? ld(t, ra) : 0.0;
+        bv[q] = (t < K && rb < n) ? ld(t, rb) : 0.0;
+    }
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < KMAX / 4; ++q)
+        if (4 * q < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+    return acc;
+}
+
 struct FactorArgs {
     const double *A;       // local CSR values of the subgraph
     double *V;             // factor values of the subgraph
@@ -252,26 +271,43 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
         if (w > 0) {
             const double *T = X.gws + e.x;
             double *Y = X.gws + e.x + (int64_t)f * w;
-            for (int idx = r; idx < nc * w; idx += n) {  // Y = Linv T
+            const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
+            const uint16_t *rs_ = X.rel + X.sn_ridx[s];
+            // Y = Linv T; inner sums in groups of four so that four independent loads are in flight
+            for (int idx = r; idx < nc * w; idx += n) {
                 const int i = idx / w, a = idx - i * w;
                 double acc = T[i * w + a] / F[i * f + i];
-                for (int t = 0; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
+                int t = 0;
+                for (; t + 4 <= i; t += 4) {
+                    const double t0 = T[t * w + a], t1 = T[(t + 1) * w + a], t2 = T[(t + 2) * w + a],
+                                 t3 = T[(t + 3) * w + a];
+                    acc += F[t * f + i] * t0 + F[(t + 1) * f + i] * t1 + F[(t + 2) * f + i] * t2 +
+                           F[(t + 3) * f + i] * t3;
+                }
+                for (; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
                 Y[idx] = acc;
             }
             team_sync<BLK>();
-            const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
-            const uint16_t *rs_ = X.rel + X.sn_ridx[s];
             for (int idx = r; idx < m * w; idx += n) {  // T[nc:] - L21 Y into the parent's port front
                 const int q = idx / w, a = idx - q * w;
                 double acc = T[(nc + q) * w + a];
-                for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + q] * Y[t * w + a];
+                int t = 0;
+                for (; t + 4 <= nc; t += 4) {
+                    const double y0 = Y[t * w + a], y1 = Y[(t + 1) * w + a], y2 = Y[(t + 2) * w + a],
+                                 y3 = Y[(t + 3) * w + a];
+                    acc -= F[t * f + nc + q] * y0 + F[(t + 1) * f + nc + q] * y1 + F[(t + 2) * f + nc + q] * y2 +
+                           F[(t + 3) * f + nc + q] * y3;
+                }
+                for (; t < nc; ++t) acc -= F[t * f + nc + q] * Y[t * w + a];
                 X.gws[e.z + (int64_t)rs_[q] * pw + a + (pc0 - ppc0)] = acc;
             }
             const int tw = (w + 15) >> 4, kr = lane >> 4;
             for (int it = wv; it < tw * (tw + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
                 tri_tile(it, ta, tb);
-                const f64x4 acc = gram_tile(ta, tb, nc, w, lane, [&](int t, int a) { return Y[t * w + a]; });
+                const auto ldy = [&](int t, int a) { return Y[t * w + a]; };
+                const f64x4 acc = nc <= 20 ? gram_tile_unrolled<20>(ta, tb, nc, w, lane, ldy)
+                                                : gram_tile(ta, tb, nc, w, lane, ldy);
                 const int b = 16 * tb + (lane & 15);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
