@@ -174,8 +174,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="128^2 version of the workload (quick check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="ir_lrn,fp64_diag_sub,ir_diag",
-                    help="comma list of {ir,fp64}_{lrn,diag,aNN}[_sub|_port]: precision, impedance rule "
-                         "(learned network, diagonal, or NN times the diagonal), sweep mode (substitution, "
+                    help="comma list of {ir,fp64}_{lrn,match,diag,aNN}[_sub|_port]: precision, impedance rule "
+                         "(learned network, impedance matching, diagonal, or NN times the diagonal), sweep mode (substitution, "
                          "port-reduced, default chosen by the library); the first is the headline, the "
                          "second its comparison")
     ap.add_argument("--check-every", type=int, default=0, help="0 = adaptive test placement")
@@ -225,6 +225,8 @@ def main():
             z_rule, z = B.VTM_Z_DIAG, None
         elif zr == "lrn":
             z_rule, z, params = B.VTM_Z_LEARNED, None, Zm.load()
+        elif zr == "match":
+            z_rule, z = B.VTM_Z_MATCHED, None
         else:  # uniform multiplier alpha on the diagonal rule, e.g. a64
             alpha = float(zr[1:])
             hh = B.VTM(device=-1)

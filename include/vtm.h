@@ -60,7 +60,7 @@ enum { VTM_FP64 = 0, VTM_FP32_IR = 1 };
 enum { VTM_PART_GRID = 0, VTM_PART_RCB = 1, VTM_PART_GRAPH = 2, VTM_PART_USER = 3 };
 enum { VTM_SPLIT_BRANCH = 0, VTM_SPLIT_EQUAL = 1 };
 enum { VTM_TOPO_FACE = 0, VTM_TOPO_COMPLETE = 1 };
-enum { VTM_Z_DIAG = 0, VTM_Z_USER = 1, VTM_Z_LEARNED = 2 };
+enum { VTM_Z_DIAG = 0, VTM_Z_USER = 1, VTM_Z_LEARNED = 2, VTM_Z_MATCHED = 3 };
 
 typedef struct vtm_ctx *vtm_handle;
 
@@ -205,10 +205,28 @@ vtm_status vtm_get_partition(vtm_handle h, int64_t *s_ptr, int32_t *s_idx, int64
  *          VTM_Z_USER   : z_vtl[nvtl] host array, finite and > 0
  *          VTM_Z_LEARNED: the loaded impedance model predicts ln(Z a_vv) per VTL
  *                         (vtm_zmodel_load first); z_vtl ignored
+ *          VTM_Z_MATCHED: impedance matching (Section 7.1): starting from 1/a_vv, twice
+ *                         set each VTL's Z to the geometric mean of its two ports' input
+ *                         impedances (vtm_input_impedance), kept within [1/4, 4096] / a_vv,
+ *                         and factor again; needs at most 2048 port vertices per subgraph
+ *                         (else VTM_ERR_INVALID); setup_ms covers all three factorisations
  * Resets the waves to zero.  Errors: VTM_ERR_STATE (no partition),
  * VTM_ERR_INVALID (Z), VTM_ERR_NOT_SPD (first failing subgraph in the message).
  */
 vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl);
+
+/*
+ * Definition 7.1: the input impedance of every port, i.e. its potential for a unit inflow current
+ * there, with every other port of its subgraph terminated by its current characteristic impedance
+ * (as Z grows the terminations vanish and this tends to the definition's value with the other ports
+ * open, which needs an SPD piece).  From the port Green's functions of the last vtm_setup: with g
+ * the diagonal entry of R K_k^{-1} R^T at the port's vertex, r = 1 / (1/g - 1/Z_p); +inf where the
+ * port's own termination is what makes K_k definite.
+ *   r_port[nports]: host array, ports in partition order.
+ * Errors: VTM_ERR_STATE (no setup, or the setup built no Green's functions: sweep_mode 1 or more
+ * than 2048 port vertices in a subgraph).
+ */
+vtm_status vtm_input_impedance(vtm_handle h, double *r_port);
 
 /*
  * Solve A X = B for nrhs right-hand sides: zero initial waves (Example 5.1),

@@ -22,7 +22,7 @@ VTM_FP64, VTM_FP32_IR = 0, 1
 KIND = {"grid": 0, "rcb": 1, "graph": 2, "user": 3}
 SPLIT = {"branch": 0, "equal": 1}
 TOPO = {"face": 0, "complete": 1}
-VTM_Z_DIAG, VTM_Z_USER, VTM_Z_LEARNED = 0, 1, 2
+VTM_Z_DIAG, VTM_Z_USER, VTM_Z_LEARNED, VTM_Z_MATCHED = 0, 1, 2, 3
 
 
 class Options(C.Structure):
@@ -65,7 +65,7 @@ _lib = None
 # exported symbols declared in include/vtm.h and include/vtm_debug.h
 EXPORTS = ("vtm_create", "vtm_destroy", "vtm_last_error", "vtm_evs_partition", "vtm_get_partition", "vtm_setup",
            "vtm_solve", "vtm_run_sweeps", "vtm_reset_waves", "vtm_get_waves", "vtm_set_waves", "vtm_get_stats",
-           "vtm_debug_class", "vtm_zfeatures", "vtm_zmodel_load", "vtm_get_z", "vtm_trainer_create",
+           "vtm_debug_class", "vtm_zfeatures", "vtm_zmodel_load", "vtm_get_z", "vtm_input_impedance", "vtm_trainer_create",
            "vtm_trainer_destroy", "vtm_trainer_set_data", "vtm_trainer_grad", "vtm_trainer_epoch",
            "vtm_trainer_predict", "vtm_trainer_get_params", "vtm_autotune")
 NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 12, 5081, 5057
@@ -94,6 +94,7 @@ def lib():
         L.vtm_zfeatures.argtypes = [P, P]
         L.vtm_zmodel_load.argtypes = [P, P]
         L.vtm_get_z.argtypes = [P, P]
+        L.vtm_input_impedance.argtypes = [P, P]
         L.vtm_trainer_create.argtypes = [C.c_int32, P, C.POINTER(C.c_void_p)]
         L.vtm_trainer_destroy.argtypes = [P]
         L.vtm_trainer_set_data.argtypes = [P, P, P, C.c_int64]
@@ -322,6 +323,12 @@ class VTM:
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.shape == (ZMODEL_PARAMS,)
         _check(lib().vtm_zmodel_load(self._h, _np_ptr(p)))
+
+    def input_impedance(self) -> np.ndarray:
+        """Input impedance of every port (Definition 7.1) with the other ports terminated by their Z."""
+        r = np.zeros(self.info["nports"])
+        _check(lib().vtm_input_impedance(self._h, _np_ptr(r)))
+        return r
 
     def get_z(self) -> np.ndarray:
         z = np.zeros(self.info["nvtl"])

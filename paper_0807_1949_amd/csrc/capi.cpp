@@ -80,7 +80,7 @@ struct vtm_ctx {
     DevBuf d_gsn, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws, d_levmaxf;
     int plan_state = 0;  // 0 not built, 1 ready, -1 not applicable (fall back to per-column solves)
     int64_t gws_total = 0;
-    std::vector<int32_t> h_pgptr;
+    std::vector<int32_t> h_pgptr, h_pgbeg, h_pgcnt;
     std::vector<uint16_t> h_pgpos;
     int32_t max_nu = 0;
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
@@ -433,6 +433,8 @@ vtm_status upload_partition(vtm_ctx *h) {
     h->total_ws = wo;
     h->h_pgptr = pgptr;
     h->h_pgpos = pgpos;
+    h->h_pgbeg = pgbeg;
+    h->h_pgcnt = pgcnt;
     h->plan_state = 0;
     {
         std::vector<int64_t> goff(nsub + 1, 0);
@@ -1030,6 +1032,139 @@ vtm_status learned_z(vtm_ctx *h) {
     return VTM_OK;
 }
 
+// Impedances set, augmentation, factorisation and (when wanted or forced) the port Green's functions.
+vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, bool force_green) {
+    const vtm::Partition &P = h->P;
+    hipStream_t st = h->stream;
+    if (z_rule == VTM_Z_LEARNED) {
+        vtm_status rc = learned_z(h);
+        if (rc) return rc;
+    } else {
+        HIP_TRY(upload(h->d_z, z, st));
+    }
+    HIP_TRY(ensure(h->d_invz64, sizeof(double) * (h->nports + 1)));
+    HIP_TRY(ensure(h->d_invz32, sizeof(float) * (h->nports + 1)));
+    HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
+    HIP_TRY(ensure(h->d_status, sizeof(int32_t) * (P.nsub + 1)));
+    DevBuf ws;
+    HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
+    // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
+    const bool want_green = h->max_p > 0 && h->max_p <= 2048 &&
+                            (force_green || (h->opt.sweep_mode != 1 && (h->opt.sweep_mode == 2 ||
+                                             (double)h->total_g <= kGreenRatio * (double)h->total_lower)));
+    if (want_green && h->plan_state == 0) {
+        vtm_status rc = build_green_plan(h);
+        if (rc) return rc;
+    }
+    if (want_green && h->plan_state == 1) HIP_TRY(ensure(h->d_gws, sizeof(double) * (h->gws_total + 2)));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+    vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
+                     h->d_invz32.as<float>(), h->nports, st);
+    const bool fused = want_green && h->plan_state == 1;
+    if (want_green) {
+        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
+        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
+        if (fused) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
+    }
+    vtm::launch_factor(dev_sym(h), dev_sub(h), P.nsub, h->max_front, h->d_aval.as<double>(),
+                       h->d_invz64.as<double>(), h->d_vals64.as<double>(), ws.as<double>(),
+                       h->d_status.as<int32_t>(), dev_green(h, fused), h->d_goff.as<int64_t>(),
+                       want_green ? h->d_G64.as<double>() : nullptr, st);
+    if (h->fp32()) {
+        HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
+        vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
+    }
+    h->have_green = false;
+    if (want_green) {
+        if (!fused)
+            vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p,
+                              h->d_vals64.as<double>(), h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
+        if (h->fp32()) {
+            HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 4)));
+            vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);
+        }
+        h->have_green = true;
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipGetLastError());
+    std::vector<int32_t> status(P.nsub);
+    HIP_TRY(hipMemcpyAsync(status.data(), h->d_status.p, sizeof(int32_t) * P.nsub, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ws.release();
+    h->stats.setup_ms = ms;
+    for (int32_t k = 0; k < P.nsub; ++k)
+        if (status[k]) {
+            h->set_up = false;
+            return fail(VTM_ERR_NOT_SPD, "non-positive pivot in subgraph " + std::to_string(k) + " (supernode " +
+                                             std::to_string(status[k] - 1) + ")");
+        }
+    h->set_up = true;
+    h->wave_nrhs = 0;  // fresh zero waves on the next solve
+    h->drop_graphs();
+    return VTM_OK;
+}
+
+// Input impedance of every port (Definition 7.1) with the other ports terminated by their current Z:
+// with g the diagonal entry of G_k = R K_k^{-1} R^T at the port's vertex, removing the port's own
+// termination 1/Z_p from K_k gives r = 1 / (1/g - 1/Z_p) (Sherman-Morrison).  Needs G.
+vtm_status port_rin(vtm_ctx *h, const std::vector<double> &z, std::vector<double> &r) {
+    if (!h->have_green) return fail(VTM_ERR_STATE, "input impedances need the port Green's functions");
+    DevBuf gd;
+    HIP_TRY(ensure(gd, sizeof(double) * (h->npg + 1)));
+    vtm::launch_gdiag(dev_sub(h), h->P.nsub, h->d_goff.as<int64_t>(), h->d_G64.as<double>(), gd.as<double>(), h->stream);
+    std::vector<double> g(h->npg);
+    HIP_TRY(hipMemcpyAsync(g.data(), gd.p, sizeof(double) * h->npg, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    gd.release();
+    r.assign(h->nports, 0.0);
+    for (int32_t q = 0; q < h->npg; ++q)
+        for (int32_t j = 0; j < h->h_pgcnt[q]; ++j) {
+            const int64_t p = h->h_pgbeg[q] + j;
+            const double d = 1.0 / g[q] - 1.0 / z[h->P.port_vtl[p]];
+            r[p] = d > 1e-14 / g[q] ? 1.0 / d : std::numeric_limits<double>::infinity();
+        }
+    return VTM_OK;
+}
+
+// Impedance matching (Section 7.1): starting from the diagonal rule, kMatchIters times set every VTL's
+// Z to the geometric mean of its two ports' input impedances (each near "the input impedance of
+// either port"), within [1/4, 4096] / a_vv, and set up again.
+constexpr int kMatchIters = 2;
+
+vtm_status matched_setup(vtm_ctx *h) {
+    const vtm::Partition &P = h->P;
+    const int64_t nvtl = (int64_t)P.vtl_v.size();
+    if (h->max_p > 2048) return fail(VTM_ERR_INVALID, "impedance matching needs at most 2048 port vertices per subgraph");
+    std::vector<int64_t> ends(2 * nvtl, -1);
+    for (int64_t p = 0; p < (int64_t)P.port_vtl.size(); ++p) {
+        const int64_t l = P.port_vtl[p];
+        ends[2 * l + (ends[2 * l] < 0 ? 0 : 1)] = p;
+    }
+    std::vector<double> z = P.zdiag, r;
+    double total_ms = 0.0;
+    for (int it = 0; it < kMatchIters; ++it) {
+        vtm_status rc = setup_core(h, VTM_Z_USER, z, true);
+        if (rc) return rc;
+        total_ms += h->stats.setup_ms;
+        if ((rc = port_rin(h, z, r))) return rc;
+        for (int64_t l = 0; l < nvtl; ++l) {
+            const double a = r[ends[2 * l]], b = r[ends[2 * l + 1]];
+            const double m = std::sqrt(a) * std::sqrt(b);
+            z[l] = std::min(std::max(std::isfinite(m) ? m : 1e300, 0.25 * P.zdiag[l]), 4096.0 * P.zdiag[l]);
+        }
+    }
+    vtm_status rc = setup_core(h, VTM_Z_USER, z, false);
+    h->stats.setup_ms += total_ms;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1148,81 +1283,23 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
             if (!(z[l] > 0.0) || !std::isfinite(z[l])) return fail(VTM_ERR_INVALID, "Z must be finite and > 0");
     } else if (z_rule == VTM_Z_LEARNED) {
         if (!h->model_loaded) return fail(VTM_ERR_STATE, "VTM_Z_LEARNED before vtm_zmodel_load");
+    } else if (z_rule == VTM_Z_MATCHED) {
+        return matched_setup(h);
     } else {
         return fail(VTM_ERR_INVALID, "unknown z_rule");
     }
-    hipStream_t st = h->stream;
-    if (z_rule == VTM_Z_LEARNED) {
-        vtm_status rc = learned_z(h);
-        if (rc) return rc;
-    } else {
-        HIP_TRY(upload(h->d_z, z, st));
-    }
-    HIP_TRY(ensure(h->d_invz64, sizeof(double) * (h->nports + 1)));
-    HIP_TRY(ensure(h->d_invz32, sizeof(float) * (h->nports + 1)));
-    HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
-    HIP_TRY(ensure(h->d_status, sizeof(int32_t) * (P.nsub + 1)));
-    DevBuf ws;
-    HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
-    // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
-    const bool want_green = h->opt.sweep_mode != 1 && h->max_p > 0 && h->max_p <= 2048 &&
-                            (h->opt.sweep_mode == 2 || (double)h->total_g <= kGreenRatio * (double)h->total_lower);
-    if (want_green && h->plan_state == 0) {
-        vtm_status rc = build_green_plan(h);
-        if (rc) return rc;
-    }
-    if (want_green && h->plan_state == 1) HIP_TRY(ensure(h->d_gws, sizeof(double) * (h->gws_total + 2)));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
-    vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
-                     h->d_invz32.as<float>(), h->nports, st);
-    const bool fused = want_green && h->plan_state == 1;
-    if (want_green) {
-        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
-        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
-        if (fused) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
-    }
-    vtm::launch_factor(dev_sym(h), dev_sub(h), P.nsub, h->max_front, h->d_aval.as<double>(),
-                       h->d_invz64.as<double>(), h->d_vals64.as<double>(), ws.as<double>(),
-                       h->d_status.as<int32_t>(), dev_green(h, fused), h->d_goff.as<int64_t>(),
-                       want_green ? h->d_G64.as<double>() : nullptr, st);
-    if (h->fp32()) {
-        HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
-        vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
-    }
-    h->have_green = false;
-    if (want_green) {
-        if (!fused)
-            vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p,
-                              h->d_vals64.as<double>(), h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
-        if (h->fp32()) {
-            HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 4)));
-            vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);
-        }
-        h->have_green = true;
-    }
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipGetLastError());
-    std::vector<int32_t> status(P.nsub);
-    HIP_TRY(hipMemcpyAsync(status.data(), h->d_status.p, sizeof(int32_t) * P.nsub, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    ws.release();
-    h->stats.setup_ms = ms;
-    for (int32_t k = 0; k < P.nsub; ++k)
-        if (status[k]) {
-            h->set_up = false;
-            return fail(VTM_ERR_NOT_SPD, "non-positive pivot in subgraph " + std::to_string(k) + " (supernode " +
-                                             std::to_string(status[k] - 1) + ")");
-        }
-    h->set_up = true;
-    h->wave_nrhs = 0;  // fresh zero waves on the next solve
-    h->drop_graphs();
+    return setup_core(h, z_rule, z, false);
+}
+
+vtm_status vtm_input_impedance(vtm_handle h, double *r_port) {
+    if (!h || !r_port) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "vtm_input_impedance before vtm_setup");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    std::vector<double> z(h->P.vtl_v.size()), r;
+    HIP_TRY(hipMemcpy(z.data(), h->d_z.p, sizeof(double) * z.size(), hipMemcpyDeviceToHost));
+    vtm_status rc = port_rin(h, z, r);
+    if (rc) return rc;
+    std::copy(r.begin(), r.end(), r_port);
     return VTM_OK;
 }
 

@@ -626,6 +626,14 @@ __global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double 
     }
 }
 
+// Diagonal of every G_k (one entry per port vertex), from the packed layout.
+__global__ void k_gdiag(DevSub D, const int64_t *__restrict__ goff, const double *__restrict__ G,
+                        double *__restrict__ gd) {
+    const int k = blockIdx.x;
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0, nb = (p + 15) >> 4;
+    for (int j = threadIdx.x; j < p; j += blockDim.x) gd[pg0 + j] = G[goff[k] + gpack_index(nb, j, j)];
+}
+
 // c[g][q][c] = K^{-1} b~ at the port vertices (local solutions of a zero-wave solve).
 template <typename T>
 __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
@@ -1192,6 +1200,10 @@ void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk
     const dim3 grid(nsub, (max_p + 3) / 4);
     if (V) hipLaunchKernelGGL(k_green<1>, grid, dim3(256), shm, st, S, D, vals, goff, G);
     else hipLaunchKernelGGL(k_green<0>, grid, dim3(256), shm, st, S, D, vals, goff, G);
+}
+
+void launch_gdiag(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, double *gd, hipStream_t st) {
+    hipLaunchKernelGGL(k_gdiag, dim3(nsub), dim3(128), 0, st, D, goff, G, gd);
 }
 
 template <typename T>

@@ -108,6 +108,8 @@ hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_
 // (FP64, packed like above); used when the column plan does not apply.
 void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
                   const double *vals, const int64_t *goff, double *G, hipStream_t st);
+// gd[port vertex] = diagonal entry of its G_k (FP64).
+void launch_gdiag(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, double *gd, hipStream_t st);
 // cport[g][port vertex][R] = local solutions at the port vertices.
 template <typename T>
 void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,
