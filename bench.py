@@ -166,6 +166,51 @@ def run_configs(names, B, Zm, torch, out_path=None, sweep_mode=0):
     return rows
 
 
+def paper_shape(B, Zm, out_path=None):
+    """Section 9's experiments in shape (the paper's figures are absent, so there is no number to
+    compare with): a 5-point Dirichlet Laplacian, (i) 65 x 65 (n = 4225) on p = 4 ... 128 tiles,
+    (ii) p = 64 tiles for n = 17^2 ... 121^2.  The exact solution x* is seeded uniform[-1, 1] and
+    b = A x*; plain FP64 VTM (substitution sweeps) with the diagonal rule, impedance matching
+    and the learned rule; K = sweeps until the RMS error against x* falls below 1e-12 RMS(x*) (tested every
+    5 sweeps; the double-precision floor of this iteration lies near 1e-14)."""
+    import numpy as np
+
+    from gen import systems as S
+
+    tiles = {4: (2, 2), 8: (4, 2), 16: (4, 4), 32: (8, 4), 64: (8, 8), 128: (16, 8)}
+    cases = [("p", p, 65) for p in (4, 8, 16, 32, 64, 128)] + [("n", 64, nx) for nx in (17, 33, 49, 65, 97, 121)]
+    rows = []
+    for kind, p, nx in cases:
+        A = S.laplace2d_dirichlet(nx)
+        xs = np.random.default_rng([9, nx]).uniform(-1.0, 1.0, A.n)
+        b = (A.to_scipy() @ xs)[None, :]
+        px, py = tiles[p]
+        spec = dict(kind="grid", dims=(nx, nx, 1), parts=(px, py, 1))
+        row = dict(series=kind, p=p, n=A.n)
+        for rule, label in ((B.VTM_Z_DIAG, "diag"), (B.VTM_Z_MATCHED, "matched"), (B.VTM_Z_LEARNED, "learned")):
+            h = B.VTM(device=0, precision=B.VTM_FP64, sweep_mode=1)
+            h.evs_partition(A, spec)
+            if rule == B.VTM_Z_LEARNED:
+                h.zmodel_load(Zm.load())
+            h.setup(rule)
+            k, err, floor = 0, 1.0, 1.0
+            while k < 40000:
+                x = h.run_sweeps(b, 5)[0]
+                k += 5
+                err = float(np.sqrt(np.mean((x - xs) ** 2)) / np.sqrt(np.mean(xs ** 2)))
+                floor = min(floor, err)
+                if err <= 1e-12:
+                    break
+            row[label] = k if err <= 1e-12 else None
+            h.close()
+        rows.append(row)
+        log(f"  {kind}: p {p:3d} n {A.n:6d}  K(diag) {row['diag']}  K(matched) {row['matched']}  K(learned) {row['learned']}")
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(rows, f, indent=1)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +229,8 @@ def main():
                     "size (comma list of c1..c5) against the oracle")
     ap.add_argument("--configs-out", default="", help="write the --configs results as JSON to this path")
     ap.add_argument("--configs-mode", type=int, default=0, help="sweep mode for --configs (0 library choice, 1, 2)")
+    ap.add_argument("--paper-shape", default="", help="instead of the benchmark line: Section 9's K(p), K(n) "
+                    "experiments; write the table as JSON to this path")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="copy this many MiB with a plain device copy first (counter calibration)")
     args = ap.parse_args()
@@ -198,6 +245,9 @@ def main():
     from paper_0807_1949_amd import binding as B
     from paper_0807_1949_amd import zmodel as Zm
 
+    if args.paper_shape:
+        paper_shape(B, Zm, args.paper_shape)
+        return
     if args.configs:
         run_configs(args.configs.split(","), B, Zm, torch, args.configs_out or None, args.configs_mode)
         return
