@@ -63,24 +63,45 @@ def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warm
     return out
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the sweep kernel from the committed counter summary, or None when the
-    kernels' source has changed since the counters were taken (or the kernel is another one)."""
+def _profile_fields(name, keys):
+    """Fields of a committed counter summary under profiles/, or None when the kernels' source has
+    changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "sweep_traffic_c2_lognormal_1024.md")
-    key = kernel + "-traffic-bytes-per-launch"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0].strip() in ("kernels-source-sha256", key):
+        if ":" in line and line.split(":", 1)[0].strip() in keys + ("kernels-source-sha256",):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_0807_1949_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernels-source-sha256") or key not in fields:
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("kernels-source-sha256"):
         return None
-    return float(fields[key])
+    if any(k not in fields for k in keys):
+        return None
+    return fields
+
+
+def measured_traffic(kernel):
+    """HBM bytes per sweep of the sweep kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None."""
+    key = kernel + "-traffic-bytes-per-sweep"
+    f = _profile_fields("sweep_traffic_c2_lognormal_1024.md", (key,))
+    return None if f is None else float(f[key])
+
+
+def setup_mfma():
+    """Matrix-core use of the factorisation kernel from its counters (FP64 MFMA FLOPs per launch over
+    the launch's duration), or None when the kernels have changed since."""
+    keys = ("k_factor-mfma-flops-per-launch", "k_factor-duration-us")
+    f = _profile_fields("setup_mfma_c2_lognormal_1024.md", keys)
+    if f is None:
+        return None
+    flops, us = float(f[keys[0]]), float(f[keys[1]])
+    achieved = flops / (us * 1e-6) / 1e12
+    return dict(kernel="k_factor", bound="latency", mfma_dtype="f64", flops_per_launch=flops, avg_launch_us=us,
+                achieved=achieved, peak=78.6, unit="TFLOP/s", frac=achieved / 78.6)
 
 
 def cpu_baseline(O, A, spec, b, z):
@@ -318,6 +339,7 @@ def main():
     )
     if len(variants) > 1:
         line["speedup_vs_" + variants[1]] = results[variants[1]]["step_s"] / head["step_s"]
+    line["setup_mfma"] = setup_mfma()
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 
