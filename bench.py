@@ -335,7 +335,11 @@ def main():
                   for v, r in results.items()},
         roofline=dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(kernel),
-                      bytes_per_launch=st["bytes_per_sweep"], avg_launch_us=sweep_s * 1e6),
+                      bytes_per_sweep=st["bytes_per_sweep"], avg_sweep_us=sweep_s * 1e6,
+                      note=("one persistent launch per batch of sweeps: G_k read once per launch, the per-sweep "
+                            "time is set by the latency of the wave exchange between neighbouring workgroups, "
+                            "not by bandwidth; achieved and traffic are per sweep") if st["persistent"] else
+                           "one launch per sweep; achieved and traffic are per launch"),
     )
     if len(variants) > 1:
         line["speedup_vs_" + variants[1]] = results[variants[1]]["step_s"] / head["step_s"]

@@ -119,6 +119,8 @@ struct vtm_ctx {
     DevBuf d_tw, d_abort;
     int32_t tag = 1;
     int64_t persist_launches = 0;  // persistent launches of the current solve or run
+    int32_t *abort_host = nullptr;  // pinned copy of the abort flag, read at the next synchronisation
+    bool abort_pending = false;
     vtm_stats stats{};
 
     vtm_ctx() {
@@ -137,6 +139,7 @@ struct vtm_ctx {
         (void)hipSetDevice(opt.device);
         drop_graphs();
         for (DevBuf *b : all) b->release();
+        if (abort_host) (void)hipHostFree(abort_host);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     bool fp32() const { return opt.precision == VTM_FP32_IR; }
@@ -561,13 +564,26 @@ vtm_status stage_b(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb) {
     return VTM_OK;
 }
 
+// After a stream synchronisation: did a persistent launch since the last check give up on a wait?
+vtm_status check_abort(vtm_ctx *h) {
+    if (!h->abort_pending) return VTM_OK;
+    h->abort_pending = false;
+    if (h->abort_host && *h->abort_host) {
+        *h->abort_host = 0;
+        HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return fail(VTM_ERR_HIP, "persistent sweep: a wave exchange wait timed out");
+    }
+    return VTM_OK;
+}
+
 vtm_status write_x(vtm_ctx *h, const double *src, double *x, int32_t nrhs, int64_t ldx) {
     const int64_t n = h->P.n;
     hipMemcpyKind kind = is_device_ptr(x) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIP_TRY(hipMemcpy2DAsync(x, sizeof(double) * ldx, src, sizeof(double) * n, sizeof(double) * n, nrhs, kind,
                              h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    return VTM_OK;
+    return check_abort(h);
 }
 
 template <typename T>
@@ -650,8 +666,14 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
         if (schur && persistent_ok(h, R, ng)) {
             const int64_t nw = (int64_t)ng * h->nports * R;
             HIP_TRY(ensure(h->d_tw, sizeof(unsigned long long) * (2 * nw + 2)));
-            HIP_TRY(ensure(h->d_abort, sizeof(int32_t) * 2));
-            HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
+            if (!h->d_abort.p) {
+                HIP_TRY(ensure(h->d_abort, sizeof(int32_t) * 2));
+                HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
+            }
+            if (!h->abort_host) {
+                HIP_TRY(hipHostMalloc((void **)&h->abort_host, sizeof(int32_t), hipHostMallocDefault));
+                *h->abort_host = 0;
+            }
             bool refused = false;
             for (int64_t left = count; left > 0;) {
                 const int32_t nsw = (int32_t)std::min<int64_t>(left, 1 << 20);
@@ -675,11 +697,10 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
                 ++h->persist_launches;
                 left -= nsw;
             }
-            int32_t aborted = 0;
             if (refused) goto per_sweep;
-            HIP_TRY(hipMemcpyAsync(&aborted, h->d_abort.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipStreamSynchronize(h->stream));
-            if (aborted) return fail(VTM_ERR_HIP, "persistent sweep: a wave exchange wait timed out");
+            // the flag is read at the caller's next synchronisation (check_abort); it stays set until then
+            HIP_TRY(hipMemcpyAsync(h->abort_host, h->d_abort.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+            h->abort_pending = true;
             h->waves_zero = false;
             h->stats.persistent = 1;
             return VTM_OK;
@@ -790,7 +811,7 @@ vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::v
     rel.resize((size_t)h->P.nsys * nrhs);
     HIP_TRY(hipMemcpyAsync(rel.data(), h->d_relres.p, sizeof(double) * rel.size(), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    return VTM_OK;
+    return check_abort(h);
 }
 
 template <typename T>
@@ -1413,6 +1434,7 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
             if (!rc) rc = h->fp32() ? run_sweeps_dev<float>(h, timed) : run_sweeps_dev<double>(h, timed);
             HIP_TRY(hipEventRecord(e1, h->stream));
             HIP_TRY(hipEventSynchronize(e1));
+            if (!rc) rc = check_abort(h);
             if (rc) { h->opt = saved; return rc; }
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
