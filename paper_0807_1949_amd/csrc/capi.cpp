@@ -84,7 +84,7 @@ struct vtm_ctx {
     std::vector<uint16_t> h_pgpos;
     int32_t max_nu = 0;
     DevBuf d_cls, d_lev, d_colsn, d_snc0, d_snnc, d_snm, d_snval, d_snridx, d_snuoff, d_ridx, d_rel, d_chptr, d_chidx,
-        d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scsrc, d_scdst;
+        d_segptr, d_segoff, d_segc0, d_segnc, d_scptr, d_scdst;
     // subgraph level
     DevBuf d_subcls, d_subval, d_subx, d_subaval, d_subws, d_pgptr, d_pgpos, d_pgbeg, d_pgcnt, d_portptr;
     // maps, matrix, ports
@@ -125,7 +125,7 @@ struct vtm_ctx {
 
     vtm_ctx() {
         DevBuf *list[] = {&d_cls, &d_lev, &d_colsn, &d_snc0, &d_snnc, &d_snm, &d_snval, &d_snridx, &d_snuoff, &d_ridx,
-                          &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr, &d_scsrc,
+                          &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr,
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
@@ -200,7 +200,6 @@ vtm::DevSym dev_sym(vtm_ctx *h) {
     s.u_sn = h->d_usn.as<uint16_t>();
     s.lev_u = h->d_levu.as<int32_t>();
     s.sc_ptr = h->d_scptr.as<int32_t>();
-    s.sc_src = h->d_scsrc.as<int32_t>();
     s.sc_dst = h->d_scdst.as<int32_t>();
     return s;
 }
@@ -349,7 +348,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     // ---- class arrays
     std::vector<vtm::ClassDev> cls;
     std::vector<int32_t> lev, colsn, snc0, snnc, snm, snval, snridx, snuoff, chptr, chidx, segptr, segoff, scptr,
-        scsrc, scdst;
+        scdst;
     std::vector<uint16_t> ridx, rel, segc0, segnc, segu, usn;
     std::vector<int32_t> levu, colrec, urec, levmaxf;
     h->max_nk = 0;
@@ -368,7 +367,7 @@ vtm_status upload_partition(vtm_ctx *h) {
         d.o_colp = (int32_t)segptr.size();
         d.o_ridx = (int32_t)ridx.size();
         d.o_seg = (int32_t)segoff.size();
-        d.o_sc = (int32_t)scsrc.size();
+        d.o_sc = (int32_t)scdst.size();
         d.o_chi = (int32_t)chidx.size();
         d.nval = C.nval;
         d.ws_u = C.ws_u;
@@ -398,7 +397,6 @@ vtm_status upload_partition(vtm_ctx *h) {
         segnc.insert(segnc.end(), C.seg_nc.begin(), C.seg_nc.end());
         ridx.insert(ridx.end(), C.ridx.begin(), C.ridx.end());
         rel.insert(rel.end(), C.rel.begin(), C.rel.end());
-        scsrc.insert(scsrc.end(), C.sc_src.begin(), C.sc_src.end());
         scdst.insert(scdst.end(), C.sc_dst.begin(), C.sc_dst.end());
         h->max_nk = std::max(h->max_nk, C.nk);
         h->max_front = std::max(h->max_front, C.max_front);
@@ -409,6 +407,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     std::vector<int32_t> subcls(nsub), pgptr(nsub + 1, 0), pgbeg, pgcnt;
     std::vector<int64_t> subval(nsub), subx(nsub), subaval(nsub), subws(nsub);
     std::vector<uint16_t> pgpos;
+    std::vector<double> afront;  // lower entries of every local matrix in the order of its class's scatter list
     int64_t vo = 0, wo = 0;
     h->total_lower = 0;
     for (int32_t k = 0; k < nsub; ++k) {
@@ -419,7 +418,8 @@ vtm_status upload_partition(vtm_ctx *h) {
         vo += C.nval;
         h->total_lower += C.nlower;
         subx[k] = P.loc_ptr[k];
-        subaval[k] = P.lrp[P.loc_ptr[k]];
+        subaval[k] = (int64_t)afront.size();
+        for (const int32_t src : C.sc_src) afront.push_back(P.lval[P.lrp[P.loc_ptr[k]] + src]);
         subws[k] = wo;
         wo += C.ws_u + (int64_t)C.max_front * C.max_front + ((C.nk + 1) & ~1);  // updates, front, port diagonal
         for (int64_t p = P.port_ptr[k]; p < P.port_ptr[k + 1];) {
@@ -497,7 +497,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     UP(d_cls, cls); UP(d_lev, lev); UP(d_levmaxf, levmaxf); UP(d_colsn, colsn); UP(d_snc0, snc0); UP(d_snnc, snnc); UP(d_snm, snm);
     UP(d_snval, snval); UP(d_snridx, snridx); UP(d_snuoff, snuoff); UP(d_ridx, ridx); UP(d_rel, rel);
     UP(d_chptr, chptr); UP(d_chidx, chidx); UP(d_segptr, segptr); UP(d_segoff, segoff); UP(d_segc0, segc0);
-    UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_colrec, colrec); UP(d_urec, urec); UP(d_scptr, scptr); UP(d_scsrc, scsrc); UP(d_scdst, scdst);
+    UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_colrec, colrec); UP(d_urec, urec); UP(d_scptr, scptr); UP(d_scdst, scdst);
     UP(d_subcls, subcls); UP(d_subval, subval); UP(d_subx, subx); UP(d_subaval, subaval); UP(d_subws, subws);
     UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt);
     {
@@ -508,7 +508,7 @@ vtm_status upload_partition(vtm_ctx *h) {
         UP(d_portptr, portptr);
     }
     UP(d_fvtx, fvtx); UP(d_fmul, fmul); UP(d_cpptr, P.s_ptr); UP(d_cpidx, cpidx);
-    UP(d_rp, h->A.rp); UP(d_ci, h->A.ci); UP(d_v, h->A.v); UP(d_aval, P.lval);
+    UP(d_rp, h->A.rp); UP(d_ci, h->A.ci); UP(d_v, h->A.v); UP(d_aval, afront);
     UP(d_twin, twin); UP(d_portvtl, portvtl); UP(d_chunkrow, chunkrow); UP(d_chunksys, chunksys);
     UP(d_syschunk, syschunk);
 #undef UP

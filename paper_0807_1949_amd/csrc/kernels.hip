@@ -45,26 +45,33 @@ __global__ void k_to_f32(const double *__restrict__ s, float *__restrict__ d, in
 //
 // One workgroup per subgraph walks the assembly tree level by level.  A level whose fronts are
 // small is spread over the waves (one supernode per wave at a time, wave-level synchronisation
-// only); otherwise the whole workgroup takes its supernodes one after the other.  Per supernode s
-// (front F of order f = nc + m in LDS, row-major; only its lower triangle carries the matrix, so the
-// strictly upper part of the leading nc x nc block and the nc x m block to its right are scratch):
-//   1. assemble: local entries, the port diagonal Z^{-1}, the children's update matrices;
-//   2. L11 = chol(F11) in place (one wave when nc <= kWaveChol, else the workgroup);
-//   3. Linv = L11^{-1}, column j by one thread: strictly lower part stored transposed in the upper
-//      triangle (Linv[i][j] at F[j][i]); the diagonal is 1 / L11[j][j];
-//   4. L21 = F21 L11^{-T}, stored transposed in the upper-right block (L21[q][t] at F[t][nc + q]);
-//   5. outputs Linv and W = L21 Linv, and the update matrix F22 - L21 L21^T written straight to
-//      the workspace (lower triangle); the rank-nc update runs on the FP64 matrix cores in 16 x 16
-//      tiles when m >= 16;
-//   6. (port Green's functions) the forward substitution of all port columns through s, while
-//      Linv and L21 are still in LDS: with E the unit columns of the port vertices, Y = L^{-1} E
-//      and G_k = E^T K_k^{-1} E = Y^T Y.  Column j of Y is non-zero only on the supernodes above
-//      the one holding port j, so s carries just the w_s ports below it (a contiguous range, see
-//      DevGreen).  Its port front T_s ((nc + m) x w_s, workspace) holds the unit entries of its
-//      own ports and what the children pushed; Y_s = Linv T_s, the update T_s[nc:] - L21 Y_s goes
-//      into the parent's port front (siblings own disjoint columns: plain stores), and
-//      G[ports of s, ports of s] += Y_s^T Y_s on the matrix cores (siblings own disjoint blocks).
+// only); otherwise the whole workgroup takes its supernodes one after the other.
+//
+// Fronts that fit in LDS (factor_front): the front F of order f = nc + m is assembled (local
+// entries with the port diagonal Z^{-1}, then the children's update matrices) and eliminated by
+// nc rank-1 steps that produce everything the sweep and the parent need at once.  With B the
+// f x nc right side [I; 0] carried along (forward substitution with the front's unit lower factor),
+// step k takes d = sqrt(F[k][k]), scales column k by 1/d and applies the rank-1 update to every
+// column c > k over all rows; B[c][i] lives at F[i][c] (i < c, the strictly upper part, which the
+// symmetric matrix does not use) and row k of it is reset when k becomes the pivot.  After nc
+// steps
+//   F[j][i], j <= i < nc   Linv = L11^{-1} (its diagonal 1/d kept beside the front),
+//   F[j][nc + q]           -W = -L21 L11^{-1},
+//   F[nc + a][nc + b]      the update matrix F22 - L21 L21^T (lower triangle).
+// Port Green's functions: with E the unit columns of the port vertices, Y = L^{-1} E and
+// G_k = E^T K_k^{-1} E = Y^T Y.  Column j of Y is non-zero only on the supernodes above the one
+// holding port j, so s carries just the w_s ports below it (a contiguous range, see DevGreen).  Its
+// port front T_s ((nc + m) x w_s, workspace) holds the unit entries of its own ports and what the
+// children pushed; [Y_s; U_s] = [Linv; -W] T_s[:nc] + [0; T_s[nc:]] is one product on the FP64
+// matrix cores, U_s goes into the parent's port front (siblings own disjoint columns: plain
+// stores) and G[ports of s, ports of s] += Y_s^T Y_s (matrix cores; atomic adds that never meet
+// another add to the same entry inside one level, so the sums keep their order).
+//
+// Fronts too large for LDS (factor_node) keep the front in the workspace and run the same
+// algebra step by step: Cholesky, Linv, L21, outputs, update (matrix cores), Green's functions.
 constexpr int kWaveChol = 48;
+constexpr int kPreA = 4, kPreU = 8;  // assembly entries per thread loaded before the first LDS store
+constexpr int kFactorLds = 5056;     // doubles of LDS per workgroup for the fronts (four workgroups per CU)
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -77,7 +84,7 @@ __device__ inline void team_sync() {
     else wave_sync();
 }
 
-// Lower-triangle tile (ta, tb <= ta) of tile number it in row-major triangular order.
+// Lower-triangle entry (ta, tb <= ta) of number it in row-major triangular order.
 __device__ inline void tri_tile(int it, int &ta, int &tb) {
     ta = (int)((sqrtf(8.0f * (float)it + 1.0f) - 1.0f) * 0.5f);
     while (ta * (ta + 1) / 2 > it) --ta;
@@ -85,17 +92,37 @@ __device__ inline void tri_tile(int it, int &ta, int &tb) {
     tb = it - ta * (ta + 1) / 2;
 }
 
+// Cover of a rows x cols rectangle by a team of n threads (n a power of two): the low bits of the
+// rank pick the column (stride cw), the high bits the first row (stride rs); no integer division.
+struct Cover {
+    int c, cw, r0, rs;
+};
+__device__ inline Cover cover(int cols, int r, int n) {
+    int cw = cols <= 1 ? 1 : 1 << (32 - __clz(cols - 1));
+    if (cw > n) cw = n;
+    const int lw = __ffs(cw) - 1;
+    return Cover{r & (cw - 1), cw, r >> lw, n >> lw};
+}
+
 // 16 x 16 tile (ta, tb) of P^T P for P (K x n) read through ld(t, col): v_mfma_f64_16x16x4, where
-// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 j + l / 16][l % 16].
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 j + l / 16][l % 16].  The
+// operands of four k-steps are loaded before the first product, so that loads from global memory
+// are in flight together.
 template <typename LD>
 __device__ inline f64x4 gram_tile(int ta, int tb, int K, int n, int lane, LD ld) {
     const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15), kr = lane >> 4;
     f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int t0 = 0; t0 < K; t0 += 4) {
-        const int t = t0 + kr;
-        const double av = (t < K && ra < n) ? ld(t, ra) : 0.0;
-        const double bv = (t < K && rb < n) ? ld(t, rb) : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    for (int t0 = 0; t0 < K; t0 += 16) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + 4 * q + kr;
+            av[q] = (t < K && ra < n) ? ld(t, ra) : 0.0;
+            bv[q] = (t < K && rb < n) ? ld(t, rb) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (t0 + 4 * q < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
     }
     return acc;
 }
@@ -109,32 +136,13 @@ __device__ inline int64_t gpack_index(int nb, int i, int j) {
     return ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + (i & 15) * 16 + (j & 15);
 }
 
-// The same tile with the k loop unrolled to KMAX (K <= KMAX): all operand loads are independent and
-// issued together, which matters when they come from global memory.
-template <int KMAX, typename LD>
-__device__ inline f64x4 gram_tile_unrolled(int ta, int tb, int K, int n, int lane, LD ld) {
-    const int ra = 16 * ta + (lane & 15), rb = 16 * tb + (lane & 15), kr = lane >> 4;
-    double av[KMAX / 4], bv[KMAX / 4];
-#pragma unroll
-    for (int q = 0; q < KMAX / 4; ++q) {
-        const int t = 4 * q + kr;
-        av[q] = (t < K && ra < n) ? ld(t, ra) : 0.0;
-        bv[q] = (t < K && rb < n) ? ld(t, rb) : 0.0;
-    }
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < KMAX / 4; ++q)
-        if (4 * q < K) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
-    return acc;
-}
-
 struct FactorArgs {
-    const double *A;       // local CSR values of the subgraph
+    const double *A;       // assembly values of the subgraph (scatter order)
     double *V;             // factor values of the subgraph
     double *W;             // update-matrix workspace of the subgraph
     const double *dplus;   // port diagonal per factor position
     const int32_t *sn_c0, *sn_nc, *sn_m, *sn_val, *sn_uoff, *sn_ridx;
-    const int32_t *ch_ptr, *ch_idx, *sc_ptr, *sc_src, *sc_dst;
+    const int32_t *ch_ptr, *ch_idx, *sc_ptr, *sc_dst;
     const uint16_t *rel;
     // port Green's functions (gpl == nullptr: not computed)
     const int4 *gpl;
@@ -144,32 +152,238 @@ struct FactorArgs {
     int nb;  // 16 x 16 blocks per row of the packed G_k
 };
 
-// Supernode s by a team of n threads (this thread has rank r; wv / nw: its wave in the team and
-// the team's waves); F is the team's LDS front.
+// G[ports a, b of s] += acc for the lower part of tile (ta, tb) of Y_s^T Y_s.
+__device__ inline void green_add(const FactorArgs &X, int pc0, int w, int ta, int tb, int lane, const f64x4 &acc) {
+    const int b = 16 * tb + (lane & 15), kr = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int a = 16 * ta + 4 * j + kr;
+        if (a < w && b < w && b <= a) {
+            const int ja = X.perm[pc0 + a], jb = X.perm[pc0 + b];
+            const int64_t e1 = gpack_index(X.nb, ja, jb), e2 = gpack_index(X.nb, jb, ja);
+            if (e1 >= 0) atomicAdd(X.Gk + e1, acc[j]);
+            if (a != b && e2 >= 0) atomicAdd(X.Gk + e2, acc[j]);
+        }
+    }
+}
+
+// Supernode s by a team of n threads (rank r; wv / nw: its wave in the team and the team's
+// waves) in the LDS region F of cap doubles: the front (f x f), the pivot column (f), the inverse
+// pivots (nc) and, when room is left, Y_s (nc x w_s).
 template <bool BLK>
-__device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n, int wv, int nw, int *sbad) {
-    const int lane = threadIdx.x & 63;
+__device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int r, int n, int wv, int nw,
+                             int *sbad) {
+    s = __builtin_amdgcn_readfirstlane(s);  // the same supernode in every lane of the wave
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane), "+v"(r));  // lane-derived values are recomputed per supernode, not kept live
     const int c0 = X.sn_c0[s], nc = X.sn_nc[s], m = X.sn_m[s], f = nc + m;
-    // 1. assembly
+    double *pk = F + f * f, *dg = pk + f;
+    const int sc0 = X.sc_ptr[s], nsc = X.sc_ptr[s + 1] - sc0;
+    const int ch0 = X.ch_ptr[s], nch = X.ch_ptr[s + 1] - ch0;
+    // 1. assembly.  The loads of the common case (this thread's first kPreA local entries, with the
+    //    port diagonal on the first nc, which are the diagonals of the own columns; its first kPreU
+    //    entries of the first two children's packed update matrices) are all issued before the
+    //    front is cleared, so the supernode waits for memory once.
+    double av[kPreA];
+    int ap[kPreA];
+#pragma unroll
+    for (int q = 0; q < kPreA; ++q) {
+        const int e = r + q * n;
+        ap[q] = -1;
+        av[q] = 0.0;
+        if (e < nsc) {
+            ap[q] = X.sc_dst[sc0 + e];
+            av[q] = X.A[sc0 + e] + (e < nc ? X.dplus[c0 + e] : 0.0);
+        }
+    }
+    double uv[2][kPreU];
+    int up[2][kPreU];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        int mc = 0;
+        const double *U = nullptr;
+        const uint16_t *rc = nullptr;
+        if (h < nch) {
+            const int c = X.ch_idx[ch0 + h];
+            mc = X.sn_m[c];
+            U = X.W + X.sn_uoff[c];
+            rc = X.rel + X.sn_ridx[c];
+        }
+        const int nt = mc * (mc + 1) / 2;
+#pragma unroll
+        for (int q = 0; q < kPreU; ++q) {
+            const int t = r + q * n;
+            up[h][q] = -1;
+            uv[h][q] = 0.0;
+            if (t < nt) {
+                int a, b;
+                tri_tile(t, a, b);
+                up[h][q] = rc[a] * f + rc[b];
+                uv[h][q] = U[t];
+            }
+        }
+    }
     for (int i = r; i < f * f; i += n) F[i] = 0.0;
     team_sync<BLK>();
-    for (int e = X.sc_ptr[s] + r; e < X.sc_ptr[s + 1]; e += n) F[X.sc_dst[e]] = X.A[X.sc_src[e]];
-    team_sync<BLK>();
-    for (int j = r; j < nc; j += n) F[j * f + j] += X.dplus[c0 + j];
-    for (int q = X.ch_ptr[s]; q < X.ch_ptr[s + 1]; ++q) {  // children one at a time (they share rows)
+#pragma unroll
+    for (int q = 0; q < kPreA; ++q)
+        if (ap[q] >= 0) F[ap[q]] = av[q];
+    for (int e = r + kPreA * n; e < nsc; e += n) F[X.sc_dst[sc0 + e]] = X.A[sc0 + e] + (e < nc ? X.dplus[c0 + e] : 0.0);
+    for (int h = 0; h < nch; ++h) {  // children one after the other: their rows overlap
         team_sync<BLK>();
-        const int c = X.ch_idx[q], mc = X.sn_m[c];
+        const int c = X.ch_idx[ch0 + h], mc = X.sn_m[c], nt = mc * (mc + 1) / 2;
         const double *U = X.W + X.sn_uoff[c];
         const uint16_t *rc = X.rel + X.sn_ridx[c];
-        for (int idx = r; idx < mc * mc; idx += n) {
-            const int a = idx / mc, b = idx - a * mc;
-            if (b <= a) F[rc[a] * f + rc[b]] += U[idx];
+        int t = r;
+        if (h == 0 || h == 1) {
+#pragma unroll
+            for (int q = 0; q < kPreU; ++q) {
+                const int p = h == 0 ? up[0][q] : up[1][q];
+                if (p >= 0) F[p] += h == 0 ? uv[0][q] : uv[1][q];
+            }
+            t = r + kPreU * n;
+        }
+        for (; t < nt; t += n) {
+            int a, b;
+            tri_tile(t, a, b);
+            F[rc[a] * f + rc[b]] += U[t];
         }
     }
     team_sync<BLK>();
-    // 2. Cholesky of the diagonal block (right-looking)
-    if (!BLK || nc <= kWaveChol) {
-        if (!BLK || wv == 0) {
+    // 2. elimination: nc rank-1 steps (see the section comment)
+    for (int k = 0; k < nc; ++k) {
+        double d = F[k * f + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (r == 0) atomicMin(sbad, s + 1);
+            d = 1.0;
+        }
+        const double rd = 1.0 / sqrt(d);
+        for (int i = r; i < f; i += n) {
+            const double p = i == k ? rd : F[i * f + k] * rd;
+            pk[i] = p;
+            if (i < k) F[i * f + k] = p;  // row k of B, final
+        }
+        if (r == 0) dg[k] = rd;
+        team_sync<BLK>();
+        const int ncol = f - k - 1;
+        if (ncol > 0) {
+            const Cover cv = cover(ncol, r, n);
+            for (int cc = cv.c; cc < ncol; cc += cv.cw) {
+                const int c = k + 1 + cc;
+                const double pc = pk[c];
+                for (int i = cv.r0; i < f; i += cv.rs) {
+                    double *q = F + i * f + c;
+                    *q = (i == k ? 0.0 : *q) - pk[i] * pc;
+                }
+            }
+        }
+        team_sync<BLK>();
+    }
+    // 3. outputs: Linv and W (f x nc, row-major), the update matrix (packed lower triangle)
+    double *Vs = X.V + X.sn_val[s];
+    {
+        const Cover cv = cover(nc, r, n);
+        for (int j = cv.c; j < nc; j += cv.cw)
+            for (int i = cv.r0; i < f; i += cv.rs)
+                Vs[i * nc + j] = i < nc ? (j < i ? F[j * f + i] : (j == i ? dg[i] : 0.0)) : -F[j * f + i];
+    }
+    if (m > 0) {
+        double *Us = X.W + X.sn_uoff[s];
+        const Cover cv = cover(m, r, n);
+        for (int b = cv.c; b < m; b += cv.cw)
+            for (int a = cv.r0; a < m; a += cv.rs)
+                if (b <= a) Us[a * (a + 1) / 2 + b] = F[(nc + a) * f + nc + b];
+    }
+    // 4. port Green's functions through s
+    if (X.gpl) {
+        const int4 e = X.gpl[s];
+        const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
+        if (w > 0) {
+            const double *T = X.gws + e.x;
+            double *Yg = X.gws + e.x + (int64_t)f * w;
+            const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
+            const uint16_t *rs_ = X.rel + X.sn_ridx[s];
+            double *Yl = f * f + f + nc + nc * w <= cap ? dg + nc : nullptr;
+            const int tr = (f + 15) >> 4, tcn = (w + 15) >> 4, kr = lane >> 4, l16 = lane & 15;
+            // [Y; U] = [Linv; -W] T[:nc] + [0; T[nc:]], 16 x 16 tiles over (rows of the front, ports)
+            for (int it = wv; it < tr * tcn; it += nw) {
+                const int ti = it / tcn, tj = it - ti * tcn;
+                const int i = 16 * ti + l16, a = 16 * tj + l16;
+                double tadd[4];
+                int prow[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int row = 16 * ti + 4 * jj + kr;
+                    const bool low = row >= nc && row < f;
+                    tadd[jj] = low && a < w ? T[row * w + a] : 0.0;
+                    prow[jj] = low ? rs_[row - nc] : 0;
+                }
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < nc; k0 += 16) {
+                    double bv[4], lv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = k0 + 4 * q + kr;
+                        bv[q] = j < nc && a < w ? T[j * w + a] : 0.0;
+                        lv[q] = j < nc && i < f && j <= i ? (j == i ? dg[i] : F[j * f + i]) : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (k0 + 4 * q < nc) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(lv[q], bv[q], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int row = 16 * ti + 4 * jj + kr;
+                    if (row < f && a < w) {
+                        const double v = acc[jj] + tadd[jj];
+                        if (row < nc) {
+                            Yg[row * w + a] = v;
+                            if (Yl) Yl[row * w + a] = v;
+                        } else {
+                            X.gws[e.z + (int64_t)prow[jj] * pw + a + (pc0 - ppc0)] = v;
+                        }
+                    }
+                }
+            }
+            team_sync<BLK>();
+            for (int it = wv; it < tcn * (tcn + 1) / 2; it += nw) {  // G += Y^T Y
+                int ta, tb;
+                tri_tile(it, ta, tb);
+                const f64x4 acc = Yl ? gram_tile(ta, tb, nc, w, lane, [&](int t, int c) { return Yl[t * w + c]; })
+                                     : gram_tile(ta, tb, nc, w, lane, [&](int t, int c) { return Yg[t * w + c]; });
+                green_add(X, pc0, w, ta, tb, lane, acc);
+            }
+        }
+    }
+    team_sync<BLK>();
+}
+
+// Supernode s by the workgroup with its front F in the workspace (fronts too large for LDS).
+__device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n, int wv, int nw, int *sbad) {
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane), "+v"(r));  // lane-derived values are recomputed per supernode, not kept live
+    const int c0 = X.sn_c0[s], nc = X.sn_nc[s], m = X.sn_m[s], f = nc + m;
+    // 1. assembly
+    for (int i = r; i < f * f; i += n) F[i] = 0.0;
+    __syncthreads();
+    for (int e = X.sc_ptr[s] + r; e < X.sc_ptr[s + 1]; e += n) F[X.sc_dst[e]] = X.A[e];
+    __syncthreads();
+    for (int j = r; j < nc; j += n) F[j * f + j] += X.dplus[c0 + j];
+    for (int q = X.ch_ptr[s]; q < X.ch_ptr[s + 1]; ++q) {  // children one at a time (they share rows)
+        __syncthreads();
+        const int c = X.ch_idx[q], mc = X.sn_m[c];
+        const double *U = X.W + X.sn_uoff[c];
+        const uint16_t *rc = X.rel + X.sn_ridx[c];
+        for (int t = r; t < mc * (mc + 1) / 2; t += n) {
+            int a, b;
+            tri_tile(t, a, b);
+            F[rc[a] * f + rc[b]] += U[t];
+        }
+    }
+    __syncthreads();
+    // 2. Cholesky of the diagonal block (right-looking; one wave when nc <= kWaveChol)
+    if (nc <= kWaveChol) {
+        if (wv == 0) {
             for (int kk = 0; kk < nc; ++kk) {
                 double d = F[kk * f + kk];
                 if (!(d > 0.0) || !isfinite(d)) {
@@ -209,8 +423,8 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
             __syncthreads();
         }
     }
-    team_sync<BLK>();
-    // 3. Linv[i][j] = -(sum_{j <= t < i} L[i][t] Linv[t][j]) / L[i][i]
+    __syncthreads();
+    // 3. Linv[i][j] = -(sum_{j <= t < i} L[i][t] Linv[t][j]) / L[i][i], stored at F[j][i]
     for (int j = r; j < nc; j += n) {
         const double djj = 1.0 / F[j * f + j];
         for (int i = j + 1; i < nc; ++i) {
@@ -219,8 +433,8 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
             F[j * f + i] = -acc / F[i * f + i];
         }
     }
-    team_sync<BLK>();
-    // 4. L21[q][t] = sum_{u <= t} F21[q][u] Linv[t][u]
+    __syncthreads();
+    // 4. L21[q][t] = sum_{u <= t} F21[q][u] Linv[t][u], stored at F[t][nc + q]
     for (int idx = r; idx < m * nc; idx += n) {
         const int q = idx / nc, t = idx - q * nc;
         const double *row = F + (nc + q) * f;
@@ -228,7 +442,7 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
         for (int u = 0; u < t; ++u) acc += row[u] * F[u * f + t];
         F[t * f + nc + q] = acc;
     }
-    team_sync<BLK>();
+    __syncthreads();
     // 5. outputs
     double *Vs = X.V + X.sn_val[s];
     for (int idx = r; idx < nc * nc; idx += n) {
@@ -242,26 +456,16 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
         Vs[nc * nc + idx] = acc;
     }
     double *Us = X.W + X.sn_uoff[s];
-    if (m >= 16) {  // update = F22 - L21 L21^T, L21^T read from the upper-right block
-        const int tm = (m + 15) >> 4, kr = lane >> 4;
-        for (int it = wv; it < tm * (tm + 1) / 2; it += nw) {
-            int ta, tb;
-            tri_tile(it, ta, tb);
-            const f64x4 acc = gram_tile(ta, tb, nc, m, lane, [&](int t, int a) { return F[t * f + nc + a]; });
-            const int b = 16 * tb + (lane & 15);
+    const int tm = (m + 15) >> 4, kr = lane >> 4;
+    for (int it = wv; it < tm * (tm + 1) / 2; it += nw) {  // update = F22 - L21 L21^T, packed lower
+        int ta, tb;
+        tri_tile(it, ta, tb);
+        const f64x4 acc = gram_tile(ta, tb, nc, m, lane, [&](int t, int a) { return F[t * f + nc + a]; });
+        const int b = 16 * tb + (lane & 15);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int a = 16 * ta + 4 * j + kr;
-                if (a < m && b < m && b <= a) Us[a * m + b] = F[(nc + a) * f + nc + b] - acc[j];
-            }
-        }
-    } else {
-        for (int idx = r; idx < m * m; idx += n) {
-            const int a = idx / m, b = idx - a * m;
-            if (b > a) continue;
-            double acc = F[(nc + a) * f + nc + b];
-            for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + a] * F[t * f + nc + b];
-            Us[idx] = acc;
+        for (int j = 0; j < 4; ++j) {
+            const int a = 16 * ta + 4 * j + kr;
+            if (a < m && b < m && b <= a) Us[a * (a + 1) / 2 + b] = F[(nc + a) * f + nc + b] - acc[j];
         }
     }
     // 6. port Green's functions through s
@@ -273,61 +477,34 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
             double *Y = X.gws + e.x + (int64_t)f * w;
             const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
             const uint16_t *rs_ = X.rel + X.sn_ridx[s];
-            // Y = Linv T; inner sums in groups of four so that four independent loads are in flight
-            for (int idx = r; idx < nc * w; idx += n) {
+            for (int idx = r; idx < nc * w; idx += n) {  // Y = Linv T
                 const int i = idx / w, a = idx - i * w;
                 double acc = T[i * w + a] / F[i * f + i];
-                int t = 0;
-                for (; t + 4 <= i; t += 4) {
-                    const double t0 = T[t * w + a], t1 = T[(t + 1) * w + a], t2 = T[(t + 2) * w + a],
-                                 t3 = T[(t + 3) * w + a];
-                    acc += F[t * f + i] * t0 + F[(t + 1) * f + i] * t1 + F[(t + 2) * f + i] * t2 +
-                           F[(t + 3) * f + i] * t3;
-                }
-                for (; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
+                for (int t = 0; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
                 Y[idx] = acc;
             }
-            team_sync<BLK>();
+            __syncthreads();
             for (int idx = r; idx < m * w; idx += n) {  // T[nc:] - L21 Y into the parent's port front
                 const int q = idx / w, a = idx - q * w;
                 double acc = T[(nc + q) * w + a];
-                int t = 0;
-                for (; t + 4 <= nc; t += 4) {
-                    const double y0 = Y[t * w + a], y1 = Y[(t + 1) * w + a], y2 = Y[(t + 2) * w + a],
-                                 y3 = Y[(t + 3) * w + a];
-                    acc -= F[t * f + nc + q] * y0 + F[(t + 1) * f + nc + q] * y1 + F[(t + 2) * f + nc + q] * y2 +
-                           F[(t + 3) * f + nc + q] * y3;
-                }
-                for (; t < nc; ++t) acc -= F[t * f + nc + q] * Y[t * w + a];
+                for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + q] * Y[t * w + a];
                 X.gws[e.z + (int64_t)rs_[q] * pw + a + (pc0 - ppc0)] = acc;
             }
-            const int tw = (w + 15) >> 4, kr = lane >> 4;
+            const int tw = (w + 15) >> 4;
             for (int it = wv; it < tw * (tw + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
                 tri_tile(it, ta, tb);
-                const auto ldy = [&](int t, int a) { return Y[t * w + a]; };
-                const f64x4 acc = nc <= 20 ? gram_tile_unrolled<20>(ta, tb, nc, w, lane, ldy)
-                                                : gram_tile(ta, tb, nc, w, lane, ldy);
-                const int b = 16 * tb + (lane & 15);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int a = 16 * ta + 4 * j + kr;
-                    if (a < w && b < w && b <= a) {
-                        const int ja = X.perm[pc0 + a], jb = X.perm[pc0 + b];
-                        const int64_t e1 = gpack_index(X.nb, ja, jb), e2 = gpack_index(X.nb, jb, ja);
-                        if (e1 >= 0) X.Gk[e1] += acc[j];
-                        if (a != b && e2 >= 0) X.Gk[e2] += acc[j];
-                    }
-                }
+                const f64x4 acc = gram_tile(ta, tb, nc, w, lane, [&](int t, int a) { return Y[t * w + a]; });
+                green_add(X, pc0, w, ta, tb, lane, acc);
             }
         }
     }
-    team_sync<BLK>();
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const double *__restrict__ aval,
+__global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, const double *__restrict__ aval,
                                                      const double *__restrict__ invz, double *__restrict__ vals,
-                                                     double *__restrict__ ws, int lds_front, int lds_doubles,
+                                                     double *__restrict__ ws, int lds_doubles,
                                                      int32_t *__restrict__ status, DevGreen Gp,
                                                      const int64_t *__restrict__ goff, double *__restrict__ G) {
     extern __shared__ double sm[];
@@ -351,7 +528,6 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
     X.ch_ptr = S.ch_ptr + C.o_snp;
     X.ch_idx = S.ch_idx + C.o_chi;
     X.sc_ptr = S.sc_ptr + C.o_snp;
-    X.sc_src = S.sc_src + C.o_sc;
     X.sc_dst = S.sc_dst + C.o_sc;
     X.rel = S.rel + C.o_ridx;
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
@@ -377,15 +553,23 @@ __global__ __launch_bounds__(kThreads) void k_factor(DevSym S, DevSub D, const d
     __syncthreads();
     for (int lv = 0; lv < C.nlev; ++lv) {
         const int s0 = col_sn[lev_c0[lv]], s1 = lv + 1 < C.nlev ? col_sn[lev_c0[lv + 1]] : C.nsn;
-        const int mf = lev_maxf[lv];
-        if (s1 - s0 > 1 && nw * mf * mf <= lds_doubles) {
-            double *F = sm + wv * mf * mf;
-            for (int s = s0 + wv; s < s1; s += nw) factor_node<false>(X, s, F, lane, 64, 0, 1, &sbad);
-            __syncthreads();
+        const int mf = lev_maxf[lv], need = mf * mf + 2 * mf;
+        if (need <= lds_doubles) {
+            const int fit = lds_doubles / need, nwa = fit < nw ? fit : nw;
+            if (s1 - s0 > 1 && nwa >= 2) {  // one supernode per wave, nwa waves at a time
+                const int cap = lds_doubles / nwa;
+                if (wv < nwa)
+                    for (int s = s0 + wv; s < s1; s += nwa)
+                        factor_front<false>(X, s, sm + wv * cap, cap, lane, 64, 0, 1, &sbad);
+            } else {
+                for (int s = s0; s < s1; ++s) factor_front<true>(X, s, sm, lds_doubles, tid, nt, wv, nw, &sbad);
+            }
         } else {
-            double *F = lds_front ? sm : X.W + C.ws_u;
-            for (int s = s0; s < s1; ++s) factor_node<true>(X, s, F, tid, nt, wv, nw, &sbad);
+            for (int s = s0; s < s1; ++s) factor_node(X, s, X.W + C.ws_u, tid, nt, wv, nw, &sbad);
         }
+        // every store and atomic add of this level lands before the next level reads or adds
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
     if (tid == 0) status[k] = sbad == 0x7FFFFFFF ? 0 : sbad;
 }
@@ -1124,14 +1308,15 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
                    const double *invz, double *vals, double *ws, int32_t *status, const DevGreen &Gp,
                    const int64_t *goff, double *G, hipStream_t st) {
-    // the workgroup's front (in the workspace when larger than 96 KiB), or four per-wave fronts of
-    // order <= 24 on the lower levels
-    const int lds_front = max_front * max_front <= 96 * 1024 / 8;
-    const int lds_doubles = std::max(lds_front ? max_front * max_front : 0, 4 * 24 * 24);
+    // 40 KiB of fronts per workgroup keeps four workgroups on a CU; larger fronts get the room they
+    // need up to the CU's LDS, beyond that they stay in the workspace
+    int lds_doubles = kFactorLds;
+    const int need = max_front * max_front + 2 * max_front;
+    if (need > lds_doubles && need <= (int)((kMaxLds - 1024) / sizeof(double))) lds_doubles = need;
     const size_t shm = sizeof(double) * (size_t)lds_doubles;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_front, lds_doubles,
-                       status, Gp, goff, G);
+    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_doubles, status,
+                       Gp, goff, G);
 }
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {

@@ -17,7 +17,7 @@ struct ClassDev {
     int32_t o_colp;  // seg_ptr       (nk + 1 per class)
     int32_t o_ridx;  // ridx, rel
     int32_t o_seg;   // seg_off, seg_c0, seg_nc
-    int32_t o_sc;    // sc_src, sc_dst
+    int32_t o_sc;    // sc_ptr entries of the class (assembly scatter list)
     int32_t o_chi;   // ch_idx
     int32_t nu;      // update entries (sum of m over supernodes)
     int64_t nval, ws_u;
@@ -35,14 +35,14 @@ struct DevSym {
     const uint16_t *seg_u, *u_sn;   // update-entry lists (variant 1 of the sweep)
     const int32_t *colrec, *urec;   // packed per-column and per-update-entry records
     const int32_t *lev_u;           // update-entry range per level (lev offsets)
-    const int32_t *sc_ptr, *sc_src, *sc_dst;
+    const int32_t *sc_ptr, *sc_dst;
 };
 
 struct DevSub {
     const int32_t *cls;
     const int64_t *val;   // factor value offset
     const int64_t *x;     // offset of the subgraph's entries in split vectors (factor order)
-    const int64_t *aval;  // offset of the local CSR values
+    const int64_t *aval;  // offset of the subgraph's assembly values (lower local entries, scatter order)
     const int64_t *ws;    // factorisation workspace offset
     const int32_t *pg_ptr;   // port groups of each subgraph (nsub + 1)
     const uint16_t *pg_pos;  // factor position of the group's vertex

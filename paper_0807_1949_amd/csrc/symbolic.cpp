@@ -351,10 +351,22 @@ int analyse(const Partition &P, int32_t k, int leaf, ClassSym &C, std::string &e
             }
             sc[t].push_back({(int32_t)(e - e0), row * f + (pj - c0)});
         }
+    // each front's list starts with the diagonals of its own columns in column order (every local row
+    // holds its diagonal), so the assembly adds the port diagonal of column j to entry j
     C.sc_ptr.assign(nb + 1, 0);
     for (int32_t t = 0; t < nb; ++t) {
+        const int32_t nc = C.sn_nc[t], f = nc + C.sn_m[t];
+        std::vector<std::pair<int32_t, int32_t>> diag(nc, {-1, -1}), rest;
+        for (auto &pr : sc[t]) {
+            const int32_t row = pr.second / f, col = pr.second % f;
+            if (row == col && row < nc) diag[row] = pr;
+            else rest.push_back(pr);
+        }
+        for (int32_t j = 0; j < nc; ++j)
+            if (diag[j].first < 0) { err = "front misses a diagonal entry"; return VTM_ERR_PARTITION; }
         C.sc_ptr[t + 1] = C.sc_ptr[t] + (int32_t)sc[t].size();
-        for (auto &pr : sc[t]) { C.sc_src.push_back(pr.first); C.sc_dst.push_back(pr.second); }
+        for (auto &pr : diag) { C.sc_src.push_back(pr.first); C.sc_dst.push_back(pr.second); }
+        for (auto &pr : rest) { C.sc_src.push_back(pr.first); C.sc_dst.push_back(pr.second); }
     }
     return VTM_OK;
 }
