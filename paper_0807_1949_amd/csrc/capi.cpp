@@ -95,7 +95,8 @@ struct vtm_ctx {
     DevBuf d_z, d_invz64, d_invz32, d_vals64, d_vals32, d_status;
     // learned impedance model
     DevBuf d_zparams, d_feat, d_avvl, d_pred;
-    bool model_loaded = false, feats_ready = false;
+    DevBuf d_ws;  // factorisation workspace (update matrices, large fronts, port diagonal), kept between set-ups
+    bool model_loaded = false, feats_ready = false, feats_on_dev = false;
     std::vector<float> feats;
     // solve state
     DevBuf d_o[2], d_bsplit, d_xloc, d_x, d_xt, d_r, d_rt, d_b, d_part, d_relres;
@@ -129,7 +130,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -1040,10 +1041,13 @@ vtm_status learned_z(vtm_ctx *h) {
     ensure_features(h);
     const vtm::Partition &P = h->P;
     const int64_t nvtl = (int64_t)P.vtl_v.size();
-    std::vector<double> avv(nvtl);
-    for (int64_t l = 0; l < nvtl; ++l) avv[l] = P.adiag[P.vtl_v[l]];
-    HIP_TRY(upload(h->d_feat, h->feats, h->stream));
-    HIP_TRY(upload(h->d_avvl, avv, h->stream));
+    if (!h->feats_on_dev) {  // features and diagonals depend on the partition only
+        std::vector<double> avv(nvtl);
+        for (int64_t l = 0; l < nvtl; ++l) avv[l] = P.adiag[P.vtl_v[l]];
+        HIP_TRY(upload(h->d_feat, h->feats, h->stream));
+        HIP_TRY(upload(h->d_avvl, avv, h->stream));
+        h->feats_on_dev = true;
+    }
     HIP_TRY(ensure(h->d_pred, sizeof(float) * (nvtl + 1)));
     HIP_TRY(ensure(h->d_z, sizeof(double) * (nvtl + 1)));
     vtm::launch_mlp_predict(h->d_zparams.as<float>(), h->d_feat.as<float>(), nvtl, h->d_pred.as<float>(), h->stream);
@@ -1067,7 +1071,7 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     HIP_TRY(ensure(h->d_invz32, sizeof(float) * (h->nports + 1)));
     HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
     HIP_TRY(ensure(h->d_status, sizeof(int32_t) * (P.nsub + 1)));
-    DevBuf ws;
+    DevBuf &ws = h->d_ws;
     HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
     // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
     const bool want_green = h->max_p > 0 && h->max_p <= 2048 &&
@@ -1118,7 +1122,6 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    ws.release();
     h->stats.setup_ms = ms;
     for (int32_t k = 0; k < P.nsub; ++k)
         if (status[k]) {
@@ -1243,7 +1246,7 @@ vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, con
     if (rowptr[0] != 0 || rowptr[n] < n) return fail(VTM_ERR_INVALID, "rowptr invalid");
     if (!h->host_only()) HIP_TRY(hipSetDevice(h->opt.device));
     h->partitioned = h->set_up = false;
-    h->feats_ready = false;
+    h->feats_ready = h->feats_on_dev = false;
     h->A.n = n;
     h->A.rp.assign(rowptr, rowptr + n + 1);
     h->A.ci.assign(col, col + rowptr[n]);

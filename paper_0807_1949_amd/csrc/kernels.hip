@@ -71,6 +71,13 @@ __global__ void k_to_f32(const double *__restrict__ s, float *__restrict__ d, in
 // algebra step by step: Cholesky, Linv, L21, outputs, update (matrix cores), Green's functions.
 constexpr int kWaveChol = 48;
 constexpr int kPreA = 4, kPreU = 8;  // assembly entries per thread loaded before the first LDS store
+constexpr int kTile = 5;             // register tile of the front per thread (rows x columns)
+
+// LDS doubles after the front for the pivot column(s): two padded buffers and spare slots for the
+// register elimination, or 2 f for the LDS one (BLK: the team is the workgroup of 256 threads).
+__host__ __device__ constexpr int pivot_len(int f, bool blk) {
+    return 2 * (blk ? 16 : 8) * kTile + (blk ? 16 : 8) > 2 * f ? 2 * (blk ? 16 : 8) * kTile + (blk ? 16 : 8) : 2 * f;
+}
 constexpr int kFactorLds = 5056;     // doubles of LDS per workgroup for the fronts (four workgroups per CU)
 
 __device__ inline void wave_sync() {
@@ -152,14 +159,17 @@ struct FactorArgs {
     int nb;  // 16 x 16 blocks per row of the packed G_k
 };
 
-// G[ports a, b of s] += acc for the lower part of tile (ta, tb) of Y_s^T Y_s.
-__device__ inline void green_add(const FactorArgs &X, int pc0, int w, int ta, int tb, int lane, const f64x4 &acc) {
+// G[ports a, b of s] += acc for the lower part of tile (ta, tb) of Y_s^T Y_s; port(x) is the port
+// number of column x of s.
+template <typename PORT>
+__device__ inline void green_add(const FactorArgs &X, int w, int ta, int tb, int lane, const f64x4 &acc, PORT port) {
     const int b = 16 * tb + (lane & 15), kr = lane >> 4;
+    const int jb = port(b);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int a = 16 * ta + 4 * j + kr;
+        const int ja = port(a);
         if (a < w && b < w && b <= a) {
-            const int ja = X.perm[pc0 + a], jb = X.perm[pc0 + b];
             const int64_t e1 = gpack_index(X.nb, ja, jb), e2 = gpack_index(X.nb, jb, ja);
             if (e1 >= 0) atomicAdd(X.Gk + e1, acc[j]);
             if (a != b && e2 >= 0) atomicAdd(X.Gk + e2, acc[j]);
@@ -167,17 +177,97 @@ __device__ inline void green_add(const FactorArgs &X, int pc0, int w, int ta, in
     }
 }
 
+// Elimination of a front held in registers: the team is a G x G grid (G = 8 for a wave, 16 for the
+// workgroup) and thread (lr, lc) keeps the entries (lr + G a, lc + G b), a, b < KT, of F.  Step k reads
+// only the pivot column, published in one of two LDS buffers (pk and pk + kPad, each kPad = G kTile
+// long, so that rows past the front need no guard; G spare slots follow) by the threads owning it; a
+// step costs one barrier.  Column k is final after step k: its rows <= k (row k of B and the diagonal 1/d of Linv)
+// go straight to the front, its other rows are never read again.  Row k restarts from zero as row
+// k of B.  Columns < k keep being updated in registers but are never read
+// again; columns >= nc go back to the front at the end.
+template <int KT, bool BLK>
+__device__ __forceinline__ void elim_regs(double *F, double *pk, int f, int nc, int r, int s, int *sbad) {
+    constexpr int G = BLK ? 16 : 8, kPad = G * kTile;
+    const int lr = r / G, lc = r & (G - 1);
+    double v[KT][KT];
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < KT; ++b) {
+            const int i = lr + G * a, c = lc + G * b;
+            v[a][b] = i < f && c < f ? F[i * f + c] : 0.0;
+        }
+    if (lc == 0)
+#pragma unroll
+        for (int a = 0; a < KT; ++a) pk[lr + G * a] = v[a][0];
+    team_sync<BLK>();
+    for (int k = 0; k < nc; ++k) {
+        const double *cb = pk + (k & 1) * kPad;
+        double *cn = pk + (~k & 1) * kPad;
+        double d = cb[k];
+        if (!(d > 0.0) || !isfinite(d)) {
+            if (r == 0) atomicMin(sbad, s + 1);
+            d = 1.0;
+        }
+        const double rd = 1.0 / sqrt(d);
+        double pi[KT];
+#pragma unroll
+        for (int a = 0; a < KT; ++a) {
+            const int i = lr + G * a;
+            pi[a] = i == k ? rd : cb[i] * rd;
+        }
+        if (lc == 0)  // the finished column: rows <= k into the front (row k of B, diagonal of Linv)
+#pragma unroll
+            for (int a = 0; a < KT; ++a) {
+                const int i = lr + G * a;
+                double *dst = i < f ? F + i * f + k : pk + 2 * kPad + lr;  // rows past the front: spare slots
+                *dst = pi[a];  // rows k < i < f are entries of L that nothing reads
+            }
+        if (lr == (k & (G - 1))) {  // row k restarts as row k of B
+            const int aa = k / G;
+#pragma unroll
+            for (int a = 0; a < KT; ++a)
+                if (a == aa)
+#pragma unroll
+                    for (int b = 0; b < KT; ++b) v[a][b] = 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < KT; ++b) {
+            const double pc = cb[lc + G * b] * rd;
+#pragma unroll
+            for (int a = 0; a < KT; ++a) v[a][b] = fma(-pi[a], pc, v[a][b]);
+        }
+        if (k + 1 < nc && lc == ((k + 1) & (G - 1))) {  // publish column k + 1
+            const int bb = (k + 1) / G;
+#pragma unroll
+            for (int b = 0; b < KT; ++b)
+                if (b == bb)
+#pragma unroll
+                    for (int a = 0; a < KT; ++a) cn[lr + G * a] = v[a][b];
+        }
+        team_sync<BLK>();
+    }
+#pragma unroll
+    for (int a = 0; a < KT; ++a)
+#pragma unroll
+        for (int b = 0; b < KT; ++b) {
+            const int i = lr + G * a, c = lc + G * b;
+            if (i < f && c < f && c >= nc) F[i * f + c] = v[a][b];
+        }
+    team_sync<BLK>();
+}
+
 // Supernode s by a team of n threads (rank r; wv / nw: its wave in the team and the team's
-// waves) in the LDS region F of cap doubles: the front (f x f), the pivot column (f), the inverse
-// pivots (nc) and, when room is left, Y_s (nc x w_s).
+// waves; n = 64 for a wave, 256 for the workgroup) in the LDS region F of cap doubles: the front
+// (f x f), the pivot-column buffers (pivot_len) and, when room is left, Y_s (nc x w_s).
 template <bool BLK>
-__device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int r, int n, int wv, int nw,
+__device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int r, int n, int wv, int nw,
                              int *sbad) {
     s = __builtin_amdgcn_readfirstlane(s);  // the same supernode in every lane of the wave
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane), "+v"(r));  // lane-derived values are recomputed per supernode, not kept live
     const int c0 = X.sn_c0[s], nc = X.sn_nc[s], m = X.sn_m[s], f = nc + m;
-    double *pk = F + f * f, *dg = pk + f;
+    double *pk = F + f * f;
     const int sc0 = X.sc_ptr[s], nsc = X.sc_ptr[s + 1] - sc0;
     const int ch0 = X.ch_ptr[s], nch = X.ch_ptr[s + 1] - ch0;
     // 1. assembly.  The loads of the common case (this thread's first kPreA local entries, with the
@@ -251,33 +341,40 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
     }
     team_sync<BLK>();
     // 2. elimination: nc rank-1 steps (see the section comment)
-    for (int k = 0; k < nc; ++k) {
-        double d = F[k * f + k];
-        if (!(d > 0.0) || !isfinite(d)) {
-            if (r == 0) atomicMin(sbad, s + 1);
-            d = 1.0;
-        }
-        const double rd = 1.0 / sqrt(d);
-        for (int i = r; i < f; i += n) {
-            const double p = i == k ? rd : F[i * f + k] * rd;
-            pk[i] = p;
-            if (i < k) F[i * f + k] = p;  // row k of B, final
-        }
-        if (r == 0) dg[k] = rd;
-        team_sync<BLK>();
-        const int ncol = f - k - 1;
-        if (ncol > 0) {
-            const Cover cv = cover(ncol, r, n);
-            for (int cc = cv.c; cc < ncol; cc += cv.cw) {
-                const int c = k + 1 + cc;
-                const double pc = pk[c];
-                for (int i = cv.r0; i < f; i += cv.rs) {
-                    double *q = F + i * f + c;
-                    *q = (i == k ? 0.0 : *q) - pk[i] * pc;
+    constexpr int G = BLK ? 16 : 8;  // the team as a G x G grid of threads
+    if (f <= 3 * G) {
+        elim_regs<3, BLK>(F, pk, f, nc, r, s, sbad);
+    } else if (f <= kTile * G) {
+        elim_regs<kTile, BLK>(F, pk, f, nc, r, s, sbad);
+    } else {
+        for (int k = 0; k < nc; ++k) {
+            double d = F[k * f + k];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (r == 0) atomicMin(sbad, s + 1);
+                d = 1.0;
+            }
+            const double rd = 1.0 / sqrt(d);
+            for (int i = r; i < f; i += n) {
+                const double p = i == k ? rd : F[i * f + k] * rd;
+                pk[i] = p;
+                if (i < k) F[i * f + k] = p;  // row k of B, final
+            }
+            team_sync<BLK>();
+            if (r == 0) F[k * f + k] = rd;  // diagonal of Linv
+            const int ncol = f - k - 1;
+            if (ncol > 0) {
+                const Cover cv = cover(ncol, r, n);
+                for (int cc = cv.c; cc < ncol; cc += cv.cw) {
+                    const int c = k + 1 + cc;
+                    const double pc = pk[c];
+                    for (int i = cv.r0; i < f; i += cv.rs) {
+                        double *q = F + i * f + c;
+                        *q = (i == k ? 0.0 : *q) - pk[i] * pc;
+                    }
                 }
             }
+            team_sync<BLK>();
         }
-        team_sync<BLK>();
     }
     // 3. outputs: Linv and W (f x nc, row-major), the update matrix (packed lower triangle)
     double *Vs = X.V + X.sn_val[s];
@@ -285,7 +382,7 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
         const Cover cv = cover(nc, r, n);
         for (int j = cv.c; j < nc; j += cv.cw)
             for (int i = cv.r0; i < f; i += cv.rs)
-                Vs[i * nc + j] = i < nc ? (j < i ? F[j * f + i] : (j == i ? dg[i] : 0.0)) : -F[j * f + i];
+                Vs[i * nc + j] = i < nc ? (j <= i ? F[j * f + i] : 0.0) : -F[j * f + i];
     }
     if (m > 0) {
         double *Us = X.W + X.sn_uoff[s];
@@ -303,7 +400,48 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
             double *Yg = X.gws + e.x + (int64_t)f * w;
             const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
             const uint16_t *rs_ = X.rel + X.sn_ridx[s];
-            double *Yl = f * f + f + nc + nc * w <= cap ? dg + nc : nullptr;
+            // the parent rows of the update rows and the port numbers of s, two per lane (read through
+            // lane shuffles below, so that no global load sits behind this supernode's stores)
+            const bool rsh = m <= 128, psh = w <= 128;
+            int rv0 = 0, rv1 = 0, pv0 = 0, pv1 = 0;
+            if (rsh) {
+                rv0 = lane < m ? rs_[lane] : 0;
+                rv1 = lane + 64 < m ? rs_[lane + 64] : 0;
+            }
+            if (psh) {
+                pv0 = lane < w ? X.perm[pc0 + lane] : 0;
+                pv1 = lane + 64 < w ? X.perm[pc0 + lane + 64] : 0;
+            }
+            const auto prow_of = [&](int q) {  // parent row of update row q (all lanes call it)
+                if (!rsh) return q >= 0 && q < m ? (int)rs_[q] : 0;
+                const int x0 = __shfl(rv0, q & 63), x1 = __shfl(rv1, q & 63);
+                return q < 64 ? x0 : x1;
+            };
+            const auto port_of = [&](int x) {  // port number of column x of s (all lanes call it)
+                if (!psh) return x < w ? (int)X.perm[pc0 + x] : 0;
+                const int x0 = __shfl(pv0, x & 63), x1 = __shfl(pv1, x & 63);
+                return x < 64 ? x0 : x1;
+            };
+            // LDS after the product's operand rows F[:nc] (the rest of the front is consumed): the port
+            // front T (f x w) and Y (nc x w) when both fit; else Y alone after the pivot buffers
+            const int offT = nc * f, offY = offT + f * w;
+            const bool staged = offY + nc * w <= cap;
+            double *Ts = staged ? F + offT : nullptr;
+            double *Yl = staged ? F + offY
+                                : (f * f + pivot_len(f, BLK) + nc * w <= cap ? pk + pivot_len(f, BLK) : nullptr);
+            if (staged) {
+                team_sync<BLK>();  // the outputs have read the front
+                for (int i0 = r; i0 < f * w; i0 += 16 * n) {
+                    double t[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) t[q] = i0 + q * n < f * w ? T[i0 + q * n] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        if (i0 + q * n < f * w) Ts[i0 + q * n] = t[q];
+                }
+                team_sync<BLK>();
+            }
+            const double *Tp = staged ? Ts : T;
             const int tr = (f + 15) >> 4, tcn = (w + 15) >> 4, kr = lane >> 4, l16 = lane & 15;
             // [Y; U] = [Linv; -W] T[:nc] + [0; T[nc:]], 16 x 16 tiles over (rows of the front, ports)
             for (int it = wv; it < tr * tcn; it += nw) {
@@ -315,8 +453,8 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
                 for (int jj = 0; jj < 4; ++jj) {
                     const int row = 16 * ti + 4 * jj + kr;
                     const bool low = row >= nc && row < f;
-                    tadd[jj] = low && a < w ? T[row * w + a] : 0.0;
-                    prow[jj] = low ? rs_[row - nc] : 0;
+                    tadd[jj] = low && a < w ? Tp[row * w + a] : 0.0;
+                    prow[jj] = prow_of(row - nc);
                 }
                 f64x4 acc = {0.0, 0.0, 0.0, 0.0};
                 for (int k0 = 0; k0 < nc; k0 += 16) {
@@ -324,8 +462,8 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int j = k0 + 4 * q + kr;
-                        bv[q] = j < nc && a < w ? T[j * w + a] : 0.0;
-                        lv[q] = j < nc && i < f && j <= i ? (j == i ? dg[i] : F[j * f + i]) : 0.0;
+                        bv[q] = j < nc && a < w ? Tp[j * w + a] : 0.0;
+                        lv[q] = j < nc && i < f && j <= i ? F[j * f + i] : 0.0;
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
@@ -337,8 +475,8 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
                     if (row < f && a < w) {
                         const double v = acc[jj] + tadd[jj];
                         if (row < nc) {
-                            Yg[row * w + a] = v;
                             if (Yl) Yl[row * w + a] = v;
+                            else Yg[row * w + a] = v;
                         } else {
                             X.gws[e.z + (int64_t)prow[jj] * pw + a + (pc0 - ppc0)] = v;
                         }
@@ -351,7 +489,7 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
                 tri_tile(it, ta, tb);
                 const f64x4 acc = Yl ? gram_tile(ta, tb, nc, w, lane, [&](int t, int c) { return Yl[t * w + c]; })
                                      : gram_tile(ta, tb, nc, w, lane, [&](int t, int c) { return Yg[t * w + c]; });
-                green_add(X, pc0, w, ta, tb, lane, acc);
+                green_add(X, w, ta, tb, lane, acc, port_of);
             }
         }
     }
@@ -359,7 +497,7 @@ __device__ void factor_front(const FactorArgs &X, int s, double *F, int cap, int
 }
 
 // Supernode s by the workgroup with its front F in the workspace (fronts too large for LDS).
-__device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n, int wv, int nw, int *sbad) {
+__device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n, int wv, int nw, int *sbad) {
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane), "+v"(r));  // lane-derived values are recomputed per supernode, not kept live
     const int c0 = X.sn_c0[s], nc = X.sn_nc[s], m = X.sn_m[s], f = nc + m;
@@ -495,7 +633,7 @@ __device__ void factor_node(const FactorArgs &X, int s, double *F, int r, int n,
                 int ta, tb;
                 tri_tile(it, ta, tb);
                 const f64x4 acc = gram_tile(ta, tb, nc, w, lane, [&](int t, int a) { return Y[t * w + a]; });
-                green_add(X, pc0, w, ta, tb, lane, acc);
+                green_add(X, w, ta, tb, lane, acc, [&](int x) { return x < w ? (int)X.perm[pc0 + x] : 0; });
             }
         }
     }
@@ -553,17 +691,14 @@ __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, cons
     __syncthreads();
     for (int lv = 0; lv < C.nlev; ++lv) {
         const int s0 = col_sn[lev_c0[lv]], s1 = lv + 1 < C.nlev ? col_sn[lev_c0[lv + 1]] : C.nsn;
-        const int mf = lev_maxf[lv], need = mf * mf + 2 * mf;
-        if (need <= lds_doubles) {
-            const int fit = lds_doubles / need, nwa = fit < nw ? fit : nw;
-            if (s1 - s0 > 1 && nwa >= 2) {  // one supernode per wave, nwa waves at a time
-                const int cap = lds_doubles / nwa;
-                if (wv < nwa)
-                    for (int s = s0 + wv; s < s1; s += nwa)
-                        factor_front<false>(X, s, sm + wv * cap, cap, lane, 64, 0, 1, &sbad);
-            } else {
-                for (int s = s0; s < s1; ++s) factor_front<true>(X, s, sm, lds_doubles, tid, nt, wv, nw, &sbad);
-            }
+        const int mf = lev_maxf[lv], need_w = mf * mf + pivot_len(mf, false), need_b = mf * mf + pivot_len(mf, true);
+        const int fit = lds_doubles / need_w, nwa = fit < nw ? fit : nw;
+        if (s1 - s0 > 1 && nwa >= 2) {  // one supernode per wave, nwa waves at a time
+            const int cap = lds_doubles / nwa;
+            if (wv < nwa)
+                for (int s = s0 + wv; s < s1; s += nwa) factor_front<false>(X, s, sm + wv * cap, cap, lane, 64, 0, 1, &sbad);
+        } else if (need_b <= lds_doubles) {
+            for (int s = s0; s < s1; ++s) factor_front<true>(X, s, sm, lds_doubles, tid, nt, wv, nw, &sbad);
         } else {
             for (int s = s0; s < s1; ++s) factor_node(X, s, X.W + C.ws_u, tid, nt, wv, nw, &sbad);
         }
@@ -1311,7 +1446,7 @@ void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_f
     // 40 KiB of fronts per workgroup keeps four workgroups on a CU; larger fronts get the room they
     // need up to the CU's LDS, beyond that they stay in the workspace
     int lds_doubles = kFactorLds;
-    const int need = max_front * max_front + 2 * max_front;
+    const int need = max_front * max_front + pivot_len(max_front, true);
     if (need > lds_doubles && need <= (int)((kMaxLds - 1024) / sizeof(double))) lds_doubles = need;
     const size_t shm = sizeof(double) * (size_t)lds_doubles;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
