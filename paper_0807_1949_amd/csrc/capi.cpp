@@ -76,6 +76,9 @@ struct vtm_ctx {
     int64_t total_g = 0;   // stored entries of all packed G_k
     double total_pp = 0;   // sum of p_k^2 (entries of the full G_k)
     bool have_green = false;
+    bool have_y = false;  // the set-up kept the Y blocks (FP64 workspace, FP32 copy when sweeping in FP32)
+    bool yb_ok = false;   // yb holds L^{-1} b~ of the current source split
+    bool have_y32 = false;  // d_gws32 is written by the factorisation
     // column plan of the multifrontal Green's-function computation (built on first use)
     DevBuf d_gsn, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws, d_levmaxf;
     int plan_state = 0;  // 0 not built, 1 ready, -1 not applicable (fall back to per-column solves)
@@ -96,6 +99,7 @@ struct vtm_ctx {
     // learned impedance model
     DevBuf d_zparams, d_feat, d_avvl, d_pred;
     DevBuf d_ws;  // factorisation workspace (update matrices, large fronts, port diagonal), kept between set-ups
+    DevBuf d_gws32, d_yb;  // FP32 copy of the Y blocks; y_b = L^{-1} b~ per RHS group
     bool model_loaded = false, feats_ready = false, feats_on_dev = false;
     std::vector<float> feats;
     // solve state
@@ -130,7 +134,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -317,6 +321,7 @@ vtm::DevGreen dev_green(vtm_ctx *h, bool on) {
     g.idoff = h->d_gidoff.as<int32_t>();
     g.perm = h->d_gperm.as<uint16_t>();
     g.ws = h->d_gws.as<double>();
+    g.ws32 = h->have_y32 ? h->d_gws32.as<float>() : nullptr;
     return g;
 }
 
@@ -717,7 +722,7 @@ per_sweep:
             vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R, nt, h->nsplit,
                                  h->nports, vals_of<T>(h), h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(),
                                  invz_of<T>(h), h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(),
-                                 last ? vtm::kSweepWriteX : 0, h->stream);
+                                 nullptr, last ? vtm::kSweepWriteX : 0, h->stream);
     };
     // Batches of kGraphBatch sweeps (even, so the wave buffer returns to its start) are captured once
     // per starting buffer and replayed; the remaining sweeps, including the last, are launched directly.
@@ -763,25 +768,58 @@ per_sweep:
 }
 
 // Substitution solve with the incoming waves of the last sweep (or zero waves), local solutions to xloc;
-// the waves are not advanced.
+// the waves are not advanced.  write_y also keeps y = L^{-1} (right side) in yb.
 template <typename T>
-void local_solve(vtm_ctx *h, bool zero_waves) {
+void local_solve(vtm_ctx *h, bool zero_waves, bool write_y = false) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
     vtm::launch_sweep<T>(dev_sym(h), dev_sub(h), h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R,
                          sweep_threads(h), h->nsplit, h->nports, vals_of<T>(h), h->d_bsplit.as<T>(),
                          h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur ^ 1].as<T>(), h->d_o[h->cur].as<T>(),
-                         h->d_xloc.as<T>(),
-                         vtm::kSweepWriteX | vtm::kSweepNoWaves | (zero_waves ? vtm::kSweepZeroWaves : 0), h->stream);
+                         h->d_xloc.as<T>(), write_y ? h->d_yb.as<T>() : nullptr,
+                         vtm::kSweepWriteX | vtm::kSweepNoWaves | (zero_waves ? vtm::kSweepZeroWaves : 0) |
+                             (write_y ? vtm::kSweepWriteY : 0),
+                         h->stream);
 }
 
-// After a new source split: c = K^{-1} b~ at the port vertices (port-reduced sweeps only).
+// Y blocks of the port Green's columns in the sweep precision (FP64 workspace or its FP32 copy).
+template <typename T>
+const T *yblocks_of(vtm_ctx *h);
+template <>
+const double *yblocks_of<double>(vtm_ctx *h) { return h->d_gws.as<double>(); }
+template <>
+const float *yblocks_of<float>(vtm_ctx *h) { return h->d_gws32.as<float>(); }
+
+// Local solutions of a convergence test (incoming waves of the last sweep): from the stored Y blocks
+// and y_b when the set-up kept them, else by substitution.
+template <typename T>
+vtm_status test_solve(vtm_ctx *h) {
+    const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
+    if (h->have_y && h->yb_ok && vtm::prepare_ysolve<T>(h->max_nk, h->max_p, R) == hipSuccess) {
+        vtm::launch_ysolve<T>(dev_sym(h), dev_sub(h), dev_green(h, true), yblocks_of<T>(h), h->P.nsub, h->max_nk,
+                              h->max_p, ng, R, h->nsplit, h->nports, vals_of<T>(h), h->d_yb.as<T>(),
+                              h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur ^ 1].as<T>(), h->d_xloc.as<T>(),
+                              h->stream);
+        return VTM_OK;
+    }
+    (void)hipGetLastError();
+    local_solve<T>(h, false);
+    return VTM_OK;
+}
+
+// After a new source split: c = K^{-1} b~ at the port vertices (port-reduced sweeps only), and
+// y_b = L^{-1} b~ for the tests when the Y blocks are kept.
 template <typename T>
 vtm_status port_constants(vtm_ctx *h) {
     if (!use_schur(h)) return VTM_OK;
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
     HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
     HIP_TRY(ensure(h->d_cport, sizeof(T) * ((size_t)ng * h->npg * R + 1)));
-    local_solve<T>(h, true);
+    h->yb_ok = false;
+    if (h->have_y) {
+        HIP_TRY(ensure(h->d_yb, sizeof(T) * ((size_t)ng * h->nsplit * R + 1)));
+        h->yb_ok = true;
+    }
+    local_solve<T>(h, true, h->yb_ok);
     vtm::launch_gather_ports<T>(dev_sub(h), h->P.nsub, ng, h->nsplit, h->npg, R, h->d_xloc.as<T>(),
                                 h->d_cport.as<T>(), h->stream);
     return VTM_OK;
@@ -828,9 +866,11 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     const int32_t nsys = h->P.nsys, R = h->wave_R;
     const vtm::DevMaps M = dev_maps(h);
     // fixed cadence, or (check_every == 0) the next test is placed where the observed contraction
-    // rate predicts the tolerance (between 5 and 200 sweeps later), a little past it when a test
-    // costs more than a sweep: the margin is at most the test's measured cost in sweeps and 15 %
-    // of the prediction.  A refinement restart keeps the rate: the operator is the same.
+    // rate predicts the target (between 5 and 200 sweeps later), past it by a margin of half the
+    // prediction, at most the test's measured cost in sweeps: the rate measured early is faster than
+    // the asymptotic one, and a test that falls short costs a further test.  A refinement restart
+    // keeps the rate (the operator is the same) and is taken once the inner solve has gained a third
+    // of its factor eta.
     const bool adaptive = h->opt.check_every <= 0;
     int64_t cadence = adaptive ? 10 : h->opt.check_every;
     const int64_t maxsw = h->opt.max_sweeps > 0 ? h->opt.max_sweeps : 100000;
@@ -860,6 +900,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     const bool schur = use_schur(h);
     double rel_outer = 1.0, rel_prev = 1e300;
     const double eta = 1e-5;
+    constexpr double kMargin = 0.5;
     double rate_ref = -1.0;  // worst residual at the previous test of the current inner solve
     double lr_known = 0.0;   // last measured log contraction per sweep (< 0 when known)
     double test_sweeps = 0.0;  // cost of one test in sweeps (measured)
@@ -873,7 +914,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         sweeps += cnt;
         ++checks;
         ++inner_checks;
-        if (schur) local_solve<T>(h, false);  // interior potentials of the last sweep
+        if (schur && (rc = test_solve<T>(h))) return rc;  // interior potentials of the last sweep
         // merged potentials (plus the refined x in FP32_IR), FP64 residual
         vtm::launch_merge<T>(M, n, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, h->stream);
         HIP_TRY(hipEventRecord(c1, h->stream));
@@ -901,7 +942,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             if (lr_known < 0.0) {
                 const double target = refine ? std::max(tol, eta * rel_outer) : tol;
                 const double need = std::log(target / worst) / lr_known;
-                const double margin = std::min(0.15 * need, test_sweeps);
+                const double margin = std::min(kMargin * need, test_sweeps);
                 next = need > 0 ? (int64_t)std::ceil(need + std::max(0.0, margin)) : 5;
             }
             cadence = std::max<int64_t>(5, std::min<int64_t>(200, next));
@@ -917,7 +958,7 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             continue;
         }
         // FP32 inner solve: restart on the new residual once it has gained a factor eta or stalls
-        const bool gained = worst <= eta * rel_outer;
+        const bool gained = worst <= 3.0 * eta * rel_outer;
         const bool stalled = inner_checks >= 2 && worst > 0.995 * rel_prev;
         rel_prev = worst;
         if ((gained || stalled) && worst < rel_outer) {
@@ -930,7 +971,8 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             if (adaptive) {  // first test of the new inner solve from the known rate
                 const double target = std::max(tol, eta * rel_outer);
                 const double need = lr_known < 0.0 ? std::log(target / rel_outer) / lr_known : 10.0;
-                cadence = std::max<int64_t>(5, std::min<int64_t>(200, (int64_t)std::ceil(need)));
+                const double margin = std::min(kMargin * need, test_sweeps);
+                cadence = std::max<int64_t>(5, std::min<int64_t>(200, (int64_t)std::ceil(need + margin)));
             }
             ++outer;
             vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
@@ -1089,6 +1131,11 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
                      h->d_invz32.as<float>(), h->nports, st);
     const bool fused = want_green && h->plan_state == 1;
+    h->have_y = h->have_y32 = h->yb_ok = false;
+    if (fused && h->fp32()) {
+        HIP_TRY(ensure(h->d_gws32, sizeof(float) * (h->gws_total + 2)));
+        h->have_y32 = true;
+    }
     if (want_green) {
         HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
         HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
@@ -1112,6 +1159,7 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
             vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);
         }
         h->have_green = true;
+        h->have_y = fused;
     }
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipGetLastError());

@@ -25,7 +25,7 @@ namespace {
 
 constexpr int kThreads = 256;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kWriteX = 1, kNoWaves = 2, kZeroWaves = 4;
+constexpr int kWriteX = 1, kNoWaves = 2, kZeroWaves = 4, kWriteY = 8;
 
 __global__ void k_invz(const double *__restrict__ z, const int32_t *__restrict__ port_vtl, double *__restrict__ i64,
                        float *__restrict__ i32, int64_t np) {
@@ -154,6 +154,7 @@ struct FactorArgs {
     // port Green's functions (gpl == nullptr: not computed)
     const int4 *gpl;
     double *gws;
+    float *gws32;  // FP32 copy of the Y blocks (same offsets), or nullptr
     const uint16_t *perm;
     double *Gk;
     int nb;  // 16 x 16 blocks per row of the packed G_k
@@ -475,8 +476,9 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                     if (row < f && a < w) {
                         const double v = acc[jj] + tadd[jj];
                         if (row < nc) {
+                            Yg[row * w + a] = v;
                             if (Yl) Yl[row * w + a] = v;
-                            else Yg[row * w + a] = v;
+                            if (X.gws32) X.gws32[e.x + (int64_t)f * w + row * w + a] = (float)v;
                         } else {
                             X.gws[e.z + (int64_t)prow[jj] * pw + a + (pc0 - ppc0)] = v;
                         }
@@ -620,6 +622,7 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
                 double acc = T[i * w + a] / F[i * f + i];
                 for (int t = 0; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
                 Y[idx] = acc;
+                if (X.gws32) X.gws32[e.x + (int64_t)f * w + idx] = (float)acc;
             }
             __syncthreads();
             for (int idx = r; idx < m * w; idx += n) {  // T[nc:] - L21 Y into the parent's port front
@@ -673,6 +676,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, cons
     if (Gp.sn && p > 0) {
         X.gpl = Gp.sn + Gp.base[k];
         X.gws = Gp.ws + Gp.wso[k];
+        X.gws32 = Gp.ws32 ? Gp.ws32 + Gp.wso[k] : nullptr;
         X.perm = Gp.perm + pg0;
         X.Gk = G + goff[k];
         X.nb = (p + 15) >> 4;
@@ -743,10 +747,10 @@ __device__ inline ColRec load_col(const int32_t *__restrict__ rec, int i) {
 __device__ inline int hi16(int32_t w) { return (int)((uint32_t)w >> 16); }
 __device__ inline int lo16(int32_t w) { return (int)((uint32_t)w & 0xFFFFu); }
 
-// Forward and backward substitution of one subgraph, R right-hand sides interleaved in LDS.
-// In: vec = right side.  Out: tmp = x, vec = y (forward result).  Ends with a barrier.
+// Forward substitution of one subgraph, R right-hand sides interleaved in LDS.
+// In: vec = right side.  Out: vec = y = L^{-1} (right side) (tmp, ubuf: scratch).  Ends with a barrier.
 template <typename T, int R, int V>
-__device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, T *vec, T *tmp, T *ubuf) {
+__device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, T *vec, T *tmp, T *ubuf) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *lev_u = S.lev_u + C.o_lev;
     const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
@@ -822,7 +826,16 @@ __device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict
         }
         __syncthreads();
     }
-    // backward substitution, root level first: x_s = Linv^T y_s - W^T x_R  (x kept in tmp)
+}
+
+// Backward substitution of one subgraph: x_s = Linv^T y_s - W^T x_R, root level first.
+// In: vec = y.  Out: tmp = x.  Ends with a barrier.
+template <typename T, int R>
+__device__ void backward_subst(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, const T *vec, T *tmp) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int32_t *lev_c0 = S.lev_c0 + C.o_lev;
+    const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
+    const uint16_t *ridx = S.ridx + C.o_ridx;
     for (int lv = C.nlev - 1; lv >= 0; --lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
         for (int j = cb + tid; j < ce; j += nt) {
@@ -852,14 +865,22 @@ __device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict
     }
 }
 
+// Forward and backward substitution.  In: vec = right side.  Out: tmp = x, vec = y.
+template <typename T, int R, int V>
+__device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, T *vec, T *tmp, T *ubuf) {
+    forward_subst<T, R, V>(C, S, Vk, vec, tmp, ubuf);
+    backward_subst<T, R>(C, S, Vk, vec, tmp);
+}
+
 // One VTM sweep.  flags: kWriteX stores the local solutions; kNoWaves leaves o_next untouched
-// (a read-only solve with the current incoming waves); kZeroWaves ignores o_prev (a = 0).
+// (a read-only solve with the current incoming waves); kZeroWaves ignores o_prev (a = 0); kWriteY
+// stores the forward result y = L^{-1} (right side) in yout (layout of the local solutions).
 template <typename T, int R, int V>
 __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
                                                const T *__restrict__ vals, const T *__restrict__ bsplit,
                                                const int32_t *__restrict__ twin, const T *__restrict__ invz,
                                                const T *__restrict__ o_prev, T *__restrict__ o_next,
-                                               T *__restrict__ xloc, int flags) {
+                                               T *__restrict__ xloc, T *__restrict__ yout, int flags) {
     extern __shared__ char smraw[];
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
     const ClassDev C = S.cls[D.cls[k]];
@@ -911,6 +932,84 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
         T *xo_ = xloc + xo;
         for (int i = tid; i < nk * R; i += nt) xo_[i] = tmp[i];
     }
+    if (flags & kWriteY) {
+        T *yo_ = yout + xo;
+        for (int i = tid; i < nk * R; i += nt) yo_[i] = vec[i];
+    }
+}
+
+// Local solve of a convergence test from the port Green's columns Y = L^{-1} E (E: unit columns of
+// the port vertices, in the plan's port order) kept by the factorisation:
+//   x = K^{-1} (b~ + E w) = L^{-T} (y_b + Y w),  w = Z^{-1} a summed per port vertex,
+// with y_b = L^{-1} b~ stored by the zero-wave solve of the current source.  One parallel phase and
+// the backward substitution replace the level-by-level forward substitution.  Y rows of supernode
+// s live at the plan's workspace offset (after its port front), nc_s x w_s row-major.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp, const T *__restrict__ Yw,
+                                                int64_t nsplit, int64_t nports, const T *__restrict__ vals,
+                                                const T *__restrict__ yb, const int32_t *__restrict__ twin,
+                                                const T *__restrict__ invz, const T *__restrict__ o_in,
+                                                T *__restrict__ xloc) {
+    extern __shared__ char smraw[];
+    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int nk = C.nk;
+    T *vec = reinterpret_cast<T *>(smraw);  // y
+    T *tmp = vec + (size_t)nk * R;          // x
+    T *wsrt = tmp + (size_t)nk * R;         // w per port vertex, plan order
+    const T *Vk = vals + D.val[k];
+    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R, wo = (int64_t)g * nports * R;
+    for (int i = tid; i < nk * R; i += nt) vec[i] = yb[xo + i];
+    const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
+    for (int a = tid; a < p; a += nt) {
+        const int q = pg0 + Gp.perm[pg0 + a];
+        const int pb = D.pg_beg[q], pc = D.pg_cnt[q];
+        T acc[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] = 0;
+        for (int j = 0; j < pc; ++j) {
+            const T iz = invz[pb + j];
+            const T *av = o_in + wo + (int64_t)twin[pb + j] * R;
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] += av[c] * iz;
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) wsrt[a * R + c] = acc[c];
+    }
+    __syncthreads();
+    const int4 *pl = Gp.sn + Gp.base[k];
+    const int32_t *col_sn = S.col_sn + C.o_col, *sn_c0 = S.sn_c0 + C.o_sn, *sn_nc = S.sn_nc + C.o_sn,
+                  *sn_m = S.sn_m + C.o_sn;
+    const T *Yk = Yw + Gp.wso[k];
+    for (int col = tid; col < nk; col += nt) {  // y += Y w, one factor column (row of Y) per thread
+        const int s = col_sn[col];
+        const int4 e = pl[s];
+        const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
+        if (w == 0) continue;
+        const int f = sn_nc[s] + sn_m[s];
+        const T *yr = Yk + e.x + (int64_t)f * w + (int64_t)(col - sn_c0[s]) * w;
+        const T *wr = wsrt + (size_t)pc0 * R;
+        T acc[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] = 0;
+        int a = 0;
+        for (; a + 4 <= w; a += 4) {
+            const T y0 = yr[a], y1 = yr[a + 1], y2 = yr[a + 2], y3 = yr[a + 3];
+#pragma unroll
+            for (int c = 0; c < R; ++c)
+                acc[c] += y0 * wr[a * R + c] + y1 * wr[(a + 1) * R + c] + y2 * wr[(a + 2) * R + c] +
+                          y3 * wr[(a + 3) * R + c];
+        }
+        for (; a < w; ++a)
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] += yr[a] * wr[a * R + c];
+#pragma unroll
+        for (int c = 0; c < R; ++c) vec[col * R + c] += acc[c];
+    }
+    __syncthreads();
+    backward_subst<T, R>(C, S, Vk, vec, tmp);
+    T *xo_ = xloc + xo;
+    for (int i = tid; i < nk * R; i += nt) xo_[i] = tmp[i];
 }
 
 // Port Green's functions G_k = R_k K_k^{-1} R_k^T (R_k selects the port vertices), FP64:
@@ -1489,12 +1588,12 @@ hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_
 template <typename T, int V>
 static void launch_sweep_v(const DevSym &S, const DevSub &D, dim3 grid, dim3 block, size_t shm, int32_t R,
                            int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
-                           const T *invz, const T *o_prev, T *o_next, T *xloc, int flags, hipStream_t st) {
+                           const T *invz, const T *o_prev, T *o_next, T *xloc, T *yout, int flags, hipStream_t st) {
     switch (R) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, 1, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, 2, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, 4, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
-        default: hipLaunchKernelGGL((k_sweep<T, 8, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, 1, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, 2, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, 4, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
+        default: hipLaunchKernelGGL((k_sweep<T, 8, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
     }
 }
 
@@ -1502,13 +1601,46 @@ template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
                   int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals,
                   const T *bsplit, const int32_t *twin, const T *invz, const T *o_prev, T *o_next, T *xloc,
-                  int flags, hipStream_t st) {
+                  T *yout, int flags, hipStream_t st) {
     const size_t shm = sweep_shm<T>(max_nk, max_nu, variant, R);
     const dim3 grid(nsub, ngroups), block(threads);
     if (variant == 1)
-        launch_sweep_v<T, 1>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags, st);
+        launch_sweep_v<T, 1>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags, st);
     else
-        launch_sweep_v<T, 0>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, flags, st);
+        launch_sweep_v<T, 0>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags, st);
+}
+
+template <typename T>
+static const void *ysolve_fn(int32_t R) {
+    return R == 1 ? (const void *)k_ysolve<T, 1> : R == 2 ? (const void *)k_ysolve<T, 2>
+         : R == 4 ? (const void *)k_ysolve<T, 4> : (const void *)k_ysolve<T, 8>;
+}
+
+template <typename T>
+size_t ysolve_shm(int32_t max_nk, int32_t max_p, int32_t R) {
+    return sizeof(T) * (size_t)R * (2 * (size_t)max_nk + (size_t)max_p);
+}
+
+template <typename T>
+hipError_t prepare_ysolve(int32_t max_nk, int32_t max_p, int32_t R) {
+    const size_t shm = ysolve_shm<T>(max_nk, max_p, R);
+    if (shm > kMaxLds) return hipErrorInvalidValue;
+    if (shm <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(ysolve_fn<T>(R), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+template <typename T>
+void launch_ysolve(const DevSym &S, const DevSub &D, const DevGreen &Gp, const T *Yw, int32_t nsub, int32_t max_nk,
+                   int32_t max_p, int32_t ngroups, int32_t R, int64_t nsplit, int64_t nports, const T *vals,
+                   const T *yb, const int32_t *twin, const T *invz, const T *o_in, T *xloc, hipStream_t st) {
+    const size_t shm = ysolve_shm<T>(max_nk, max_p, R);
+    const dim3 grid(nsub, ngroups), block(256);
+    switch (R) {
+        case 1: hipLaunchKernelGGL((k_ysolve<T, 1>), grid, block, shm, st, S, D, Gp, Yw, nsplit, nports, vals, yb, twin, invz, o_in, xloc); break;
+        case 2: hipLaunchKernelGGL((k_ysolve<T, 2>), grid, block, shm, st, S, D, Gp, Yw, nsplit, nports, vals, yb, twin, invz, o_in, xloc); break;
+        case 4: hipLaunchKernelGGL((k_ysolve<T, 4>), grid, block, shm, st, S, D, Gp, Yw, nsplit, nports, vals, yb, twin, invz, o_in, xloc); break;
+        default: hipLaunchKernelGGL((k_ysolve<T, 8>), grid, block, shm, st, S, D, Gp, Yw, nsplit, nports, vals, yb, twin, invz, o_in, xloc); break;
+    }
 }
 
 void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
@@ -1630,10 +1762,18 @@ template void launch_split<double>(const DevMaps &, int64_t, const double *, int
 template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, float *, hipStream_t);
 template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
                                    int32_t, int64_t, int64_t, const double *, const double *, const int32_t *,
-                                   const double *, const double *, double *, double *, int, hipStream_t);
+                                   const double *, const double *, double *, double *, double *, int, hipStream_t);
 template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
                                   int32_t, int64_t, int64_t, const float *, const float *, const int32_t *,
-                                  const float *, const float *, float *, float *, int, hipStream_t);
+                                  const float *, const float *, float *, float *, float *, int, hipStream_t);
+template hipError_t prepare_ysolve<double>(int32_t, int32_t, int32_t);
+template hipError_t prepare_ysolve<float>(int32_t, int32_t, int32_t);
+template void launch_ysolve<double>(const DevSym &, const DevSub &, const DevGreen &, const double *, int32_t, int32_t,
+                                    int32_t, int32_t, int32_t, int64_t, int64_t, const double *, const double *,
+                                    const int32_t *, const double *, const double *, double *, hipStream_t);
+template void launch_ysolve<float>(const DevSym &, const DevSub &, const DevGreen &, const float *, int32_t, int32_t,
+                                   int32_t, int32_t, int32_t, int64_t, int64_t, const float *, const float *,
+                                   const int32_t *, const float *, const float *, float *, hipStream_t);
 template hipError_t prepare_sweep<double>(int32_t, int32_t, int32_t, int32_t);
 template void launch_gather_ports<double>(const DevSub &, int32_t, int32_t, int64_t, int32_t, int32_t, const double *,
                                           double *, hipStream_t);

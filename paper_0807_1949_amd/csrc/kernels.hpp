@@ -62,6 +62,7 @@ struct DevGreen {
     const int32_t *idoff;   // per sorted port: workspace offset of its unit right-side entry
     const uint16_t *perm;   // per sorted port: its port-vertex index in the subgraph
     double *ws;             // port fronts (nc + m) x w followed by Y blocks nc x w; zero on entry
+    float *ws32;            // FP32 copy of the Y blocks at the same offsets, or nullptr
 };
 
 // Split-vector and merge maps.
@@ -98,11 +99,21 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
 template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
                   int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
-                  const T *invz, const T *o_prev, T *o_next, T *xloc, int flags, hipStream_t st);
-constexpr int kSweepWriteX = 1, kSweepNoWaves = 2, kSweepZeroWaves = 4;  // sweep flags
+                  const T *invz, const T *o_prev, T *o_next, T *xloc, T *yout, int flags, hipStream_t st);
+constexpr int kSweepWriteX = 1, kSweepNoWaves = 2, kSweepZeroWaves = 4, kSweepWriteY = 8;  // sweep flags
 // Raise the dynamic-LDS limit of the sweep kernel when needed (call outside stream capture).
 template <typename T>
 hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R);
+
+// Local solutions of a convergence test from the stored Y blocks (Yw: the Green workspace in T
+// precision) and y_b = L^{-1} b~ (yb, layout of the local solutions): one parallel product and the
+// backward substitution.  prepare_ysolve fails when the LDS need exceeds the CU's.
+template <typename T>
+hipError_t prepare_ysolve(int32_t max_nk, int32_t max_p, int32_t R);
+template <typename T>
+void launch_ysolve(const DevSym &S, const DevSub &D, const DevGreen &Gp, const T *Yw, int32_t nsub, int32_t max_nk,
+                   int32_t max_p, int32_t ngroups, int32_t R, int64_t nsplit, int64_t nports, const T *vals,
+                   const T *yb, const int32_t *twin, const T *invz, const T *o_in, T *xloc, hipStream_t st);
 
 // Port Green's functions G_k = R K_k^{-1} R^T by one substitution per group of four port columns
 // (FP64, packed like above); used when the column plan does not apply.

@@ -289,3 +289,31 @@ def test_persistent_sweeps_match_per_sweep_launches(B, name, nrhs):
     assert np.all(np.abs(r0["iters"] - r1["iters"]) <= 10)
     for c in range(nrhs):
         assert _rel(r0["x"][c], r1["x"][c]) <= 1e-6
+
+
+@pytest.mark.parametrize("name,precision", [("c2", 0), ("c1", 0), ("c3", 0), ("c2", 1)])
+def test_test_solve_from_green_columns_matches_substitution(B, name, precision):
+    """The convergence test's local solve from the stored Green's columns (y_b + Y w, then the
+    backward substitution) gives the iterate of the substitution solve: FP64 solve == run_sweeps
+    over the same sweep count (to rounding) == the oracle's iterate at that count; FP32 sweeps with
+    refinement: the returned x has the requested true residual."""
+    cfg = gen.make_config(name, small=True)
+    print(f"[parity] green-column test solve {name} precision {precision}", flush=True)
+    h, P, z = _setup(B, cfg, precision=precision, z_scale=8.0, sweep_mode=2, check_every=10)
+    b = cfg["b"][:2] if name == "c3" else cfg["b"][:1]
+    tol = 1e-6
+    r = h.solve(b, tol)
+    assert r["status"] == 0 and h.get_stats()["sweep_mode"] == 2
+    if precision == 0:
+        n = int(r["iters"].max())
+        h.reset_waves()
+        xs = h.run_sweeps(b, n)
+        xo = O.Solver(P, z).run(b, n, 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"]
+        for q in range(b.shape[0]):
+            assert _rel(r["x"][q], xs[q]) <= 1e-12, (q, _rel(r["x"][q], xs[q]))
+            assert _rel(r["x"][q], xo[q]) <= 1e-10, (q, _rel(r["x"][q], xo[q]))
+    else:
+        A = cfg["A"].to_scipy()
+        for q in range(b.shape[0]):
+            res = np.linalg.norm(b[q] - A @ r["x"][q]) / np.linalg.norm(b[q])
+            assert res <= 2 * tol, (q, res)
