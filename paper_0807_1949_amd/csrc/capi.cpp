@@ -79,6 +79,7 @@ struct vtm_ctx {
     bool have_y = false;  // the set-up kept the Y blocks (FP64 workspace, FP32 copy when sweeping in FP32)
     bool yb_ok = false;   // yb holds L^{-1} b~ of the current source split
     bool have_y32 = false;  // d_gws32 is written by the factorisation
+    bool gws_clean = false; // the port fronts in d_gws are all zero
     // column plan of the multifrontal Green's-function computation (built on first use)
     DevBuf d_gsn, d_gbase, d_gwso, d_gidoff, d_gperm, d_gws, d_levmaxf;
     int plan_state = 0;  // 0 not built, 1 ready, -1 not applicable (fall back to per-column solves)
@@ -445,6 +446,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     h->h_pgbeg = pgbeg;
     h->h_pgcnt = pgcnt;
     h->plan_state = 0;
+    h->gws_clean = false;
     {
         std::vector<int64_t> goff(nsub + 1, 0);
         h->max_p = 0;
@@ -488,7 +490,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     // residual chunks: contiguous row ranges inside one system
     std::vector<int64_t> chunkrow;
     std::vector<int32_t> chunksys, syschunk(P.nsys + 1, 0);
-    const int64_t CH = 4096;
+    const int64_t CH = 256;  // one row per thread of the residual kernel
     for (int32_t s = 0; s < P.nsys; ++s) {
         for (int64_t r = P.sys_ptr[s]; r < P.sys_ptr[s + 1]; r += CH) {
             chunkrow.push_back(r);
@@ -1111,7 +1113,7 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     }
     HIP_TRY(ensure(h->d_invz64, sizeof(double) * (h->nports + 1)));
     HIP_TRY(ensure(h->d_invz32, sizeof(float) * (h->nports + 1)));
-    HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
+
     HIP_TRY(ensure(h->d_status, sizeof(int32_t) * (P.nsub + 1)));
     DevBuf &ws = h->d_ws;
     HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
@@ -1123,7 +1125,11 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
         vtm_status rc = build_green_plan(h);
         if (rc) return rc;
     }
-    if (want_green && h->plan_state == 1) HIP_TRY(ensure(h->d_gws, sizeof(double) * (h->gws_total + 2)));
+    if (want_green && h->plan_state == 1) {
+        const void *before = h->d_gws.p;
+        HIP_TRY(ensure(h->d_gws, sizeof(double) * (h->gws_total + 2)));
+        if (h->d_gws.p != before) h->gws_clean = false;
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1139,16 +1145,20 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     if (want_green) {
         HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
         HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
-        if (fused) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
+        // the port fronts start at zero; every factorisation leaves them zero (each supernode clears
+        // the front it consumed), so the workspace is cleared only when new
+        if (fused && !h->gws_clean) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
     }
+    // FP32 sweeps take the factor in FP32 straight from the factorisation; the FP64 copy is kept
+    // when the sweeps run in FP64 or the Green's functions come from the substitution fallback
+    const bool want64 = !h->fp32() || (want_green && !fused);
+    if (want64) HIP_TRY(ensure(h->d_vals64, sizeof(double) * (h->total_val + 1)));
+    if (h->fp32()) HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
     vtm::launch_factor(dev_sym(h), dev_sub(h), P.nsub, h->max_front, h->d_aval.as<double>(),
-                       h->d_invz64.as<double>(), h->d_vals64.as<double>(), ws.as<double>(),
+                       h->d_invz64.as<double>(), want64 ? h->d_vals64.as<double>() : nullptr,
+                       h->fp32() ? h->d_vals32.as<float>() : nullptr, ws.as<double>(),
                        h->d_status.as<int32_t>(), dev_green(h, fused), h->d_goff.as<int64_t>(),
                        want_green ? h->d_G64.as<double>() : nullptr, st);
-    if (h->fp32()) {
-        HIP_TRY(ensure(h->d_vals32, sizeof(float) * (h->total_val + 1)));
-        vtm::launch_to_f32(h->d_vals64.as<double>(), h->d_vals32.as<float>(), h->total_val, st);
-    }
     h->have_green = false;
     if (want_green) {
         if (!fused)
@@ -1166,6 +1176,7 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     std::vector<int32_t> status(P.nsub);
     HIP_TRY(hipMemcpyAsync(status.data(), h->d_status.p, sizeof(int32_t) * P.nsub, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (fused) h->gws_clean = true;  // the factorisation ran to its end
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);

@@ -145,7 +145,8 @@ __device__ inline int64_t gpack_index(int nb, int i, int j) {
 
 struct FactorArgs {
     const double *A;       // assembly values of the subgraph (scatter order)
-    double *V;             // factor values of the subgraph
+    double *V;             // factor values of the subgraph (FP64), or nullptr
+    float *V32;            // the same in FP32, or nullptr
     double *W;             // update-matrix workspace of the subgraph
     const double *dplus;   // port diagonal per factor position
     const int32_t *sn_c0, *sn_nc, *sn_m, *sn_val, *sn_uoff, *sn_ridx;
@@ -378,12 +379,16 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
         }
     }
     // 3. outputs: Linv and W (f x nc, row-major), the update matrix (packed lower triangle)
-    double *Vs = X.V + X.sn_val[s];
     {
+        double *Vs = X.V ? X.V + X.sn_val[s] : nullptr;
+        float *Vs32 = X.V32 ? X.V32 + X.sn_val[s] : nullptr;
         const Cover cv = cover(nc, r, n);
         for (int j = cv.c; j < nc; j += cv.cw)
-            for (int i = cv.r0; i < f; i += cv.rs)
-                Vs[i * nc + j] = i < nc ? (j <= i ? F[j * f + i] : 0.0) : -F[j * f + i];
+            for (int i = cv.r0; i < f; i += cv.rs) {
+                const double v = i < nc ? (j <= i ? F[j * f + i] : 0.0) : -F[j * f + i];
+                if (Vs) Vs[i * nc + j] = v;
+                if (Vs32) Vs32[i * nc + j] = (float)v;
+            }
     }
     if (m > 0) {
         double *Us = X.W + X.sn_uoff[s];
@@ -397,7 +402,7 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
         const int4 e = X.gpl[s];
         const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
         if (w > 0) {
-            const double *T = X.gws + e.x;
+            double *T = X.gws + e.x;
             double *Yg = X.gws + e.x + (int64_t)f * w;
             const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
             const uint16_t *rs_ = X.rel + X.sn_ridx[s];
@@ -438,7 +443,10 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                     for (int q = 0; q < 16; ++q) t[q] = i0 + q * n < f * w ? T[i0 + q * n] : 0.0;
 #pragma unroll
                     for (int q = 0; q < 16; ++q)
-                        if (i0 + q * n < f * w) Ts[i0 + q * n] = t[q];
+                        if (i0 + q * n < f * w) {
+                            Ts[i0 + q * n] = t[q];
+                            T[i0 + q * n] = 0.0;  // the port front is left zero for the next factorisation
+                        }
                 }
                 team_sync<BLK>();
             }
@@ -486,6 +494,8 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                 }
             }
             team_sync<BLK>();
+            if (!staged)  // the port front is left zero for the next factorisation
+                for (int i = r; i < f * w; i += n) T[i] = 0.0;
             for (int it = wv; it < tcn * (tcn + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
                 tri_tile(it, ta, tb);
@@ -584,16 +594,20 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
     }
     __syncthreads();
     // 5. outputs
-    double *Vs = X.V + X.sn_val[s];
+    double *Vs = X.V ? X.V + X.sn_val[s] : nullptr;
+    float *Vs32 = X.V32 ? X.V32 + X.sn_val[s] : nullptr;
     for (int idx = r; idx < nc * nc; idx += n) {
         const int i = idx / nc, j = idx - i * nc;
-        Vs[idx] = j > i ? 0.0 : (j == i ? 1.0 / F[i * f + i] : F[j * f + i]);
+        const double v = j > i ? 0.0 : (j == i ? 1.0 / F[i * f + i] : F[j * f + i]);
+        if (Vs) Vs[idx] = v;
+        if (Vs32) Vs32[idx] = (float)v;
     }
     for (int idx = r; idx < m * nc; idx += n) {  // W[q][j] = sum_{t >= j} L21[q][t] Linv[t][j]
         const int q = idx / nc, j = idx - q * nc;
         double acc = F[j * f + nc + q] / F[j * f + j];
         for (int t = j + 1; t < nc; ++t) acc += F[t * f + nc + q] * F[j * f + t];
-        Vs[nc * nc + idx] = acc;
+        if (Vs) Vs[nc * nc + idx] = acc;
+        if (Vs32) Vs32[nc * nc + idx] = (float)acc;
     }
     double *Us = X.W + X.sn_uoff[s];
     const int tm = (m + 15) >> 4, kr = lane >> 4;
@@ -613,7 +627,7 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
         const int4 e = X.gpl[s];
         const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
         if (w > 0) {
-            const double *T = X.gws + e.x;
+            double *T = X.gws + e.x;
             double *Y = X.gws + e.x + (int64_t)f * w;
             const int pw = (int)((uint32_t)e.w >> 16), ppc0 = e.w & 0xFFFF;
             const uint16_t *rs_ = X.rel + X.sn_ridx[s];
@@ -631,6 +645,8 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
                 for (int t = 0; t < nc; ++t) acc -= F[t * f + nc + q] * Y[t * w + a];
                 X.gws[e.z + (int64_t)rs_[q] * pw + a + (pc0 - ppc0)] = acc;
             }
+            __syncthreads();
+            for (int i = r; i < f * w; i += n) T[i] = 0.0;  // the port front is left zero for the next factorisation
             const int tw = (w + 15) >> 4;
             for (int it = wv; it < tw * (tw + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
@@ -645,7 +661,7 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
 
 __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, const double *__restrict__ aval,
                                                      const double *__restrict__ invz, double *__restrict__ vals,
-                                                     double *__restrict__ ws, int lds_doubles,
+                                                     float *__restrict__ vals32, double *__restrict__ ws, int lds_doubles,
                                                      int32_t *__restrict__ status, DevGreen Gp,
                                                      const int64_t *__restrict__ goff, double *__restrict__ G) {
     extern __shared__ double sm[];
@@ -656,7 +672,8 @@ __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, cons
     const int nk = C.nk;
     FactorArgs X;
     X.A = aval + D.aval[k];
-    X.V = vals + D.val[k];
+    X.V = vals ? vals + D.val[k] : nullptr;
+    X.V32 = vals32 ? vals32 + D.val[k] : nullptr;
     X.W = ws + D.ws[k];
     double *dplus = X.W + C.ws_u + (int64_t)C.max_front * C.max_front;
     X.dplus = dplus;
@@ -816,10 +833,15 @@ __device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__res
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int j = 0; j < n; ++j) {
-                const T lj = l[j];
+            for (int j0 = 0; j0 < n; j0 += 8) {  // loads of eight entries in flight together
+                T lv[8];
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lj * t[j * R + c];
+                for (int q = 0; q < 8; ++q) lv[q] = j0 + q < n ? l[j0 + q] : (T)0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (j0 + q < n)
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[c] += lv[q] * t[(j0 + q) * R + c];
             }
 #pragma unroll
             for (int c = 0; c < R; ++c) out[c] = acc[c];
@@ -847,16 +869,29 @@ __device__ void backward_subst(const ClassDev &C, const DevSym &S, const T *__re
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int i = jj; i < nc; ++i) {
-                const T li = lcol[i * nc];
+            for (int i0 = jj; i0 < nc; i0 += 8) {  // loads of eight entries in flight together
+                T lv[8];
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += li * vec[(c0 + i) * R + c];
+                for (int q = 0; q < 8; ++q) lv[q] = i0 + q < nc ? lcol[(i0 + q) * nc] : (T)0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (i0 + q < nc)
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[c] += lv[q] * vec[(c0 + i0 + q) * R + c];
             }
-            for (int q = 0; q < m; ++q) {
-                const T wq = wcol[q * nc];
-                const T *x = tmp + rr[q] * R;
+            for (int q0 = 0; q0 < m; q0 += 8) {
+                T wv[8];
+                int ri[8];
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] -= wq * x[c];
+                for (int q = 0; q < 8; ++q) {
+                    wv[q] = q0 + q < m ? wcol[(q0 + q) * nc] : (T)0;
+                    ri[q] = q0 + q < m ? rr[q0 + q] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q0 + q < m)
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[c] -= wv[q] * tmp[ri[q] * R + c];
             }
 #pragma unroll
             for (int c = 0; c < R; ++c) tmp[j * R + c] = acc[c];
@@ -992,17 +1027,16 @@ __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp,
         T acc[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[c] = 0;
-        int a = 0;
-        for (; a + 4 <= w; a += 4) {
-            const T y0 = yr[a], y1 = yr[a + 1], y2 = yr[a + 2], y3 = yr[a + 3];
+        for (int a0 = 0; a0 < w; a0 += 16) {  // sixteen loads in flight before the first product
+            T yv[16];
 #pragma unroll
-            for (int c = 0; c < R; ++c)
-                acc[c] += y0 * wr[a * R + c] + y1 * wr[(a + 1) * R + c] + y2 * wr[(a + 2) * R + c] +
-                          y3 * wr[(a + 3) * R + c];
+            for (int q = 0; q < 16; ++q) yv[q] = a0 + q < w ? yr[a0 + q] : (T)0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (a0 + q < w)
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] += yv[q] * wr[(a0 + q) * R + c];
         }
-        for (; a < w; ++a)
-#pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] += yr[a] * wr[a * R + c];
 #pragma unroll
         for (int c = 0; c < R; ++c) vec[col * R + c] += acc[c];
     }
@@ -1540,8 +1574,8 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
 }
 
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
-                   const double *invz, double *vals, double *ws, int32_t *status, const DevGreen &Gp,
-                   const int64_t *goff, double *G, hipStream_t st) {
+                   const double *invz, double *vals, float *vals32, double *ws, int32_t *status,
+                   const DevGreen &Gp, const int64_t *goff, double *G, hipStream_t st) {
     // 40 KiB of fronts per workgroup keeps four workgroups on a CU; larger fronts get the room they
     // need up to the CU's LDS, beyond that they stay in the workspace
     int lds_doubles = kFactorLds;
@@ -1549,8 +1583,8 @@ void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_f
     if (need > lds_doubles && need <= (int)((kMaxLds - 1024) / sizeof(double))) lds_doubles = need;
     const size_t shm = sizeof(double) * (size_t)lds_doubles;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, ws, lds_doubles, status,
-                       Gp, goff, G);
+    hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, vals32, ws, lds_doubles,
+                       status, Gp, goff, G);
 }
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {

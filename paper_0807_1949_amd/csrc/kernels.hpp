@@ -86,7 +86,7 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
 // first non-positive pivot (0 if fine).  With Gp.sn set it also accumulates the port Green's functions
 // G_k = R K_k^{-1} R^T (FP64, packed lower block triangle at goff[k], see k_schur; zero on entry).
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
-                   const double *invz, double *vals, double *ws, int32_t *status, const DevGreen &Gp,
+                   const double *invz, double *vals, float *vals32, double *ws, int32_t *status, const DevGreen &Gp,
                    const int64_t *goff, double *G, hipStream_t st);
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
