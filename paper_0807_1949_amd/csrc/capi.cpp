@@ -1313,7 +1313,7 @@ vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, con
     std::string err;
     int rc = vtm::build_partition(h->A, *spec, h->P, err);
     if (rc) return fail(rc, err);
-    int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : (spec->kind == VTM_PART_RCB || (spec->kind == VTM_PART_GRID && spec->dims[2] > 1) ? 16 : 8);
+    int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : 16;
     rc = vtm::build_symbolic(h->P, leaf, h->S, err);
     if (rc) return fail(rc, err);
     if (h->host_only()) host_sizes(h);
