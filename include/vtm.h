@@ -160,7 +160,7 @@ typedef struct {
                                 persistent launches read once per launch, so averaged over its sweeps)
                                 + vectors + waves */
     double flops_per_sweep;  /* substitution: 4 * nrhs * lower-factor entries; port-reduced: 2 * nrhs * G entries */
-    int32_t sweep_mode;      /* mode of the last solve: 1 substitution, 2 port-reduced */
+    int32_t sweep_mode;      /* mode of the last solve or vtm_run_sweeps: 1 substitution, 2 port-reduced */
     int32_t persistent;      /* 1 if the last solve or run ran its sweeps in persistent launches */
 } vtm_stats;
 

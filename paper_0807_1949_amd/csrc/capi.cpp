@@ -69,7 +69,7 @@ struct vtm_ctx {
     // symbolic (class level)
     DevBuf d_segu, d_usn, d_levu, d_colrec, d_urec;
     // port-reduced sweeps
-    DevBuf d_goff, d_G64, d_G32, d_cport;
+    DevBuf d_goff, d_G64, d_G32, d_cport, d_gorder, d_portpg;
     int32_t max_p = 0, npg = 0, max_np = 0;
     int32_t persist_R = -1, persist_ng = -1;
     bool persist_fits = false;
@@ -135,7 +135,7 @@ struct vtm_ctx {
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
                           &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
-                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
+                          &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gorder, &d_portpg, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
     }
@@ -222,6 +222,8 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     d.pg_beg = h->d_pgbeg.as<int32_t>();
     d.pg_cnt = h->d_pgcnt.as<int32_t>();
     d.port_ptr = h->d_portptr.as<int32_t>();
+    d.port_pg = h->d_portpg.as<uint16_t>();
+    d.gorder = h->d_gorder.as<int32_t>();
     return d;
 }
 
@@ -413,7 +415,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     const int32_t nsub = P.nsub;
     std::vector<int32_t> subcls(nsub), pgptr(nsub + 1, 0), pgbeg, pgcnt;
     std::vector<int64_t> subval(nsub), subx(nsub), subaval(nsub), subws(nsub);
-    std::vector<uint16_t> pgpos;
+    std::vector<uint16_t> pgpos, portpg(P.port_v.size());
     std::vector<double> afront;  // lower entries of every local matrix in the order of its class's scatter list
     int64_t vo = 0, wo = 0;
     h->total_lower = 0;
@@ -432,6 +434,7 @@ vtm_status upload_partition(vtm_ctx *h) {
         for (int64_t p = P.port_ptr[k]; p < P.port_ptr[k + 1];) {
             int64_t q = p;
             while (q < P.port_ptr[k + 1] && P.port_v[q] == P.port_v[p]) ++q;
+            for (int64_t t = p; t < q; ++t) portpg[t] = (uint16_t)(pgpos.size() - pgptr[k]);
             pgpos.push_back((uint16_t)C.ipos[P.port_lidx[p]]);
             pgbeg.push_back((int32_t)p);
             pgcnt.push_back((int32_t)(q - p));
@@ -462,6 +465,13 @@ vtm_status upload_partition(vtm_ctx *h) {
         h->total_g = goff[nsub];
         h->npg = pgptr[nsub];
         HIP_TRY(upload(h->d_goff, goff, st));
+        // launch order of the port-reduced sweep: largest G_k first (ties by subgraph id)
+        std::vector<int32_t> gorder(nsub);
+        for (int32_t k = 0; k < nsub; ++k) gorder[k] = k;
+        std::stable_sort(gorder.begin(), gorder.end(), [&](int32_t a, int32_t b) {
+            return goff[a + 1] - goff[a] > goff[b + 1] - goff[b];
+        });
+        HIP_TRY(upload(h->d_gorder, gorder, st));
     }
     h->nsplit = P.loc_ptr[nsub];
     h->nports = (int64_t)P.port_v.size();
@@ -507,7 +517,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     UP(d_chptr, chptr); UP(d_chidx, chidx); UP(d_segptr, segptr); UP(d_segoff, segoff); UP(d_segc0, segc0);
     UP(d_segnc, segnc); UP(d_segu, segu); UP(d_usn, usn); UP(d_levu, levu); UP(d_colrec, colrec); UP(d_urec, urec); UP(d_scptr, scptr); UP(d_scdst, scdst);
     UP(d_subcls, subcls); UP(d_subval, subval); UP(d_subx, subx); UP(d_subaval, subaval); UP(d_subws, subws);
-    UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt);
+    UP(d_pgptr, pgptr); UP(d_pgpos, pgpos); UP(d_pgbeg, pgbeg); UP(d_pgcnt, pgcnt); UP(d_portpg, portpg);
     {
         std::vector<int32_t> portptr(nsub + 1);
         h->max_np = 0;
@@ -1033,6 +1043,7 @@ vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int6
     const int64_t n = h->P.n;
     const vtm::DevMaps M = dev_maps(h);
     vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, h->wave_R, h->d_bsplit.as<T>(), h->stream);
+    h->stats.sweep_mode = use_schur(h) ? 2 : 1;
     if (nsweeps > 0) {
         if ((rc = port_constants<T>(h))) return rc;
         if ((rc = run_sweeps_dev<T>(h, nsweeps))) return rc;

@@ -25,6 +25,7 @@ namespace {
 
 constexpr int kThreads = 256;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWriteX = 1, kNoWaves = 2, kZeroWaves = 4, kWriteY = 8;
 
 __global__ void k_invz(const double *__restrict__ z, const int32_t *__restrict__ port_vtl, double *__restrict__ i64,
@@ -137,10 +138,15 @@ __device__ inline f64x4 gram_tile(int ta, int tb, int K, int n, int lane, LD ld)
 // Position of G[i][j] in the packed symmetric layout of the port-reduced sweep (lower block
 // triangle of 16 x 16 blocks, block column by block column, each block row-major), or -1 for an
 // entry of the strictly upper block triangle (not stored).
+// Position of entry (i, j) in a 16 x 16 block of G_k: the four column quads one after another, each
+// row by row (entry (i, j) at 64 (j / 4) + 4 i + j % 4).  Lane 16 q + m of a wave then reads
+// B[m][4 q .. 4 q + 4) as one contiguous 16-byte word, and a wave reads a block in address order.
+__device__ inline int gblk_pos(int i, int j) { return 64 * (j >> 2) + 4 * i + (j & 3); }
+
 __device__ inline int64_t gpack_index(int nb, int i, int j) {
     const int I = i >> 4, J = j >> 4;
     if (I < J) return -1;
-    return ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + (i & 15) * 16 + (j & 15);
+    return ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + gblk_pos(i & 15, j & 15);
 }
 
 struct FactorArgs {
@@ -1102,12 +1108,18 @@ __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R,
 // Port-reduced sweep: u = c + G (Z^{-1} a) on the port vertices, then o_p = 2 u - a_p.
 // G_k is symmetric; it is stored as its lower block triangle of 16 x 16 blocks (diagonal blocks in
 // full, rows and columns padded with zeros to nb = ceil(p / 16) blocks), block column by block
-// column (see gpack_index).  Wave w of the workgroup owns the block columns J = 8 m + w and
-// 8 m + 7 - w (equal work for the four waves when nb is a multiple of 8).  For an off-diagonal
-// block B = G[I][J]: y_I += B x_J (summed over the 4 lanes of a block row by DPP, added to the
-// wave's LDS copy of y) and y_J += B^T x_I (kept in registers for the whole column, summed over
-// its 16 lanes once per column).  Each y entry of a wave has one writing lane per instruction, so
-// the LDS adds are atomics only to avoid waiting on a read-modify-write.  Lane l holds B[l / 4][4 (l % 4) .. + 4) with one or two 16-byte loads.
+// column (see gpack_index and gblk_pos), so that the blocks of G_k are read in storage order.
+//
+// One wave per (subgraph, RHS group): workgroup b takes subgraph gorder[b] (largest G_k first, so that
+// the longest waves start early and the short ones fill the tail).  The wave streams its blocks with
+// PF of them in flight.  Lane l = 16 q + m holds B[m][4 q .. 4 q + 4) of a block B = G[I][J] (one
+// or two 16-byte loads).  For every block, y_I += B x_J runs on the matrix cores: four
+// v_mfma_*_16x16x4 whose A operand is the lane's four entries and whose B operand is x_J (column
+// c < R of the 16 x 16 operand holds right-hand side c, the rest zero); the product is added to y_I
+// in LDS.  For an off-diagonal block, y_J += B^T x_I runs on the vector units: lane (m, q) adds
+// B[m][4 q + kk] x_I[m][c] into registers for the whole block column, and the 16 lanes of each q
+// are summed once per column (DPP row rotations).  A single wave adds into y in program order, so
+// the result does not depend on timing.  LDS holds Z^{-1} a and y, 2 pp R values.
 template <typename T> struct Quad;
 template <> struct Quad<float> {
     float4 v;
@@ -1123,7 +1135,7 @@ template <> struct Quad<double> {
     __device__ double operator[](int i) const { return i == 0 ? a.x : i == 1 ? a.y : i == 2 ? b.x : b.y; }
 };
 
-// Sum over the 4 lanes of a quad (DPP quad permutations: xor 1, then xor 2).
+// Lane moves by DPP (quad permutations and row rotations); a double moves as its two halves.
 template <int CTRL>
 __device__ inline float dpp_mov(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
@@ -1135,171 +1147,249 @@ __device__ inline double dpp_mov(double v) {
     const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
-template <typename T>
-__device__ inline T quad_sum(T v) {
-    v += dpp_mov<0xB1>(v);  // quad_perm [1, 0, 3, 2]
-    v += dpp_mov<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+// Value of lane m ^ X (X = 8, 1, 2 or 4) within each 16-lane DPP row: row_ror:8 for 8, quad
+// permutations for 1 and 2, and for 4 a shift left by 4 into banks 0 and 2 plus a shift right by 4
+// into banks 1 and 3.
+template <int X>
+__device__ inline int lane_xor(int v) {
+    if constexpr (X == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+    if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    if constexpr (X == 4) {
+        const int lo = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);
+        return __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xF, 0xA, false);
+    }
     return v;
 }
-
-// Block columns of wave w (of 4) in increasing order: the i-th one, or -1.
-__device__ inline int wave_col(int w, int i, int nb) {
-    const int J = 8 * (i >> 1) + ((i & 1) ? 7 - w : w);
-    return J < nb ? J : -1;
+template <int X>
+__device__ inline float lane_xor(float v) {
+    return __builtin_bit_cast(float, lane_xor<X>(__builtin_bit_cast(int, v)));
+}
+template <int X>
+__device__ inline double lane_xor(double v) {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = lane_xor<X>((int)x), hi = lane_xor<X>((int)(x >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Sum of v[0 .. N) over the 16 lanes of each DPP row, scattered: level by level (lane bits 3, 0, 1,
+// 2) a lane keeps the lower or upper half of its values, by its bit, and adds the partner's copy of
+// that half.  With N >= 16, lane m ends with the complete sums of the N / 16 values
+// j0 + [0, N / 16) in v[0 ..), j0 = scatter_base<N>(m).  With N < 16 the last levels add the single
+// value of both partners, so that every lane of a group holds the sum; the group's lane with the
+// unused bits zero writes it (scatter_writer<N>).
+template <typename T, int N, int L = 0>
+__device__ inline void row16_reduce_scatter(T (&v)[N], int m) {
+    if constexpr (L < 4) {
+        constexpr int X = L == 0 ? 8 : L == 1 ? 1 : L == 2 ? 2 : 4;
+        constexpr int S = L == 0 ? 3 : L == 1 ? 0 : L == 2 ? 1 : 2;
+        constexpr int C = (N >> L) > 1 ? (N >> L) : 1;  // values held before this level
+        if constexpr (C > 1) {
+            const bool up = (m >> S) & 1;
+#pragma unroll
+            for (int i = 0; i < C / 2; ++i) {
+                const T keep = up ? v[C / 2 + i] : v[i], send = up ? v[i] : v[C / 2 + i];
+                v[i] = keep + lane_xor<X>(send);
+            }
+        } else {
+            v[0] += lane_xor<X>(v[0]);
+        }
+        row16_reduce_scatter<T, N, L + 1>(v, m);
+    }
+}
+template <int N>
+__device__ inline int scatter_base(int m) {
+    int j0 = 0, c = N;
+    const int bits[4] = {3, 0, 1, 2};
+#pragma unroll
+    for (int L = 0; L < 4; ++L)
+        if (c > 1) {
+            if ((m >> bits[L]) & 1) j0 += c / 2;
+            c /= 2;
+        }
+    return j0;
+}
+template <int N>
+__device__ inline bool scatter_writer(int m) {
+    int c = N;
+    const int bits[4] = {3, 0, 1, 2};
+    bool w = true;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+        if (c <= 1 && ((m >> bits[L]) & 1)) w = false;
+        c = c > 1 ? c / 2 : 1;
+    }
+    return w;
+}
+
+// 16 x 16 x 4 matrix-core step D += A B: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// accumulator register i of lane l holds D[row(l / 16, i)][l % 16], with row 4 (l / 16) + i for the
+// FP32 instruction and 4 i + l / 16 for the FP64 one.
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+    typedef f32x4 acc;
+    __device__ static acc step(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int q, int i) { return 4 * q + i; }
+    __device__ static int yrow(int r) { return r; }  // accumulator rows 4 q + i are consecutive
+};
+template <> struct Mma<double> {
+    typedef f64x4 acc;
+    __device__ static acc step(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int q, int i) { return 4 * i + q; }
+    __device__ static int yrow(int r) { return 4 * (r & 3) + (r >> 2); }  // stores row 4 i + q at 4 q + i
+};
+
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_schur(DevSub D, int32_t npg, int64_t nports, int32_t max_np,
-                                               const T *__restrict__ G,
-                                               const int64_t *__restrict__ goff, const T *__restrict__ cport,
-                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
-                                               const T *__restrict__ o_prev, T *__restrict__ o_next) {
+__global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
+                                              const int64_t *__restrict__ goff, const T *__restrict__ cport,
+                                              const int32_t *__restrict__ twin, const T *__restrict__ invz,
+                                              const T *__restrict__ o_prev, T *__restrict__ o_next) {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8, "right-hand sides per wave");
     extern __shared__ char smraw[];
-    constexpr int PF = sizeof(T) == 4 ? 8 : 4;  // blocks in flight per wave
-    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int PF = sizeof(T) == 4 ? 16 : 8;  // blocks in flight (16 KB)
+    constexpr int U = 4;                          // ports per lane whose loads are issued together
+    constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
+    typedef typename Mma<T>::acc Acc;
+    const int k = D.gorder[blockIdx.x], g = blockIdx.y, lane = threadIdx.x;
+    const int m = lane & 15, q = lane >> 4;
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
-    const int nb = (p + 15) >> 4, pp = nb * 16;
+    const int nb = (p + 15) >> 4, pp = nb * 16, nblk = nb * (nb + 1) / 2;
+    const int ps = pp + 4;                         // row stride of y (staggers the LDS banks of the RHS)
     const int64_t wo = (int64_t)g * nports * R;
     T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a per port vertex [pp][R]
-    T *yw = xz + (size_t)pp * R;           // per-wave partial y [4][pp][R]
-    const T *Gk = G + goff[k];
-    const int r = lane >> 2, c0 = 4 * (lane & 3);
-    // cursor over this wave's blocks: column index ci (J = wave_col(wv, ci)), row block I >= J
-    int ci = 0, J = wave_col(wv, 0, nb), I = J;
+    T *y = xz + (size_t)pp * R;            // G Z^{-1} a per RHS [R][ps], rows in yrow order
+    const T *Gl = G + goff[k] + 4 * lane;  // B[m][4 q .. 4 q + 4), see gblk_pos
+    // Every slot issues one load per refill, past the last block too (it then re-reads block 0, which
+    // stays unused): with the same number of loads in flight on every path, each use waits only for
+    // its own block.  The loads are kept in slot order (scheduling barriers), as the refills are
+    // issued: then the queue is in the same order on entry to the loop and around it.
     Quad<T> pre[PF];
-    int pI[PF], pJ[PF];
 #pragma unroll
     for (int f = 0; f < PF; ++f) {
-        pJ[f] = J;
-        pI[f] = I;
-        if (J >= 0) {
-            pre[f].load(Gk + ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + r * 16 + c0);
-            if (++I == nb) { ++ci; J = wave_col(wv, ci, nb); I = J; }
-        }
+        pre[f].load(Gl + (int64_t)(f < nblk ? f : 0) * 256);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    // incoming waves a_p = o_twin(p) and Z^{-1}, one thread per port, kept in LDS for the output
+    for (int i = lane; i < pp * R; i += 64) xz[i] = 0;
+    for (int i = lane; i < ps * R; i += 64) y[i] = 0;
+    __syncthreads();
+    // xz[v] = sum over the ports at vertex v of Z^{-1} a_p, a_p = o_twin(p); the loads of U ports per
+    // lane are issued before the first of them is used
     const int port0 = D.port_ptr[k], np_k = D.port_ptr[k + 1] - port0;
-    T *al = yw + (size_t)4 * pp * R;       // a per local port [np_k][R]
-    T *izl = al + (size_t)max_np * R;      // Z^{-1} per local port
-    int qb = 0, qc = 0;                    // this thread's port group (q = tid): first local port, count
-    T cq[R];
-    if (tid < p) {
-        qb = D.pg_beg[pg0 + tid] - port0;
-        qc = D.pg_cnt[pg0 + tid];
+    for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
+        int tw[U], v[U];
+        T iz[U], a[U][R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) cq[c] = cport[((int64_t)g * npg + pg0 + tid) * R + c];
-    }
-    for (int t = tid; t < np_k; t += nt) {
-        const int tw = twin[port0 + t];
-        izl[t] = invz[port0 + t];
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
+            tw[u] = twin[pt];
+            v[u] = t < np_k ? (int)D.port_pg[pt] : -1;
+            iz[u] = invz[pt];
+        }
 #pragma unroll
-        for (int c = 0; c < R; ++c) al[t * R + c] = o_prev[wo + (int64_t)tw * R + c];
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v[u] >= 0)
+#pragma unroll
+                for (int c = 0; c < R; ++c) atomicAdd(&xz[v[u] * R + c], a[u][c] * iz[u]);
     }
     __syncthreads();
-    for (int q = tid; q < pp; q += nt) {  // xz = sum over the group's ports of Z^{-1} a (fixed order)
-        int b0 = qb, cnt = qc;
-        if (q != tid) {
-            b0 = q < p ? D.pg_beg[pg0 + q] - port0 : 0;
-            cnt = q < p ? D.pg_cnt[pg0 + q] : 0;
-        } else if (q >= p) {
-            cnt = 0;
-        }
-        T acc[R];
+    // B operand of y_I += B x_J: lane (m, q) gives x_J[4 q + kk][m] for m < R
+    T xb[4];
+    auto load_xb = [&](int J) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) acc[c] = 0;
-        for (int j = 0; j < cnt; ++j)
-#pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] += al[(b0 + j) * R + c] * izl[b0 + j];
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            xz[q * R + c] = acc[c];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) yw[((size_t)w * pp + q) * R + c] = 0;
-        }
-    }
-    __syncthreads();
-    T *y = yw + (size_t)wv * pp * R;
-    int cur = -1;   // block column being accumulated
-    T xj[4][R], t[4][R];
-    auto flush = [&]() {  // y_J += column sums of B^T x_I over the 16 lanes of each column quad
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int c = 0; c < R; ++c) {
-                T v = t[j][c];
-                v += __shfl_xor(v, 4);
-                v += __shfl_xor(v, 8);
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
-                t[j][c] = v;
-            }
-        if (lane < 4)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int c = 0; c < R; ++c) atomicAdd(&y[(cur * 16 + c0 + j) * R + c], t[j][c]);
+        for (int kk = 0; kk < 4; ++kk) xb[kk] = m < R ? xz[(J * 16 + 4 * q + kk) * R + (m < R ? m : 0)] : (T)0;
     };
-    while (pJ[0] >= 0) {
+    T tc[NV];  // partial column sums of B^T x_I for the current block column
+#pragma unroll
+    for (int j = 0; j < NV; ++j) tc[j] = 0;
+    // x_I[m][.] of the next block is read one block ahead
+    T xi[R];
+    auto load_xi = [&](int I) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) xi[c] = xz[(I * 16 + m) * R + c];
+    };
+    // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator
+    T *yl = y + (m < R ? m : 0) * ps + 4 * q;
+    const int j0 = scatter_base<NV>(m);
+    const bool writer = scatter_writer<NV>(m);
+    int J = 0, I = 0;
+    load_xb(0);
+    load_xi(0);
+    for (int b0 = 0; b0 < nblk; b0 += PF) {
 #pragma unroll
         for (int f = 0; f < PF; ++f) {
-            const int bJ = pJ[f], bI = pI[f];
-            if (bJ >= 0) {
-                if (bJ != cur) {
-                    if (cur >= 0) flush();
-                    cur = bJ;
+            if (b0 + f < nblk) {
+                const Quad<T> vb = pre[f];
+                T yv[4];
+                if (m < R)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int i = 0; i < 4; ++i) yv[i] = yl[I * 16 + i];
+                Acc acc = {0, 0, 0, 0};
 #pragma unroll
-                        for (int c = 0; c < R; ++c) {
-                            xj[j][c] = xz[(bJ * 16 + c0 + j) * R + c];
-                            t[j][c] = 0;
+                for (int kk = 0; kk < 4; ++kk) acc = Mma<T>::step(vb[kk], xb[kk], acc);
+                T xc[R];
+#pragma unroll
+                for (int c = 0; c < R; ++c) xc[c] = xi[c];
+                const bool last = I + 1 == nb;
+                const int In = last ? J + 1 : I + 1;  // next block's row (its column is J or J + 1)
+                if (In < nb) load_xi(In);
+                if (I != J)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int c = 0; c < R; ++c) tc[c * 4 + kk] += vb[kk] * xc[c];
+                // one wave owns y and each lane its own entries: a plain read-modify-write
+                if (m < R)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) yl[I * 16 + i] = yv[i] + acc[i];
+                if (last) {  // end of block column J: y_J += its column sums, then the next column
+                    row16_reduce_scatter<T, NV>(tc, m);
+                    if (writer)
+#pragma unroll
+                        for (int i = 0; i < (NV >= 16 ? NV / 16 : 1); ++i) {
+                            const int jj = j0 + i, c = jj >> 2, kk = jj & 3;
+                            T *yj = y + c * ps + J * 16 + Mma<T>::yrow(4 * q + kk);
+                            *yj += tc[i];
                         }
-                }
-                const Quad<T> v = pre[f];
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const T sr = quad_sum(v[0] * xj[0][c] + v[1] * xj[1][c] + v[2] * xj[2][c] + v[3] * xj[3][c]);
-                    // one lane per row adds (no-return LDS atomic: no read-after-write wait)
-                    if ((lane & 3) == 0) atomicAdd(&y[(bI * 16 + r) * R + c], sr);
-                    if (bI != bJ) {
-                        const T xi = xz[(bI * 16 + r) * R + c];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) t[j][c] += v[j] * xi;
-                    }
+                    for (int j = 0; j < NV; ++j) tc[j] = 0;
+                    J = In;
+                    if (J < nb) load_xb(J);
                 }
+                I = In;
             }
-            // refill this slot with the block PF positions ahead
-            pJ[f] = J;
-            pI[f] = I;
-            if (J >= 0) {
-                pre[f].load(Gk + ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + r * 16 + c0);
-                if (++I == nb) { ++ci; J = wave_col(wv, ci, nb); I = J; }
-            }
+            const int nx = b0 + f + PF;
+            pre[f].load(Gl + (int64_t)(nx < nblk ? nx : 0) * 256);
         }
     }
-    if (cur >= 0) flush();
     __syncthreads();
-    for (int q = tid; q < p; q += nt) {  // u = c + y, o_p = 2 u - a_p
-        int b0 = qb, cnt = qc;
-        T u[R];
-        if (q != tid) {
-            b0 = D.pg_beg[pg0 + q] - port0;
-            cnt = D.pg_cnt[pg0 + q];
+    // u = c + y at each port vertex; o_p = 2 u - a_p (loads of U ports per lane issued together)
+    for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
+        int tw[U], v[U];
+        T a[U][R], cu[U][R];
 #pragma unroll
-            for (int c = 0; c < R; ++c) u[c] = cport[((int64_t)g * npg + pg0 + q) * R + c];
-        } else {
-#pragma unroll
-            for (int c = 0; c < R; ++c) u[c] = cq[c];
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
+            tw[u] = twin[pt];
+            v[u] = D.port_pg[pt];
         }
 #pragma unroll
-        for (int c = 0; c < R; ++c)
-            u[c] += yw[(size_t)q * R + c] + yw[((size_t)pp + q) * R + c] + yw[((size_t)2 * pp + q) * R + c] +
-                    yw[((size_t)3 * pp + q) * R + c];
-        for (int j = 0; j < cnt; ++j) {
-            T *o = o_next + wo + (int64_t)(port0 + b0 + j) * R;
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int c = 0; c < R; ++c) o[c] = (T)2 * u[c] - al[(b0 + j) * R + c];
+            for (int c = 0; c < R; ++c) {
+                a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
+                cu[u][c] = cport[((int64_t)g * npg + pg0 + v[u]) * R + c];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + 64 * u + lane, yr = (v[u] & ~15) + Mma<T>::yrow(v[u] & 15);
+            if (t < np_k)
+#pragma unroll
+                for (int c = 0; c < R; ++c)
+                    o_next[wo + (int64_t)(port0 + t) * R + c] = (T)2 * (cu[u][c] + y[c * ps + yr]) - a[u][c];
         }
     }
 }
@@ -1383,8 +1473,8 @@ __global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg,
             float v = 0.f;
             if (i < p && j < p) {
                 const int I = i >> 4, J = j >> 4;
-                v = I >= J ? Gk[((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + (i & 15) * 16 + (j & 15)]
-                           : Gk[((int64_t)I * nb - (int64_t)I * (I - 1) / 2 + (J - I)) * 256 + (j & 15) * 16 + (i & 15)];
+                v = I >= J ? Gk[((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + gblk_pos(i & 15, j & 15)]
+                           : Gk[((int64_t)I * nb - (int64_t)I * (I - 1) / 2 + (J - I)) * 256 + gblk_pos(j & 15, i & 15)];
             }
             gr[rr][cc] = v;
         }
@@ -1698,9 +1788,9 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
     hipLaunchKernelGGL(k_gather_ports<T>, dim3(nsub, ngroups), dim3(128), 0, st, D, nsplit, npg, R, xloc, cport);
 }
 
-size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R) {
+size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t, int32_t R) {
     const size_t pp = (size_t)((max_p + 15) & ~15);
-    return tsize * ((size_t)R * (5 * pp + (size_t)max_np) + (size_t)max_np);  // xz, 4 x y, a, Z^{-1}
+    return tsize * (2 * pp + 4) * (size_t)R;  // Z^{-1} a [pp][R] and y [R][pp + 4]
 }
 
 template <typename T>
@@ -1722,12 +1812,12 @@ void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int
                   int32_t npg, int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
                   const T *invz, const T *o_prev, T *o_next, hipStream_t st) {
     const size_t shm = schur_shm<T>(max_p, max_np, R);
-    const dim3 grid(nsub, ngroups), block(256);
+    const dim3 grid(nsub, ngroups), block(64);
     switch (R) {
-        case 1: hipLaunchKernelGGL((k_schur<T, 1>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 2: hipLaunchKernelGGL((k_schur<T, 2>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
-        default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, max_np, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 1: hipLaunchKernelGGL((k_schur<T, 1>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 2: hipLaunchKernelGGL((k_schur<T, 2>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
     }
 }
 

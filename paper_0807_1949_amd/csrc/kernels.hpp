@@ -49,6 +49,8 @@ struct DevSub {
     const int32_t *pg_beg;   // first port of the group
     const int32_t *pg_cnt;   // ports in the group
     const int32_t *port_ptr; // first port of each subgraph (nsub + 1)
+    const uint16_t *port_pg; // port -> index of its port vertex (group) in its subgraph
+    const int32_t *gorder;   // subgraphs by decreasing size of G_k (launch order of the port-reduced sweep)
 };
 
 // Column plan of the port Green's functions computed inside the factorisation.  Ports of a subgraph
