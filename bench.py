@@ -84,11 +84,39 @@ def _profile_fields(name, keys):
     return fields
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, summary="sweep_traffic_c2_lognormal_1024.md"):
     """HBM bytes per sweep of the sweep kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None."""
     key = kernel + "-traffic-bytes-per-sweep"
-    f = _profile_fields("sweep_traffic_c2_lognormal_1024.md", (key,))
+    f = _profile_fields(summary, (key,))
     return None if f is None else float(f[key])
+
+
+def streaming_sweep_roofline(B, Zm, torch, nsweeps=48):
+    """The port-reduced sweep where it streams G from HBM: the 3D Poisson 128^3 workload (4096 RCB
+    subgraphs, 8 RHS, FP32 sweeps, learned impedances), one kernel launch per sweep.  Algorithmic
+    bytes per sweep (every packed G_k once, the port constants, the incoming and outgoing waves) over
+    the event-timed duration of the sweep launches."""
+    import gen
+
+    cfg = gen.make_config("c3")
+    h = B.VTM(device=0, precision=B.VTM_FP32_IR, check_every=nsweeps, max_sweeps=nsweeps, sweep_mode=2, persistent=1)
+    info = h.evs_partition(cfg["A"], cfg["spec"])
+    h.zmodel_load(Zm.load())
+    h.setup(B.VTM_Z_LEARNED)
+    b_dev = torch.tensor(cfg["b"], dtype=torch.float64, device="cuda")
+    x_dev = torch.empty_like(b_dev)
+    for _ in range(2):  # the first solve warms up (graph capture)
+        h.reset_waves()
+        h.solve(b_dev, 1e-30, x_dev, raise_on=())
+    st = h.get_stats()
+    h.close()
+    sweep_s = st["sweep_ms"] / 1e3 / max(st["sweeps"], 1)
+    achieved = st["bytes_per_sweep"] / sweep_s / 1e9
+    return dict(kernel="k_schur", workload=cfg["name"] + " (3D 7-point Poisson 128^3, 4096 RCB subgraphs, 8 RHS, FP32)",
+                bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                traffic=measured_traffic("k_schur", "sweep_traffic_c3_poisson_128.md"),
+                bytes_per_sweep=st["bytes_per_sweep"], avg_sweep_us=sweep_s * 1e6, sweeps_timed=int(st["sweeps"]),
+                nsub=int(info["nsub"]))
 
 
 def setup_mfma():
@@ -239,6 +267,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--small", action="store_true", help="128^2 version of the workload (quick check)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-streaming-roofline", action="store_true",
+                    help="skip the port-reduced sweep's HBM roofline on the 3D Poisson workload")
     ap.add_argument("--variants", default="ir_lrn,fp64_diag_sub,ir_diag",
                     help="comma list of {ir,fp64}_{lrn,match,diag,aNN}[_sub|_port]: precision, impedance rule "
                          "(learned network, impedance matching, diagonal, or NN times the diagonal), sweep mode (substitution, "
@@ -344,6 +374,9 @@ def main():
     if len(variants) > 1:
         line["speedup_vs_" + variants[1]] = results[variants[1]]["step_s"] / head["step_s"]
     line["setup_mfma"] = setup_mfma()
+    if not args.no_streaming_roofline:
+        log("streaming sweep roofline (3D Poisson 128^3, 8 RHS)")
+        line["streaming_sweep_roofline"] = streaming_sweep_roofline(B, Zm, torch)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 

@@ -1239,6 +1239,21 @@ template <> struct Mma<double> {
     __device__ static int yrow(int r) { return 4 * (r & 3) + (r >> 2); }  // stores row 4 i + q at 4 q + i
 };
 
+// Four consecutive values from or to LDS in one 16-byte access (two for doubles); p is 16-byte aligned.
+__device__ inline void lds_get4(const float *p, float (&v)[4]) {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ inline void lds_put4(float *p, const float (&v)[4]) { *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]); }
+__device__ inline void lds_get4(const double *p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ inline void lds_put4(double *p, const double (&v)[4]) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+
 template <typename T, int R>
 __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
                                               const int64_t *__restrict__ goff, const T *__restrict__ cport,
@@ -1256,8 +1271,12 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     const int nb = (p + 15) >> 4, pp = nb * 16, nblk = nb * (nb + 1) / 2;
     const int ps = pp + 4;                         // row stride of y (staggers the LDS banks of the RHS)
     const int64_t wo = (int64_t)g * nports * R;
-    T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a per port vertex [pp][R]
+    T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a per port vertex [pp][R], entries at xzi
     T *y = xz + (size_t)pp * R;            // G Z^{-1} a per RHS [R][ps], rows in yrow order
+    T *scr = y;                            // before y: Z^{-1} a per port [np_k][R]
+    // With 8 RHS, the two halves of a row of xz swap places in every other group of 4 rows, so that
+    // the 16-byte reads of 8 consecutive rows fall in distinct LDS banks.
+    auto xzi = [](int r, int c) { return r * R + (R == 8 ? (c ^ (((r >> 2) & 1) << 2)) : c); };
     const T *Gl = G + goff[k] + 4 * lane;  // B[m][4 q .. 4 q + 4), see gblk_pos
     // Every slot issues one load per refill, past the last block too (it then re-reads block 0, which
     // stays unused): with the same number of loads in flight on every path, each use waits only for
@@ -1269,20 +1288,17 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
         pre[f].load(Gl + (int64_t)(f < nblk ? f : 0) * 256);
         __builtin_amdgcn_sched_barrier(0);
     }
-    for (int i = lane; i < pp * R; i += 64) xz[i] = 0;
-    for (int i = lane; i < ps * R; i += 64) y[i] = 0;
-    __syncthreads();
-    // xz[v] = sum over the ports at vertex v of Z^{-1} a_p, a_p = o_twin(p); the loads of U ports per
-    // lane are issued before the first of them is used
+    // Z^{-1} a_p for every port (a_p = o_twin(p)) into the scratch, with the loads of U ports per lane
+    // issued before the first of them is used; then xz[v] = the sum over the ports at vertex v, in
+    // port order (no LDS atomics: a float atomic costs far more than a read and a write)
     const int port0 = D.port_ptr[k], np_k = D.port_ptr[k + 1] - port0;
     for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
-        int tw[U], v[U];
+        int tw[U];
         T iz[U], a[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
             tw[u] = twin[pt];
-            v[u] = t < np_k ? (int)D.port_pg[pt] : -1;
             iz[u] = invz[pt];
         }
 #pragma unroll
@@ -1290,17 +1306,44 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
 #pragma unroll
             for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (v[u] >= 0)
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + 64 * u + lane;
+            if (t < np_k)
 #pragma unroll
-                for (int c = 0; c < R; ++c) atomicAdd(&xz[v[u] * R + c], a[u][c] * iz[u]);
+                for (int c = 0; c < R; ++c) scr[t * R + c] = a[u][c] * iz[u];
+        }
     }
     __syncthreads();
-    // B operand of y_I += B x_J: lane (m, q) gives x_J[4 q + kk][m] for m < R
-    T xb[4];
-    auto load_xb = [&](int J) {
+    for (int v0 = 0; v0 < pp; v0 += 64 * U) {
+        int b0[U], cnt[U];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) xb[kk] = m < R ? xz[(J * 16 + 4 * q + kk) * R + (m < R ? m : 0)] : (T)0;
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + 64 * u + lane;
+            b0[u] = v < p ? D.pg_beg[pg0 + v] - port0 : 0;
+            cnt[u] = v < p ? D.pg_cnt[pg0 + v] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + 64 * u + lane;
+            T s[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) s[c] = 0;
+            for (int j = 0; j < cnt[u]; ++j)
+#pragma unroll
+                for (int c = 0; c < R; ++c) s[c] += scr[(b0[u] + j) * R + c];
+            if (v < pp)
+#pragma unroll
+                for (int c = 0; c < R; ++c) xz[xzi(v, c)] = s[c];
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < ps * R; i += 64) y[i] = 0;
+    __syncthreads();
+    // B operand of y_I += B x_J: lane (m, q) gives x_J[4 q + kk][m] for m < R
+    T xb[4], xbn[4];
+    auto load_xb = [&](T (&d)[4], int J) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) d[kk] = m < R ? xz[xzi(J * 16 + 4 * q + kk, m < R ? m : 0)] : (T)0;
     };
     T tc[NV];  // partial column sums of B^T x_I for the current block column
 #pragma unroll
@@ -1308,15 +1351,37 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     // x_I[m][.] of the next block is read one block ahead
     T xi[R];
     auto load_xi = [&](int I) {
+        const int r = I * 16 + m;
+        if constexpr (R == 8) {
+            T h0[4], h1[4];
+            lds_get4(xz + xzi(r, 0), h0);
+            lds_get4(xz + xzi(r, 4), h1);
 #pragma unroll
-        for (int c = 0; c < R; ++c) xi[c] = xz[(I * 16 + m) * R + c];
+            for (int c = 0; c < 4; ++c) {
+                xi[c] = h0[c];
+                xi[4 + c] = h1[c];
+            }
+        } else if constexpr (R == 4) {
+            T h0[4];
+            lds_get4(xz + r * 4, h0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) xi[c] = h0[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < R; ++c) xi[c] = xz[r * R + c];
+        }
     };
-    // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator
+    // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator.
+    // The product of block b is added to y while block b + 1 is on the matrix cores (the rows of two
+    // consecutive blocks of a column differ); at the end of a column it is added at once.
     T *yl = y + (m < R ? m : 0) * ps + 4 * q;
     const int j0 = scatter_base<NV>(m);
     const bool writer = scatter_writer<NV>(m);
+    Acc accP = {0, 0, 0, 0};
+    T yvP[4] = {0, 0, 0, 0};
+    int IP = -1;
     int J = 0, I = 0;
-    load_xb(0);
+    load_xb(xb, 0);
     load_xi(0);
     for (int b0 = 0; b0 < nblk; b0 += PF) {
 #pragma unroll
@@ -1324,28 +1389,36 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
             if (b0 + f < nblk) {
                 const Quad<T> vb = pre[f];
                 T yv[4];
-                if (m < R)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) yv[i] = yl[I * 16 + i];
+                if (m < R) lds_get4(yl + I * 16, yv);
                 Acc acc = {0, 0, 0, 0};
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) acc = Mma<T>::step(vb[kk], xb[kk], acc);
+                if (IP >= 0 && m < R) {  // the previous block's product (one wave owns y: plain read-modify-write)
+                    T w[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w[i] = yvP[i] + accP[i];
+                    lds_put4(yl + IP * 16, w);
+                }
                 T xc[R];
 #pragma unroll
                 for (int c = 0; c < R; ++c) xc[c] = xi[c];
                 const bool last = I + 1 == nb;
                 const int In = last ? J + 1 : I + 1;  // next block's row (its column is J or J + 1)
                 if (In < nb) load_xi(In);
+                if (last && In < nb) load_xb(xbn, In);
                 if (I != J)
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                         for (int c = 0; c < R; ++c) tc[c * 4 + kk] += vb[kk] * xc[c];
-                // one wave owns y and each lane its own entries: a plain read-modify-write
-                if (m < R)
+                if (last) {  // end of block column J: this block's product, y_J += the column sums
+                    if (m < R) {
+                        T w[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) yl[I * 16 + i] = yv[i] + acc[i];
-                if (last) {  // end of block column J: y_J += its column sums, then the next column
+                        for (int i = 0; i < 4; ++i) w[i] = yv[i] + acc[i];
+                        lds_put4(yl + I * 16, w);
+                    }
+                    IP = -1;
                     row16_reduce_scatter<T, NV>(tc, m);
                     if (writer)
 #pragma unroll
@@ -1356,8 +1429,16 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                         }
 #pragma unroll
                     for (int j = 0; j < NV; ++j) tc[j] = 0;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) xb[kk] = xbn[kk];
                     J = In;
-                    if (J < nb) load_xb(J);
+                } else {
+                    IP = I;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        accP[i] = acc[i];
+                        yvP[i] = yv[i];
+                    }
                 }
                 I = In;
             }
@@ -1788,9 +1869,10 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
     hipLaunchKernelGGL(k_gather_ports<T>, dim3(nsub, ngroups), dim3(128), 0, st, D, nsplit, npg, R, xloc, cport);
 }
 
-size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t, int32_t R) {
+size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R) {
     const size_t pp = (size_t)((max_p + 15) & ~15);
-    return tsize * (2 * pp + 4) * (size_t)R;  // Z^{-1} a [pp][R] and y [R][pp + 4]
+    // Z^{-1} a [pp][R], then y [R][pp + 4], which holds Z^{-1} a per port [np][R] before
+    return tsize * (pp + std::max(pp + 4, (size_t)max_np)) * (size_t)R;
 }
 
 template <typename T>
