@@ -1261,7 +1261,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                                               const T *__restrict__ o_prev, T *__restrict__ o_next) {
     static_assert(R == 1 || R == 2 || R == 4 || R == 8, "right-hand sides per wave");
     extern __shared__ char smraw[];
-    constexpr int PF = sizeof(T) == 4 ? 16 : 8;  // blocks in flight (16 KB)
+    constexpr int PF = sizeof(T) == 4 ? 8 : 4;   // blocks in flight (8 KB)
     constexpr int U = 4;                          // ports per lane whose loads are issued together
     constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
     typedef typename Mma<T>::acc Acc;
@@ -1290,17 +1290,29 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     }
     // Z^{-1} a_p for every port (a_p = o_twin(p)) into the scratch, with the loads of U ports per lane
     // issued before the first of them is used; then xz[v] = the sum over the ports at vertex v, in
-    // port order (no LDS atomics: a float atomic costs far more than a read and a write)
+    // port order (no LDS atomics: a float atomic costs far more than a read and a write).  The first
+    // U ports of each lane keep their twin, vertex and incoming wave in registers for the write-back,
+    // and the first vertex records are requested with them.
     const int port0 = D.port_ptr[k], np_k = D.port_ptr[k + 1] - port0;
+    int tw0[U], v0r[U], vb0[U], vc0[U];
+    T a0[U][R];
+    auto vertex_rec = [&](int v, int &b, int &c) {
+        b = v < p ? D.pg_beg[pg0 + v] - port0 : 0;
+        c = v < p ? D.pg_cnt[pg0 + v] : 0;
+    };
     for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
-        int tw[U];
+        int tw[U], vv[U];
         T iz[U], a[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
             tw[u] = twin[pt];
             iz[u] = invz[pt];
+            vv[u] = D.port_pg[pt];
         }
+        if (t0 == 0)
+#pragma unroll
+            for (int u = 0; u < U; ++u) vertex_rec(64 * u + lane, vb0[u], vc0[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -1312,28 +1324,39 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
 #pragma unroll
                 for (int c = 0; c < R; ++c) scr[t * R + c] = a[u][c] * iz[u];
         }
+        if (t0 == 0)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                tw0[u] = tw[u];
+                v0r[u] = vv[u];
+#pragma unroll
+                for (int c = 0; c < R; ++c) a0[u][c] = a[u][c];
+            }
     }
     __syncthreads();
     for (int v0 = 0; v0 < pp; v0 += 64 * U) {
         int b0[U], cnt[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int v = v0 + 64 * u + lane;
-            b0[u] = v < p ? D.pg_beg[pg0 + v] - port0 : 0;
-            cnt[u] = v < p ? D.pg_cnt[pg0 + v] : 0;
+            if (v0 == 0) {
+                b0[u] = vb0[u];
+                cnt[u] = vc0[u];
+            } else {
+                vertex_rec(v0 + 64 * u + lane, b0[u], cnt[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int v = v0 + 64 * u + lane;
-            T s[R];
+            T s_[R];
 #pragma unroll
-            for (int c = 0; c < R; ++c) s[c] = 0;
+            for (int c = 0; c < R; ++c) s_[c] = 0;
             for (int j = 0; j < cnt[u]; ++j)
 #pragma unroll
-                for (int c = 0; c < R; ++c) s[c] += scr[(b0[u] + j) * R + c];
+                for (int c = 0; c < R; ++c) s_[c] += scr[(b0[u] + j) * R + c];
             if (v < pp)
 #pragma unroll
-                for (int c = 0; c < R; ++c) xz[xzi(v, c)] = s[c];
+                for (int c = 0; c < R; ++c) xz[xzi(v, c)] = s_[c];
         }
     }
     __syncthreads();
@@ -1348,9 +1371,9 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     T tc[NV];  // partial column sums of B^T x_I for the current block column
 #pragma unroll
     for (int j = 0; j < NV; ++j) tc[j] = 0;
-    // x_I[m][.] of the next block is read one block ahead
-    T xi[R];
-    auto load_xi = [&](int I) {
+    // x_I[m][.] of the next block is read one block ahead, into the other of two register sets
+    T xi[2][R];
+    auto load_xi = [&](T (&xd)[R], int I) {
         const int r = I * 16 + m;
         if constexpr (R == 8) {
             T h0[4], h1[4];
@@ -1358,17 +1381,17 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
             lds_get4(xz + xzi(r, 4), h1);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                xi[c] = h0[c];
-                xi[4 + c] = h1[c];
+                xd[c] = h0[c];
+                xd[4 + c] = h1[c];
             }
         } else if constexpr (R == 4) {
             T h0[4];
             lds_get4(xz + r * 4, h0);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) xi[c] = h0[c];
+            for (int c = 0; c < 4; ++c) xd[c] = h0[c];
         } else {
 #pragma unroll
-            for (int c = 0; c < R; ++c) xi[c] = xz[r * R + c];
+            for (int c = 0; c < R; ++c) xd[c] = xz[r * R + c];
         }
     };
     // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator.
@@ -1377,34 +1400,33 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     T *yl = y + (m < R ? m : 0) * ps + 4 * q;
     const int j0 = scatter_base<NV>(m);
     const bool writer = scatter_writer<NV>(m);
-    Acc accP = {0, 0, 0, 0};
-    T yvP[4] = {0, 0, 0, 0};
+    // block b's product and y rows live in the register set b % 2 (PF is even, so the slot's parity)
+    Acc acc[2];
+    T yv[2][4];
     int IP = -1;
     int J = 0, I = 0;
     load_xb(xb, 0);
-    load_xi(0);
+    load_xi(xi[0], 0);
     for (int b0 = 0; b0 < nblk; b0 += PF) {
 #pragma unroll
         for (int f = 0; f < PF; ++f) {
             if (b0 + f < nblk) {
+                const int e = f & 1, o = e ^ 1;  // this block's register set, the previous block's
                 const Quad<T> vb = pre[f];
-                T yv[4];
-                if (m < R) lds_get4(yl + I * 16, yv);
-                Acc acc = {0, 0, 0, 0};
+                if (m < R) lds_get4(yl + I * 16, yv[e]);
+                acc[e] = Acc{0, 0, 0, 0};
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) acc = Mma<T>::step(vb[kk], xb[kk], acc);
+                for (int kk = 0; kk < 4; ++kk) acc[e] = Mma<T>::step(vb[kk], xb[kk], acc[e]);
                 if (IP >= 0 && m < R) {  // the previous block's product (one wave owns y: plain read-modify-write)
                     T w[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) w[i] = yvP[i] + accP[i];
+                    for (int i = 0; i < 4; ++i) w[i] = yv[o][i] + acc[o][i];
                     lds_put4(yl + IP * 16, w);
                 }
-                T xc[R];
-#pragma unroll
-                for (int c = 0; c < R; ++c) xc[c] = xi[c];
+                const T(&xc)[R] = xi[e];
                 const bool last = I + 1 == nb;
                 const int In = last ? J + 1 : I + 1;  // next block's row (its column is J or J + 1)
-                if (In < nb) load_xi(In);
+                if (In < nb) load_xi(xi[o], In);
                 if (last && In < nb) load_xb(xbn, In);
                 if (I != J)
 #pragma unroll
@@ -1415,7 +1437,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                     if (m < R) {
                         T w[4];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) w[i] = yv[i] + acc[i];
+                        for (int i = 0; i < 4; ++i) w[i] = yv[e][i] + acc[e][i];
                         lds_put4(yl + I * 16, w);
                     }
                     IP = -1;
@@ -1434,11 +1456,6 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                     J = In;
                 } else {
                     IP = I;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        accP[i] = acc[i];
-                        yvP[i] = yv[i];
-                    }
                 }
                 I = In;
             }
@@ -1447,23 +1464,35 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
         }
     }
     __syncthreads();
-    // u = c + y at each port vertex; o_p = 2 u - a_p (loads of U ports per lane issued together)
+    // u = c + y at each port vertex; o_p = 2 u - a_p (loads of U ports per lane issued together; the
+    // first U ports per lane from the registers kept by the gather)
     for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
         int tw[U], v[U];
         T a[U][R], cu[U][R];
+        if (t0 == 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
-            tw[u] = twin[pt];
-            v[u] = D.port_pg[pt];
+            for (int u = 0; u < U; ++u) {
+                tw[u] = tw0[u];
+                v[u] = v0r[u];
+#pragma unroll
+                for (int c = 0; c < R; ++c) a[u][c] = a0[u][c];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
+                tw[u] = twin[pt];
+                v[u] = D.port_pg[pt];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int c = 0; c < R; ++c) {
-                a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
-                cu[u][c] = cport[((int64_t)g * npg + pg0 + v[u]) * R + c];
-            }
+            for (int c = 0; c < R; ++c) cu[u][c] = cport[((int64_t)g * npg + pg0 + v[u]) * R + c];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + 64 * u + lane, yr = (v[u] & ~15) + Mma<T>::yrow(v[u] & 15);
