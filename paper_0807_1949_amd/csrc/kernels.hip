@@ -1269,11 +1269,12 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     const int m = lane & 15, q = lane >> 4;
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
     const int nb = (p + 15) >> 4, pp = nb * 16, nblk = nb * (nb + 1) / 2;
-    const int ps = pp + 4;                         // row stride of y (staggers the LDS banks of the RHS)
+    const int ps = pp + 20;                        // row stride of y: a spare row block, then 4 to stagger banks
     const int64_t wo = (int64_t)g * nports * R;
     T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a per port vertex [pp][R], entries at xzi
     T *y = xz + (size_t)pp * R;            // G Z^{-1} a per RHS [R][ps], rows in yrow order
     T *scr = y;                            // before y: Z^{-1} a per port [np_k][R]
+    T *ydummy = y + (size_t)ps * R;        // after y (over the scratch): 4 values per lane for the unused lanes
     // With 8 RHS, the two halves of a row of xz swap places in every other group of 4 rows, so that
     // the 16-byte reads of 8 consecutive rows fall in distinct LDS banks.
     auto xzi = [](int r, int c) { return r * R + (R == 8 ? (c ^ (((r >> 2) & 1) << 2)) : c); };
@@ -1394,53 +1395,59 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
             for (int c = 0; c < R; ++c) xd[c] = xz[r * R + c];
         }
     };
-    // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator.
-    // The product of block b is added to y while block b + 1 is on the matrix cores (the rows of two
-    // consecutive blocks of a column differ); at the end of a column it is added at once.
-    T *yl = y + (m < R ? m : 0) * ps + 4 * q;
+    // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator;
+    // the other lanes (whose products are zero) read and write 4 values of their own.  The product of
+    // block b is added to y while block b + 1 is on the matrix cores (the rows of two consecutive
+    // blocks of a column differ; with none pending, the spare row block nb takes the write); at the
+    // end of a column it is added at once.  No branch separates the matrix-core steps from the
+    // vector-unit products of a block, so that they can be interleaved.
+    T *yl = m < R ? y + m * ps + 4 * q : ydummy + 4 * lane;
+    const int ystep = m < R ? 16 : 0;
     const int j0 = scatter_base<NV>(m);
     const bool writer = scatter_writer<NV>(m);
     // block b's product and y rows live in the register set b % 2 (PF is even, so the slot's parity)
-    Acc acc[2];
-    T yv[2][4];
-    int IP = -1;
+    Acc acc[2] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
+    T yv[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int IP = nb;
     int J = 0, I = 0;
     load_xb(xb, 0);
-    load_xi(xi[0], 0);
+#pragma unroll
+    for (int c = 0; c < R; ++c) xi[0][c] = 0;  // block (0, 0) is diagonal
     for (int b0 = 0; b0 < nblk; b0 += PF) {
 #pragma unroll
         for (int f = 0; f < PF; ++f) {
             if (b0 + f < nblk) {
                 const int e = f & 1, o = e ^ 1;  // this block's register set, the previous block's
                 const Quad<T> vb = pre[f];
-                if (m < R) lds_get4(yl + I * 16, yv[e]);
+                lds_get4(yl + I * ystep, yv[e]);
                 acc[e] = Acc{0, 0, 0, 0};
+                const T(&xc)[R] = xi[e];  // zero for a diagonal block (its B^T x_I is inside B x_J)
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) acc[e] = Mma<T>::step(vb[kk], xb[kk], acc[e]);
-                if (IP >= 0 && m < R) {  // the previous block's product (one wave owns y: plain read-modify-write)
+                for (int kk = 0; kk < 4; ++kk) {
+                    acc[e] = Mma<T>::step(vb[kk], xb[kk], acc[e]);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) tc[c * 4 + kk] += vb[kk] * xc[c];
+                }
+                {  // the previous block's product (one wave owns y: plain read-modify-write)
                     T w[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) w[i] = yv[o][i] + acc[o][i];
-                    lds_put4(yl + IP * 16, w);
+                    lds_put4(yl + IP * ystep, w);
                 }
-                const T(&xc)[R] = xi[e];
                 const bool last = I + 1 == nb;
                 const int In = last ? J + 1 : I + 1;  // next block's row (its column is J or J + 1)
-                if (In < nb) load_xi(xi[o], In);
-                if (last && In < nb) load_xb(xbn, In);
-                if (I != J)
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                        for (int c = 0; c < R; ++c) tc[c * 4 + kk] += vb[kk] * xc[c];
+                load_xi(xi[o], In < nb ? In : nb - 1);
                 if (last) {  // end of block column J: this block's product, y_J += the column sums
-                    if (m < R) {
+                    if (In < nb) load_xb(xbn, In);
+                    {
                         T w[4];
 #pragma unroll
                         for (int i = 0; i < 4; ++i) w[i] = yv[e][i] + acc[e][i];
-                        lds_put4(yl + I * 16, w);
+                        lds_put4(yl + I * ystep, w);
                     }
-                    IP = -1;
+                    IP = nb;
+#pragma unroll
+                    for (int c = 0; c < R; ++c) xi[o][c] = 0;  // the next block is diagonal
                     row16_reduce_scatter<T, NV>(tc, m);
                     if (writer)
 #pragma unroll
@@ -1900,8 +1907,9 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
 
 size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R) {
     const size_t pp = (size_t)((max_p + 15) & ~15);
-    // Z^{-1} a [pp][R], then y [R][pp + 4], which holds Z^{-1} a per port [np][R] before
-    return tsize * (pp + std::max(pp + 4, (size_t)max_np)) * (size_t)R;
+    // Z^{-1} a [pp][R], then y [R][pp + 20] and 4 values per lane for the unused lanes, which hold
+    // Z^{-1} a per port [np][R] before
+    return tsize * (pp * (size_t)R + std::max((pp + 20) * (size_t)R + 256, (size_t)max_np * R));
 }
 
 template <typename T>
