@@ -81,15 +81,18 @@ typedef struct {
                               port Green's functions G_k = R_k K_k^{-1} R_k^T (same iterates; the
                               substitution runs only at convergence tests); 0 = port-reduced when the packed
                               G_k hold at most 8 times the stored factor entries.
-                              Port-reduced sweeps need one workgroup's port vectors in LDS
-                              (about 5 p_k rhs_per_block values); when they do not fit, or
-                              G_k was not built (p_k > 2048), substitution sweeps run. */
+                              Port-reduced sweeps need a subgraph's port vectors in LDS
+                              (about 2 p_k rhs_per_block values per wave); when they do not fit,
+                              or G_k was not built (p_k > 2048), substitution sweeps run. */
     int32_t persistent;    /* port-reduced FP32 sweeps: 0 = one persistent cooperative launch per batch of
                               sweeps between tests when every workgroup fits on the device at once, each
                               wave's G_k blocks fit in registers and rhs_per_block <= 2 (G_k held on chip,
                               waves exchanged as tagged words), else per-sweep launches;
                               1 = per-sweep launches only */
-    int32_t reserved;
+    int32_t sweep_waves;   /* port-reduced sweeps in per-sweep launches: waves per subgraph, 1 or 2 (two
+                              waves take alternate pairs of block columns of G_k, each with its own
+                              copy of the products); 0 = two when one wave's LDS would leave fewer than
+                              two waves per SIMD */
 } vtm_options;
 
 /*

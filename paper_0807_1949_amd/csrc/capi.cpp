@@ -629,7 +629,7 @@ constexpr double kGreenRatio = 8.0;
 bool use_schur(vtm_ctx *h) {
     if (!h->have_green) return false;
     // the port vectors of a workgroup (R right-hand sides) must fit in LDS
-    if (vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, std::max(1, h->wave_R)) > vtm::kMaxLds) return false;
+    if (vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, std::max(1, h->wave_R), h->opt.sweep_waves) > vtm::kMaxLds) return false;
     if (h->opt.sweep_mode == 2) return true;
     if (h->opt.sweep_mode == 1) return false;
     return (double)h->total_g <= kGreenRatio * (double)h->total_lower;
@@ -679,7 +679,7 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R, nt = sweep_threads(h);
     HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
     const bool schur = use_schur(h);
-    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, h->max_np, R));
+    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, h->max_np, R, h->opt.sweep_waves));
     if constexpr (std::is_same<T, float>::value) {
         if (schur && persistent_ok(h, R, ng)) {
             const int64_t nw = (int64_t)ng * h->nports * R;
@@ -727,7 +727,7 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
 per_sweep:
     auto launch = [&](int cur, bool last) {
         if (schur)
-            vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
+            vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->opt.sweep_waves, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
                                  h->d_goff.as<int64_t>(), h->d_cport.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h),
                                  h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->stream);
         else
@@ -1154,8 +1154,8 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
         h->have_y32 = true;
     }
     if (want_green) {
-        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 4)));
-        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 4), st));
+        HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 256)));
+        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 256), st));
         // the port fronts start at zero; every factorisation leaves them zero (each supernode clears
         // the front it consumed), so the workspace is cleared only when new
         if (fused && !h->gws_clean) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
@@ -1176,8 +1176,8 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
             vtm::launch_green(dev_sym(h), dev_sub(h), P.nsub, h->max_nk, h->max_nu, h->max_p,
                               h->d_vals64.as<double>(), h->d_goff.as<int64_t>(), h->d_G64.as<double>(), st);
         if (h->fp32()) {
-            HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 4)));
-            vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 4, st);
+            HIP_TRY(ensure(h->d_G32, sizeof(float) * (h->total_g + 256)));
+            vtm::launch_to_f32(h->d_G64.as<double>(), h->d_G32.as<float>(), h->total_g + 256, st);
         }
         h->have_green = true;
         h->have_y = fused;
@@ -1274,6 +1274,10 @@ vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
     if (h->opt.precision != VTM_FP64 && h->opt.precision != VTM_FP32_IR) {
         delete h;
         return fail(VTM_ERR_INVALID, "unknown precision");
+    }
+    if (h->opt.sweep_waves < 0 || h->opt.sweep_waves > 2) {
+        delete h;
+        return fail(VTM_ERR_INVALID, "sweep_waves must be 0, 1 or 2");
     }
     if (h->opt.device < 0) {  // host-only handle: partition and symbolic analysis, no device work
         *out = h;
@@ -1484,7 +1488,7 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
     if (h->have_green) cands.push_back({2, 0, 256});
     for (int32_t R = 1; R <= maxR; R *= 2)
         for (const Cand &cd : cands) {
-            const size_t lds = cd.mode == 2 ? vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, R)
+            const size_t lds = cd.mode == 2 ? vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, R, h->opt.sweep_waves)
                              : h->tsize() * (size_t)R * (2 * (size_t)h->max_nk + (cd.var == 2 ? h->max_nu : 0));
             if (lds > 160 * 1024) continue;
             h->opt.rhs_per_block = R;

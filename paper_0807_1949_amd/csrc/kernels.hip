@@ -1254,8 +1254,8 @@ __device__ inline void lds_put4(double *p, const double (&v)[4]) {
     reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
 }
 
-template <typename T, int R>
-__global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
+template <typename T, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
                                               const int64_t *__restrict__ goff, const T *__restrict__ cport,
                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
                                               const T *__restrict__ o_prev, T *__restrict__ o_next) {
@@ -1265,20 +1265,45 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     constexpr int U = 4;                          // ports per lane whose loads are issued together
     constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
     typedef typename Mma<T>::acc Acc;
-    const int k = D.gorder[blockIdx.x], g = blockIdx.y, lane = threadIdx.x;
-    const int m = lane & 15, q = lane >> 4;
+    const int k = D.gorder[blockIdx.x], g = blockIdx.y, tid = threadIdx.x, nt = 64 * W;
+    const int lane = tid & 63, m = lane & 15, q = lane >> 4;
+    const int wv = W == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
-    const int nb = (p + 15) >> 4, pp = nb * 16, nblk = nb * (nb + 1) / 2;
-    const int ps = pp + 20;                        // row stride of y: a spare row block, then 4 to stagger banks
+    const int nb = (p + 15) >> 4, pp = nb * 16;
+    const int ps = pp + 4;                         // row stride of y (staggers the LDS banks of the RHS)
     const int64_t wo = (int64_t)g * nports * R;
     T *xz = reinterpret_cast<T *>(smraw);  // Z^{-1} a per port vertex [pp][R], entries at xzi
-    T *y = xz + (size_t)pp * R;            // G Z^{-1} a per RHS [R][ps], rows in yrow order
+    T *y = xz + (size_t)pp * R;            // per wave: G Z^{-1} a from its blocks [W][R][ps], rows in yrow order
     T *scr = y;                            // before y: Z^{-1} a per port [np_k][R]
-    T *ydummy = y + (size_t)ps * R;        // after y (over the scratch): 4 values per lane for the unused lanes
+    T *ydummy = y + (size_t)W * ps * R;    // after y (over the scratch): 4 values per lane for the unused lanes
     // With 8 RHS, the two halves of a row of xz swap places in every other group of 4 rows, so that
     // the 16-byte reads of 8 consecutive rows fall in distinct LDS banks.
     auto xzi = [](int r, int c) { return r * R + (R == 8 ? (c ^ (((r >> 2) & 1) << 2)) : c); };
     const T *Gl = G + goff[k] + 4 * lane;  // B[m][4 q .. 4 q + 4), see gblk_pos
+    // With W = 2 the two waves take alternate pairs of block columns (0 3 4 7 8 ... and 1 2 5 6 ...,
+    // about equal numbers of blocks), each adding into its own copy of y; the copies are summed in a
+    // fixed order at the end.
+    auto owner = [&](int j) { return W == 1 ? 0 : ((j ^ (j >> 1)) & 1); };
+    auto next_col = [&](int j) {
+        int n = j + 1;
+        while (W > 1 && n < nb && owner(n) != wv) ++n;
+        return n;
+    };
+    const int col0 = W == 1 ? 0 : (nb > wv ? wv : nb);
+    int nblk = 0;
+    for (int j = col0; j < nb; j = next_col(j)) nblk += nb - j;
+    // load cursor: block (Il, Jl) of this wave's sequence, PF blocks ahead of the one in use
+    int Jl = col0, Il = col0;
+    auto next_load = [&]() {
+        const int64_t off = Jl < nb ? ((int64_t)Jl * nb - (int64_t)Jl * (Jl - 1) / 2 + (Il - Jl)) * 256 : 0;
+        if (Il + 1 < nb) {
+            ++Il;
+        } else {
+            Jl = next_col(Jl);
+            Il = Jl;
+        }
+        return off;
+    };
     // Every slot issues one load per refill, past the last block too (it then re-reads block 0, which
     // stays unused): with the same number of loads in flight on every path, each use waits only for
     // its own block.  The loads are kept in slot order (scheduling barriers), as the refills are
@@ -1286,7 +1311,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     Quad<T> pre[PF];
 #pragma unroll
     for (int f = 0; f < PF; ++f) {
-        pre[f].load(Gl + (int64_t)(f < nblk ? f : 0) * 256);
+        pre[f].load(Gl + next_load());
         __builtin_amdgcn_sched_barrier(0);
     }
     // Z^{-1} a_p for every port (a_p = o_twin(p)) into the scratch, with the loads of U ports per lane
@@ -1301,26 +1326,26 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
         b = v < p ? D.pg_beg[pg0 + v] - port0 : 0;
         c = v < p ? D.pg_cnt[pg0 + v] : 0;
     };
-    for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
+    for (int t0 = 0; t0 < np_k; t0 += nt * U) {
         int tw[U], vv[U];
         T iz[U], a[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
+            const int t = t0 + nt * u + tid, pt = port0 + (t < np_k ? t : 0);
             tw[u] = twin[pt];
             iz[u] = invz[pt];
             vv[u] = D.port_pg[pt];
         }
         if (t0 == 0)
 #pragma unroll
-            for (int u = 0; u < U; ++u) vertex_rec(64 * u + lane, vb0[u], vc0[u]);
+            for (int u = 0; u < U; ++u) vertex_rec(nt * u + tid, vb0[u], vc0[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t = t0 + 64 * u + lane;
+            const int t = t0 + nt * u + tid;
             if (t < np_k)
 #pragma unroll
                 for (int c = 0; c < R; ++c) scr[t * R + c] = a[u][c] * iz[u];
@@ -1335,7 +1360,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
             }
     }
     __syncthreads();
-    for (int v0 = 0; v0 < pp; v0 += 64 * U) {
+    for (int v0 = 0; v0 < pp; v0 += nt * U) {
         int b0[U], cnt[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1343,12 +1368,12 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                 b0[u] = vb0[u];
                 cnt[u] = vc0[u];
             } else {
-                vertex_rec(v0 + 64 * u + lane, b0[u], cnt[u]);
+                vertex_rec(v0 + nt * u + tid, b0[u], cnt[u]);
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int v = v0 + 64 * u + lane;
+            const int v = v0 + nt * u + tid;
             T s_[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) s_[c] = 0;
@@ -1361,7 +1386,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
         }
     }
     __syncthreads();
-    for (int i = lane; i < ps * R; i += 64) y[i] = 0;
+    for (int i = tid; i < W * ps * R; i += nt) y[i] = 0;
     __syncthreads();
     // B operand of y_I += B x_J: lane (m, q) gives x_J[4 q + kk][m] for m < R
     T xb[4], xbn[4];
@@ -1398,10 +1423,12 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     // lane (m < R, q) owns y[m][rows of block I at yrow(4 q) .. + 4), the rows of its accumulator;
     // the other lanes (whose products are zero) read and write 4 values of their own.  The product of
     // block b is added to y while block b + 1 is on the matrix cores (the rows of two consecutive
-    // blocks of a column differ; with none pending, the spare row block nb takes the write); at the
+    // blocks of a column differ; with none pending, the write goes to the lane's own 4 values); at the
     // end of a column it is added at once.  No branch separates the matrix-core steps from the
     // vector-unit products of a block, so that they can be interleaved.
-    T *yl = m < R ? y + m * ps + 4 * q : ydummy + 4 * lane;
+    T *yw = y + (size_t)wv * R * ps;
+    T *const ydl = ydummy + 4 * tid;
+    T *yl = m < R ? yw + m * ps + 4 * q : ydl;
     const int ystep = m < R ? 16 : 0;
     const int j0 = scatter_base<NV>(m);
     const bool writer = scatter_writer<NV>(m);
@@ -1409,8 +1436,8 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
     Acc acc[2] = {Acc{0, 0, 0, 0}, Acc{0, 0, 0, 0}};
     T yv[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     int IP = nb;
-    int J = 0, I = 0;
-    load_xb(xb, 0);
+    int J = col0, I = col0;
+    load_xb(xb, col0 < nb ? col0 : 0);
 #pragma unroll
     for (int c = 0; c < R; ++c) xi[0][c] = 0;  // block (0, 0) is diagonal
     for (int b0 = 0; b0 < nblk; b0 += PF) {
@@ -1432,10 +1459,10 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                     T w[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) w[i] = yv[o][i] + acc[o][i];
-                    lds_put4(yl + IP * ystep, w);
+                    lds_put4(IP < nb ? yl + IP * ystep : ydl, w);
                 }
                 const bool last = I + 1 == nb;
-                const int In = last ? J + 1 : I + 1;  // next block's row (its column is J or J + 1)
+                const int In = last ? next_col(J) : I + 1;  // next block's row (its column is J or In)
                 load_xi(xi[o], In < nb ? In : nb - 1);
                 if (last) {  // end of block column J: this block's product, y_J += the column sums
                     if (In < nb) load_xb(xbn, In);
@@ -1453,7 +1480,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
 #pragma unroll
                         for (int i = 0; i < (NV >= 16 ? NV / 16 : 1); ++i) {
                             const int jj = j0 + i, c = jj >> 2, kk = jj & 3;
-                            T *yj = y + c * ps + J * 16 + Mma<T>::yrow(4 * q + kk);
+                            T *yj = yw + c * ps + J * 16 + Mma<T>::yrow(4 * q + kk);
                             *yj += tc[i];
                         }
 #pragma unroll
@@ -1466,14 +1493,13 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
                 }
                 I = In;
             }
-            const int nx = b0 + f + PF;
-            pre[f].load(Gl + (int64_t)(nx < nblk ? nx : 0) * 256);
+            pre[f].load(Gl + next_load());
         }
     }
     __syncthreads();
     // u = c + y at each port vertex; o_p = 2 u - a_p (loads of U ports per lane issued together; the
     // first U ports per lane from the registers kept by the gather)
-    for (int t0 = 0; t0 < np_k; t0 += 64 * U) {
+    for (int t0 = 0; t0 < np_k; t0 += nt * U) {
         int tw[U], v[U];
         T a[U][R], cu[U][R];
         if (t0 == 0) {
@@ -1487,7 +1513,7 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int t = t0 + 64 * u + lane, pt = port0 + (t < np_k ? t : 0);
+                const int t = t0 + nt * u + tid, pt = port0 + (t < np_k ? t : 0);
                 tw[u] = twin[pt];
                 v[u] = D.port_pg[pt];
             }
@@ -1502,11 +1528,15 @@ __global__ __launch_bounds__(64) void k_schur(DevSub D, int32_t npg, int64_t npo
             for (int c = 0; c < R; ++c) cu[u][c] = cport[((int64_t)g * npg + pg0 + v[u]) * R + c];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t = t0 + 64 * u + lane, yr = (v[u] & ~15) + Mma<T>::yrow(v[u] & 15);
+            const int t = t0 + nt * u + tid, yr = (v[u] & ~15) + Mma<T>::yrow(v[u] & 15);
             if (t < np_k)
 #pragma unroll
-                for (int c = 0; c < R; ++c)
-                    o_next[wo + (int64_t)(port0 + t) * R + c] = (T)2 * (cu[u][c] + y[c * ps + yr]) - a[u][c];
+                for (int c = 0; c < R; ++c) {
+                    T yy = y[c * ps + yr];
+#pragma unroll
+                    for (int w = 1; w < W; ++w) yy += y[((size_t)w * R + c) * ps + yr];
+                    o_next[wo + (int64_t)(port0 + t) * R + c] = (T)2 * (cu[u][c] + yy) - a[u][c];
+                }
         }
     }
 }
@@ -1905,39 +1935,59 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
     hipLaunchKernelGGL(k_gather_ports<T>, dim3(nsub, ngroups), dim3(128), 0, st, D, nsplit, npg, R, xloc, cport);
 }
 
-size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R) {
+// LDS of the port-reduced sweep with W waves per subgraph: Z^{-1} a [pp][R], then W copies of y
+// [R][pp + 4] and 4 values per lane for the unused lanes, which hold Z^{-1} a per port [np][R] before.
+static size_t schur_lds_w(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
     const size_t pp = (size_t)((max_p + 15) & ~15);
-    // Z^{-1} a [pp][R], then y [R][pp + 20] and 4 values per lane for the unused lanes, which hold
-    // Z^{-1} a per port [np][R] before
-    return tsize * (pp * (size_t)R + std::max((pp + 20) * (size_t)R + 256, (size_t)max_np * R));
+    return tsize * (pp * (size_t)R + std::max((size_t)W * ((pp + 4) * (size_t)R + 256), (size_t)max_np * R));
+}
+
+// Two waves per subgraph when one wave's LDS would leave fewer than two waves per SIMD (W = 0).
+int32_t schur_waves(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
+    if (W == 1 || W == 2) return W;
+    return schur_lds_w(tsize, max_p, max_np, R, 1) > 20 * 1024 && schur_lds_w(tsize, max_p, max_np, R, 2) <= kMaxLds ? 2 : 1;
+}
+
+size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
+    return schur_lds_w(tsize, max_p, max_np, R, schur_waves(tsize, max_p, max_np, R, W));
+}
+
+template <typename T, int W>
+static const void *schur_fn(int32_t R) {
+    return R == 1 ? (const void *)k_schur<T, 1, W> : R == 2 ? (const void *)k_schur<T, 2, W>
+         : R == 4 ? (const void *)k_schur<T, 4, W> : (const void *)k_schur<T, 8, W>;
 }
 
 template <typename T>
-size_t schur_shm(int32_t max_p, int32_t max_np, int32_t R) {
-    return schur_lds_bytes(sizeof(T), max_p, max_np, R);
-}
-
-template <typename T>
-hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R) {
-    const size_t shm = schur_shm<T>(max_p, max_np, R);
+hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
+    const size_t shm = schur_lds_bytes(sizeof(T), max_p, max_np, R, W);
     if (shm <= 64 * 1024) return hipSuccess;
-    const void *fn = R == 1 ? (const void *)k_schur<T, 1> : R == 2 ? (const void *)k_schur<T, 2>
-                   : R == 4 ? (const void *)k_schur<T, 4> : (const void *)k_schur<T, 8>;
+    const void *fn = schur_waves(sizeof(T), max_p, max_np, R, W) == 2 ? schur_fn<T, 2>(R) : schur_fn<T, 1>(R);
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
+template <typename T, int W>
+static void launch_schur_w(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, size_t shm, int32_t npg,
+                           int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
+                           const T *invz, const T *o_prev, T *o_next, hipStream_t st) {
+    const dim3 grid(nsub, ngroups), block(64 * W);
+    switch (R) {
+        case 1: hipLaunchKernelGGL((k_schur<T, 1, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 2: hipLaunchKernelGGL((k_schur<T, 2, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 4: hipLaunchKernelGGL((k_schur<T, 4, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        default: hipLaunchKernelGGL((k_schur<T, 8, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+    }
+}
+
 template <typename T>
-void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t max_np,
+void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t W, int32_t max_p, int32_t max_np,
                   int32_t npg, int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
                   const T *invz, const T *o_prev, T *o_next, hipStream_t st) {
-    const size_t shm = schur_shm<T>(max_p, max_np, R);
-    const dim3 grid(nsub, ngroups), block(64);
-    switch (R) {
-        case 1: hipLaunchKernelGGL((k_schur<T, 1>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 2: hipLaunchKernelGGL((k_schur<T, 2>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 4: hipLaunchKernelGGL((k_schur<T, 4>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        default: hipLaunchKernelGGL((k_schur<T, 8>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-    }
+    const size_t shm = schur_lds_bytes(sizeof(T), max_p, max_np, R, W);
+    if (schur_waves(sizeof(T), max_p, max_np, R, W) == 2)
+        launch_schur_w<T, 2>(D, nsub, ngroups, R, shm, npg, nports, G, goff, cport, twin, invz, o_prev, o_next, st);
+    else
+        launch_schur_w<T, 1>(D, nsub, ngroups, R, shm, npg, nports, G, goff, cport, twin, invz, o_prev, o_next, st);
 }
 
 static const void *persist_fn(int32_t R) {
@@ -2022,12 +2072,12 @@ template void launch_gather_ports<double>(const DevSub &, int32_t, int32_t, int6
                                           double *, hipStream_t);
 template void launch_gather_ports<float>(const DevSub &, int32_t, int32_t, int64_t, int32_t, int32_t, const float *,
                                          float *, hipStream_t);
-template hipError_t prepare_schur<double>(int32_t, int32_t, int32_t);
-template hipError_t prepare_schur<float>(int32_t, int32_t, int32_t);
-template void launch_schur<double>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const double *,
+template hipError_t prepare_schur<double>(int32_t, int32_t, int32_t, int32_t);
+template hipError_t prepare_schur<float>(int32_t, int32_t, int32_t, int32_t);
+template void launch_schur<double>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const double *,
                                    const int64_t *, const double *, const int32_t *, const double *, const double *,
                                    double *, hipStream_t);
-template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const float *,
+template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, int64_t, const float *,
                                   const int64_t *, const float *, const int32_t *, const float *, const float *,
                                   float *, hipStream_t);
 template hipError_t prepare_sweep<float>(int32_t, int32_t, int32_t, int32_t);

@@ -128,13 +128,15 @@ template <typename T>
 void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,
                          const T *xloc, T *cport, hipStream_t st);
 template <typename T>
-hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R);
-// LDS of the port-reduced sweep kernel; it runs only when this fits the 160 KiB of a CU.
-size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R);
+hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R, int32_t W);
+// Waves per subgraph of the port-reduced sweep (W = 0: chosen from the LDS size) and its LDS; it
+// runs only when this fits the 160 KiB of a CU.
+int32_t schur_waves(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W);
+size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W = 0);
 constexpr size_t kMaxLds = 160 * 1024;
 // Port-reduced sweep: o = 2 (c + G Z^{-1} a) - a at every port.
 template <typename T>
-void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t max_p, int32_t max_np,
+void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int32_t W, int32_t max_p, int32_t max_np,
                   int32_t npg, int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
                   const T *invz, const T *o_prev, T *o_next, hipStream_t st);
 

@@ -241,21 +241,22 @@ def test_port_reduced_sweeps_match_substitution(B, name, precision):
         assert _rel(rs["x"][r], rt["x"][r]) <= (1e-10 if precision == 0 else 1e-6)
 
 
+@pytest.mark.parametrize("W", [1, 2])
 @pytest.mark.parametrize("R", [1, 2, 4, 8])
 @pytest.mark.parametrize("name", ["c3", "c5"])
-def test_port_reduced_multi_rhs_match_oracle(B, name, R):
+def test_port_reduced_multi_rhs_match_oracle(B, name, R, W):
     """Port-reduced sweeps with 8 right-hand sides in groups of R per wave (matrix-core y_I += B x_J,
-    vector-unit y_J += B^T x_I): FP64 iterates equal the oracle's to rounding for every RHS; FP32
-    iterates to FP32 accuracy; the FP64 result does not depend on R beyond rounding."""
+    vector-unit y_J += B^T x_I), one or two waves per subgraph: FP64 iterates equal the oracle's to
+    rounding for every RHS; FP32 iterates to FP32 accuracy."""
     cfg = gen.make_config(name, small=True)
     rng = np.random.default_rng(77)
     b = rng.uniform(-1.0, 1.0, (8, cfg["A"].n))
-    print(f"[parity] port-reduced multi-RHS {name} R={R}", flush=True)
+    print(f"[parity] port-reduced multi-RHS {name} R={R} W={W}", flush=True)
     P = O.Partition(cfg["A"], cfg["spec"])
     z = 8.0 * P.zdiag
     xo = O.Solver(P, z).run(b, 23, 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"]
     for precision, tol in ((0, 1e-10), (1, 2e-5)):
-        h = B.VTM(device=0, precision=precision, check_every=10, sweep_mode=2, rhs_per_block=R)
+        h = B.VTM(device=0, precision=precision, check_every=10, sweep_mode=2, rhs_per_block=R, sweep_waves=W)
         h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
         h.setup(B.VTM_Z_USER, z)
         xg = h.run_sweeps(b, 23)
@@ -265,16 +266,17 @@ def test_port_reduced_multi_rhs_match_oracle(B, name, R):
         h.close()
 
 
-def test_port_reduced_sweeps_bitwise_repeatable(B):
-    """Two runs of the same port-reduced sweeps (FP32 and FP64, 8 RHS) give bitwise equal results:
-    every sum of the kernel has a fixed order."""
+@pytest.mark.parametrize("W", [1, 2])
+def test_port_reduced_sweeps_bitwise_repeatable(B, W):
+    """Two runs of the same port-reduced sweeps (FP32 and FP64, 8 RHS, one or two waves per subgraph)
+    give bitwise equal results: every sum of the kernel has a fixed order."""
     cfg = gen.make_config("c3", small=True)
     b = cfg["b"]
     P = O.Partition(cfg["A"], cfg["spec"])
     for precision in (0, 1):
         outs = []
         for rep in range(2):
-            h = B.VTM(device=0, precision=precision, check_every=10, sweep_mode=2, persistent=1)
+            h = B.VTM(device=0, precision=precision, check_every=10, sweep_mode=2, persistent=1, sweep_waves=W)
             h.evs_partition(cfg["A"], cfg["spec"])
             h.setup(B.VTM_Z_USER, 8.0 * P.zdiag)
             outs.append((h.run_sweeps(b, 17), h.get_waves(b.shape[0])))
