@@ -1294,8 +1294,12 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
     for (int j = col0; j < nb; j = next_col(j)) nblk += nb - j;
     // load cursor: block (Il, Jl) of this wave's sequence, PF blocks ahead of the one in use
     int Jl = col0, Il = col0;
+    // past the wave's last block a slot loads the block after G_k (inside the next G_k or the
+    // allocation's one-block padding): an address of its own, so that the load is not merged with a
+    // real one, which would make its use wait for that load
+    const int64_t past = (int64_t)nb * (nb + 1) / 2 * 256;
     auto next_load = [&]() {
-        const int64_t off = Jl < nb ? ((int64_t)Jl * nb - (int64_t)Jl * (Jl - 1) / 2 + (Il - Jl)) * 256 : 0;
+        const int64_t off = Jl < nb ? ((int64_t)Jl * nb - (int64_t)Jl * (Jl - 1) / 2 + (Il - Jl)) * 256 : past;
         if (Il + 1 < nb) {
             ++Il;
         } else {
@@ -1304,31 +1308,23 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
         }
         return off;
     };
-    // Every slot issues one load per refill, past the last block too (it then re-reads block 0, which
-    // stays unused): with the same number of loads in flight on every path, each use waits only for
-    // its own block.  The loads are kept in slot order (scheduling barriers), as the refills are
-    // issued: then the queue is in the same order on entry to the loop and around it.
-    Quad<T> pre[PF];
-#pragma unroll
-    for (int f = 0; f < PF; ++f) {
-        pre[f].load(Gl + next_load());
-        __builtin_amdgcn_sched_barrier(0);
-    }
-    // Z^{-1} a_p for every port (a_p = o_twin(p)) into the scratch, with the loads of U ports per lane
+    // Z^{-1} a_p for every port (a_p = o_twin(p)) into the scratch, with the loads of U ports per thread
     // issued before the first of them is used; then xz[v] = the sum over the ports at vertex v, in
     // port order (no LDS atomics: a float atomic costs far more than a read and a write).  The first
-    // U ports of each lane keep their twin, vertex and incoming wave in registers for the write-back,
-    // and the first vertex records are requested with them.
+    // U ports of each thread keep their twin, vertex and incoming wave in registers for the write-back,
+    // and the first vertex records are requested with them.  Loads complete in issue order, so the
+    // first ports' loads go out before the G stream starts, which would otherwise sit in front of them.
     const int port0 = D.port_ptr[k], np_k = D.port_ptr[k + 1] - port0;
     int tw0[U], v0r[U], vb0[U], vc0[U];
-    T a0[U][R];
+    T a0[U][R], iz0[U];
+    // vertex record (first port, port count) with an unconditional load (a clamped index), so that
+    // nothing waits for it before it is used; vertices past p get no ports there
     auto vertex_rec = [&](int v, int &b, int &c) {
-        b = v < p ? D.pg_beg[pg0 + v] - port0 : 0;
-        c = v < p ? D.pg_cnt[pg0 + v] : 0;
+        const int vc = v < p ? v : p - 1;
+        b = D.pg_beg[pg0 + vc];
+        c = D.pg_cnt[pg0 + vc];
     };
-    for (int t0 = 0; t0 < np_k; t0 += nt * U) {
-        int tw[U], vv[U];
-        T iz[U], a[U][R];
+    auto port_loads = [&](int t0, int (&tw)[U], int (&vv)[U], T (&iz)[U], T (&a)[U][R]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + nt * u + tid, pt = port0 + (t < np_k ? t : 0);
@@ -1343,6 +1339,8 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
+    };
+    auto port_store = [&](int t0, const T (&iz)[U], const T (&a)[U][R]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + nt * u + tid;
@@ -1350,14 +1348,24 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
 #pragma unroll
                 for (int c = 0; c < R; ++c) scr[t * R + c] = a[u][c] * iz[u];
         }
-        if (t0 == 0)
+    };
+    if (np_k > 0) port_loads(0, tw0, v0r, iz0, a0);
+    // Every slot issues one load per refill, past the last block too (see past): with the same number
+    // of loads in flight on every path, each use waits only for its own block.  The loads are kept in slot order (scheduling barriers), as the refills are
+    // issued: then the queue is in the same order on entry to the loop and around it.
+    __builtin_amdgcn_sched_barrier(0);
+    Quad<T> pre[PF];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                tw0[u] = tw[u];
-                v0r[u] = vv[u];
-#pragma unroll
-                for (int c = 0; c < R; ++c) a0[u][c] = a[u][c];
-            }
+    for (int f = 0; f < PF; ++f) {
+        pre[f].load(Gl + next_load());
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (np_k > 0) port_store(0, iz0, a0);
+    for (int t0 = nt * U; t0 < np_k; t0 += nt * U) {
+        int tw[U], vv[U];
+        T iz[U], a[U][R];
+        port_loads(t0, tw, vv, iz, a);
+        port_store(t0, iz, a);
     }
     __syncthreads();
     for (int v0 = 0; v0 < pp; v0 += nt * U) {
@@ -1373,13 +1381,13 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int v = v0 + nt * u + tid;
+            const int v = v0 + nt * u + tid, n = v < p ? cnt[u] : 0, t1 = b0[u] - port0;
             T s_[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) s_[c] = 0;
-            for (int j = 0; j < cnt[u]; ++j)
+            for (int j = 0; j < n; ++j)
 #pragma unroll
-                for (int c = 0; c < R; ++c) s_[c] += scr[(b0[u] + j) * R + c];
+                for (int c = 0; c < R; ++c) s_[c] += scr[(t1 + j) * R + c];
             if (v < pp)
 #pragma unroll
                 for (int c = 0; c < R; ++c) xz[xzi(v, c)] = s_[c];
