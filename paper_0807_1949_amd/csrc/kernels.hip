@@ -1261,7 +1261,7 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
                                               const T *__restrict__ o_prev, T *__restrict__ o_next) {
     static_assert(R == 1 || R == 2 || R == 4 || R == 8, "right-hand sides per wave");
     extern __shared__ char smraw[];
-    constexpr int PF = sizeof(T) == 4 ? 8 : 4;   // blocks in flight (8 KB)
+    constexpr int PF = 4;                         // blocks in flight (4 KB FP32, 8 KB FP64)
     constexpr int U = 4;                          // ports per lane whose loads are issued together
     constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
     typedef typename Mma<T>::acc Acc;
@@ -1284,27 +1284,30 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
     // about equal numbers of blocks), each adding into its own copy of y; the copies are summed in a
     // fixed order at the end.
     auto owner = [&](int j) { return W == 1 ? 0 : ((j ^ (j >> 1)) & 1); };
-    auto next_col = [&](int j) {
-        int n = j + 1;
-        while (W > 1 && n < nb && owner(n) != wv) ++n;
-        return n;
+    auto next_col = [&](int j) {  // the owner pattern has period 4: the next own column is 1 to 3 ahead
+        if (W == 1) return j + 1;
+        return owner(j + 1) == wv ? j + 1 : owner(j + 2) == wv ? j + 2 : j + 3;
     };
     const int col0 = W == 1 ? 0 : (nb > wv ? wv : nb);
     int nblk = 0;
     for (int j = col0; j < nb; j = next_col(j)) nblk += nb - j;
-    // load cursor: block (Il, Jl) of this wave's sequence, PF blocks ahead of the one in use
+    // load cursor: block (Il, Jl) of this wave's sequence, PF blocks ahead of the one in use, and the
+    // offset of block (Jl, Jl) (blocks of a column are consecutive)
     int Jl = col0, Il = col0;
+    int64_t coff = ((int64_t)col0 * nb - (int64_t)col0 * (col0 - 1) / 2) * 256;
     // past the wave's last block a slot loads the block after G_k (inside the next G_k or the
     // allocation's one-block padding): an address of its own, so that the load is not merged with a
     // real one, which would make its use wait for that load
     const int64_t past = (int64_t)nb * (nb + 1) / 2 * 256;
     auto next_load = [&]() {
-        const int64_t off = Jl < nb ? ((int64_t)Jl * nb - (int64_t)Jl * (Jl - 1) / 2 + (Il - Jl)) * 256 : past;
+        const int64_t off = Jl < nb ? coff + (int64_t)(Il - Jl) * 256 : past;
         if (Il + 1 < nb) {
             ++Il;
         } else {
-            Jl = next_col(Jl);
-            Il = Jl;
+            const int Jn = next_col(Jl);
+            coff = ((int64_t)Jn * nb - (int64_t)Jn * (Jn - 1) / 2) * 256;
+            Jl = Jn;
+            Il = Jn;
         }
         return off;
     };
