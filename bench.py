@@ -14,7 +14,11 @@ Prints ONE JSON line.  value = unknown-updates per second of the headline
 variant (n * nrhs * sweeps / step time).  Also reported: time to tolerance of
 every variant and the speedup of the headline over plain FP64 VTM, the sweep
 kernel's roofline (algorithmic bytes per sweep over the event-timed sweep
-duration) and the CPU oracle timed on this host.
+duration), the roofline of the streaming port-reduced sweep where G comes
+from HBM every sweep (3D Poisson 128^3, 8 RHS), the set-up's matrix-core use
+and the CPU oracle timed on this host.  Measured HBM traffic and matrix-core
+counts come from the rocprofv3 summaries under profiles/ while the kernels'
+source is the one they were taken with.
 """
 from __future__ import annotations
 
@@ -136,10 +140,11 @@ def cpu_baseline(O, A, spec, b, z):
     """Oracle (plain FP64 C, OpenMP) on a bounded sample: a few sweeps of the same system."""
     P = O.Partition(A, spec)
     s = O.Solver(P, z)
+    s.run(b[:1], 2, 0, 0.0)  # first touch of the factors
     t0 = time.perf_counter()
-    s.run(b[:1], 2, 0, 0.0)
-    t2 = time.perf_counter() - t0
-    nsw = int(max(2, min(20000, 15.0 / max(t2 / 2, 1e-6))))  # about 15 s of oracle work
+    s.run(b[:1], 20, 0, 0.0)
+    t20 = time.perf_counter() - t0
+    nsw = int(max(2, min(50000, 15.0 / max(t20 / 20, 1e-6))))  # about 15 s of oracle work
     t0 = time.perf_counter()
     s.run(b[:1], nsw, 0, 0.0)
     dt = time.perf_counter() - t0
