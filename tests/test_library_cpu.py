@@ -97,6 +97,14 @@ def test_partition_errors():
     assert e.value.code == B.VTM_ERR_STATE
 
 
+def test_option_errors():
+    """Options outside their documented range are rejected at vtm_create, before any device use."""
+    for bad in (dict(sweep_waves=3), dict(sweep_waves=-1), dict(precision=7)):
+        with pytest.raises(B.VTMError) as e:
+            B.VTM(device=-1, **bad)
+        assert e.value.code == B.VTM_ERR_INVALID
+
+
 def _emulate_multifrontal(d, lval, dplus):
     """Re-run the device factorisation in NumPy from the class data: assemble every front from the
     scatter pairs (local CSR values) and the port diagonal, extend-add the children's update
