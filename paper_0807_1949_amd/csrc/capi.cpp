@@ -126,6 +126,9 @@ struct vtm_ctx {
     int32_t tag = 1;
     int64_t persist_launches = 0;  // persistent launches of the current solve or run
     int32_t *abort_host = nullptr;  // pinned copy of the abort flag, read at the next synchronisation
+    double *relres_host = nullptr;  // pinned copy of the residual norms of a test
+    size_t relres_cap = 0;
+    hipEvent_t ev_test = nullptr;   // completion of a test's residual copy (polled)
     bool abort_pending = false;
     vtm_stats stats{};
 
@@ -146,6 +149,8 @@ struct vtm_ctx {
         drop_graphs();
         for (DevBuf *b : all) b->release();
         if (abort_host) (void)hipHostFree(abort_host);
+        if (relres_host) (void)hipHostFree(relres_host);
+        if (ev_test) (void)hipEventDestroy(ev_test);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     bool fp32() const { return opt.precision == VTM_FP32_IR; }
@@ -860,8 +865,24 @@ vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::v
                          h->d_chunksys.as<int32_t>(), h->nchunks, h->d_syschunk.as<int32_t>(), h->P.nsys,
                          h->d_part.as<double>(), h->d_relres.as<double>(), h->stream);
     rel.resize((size_t)h->P.nsys * nrhs);
-    HIP_TRY(hipMemcpyAsync(rel.data(), h->d_relres.p, sizeof(double) * rel.size(), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    // The norms go to pinned memory and the host polls the copy's completion: a blocking
+    // synchronisation would add its wake-up latency to every test.
+    if (h->relres_cap < rel.size()) {
+        if (h->relres_host) HIP_TRY(hipHostFree(h->relres_host));
+        h->relres_host = nullptr;
+        h->relres_cap = 0;
+        HIP_TRY(hipHostMalloc((void **)&h->relres_host, sizeof(double) * rel.size(), hipHostMallocDefault));
+        h->relres_cap = rel.size();
+    }
+    if (!h->ev_test) HIP_TRY(hipEventCreateWithFlags(&h->ev_test, hipEventDisableTiming));
+    HIP_TRY(hipMemcpyAsync(h->relres_host, h->d_relres.p, sizeof(double) * rel.size(), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipEventRecord(h->ev_test, h->stream));
+    hipError_t q;
+    while ((q = hipEventQuery(h->ev_test)) == hipErrorNotReady) {
+    }
+    HIP_TRY(q);
+    std::copy(h->relres_host, h->relres_host + rel.size(), rel.begin());
     return check_abort(h);
 }
 
