@@ -235,36 +235,39 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
 // Column plan of the port Green's functions (computed inside k_factor).  Ports are sorted by the
 // postorder of their supernode; the ports below supernode s then form the range [lo_s, lo_s + w_s),
 // its own ports the tail of it.  Workspace per supernode: port front (nc + m) x w_s, then Y_s (nc x w_s).
+// Postorder number of every supernode of a class's assembly tree, and the smallest postorder number
+// in its subtree (first): the subtree of s is the range [first[s], post[s]].
+void sn_postorder(const vtm::ClassSym &C, std::vector<int32_t> &post, std::vector<int32_t> &first) {
+    std::vector<std::vector<int32_t>> ch(C.nsn);
+    std::vector<int32_t> roots;
+    for (int32_t s = 0; s < C.nsn; ++s) (C.sn_parent[s] < 0 ? roots : ch[C.sn_parent[s]]).push_back(s);
+    post.assign(C.nsn, 0);
+    first.assign(C.nsn, 0);
+    int32_t cnt = 0;
+    std::vector<std::pair<int32_t, size_t>> stack;  // (supernode, next child)
+    for (int32_t r : roots) {
+        stack.push_back({r, 0});
+        first[r] = cnt;
+        while (!stack.empty()) {
+            auto &top = stack.back();
+            if (top.second < ch[top.first].size()) {
+                const int32_t q = ch[top.first][top.second++];
+                first[q] = cnt;
+                stack.push_back({q, 0});
+            } else {
+                post[top.first] = cnt++;
+                stack.pop_back();
+            }
+        }
+    }
+}
+
 vtm_status build_green_plan(vtm_ctx *h) {
     const vtm::Partition &P = h->P;
     const vtm::Symbolic &S = h->S;
     const int32_t nsub = P.nsub;
     std::vector<std::vector<int32_t>> post(S.classes.size()), first(S.classes.size());
-    for (size_t c = 0; c < S.classes.size(); ++c) {
-        const vtm::ClassSym &C = S.classes[c];
-        std::vector<std::vector<int32_t>> ch(C.nsn);
-        std::vector<int32_t> roots;
-        for (int32_t s = 0; s < C.nsn; ++s) (C.sn_parent[s] < 0 ? roots : ch[C.sn_parent[s]]).push_back(s);
-        post[c].assign(C.nsn, 0);
-        first[c].assign(C.nsn, 0);
-        int32_t cnt = 0;
-        std::vector<std::pair<int32_t, size_t>> stack;  // (supernode, next child)
-        for (int32_t r : roots) {
-            stack.push_back({r, 0});
-            first[c][r] = cnt;
-            while (!stack.empty()) {
-                auto &top = stack.back();
-                if (top.second < ch[top.first].size()) {
-                    const int32_t q = ch[top.first][top.second++];
-                    first[c][q] = cnt;
-                    stack.push_back({q, 0});
-                } else {
-                    post[c][top.first] = cnt++;
-                    stack.pop_back();
-                }
-            }
-        }
-    }
+    for (size_t c = 0; c < S.classes.size(); ++c) sn_postorder(S.classes[c], post[c], first[c]);
     std::vector<int4> sn;
     std::vector<int32_t> base(nsub + 1, 0), idoff(h->npg, 0);
     std::vector<uint16_t> perm(h->npg, 0);
@@ -424,6 +427,16 @@ vtm_status upload_partition(vtm_ctx *h) {
     std::vector<double> afront;  // lower entries of every local matrix in the order of its class's scatter list
     int64_t vo = 0, wo = 0;
     h->total_lower = 0;
+    std::vector<std::vector<int32_t>> post(S.classes.size());
+    {
+        std::vector<int32_t> first;
+        for (size_t c = 0; c < S.classes.size(); ++c) sn_postorder(S.classes[c], post[c], first);
+    }
+    struct PortGroup {
+        int32_t key, beg, cnt;
+        uint16_t pos;
+    };
+    std::vector<PortGroup> groups;
     for (int32_t k = 0; k < nsub; ++k) {
         const int32_t c = S.sub_class[k];
         const vtm::ClassSym &C = S.classes[c];
@@ -436,14 +449,24 @@ vtm_status upload_partition(vtm_ctx *h) {
         for (const int32_t src : C.sc_src) afront.push_back(P.lval[P.lrp[P.loc_ptr[k]] + src]);
         subws[k] = wo;
         wo += C.ws_u + (int64_t)C.max_front * C.max_front + ((C.nk + 1) & ~1);  // updates, front, port diagonal
+        // the port vertices (groups of ports at one vertex) in the postorder of the supernodes holding
+        // them: the ports below any supernode are then contiguous, so that the G_k block that a
+        // supernode's Y_s^T Y_s adds to is a contiguous block of the packed G_k (coalesced adds)
+        groups.clear();
         for (int64_t p = P.port_ptr[k]; p < P.port_ptr[k + 1];) {
             int64_t q = p;
             while (q < P.port_ptr[k + 1] && P.port_v[q] == P.port_v[p]) ++q;
-            for (int64_t t = p; t < q; ++t) portpg[t] = (uint16_t)(pgpos.size() - pgptr[k]);
-            pgpos.push_back((uint16_t)C.ipos[P.port_lidx[p]]);
-            pgbeg.push_back((int32_t)p);
-            pgcnt.push_back((int32_t)(q - p));
+            const uint16_t pos = (uint16_t)C.ipos[P.port_lidx[p]];
+            groups.push_back(PortGroup{post[c][C.col_sn[pos]], (int32_t)p, (int32_t)(q - p), pos});
             p = q;
+        }
+        std::stable_sort(groups.begin(), groups.end(),
+                         [](const PortGroup &a, const PortGroup &b) { return a.key < b.key; });
+        for (const PortGroup &g : groups) {
+            for (int32_t t = g.beg; t < g.beg + g.cnt; ++t) portpg[t] = (uint16_t)(pgpos.size() - pgptr[k]);
+            pgpos.push_back(g.pos);
+            pgbeg.push_back(g.beg);
+            pgcnt.push_back(g.cnt);
         }
         pgptr[k + 1] = (int32_t)pgpos.size();
     }

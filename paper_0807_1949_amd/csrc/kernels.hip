@@ -86,6 +86,17 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// 1 / sqrt(d) for a positive finite d: the hardware estimate (relative error about 2^-23) and three
+// Newton steps y <- y (3 - d y^2) / 2, each of which squares the relative error (to rounding level
+// after the third); a short dependent chain, unlike a correctly rounded square root and division.
+__device__ inline double rsqrt_newton(double d) {
+    const double h = 0.5 * d;
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 3; ++it) y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
 template <bool BLK>
 __device__ inline void team_sync() {
     if (BLK) __syncthreads();
@@ -212,18 +223,21 @@ __device__ __forceinline__ void elim_regs(double *F, double *pk, int f, int nc, 
     for (int k = 0; k < nc; ++k) {
         const double *cb = pk + (k & 1) * kPad;
         double *cn = pk + (~k & 1) * kPad;
-        double d = cb[k];
+        // every read of the step at once (the buffer is kPad long: no guards), so the step waits for
+        // LDS once
+        double d = cb[k], ci[KT], cc[KT];
+#pragma unroll
+        for (int a = 0; a < KT; ++a) ci[a] = cb[lr + G * a];
+#pragma unroll
+        for (int b = 0; b < KT; ++b) cc[b] = cb[lc + G * b];
         if (!(d > 0.0) || !isfinite(d)) {
             if (r == 0) atomicMin(sbad, s + 1);
             d = 1.0;
         }
-        const double rd = 1.0 / sqrt(d);
+        const double rd = rsqrt_newton(d);
         double pi[KT];
 #pragma unroll
-        for (int a = 0; a < KT; ++a) {
-            const int i = lr + G * a;
-            pi[a] = i == k ? rd : cb[i] * rd;
-        }
+        for (int a = 0; a < KT; ++a) pi[a] = lr + G * a == k ? rd : ci[a] * rd;
         if (lc == 0)  // the finished column: rows <= k into the front (row k of B, diagonal of Linv)
 #pragma unroll
             for (int a = 0; a < KT; ++a) {
@@ -241,7 +255,7 @@ __device__ __forceinline__ void elim_regs(double *F, double *pk, int f, int nc, 
         }
 #pragma unroll
         for (int b = 0; b < KT; ++b) {
-            const double pc = cb[lc + G * b] * rd;
+            const double pc = cc[b] * rd;
 #pragma unroll
             for (int a = 0; a < KT; ++a) v[a][b] = fma(-pi[a], pc, v[a][b]);
         }
@@ -361,7 +375,7 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                 if (r == 0) atomicMin(sbad, s + 1);
                 d = 1.0;
             }
-            const double rd = 1.0 / sqrt(d);
+            const double rd = rsqrt_newton(d);
             for (int i = r; i < f; i += n) {
                 const double p = i == k ? rd : F[i * f + k] * rd;
                 pk[i] = p;
