@@ -711,7 +711,10 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     if constexpr (std::is_same<T, float>::value) {
         if (schur && persistent_ok(h, R, ng)) {
             const int64_t nw = (int64_t)ng * h->nports * R;
+            const void *tw_before = h->d_tw.p;
             HIP_TRY(ensure(h->d_tw, sizeof(unsigned long long) * (2 * nw + 2)));
+            // tag 0 is never awaited (tags start at 1): a new buffer holds no word a launch could take
+            if (h->d_tw.p != tw_before) HIP_TRY(hipMemsetAsync(h->d_tw.p, 0, h->d_tw.bytes, h->stream));
             if (!h->d_abort.p) {
                 HIP_TRY(ensure(h->d_abort, sizeof(int32_t) * 2));
                 HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
@@ -724,8 +727,6 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
             for (int64_t left = count; left > 0;) {
                 const int32_t nsw = (int32_t)std::min<int64_t>(left, 1 << 20);
                 if (h->tag > (1 << 29)) h->tag = 1;
-                vtm::launch_tag_waves(h->d_o[h->cur].as<float>(), h->d_tw.as<unsigned long long>(), nw, h->tag,
-                                      h->stream);
                 const hipError_t e = vtm::launch_schur_persist(
                     D, h->P.nsub, ng, R, h->max_p, h->max_np, h->npg, h->nports, green_of<float>(h),
                     h->d_goff.as<int64_t>(), h->d_cport.as<float>(), h->d_twin.as<int32_t>(), invz_of<float>(h),

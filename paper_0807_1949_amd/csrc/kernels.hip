@@ -1576,7 +1576,11 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
 // single-copy-atomic word needs no separate flag or fence).  Two buffers suffice: the word of sweep
 // s overwrites the one of sweep s - 2, which the twin's owner read during its sweep s - 1, before
 // it published the sweep s - 1 word this workgroup waited for.  Neighbours thus stay within one
-// sweep of each other.  All workgroups must be resident at once (cooperative launch).  Every wait
+// sweep of each other.  A launch starting at tag t0 first publishes its starting waves with tag t0
+// and then awaits tags t0 .. t0 + nsw - 1 only; no word left from earlier launches carries one of
+// them (the host advances t0 by nsw + 2 per launch, restarts it at 1 only past 2^29, and zeroes a new
+// buffer; tag 0 is never awaited).
+// All workgroups must be resident at once (cooperative launch).  Every wait
 // is bounded: a wait that exceeds spin_limit polls raises *abort, every other wait then gives up
 // too, and the launch runs to its end with the host reporting the error.
 
@@ -1670,6 +1674,17 @@ __global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg,
         izl[t] = invz[port0 + t];
     }
     for (int e = tid; e < 2 * 128 * R; e += nt) xz2[e] = 0.f;  // rows >= p stay zero
+    // the starting waves of this workgroup's ports, published with tag t0 by the threads that publish
+    // them at every sweep (so each word's stores keep program order)
+    if (outer) {
+        const float *start = cur0 == 0 ? plain0 : plain1;
+        unsigned long long *dst = tw + (int64_t)(t0 & 1) * bstride + wo;
+        for (int j = 0; j < rc; ++j) {
+            const int64_t o = (int64_t)(port0 + rb + j) * R;
+#pragma unroll
+            for (int c = 0; c < R; ++c) store_word(dst + o + c, tag_word(t0, start[wo + o + c]));
+        }
+    }
     __syncthreads();
     for (int i = 1; i <= nsw; ++i) {
         const int s = t0 + i, par = i & 1;
@@ -1752,13 +1767,6 @@ __global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg,
 
 // Tagged wave buffers for a persistent launch starting at sweep tag t0: buffer t0 & 1 holds the
 // current waves with tag t0, the other buffer tag t0 - 1 (never the tag a reader waits for).
-__global__ void k_tag_waves(const float *__restrict__ o, unsigned long long *tw, int64_t n, int32_t t0) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        tw[(int64_t)(t0 & 1) * n + i] = tag_word(t0, o[i]);
-        tw[(int64_t)((t0 + 1) & 1) * n + i] = tag_word(t0 - 1, 0.f);
-    }
-}
-
 // ------------------------------------------------------------------ merge, residual
 template <typename T>
 __global__ void k_merge(DevMaps M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *__restrict__ xloc,
@@ -2052,13 +2060,6 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
     void *args[] = {&d, &npg, &nports, &max_np, &G, &goff, &cport, &twin, &invz, &tw, &plain0, &plain1,
                     &t0, &nsw, &cur0, &spin_limit, &abort_flag};
     return hipLaunchCooperativeKernel(persist_fn(R), dim3(nsub, ngroups), dim3(256), args, (unsigned)shm, st);
-}
-
-void launch_tag_waves(const float *o, unsigned long long *tw, int64_t n, int32_t t0, hipStream_t st) {
-    unsigned nb = blocks_for(n, 256);
-    if (nb > 4096) nb = 4096;
-    if (nb == 0) nb = 1;
-    hipLaunchKernelGGL(k_tag_waves, dim3(nb), dim3(256), 0, st, o, tw, n, t0);
 }
 
 template <typename T>

@@ -141,8 +141,9 @@ void launch_schur(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, int
                   const T *invz, const T *o_prev, T *o_next, hipStream_t st);
 
 // Persistent port-reduced sweeps (FP32, p_k <= 128): nsw sweeps in one cooperative launch, G_k rows in registers,
-// waves exchanged as tagged 64-bit words tw[2][ngroups][nports][R] (k_tag_waves sets them up from
-// the plain waves at tag t0); the last two sweeps also write the plain buffers (cur0 ^ (i & 1)).
+// waves exchanged as tagged 64-bit words tw[2][ngroups][nports][R] (the launch publishes the plain
+// waves plain[cur0] with tag t0 first, then awaits tags t0 .. t0 + nsw - 1, which no word left in tw
+// from earlier use may carry); the last two sweeps also write the plain buffers (cur0 ^ (i & 1)).
 // *abort_flag becomes 1 if a wait exceeded spin_limit polls.
 size_t persist_lds_bytes(int32_t max_p, int32_t max_np, int32_t R);
 int persist_max_p();  // largest port-vertex count per subgraph of the persistent kernel
@@ -152,7 +153,6 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
                                 const float *cport, const int32_t *twin, const float *invz, unsigned long long *tw,
                                 float *plain0, float *plain1, int32_t t0, int32_t nsw, int32_t cur0,
                                 int32_t spin_limit, int32_t *abort_flag, hipStream_t st);
-void launch_tag_waves(const float *o, unsigned long long *tw, int64_t n, int32_t t0, hipStream_t st);
 
 // xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
 template <typename T>
