@@ -290,6 +290,7 @@ vtm_status build_green_plan(vtm_ctx *h) {
         for (int32_t s = 0; s < C.nsn; ++s) {
             lo[s] = (int32_t)(std::lower_bound(ks.begin(), ks.end(), first[c][s]) - ks.begin());
             w[s] = (int32_t)(std::upper_bound(ks.begin(), ks.end(), post[c][s]) - ks.begin()) - lo[s];
+            off = (off + 3) & ~(int64_t)3;  // regions start on 4 entries (16-byte rows of the FP32 Y blocks)
             fo[s] = off;
             off += (int64_t)(2 * C.sn_nc[s] + C.sn_m[s]) * w[s];
         }
@@ -308,7 +309,7 @@ vtm_status build_green_plan(vtm_ctx *h) {
             perm[pg0 + a] = (uint16_t)j;
             idoff[pg0 + a] = (int32_t)(fo[s] + (int64_t)(pos - C.sn_c0[s]) * w[s] + (a - lo[s]));
         }
-        wso[k + 1] = wso[k] + ((off + 1) & ~(int64_t)1);
+        wso[k + 1] = wso[k] + ((off + 3) & ~(int64_t)3);
     }
     base[nsub] = (int32_t)sn.size();
     h->gws_total = wso[nsub];

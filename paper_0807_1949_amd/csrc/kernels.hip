@@ -172,11 +172,20 @@ struct FactorArgs {
     // port Green's functions (gpl == nullptr: not computed)
     const int4 *gpl;
     double *gws;
-    float *gws32;  // FP32 copy of the Y blocks (same offsets), or nullptr
+    float *gws32;  // FP32 copy of the Y blocks (at y32_pos), or nullptr
     const uint16_t *perm;
     double *Gk;
     int nb;  // 16 x 16 blocks per row of the packed G_k
 };
+
+// Position of Y_s[row][a] in the FP32 copy of the Y blocks.  A supernode's region of the Green
+// workspace starts on a multiple of 4 entries and holds (2 nc + m) w of them; the FP32 copy needs no
+// port front, so for w >= 4 its rows start at the region's start with a stride of w rounded up to 4
+// (16-byte rows for vector loads; nc (w + 3) <= (2 nc + m) w), and for w < 4 they stay where the FP64
+// Y block is.
+__host__ __device__ inline int64_t y32_pos(int64_t region, int f, int w, int row, int a) {
+    return w >= 4 ? region + (int64_t)row * ((w + 3) & ~3) + a : region + (int64_t)f * w + (int64_t)row * w + a;
+}
 
 // G[ports a, b of s] += acc for the lower part of tile (ta, tb) of Y_s^T Y_s; port(x) is the port
 // number of column x of s.
@@ -506,7 +515,7 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                         if (row < nc) {
                             Yg[row * w + a] = v;
                             if (Yl) Yl[row * w + a] = v;
-                            if (X.gws32) X.gws32[e.x + (int64_t)f * w + row * w + a] = (float)v;
+                            if (X.gws32) X.gws32[y32_pos(e.x, f, w, row, a)] = (float)v;
                         } else {
                             X.gws[e.z + (int64_t)prow[jj] * pw + a + (pc0 - ppc0)] = v;
                         }
@@ -656,7 +665,7 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
                 double acc = T[i * w + a] / F[i * f + i];
                 for (int t = 0; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
                 Y[idx] = acc;
-                if (X.gws32) X.gws32[e.x + (int64_t)f * w + idx] = (float)acc;
+                if (X.gws32) X.gws32[y32_pos(e.x, f, w, i, a)] = (float)acc;
             }
             __syncthreads();
             for (int idx = r; idx < m * w; idx += n) {  // T[nc:] - L21 Y into the parent's port front
@@ -1041,21 +1050,44 @@ __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp,
         const int4 e = pl[s];
         const int w = (int)((uint32_t)e.y >> 16), pc0 = e.y & 0xFFFF;
         if (w == 0) continue;
-        const int f = sn_nc[s] + sn_m[s];
-        const T *yr = Yk + e.x + (int64_t)f * w + (int64_t)(col - sn_c0[s]) * w;
+        const int f = sn_nc[s] + sn_m[s], row = col - sn_c0[s];
         const T *wr = wsrt + (size_t)pc0 * R;
         T acc[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[c] = 0;
-        for (int a0 = 0; a0 < w; a0 += 16) {  // sixteen loads in flight before the first product
-            T yv[16];
+        if (sizeof(T) == 4 && w >= 4) {
+            // FP32 rows of 16 bytes (y32_pos): four entries per load, sixteen in flight, the padding
+            // past w dropped (its weight index clamped into the supernode's range)
+            const f32x4 *y4 = reinterpret_cast<const f32x4 *>(Yk + y32_pos(e.x, f, w, row, 0));
+            const int n4 = (w + 3) >> 2;
+            for (int b0 = 0; b0 < n4; b0 += 4) {
+                f32x4 yv[4];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) yv[q] = a0 + q < w ? yr[a0 + q] : (T)0;
+                for (int q = 0; q < 4; ++q) yv[q] = y4[b0 + q < n4 ? b0 + q : n4 - 1];
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                if (a0 + q < w)
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int c = 0; c < R; ++c) acc[c] += yv[q] * wr[(a0 + q) * R + c];
+                    for (int j = 0; j < 4; ++j) {
+                        const int a = 4 * (b0 + q) + j;
+                        const T v = b0 + q < n4 && a < w ? (T)yv[q][j] : (T)0;
+                        const T *wa = wr + (size_t)(a < w ? a : w - 1) * R;
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[c] += v * wa[c];
+                    }
+            }
+        } else {
+            const T *yr = sizeof(T) == 4 ? Yk + y32_pos(e.x, f, w, row, 0)
+                                         : Yk + e.x + (int64_t)f * w + (int64_t)row * w;
+            for (int a0 = 0; a0 < w; a0 += 16) {  // sixteen loads in flight before the first product
+                T yv[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) yv[q] = a0 + q < w ? yr[a0 + q] : (T)0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (a0 + q < w)
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[c] += yv[q] * wr[(a0 + q) * R + c];
+            }
         }
 #pragma unroll
         for (int c = 0; c < R; ++c) vec[col * R + c] += acc[c];
