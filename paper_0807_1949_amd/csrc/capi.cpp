@@ -125,7 +125,6 @@ struct vtm_ctx {
     DevBuf d_tw, d_abort;
     int32_t tag = 1;
     int64_t persist_launches = 0;  // persistent launches of the current solve or run
-    int32_t *abort_host = nullptr;  // pinned copy of the abort flag, read at the next synchronisation
     double *relres_host = nullptr;  // pinned copy of the residual norms of a test
     size_t relres_cap = 0;
     hipEvent_t ev_test = nullptr;   // completion of a test's residual copy (polled)
@@ -148,7 +147,6 @@ struct vtm_ctx {
         (void)hipSetDevice(opt.device);
         drop_graphs();
         for (DevBuf *b : all) b->release();
-        if (abort_host) (void)hipHostFree(abort_host);
         if (relres_host) (void)hipHostFree(relres_host);
         if (ev_test) (void)hipEventDestroy(ev_test);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -571,11 +569,17 @@ int32_t pick_R(vtm_ctx *h, int32_t nrhs) {
     return want;
 }
 
+// Bytes of one wave buffer: ng x nports x R values and one spare, rounded to 16 (one fill kernel).
+template <typename T>
+size_t wave_bytes(const vtm_ctx *h, int32_t nrhs, int32_t R) {
+    const int32_t ng = (nrhs + R - 1) / R;
+    return (sizeof(T) * ((size_t)ng * h->nports * R + 1) + 15) & ~(size_t)15;
+}
+
 template <typename T>
 vtm_status ensure_waves(vtm_ctx *h, int32_t nrhs) {
     const int32_t R = pick_R(h, nrhs);
-    const int32_t ng = (nrhs + R - 1) / R;
-    const size_t bytes = sizeof(T) * (size_t)ng * h->nports * R + sizeof(T);
+    const size_t bytes = wave_bytes<T>(h, nrhs, R);
     if (h->wave_nrhs != nrhs || h->wave_R != R || !h->d_o[0].p) {
         HIP_TRY(ensure(h->d_o[0], bytes));
         HIP_TRY(ensure(h->d_o[1], bytes));
@@ -591,9 +595,8 @@ vtm_status ensure_waves(vtm_ctx *h, int32_t nrhs) {
 
 template <typename T>
 vtm_status zero_waves(vtm_ctx *h) {
-    const int32_t ng = (h->wave_nrhs + h->wave_R - 1) / h->wave_R;
-    const size_t bytes = sizeof(T) * (size_t)ng * h->nports * h->wave_R + sizeof(T);
-    HIP_TRY(hipMemsetAsync(h->d_o[h->cur].p, 0, bytes, h->stream));
+    if (h->waves_zero) return VTM_OK;  // nothing has written the waves since they were cleared
+    HIP_TRY(hipMemsetAsync(h->d_o[h->cur].p, 0, wave_bytes<T>(h, h->wave_nrhs, h->wave_R), h->stream));
     h->waves_zero = true;
     return VTM_OK;
 }
@@ -612,11 +615,16 @@ vtm_status stage_b(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb) {
 }
 
 // After a stream synchronisation: did a persistent launch since the last check give up on a wait?
-vtm_status check_abort(vtm_ctx *h) {
+// fetched is the flag as copied with the residual norms, or -1 (then it is read here).
+vtm_status check_abort(vtm_ctx *h, int fetched = -1) {
     if (!h->abort_pending) return VTM_OK;
     h->abort_pending = false;
-    if (h->abort_host && *h->abort_host) {
-        *h->abort_host = 0;
+    int32_t flag = fetched;
+    if (flag < 0) {
+        HIP_TRY(hipMemcpyAsync(&flag, h->d_abort.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    if (flag) {
         HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
         return fail(VTM_ERR_HIP, "persistent sweep: a wave exchange wait timed out");
@@ -720,10 +728,6 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
                 HIP_TRY(ensure(h->d_abort, sizeof(int32_t) * 2));
                 HIP_TRY(hipMemsetAsync(h->d_abort.p, 0, sizeof(int32_t), h->stream));
             }
-            if (!h->abort_host) {
-                HIP_TRY(hipHostMalloc((void **)&h->abort_host, sizeof(int32_t), hipHostMallocDefault));
-                *h->abort_host = 0;
-            }
             bool refused = false;
             for (int64_t left = count; left > 0;) {
                 const int32_t nsw = (int32_t)std::min<int64_t>(left, 1 << 20);
@@ -746,8 +750,8 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
                 left -= nsw;
             }
             if (refused) goto per_sweep;
-            // the flag is read at the caller's next synchronisation (check_abort); it stays set until then
-            HIP_TRY(hipMemcpyAsync(h->abort_host, h->d_abort.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+            // the flag comes to the host with the next residual norms, or is read at the caller's next
+            // synchronisation (check_abort); it stays set until then
             h->abort_pending = true;
             h->waves_zero = false;
             h->stats.persistent = 1;
@@ -878,7 +882,7 @@ vtm_status alloc_solve(vtm_ctx *h, int32_t nrhs) {
     HIP_TRY(ensure(h->d_r, sizeof(double) * (size_t)n * nrhs));
     HIP_TRY(ensure(h->d_rt, sizeof(double) * (size_t)n * nrhs));
     HIP_TRY(ensure(h->d_part, sizeof(double) * 2 * (size_t)h->nchunks * nrhs));
-    HIP_TRY(ensure(h->d_relres, sizeof(double) * (size_t)h->P.nsys * nrhs));
+    HIP_TRY(ensure(h->d_relres, sizeof(double) * ((size_t)h->P.nsys * nrhs + 1)));
     return VTM_OK;
 }
 
@@ -888,27 +892,28 @@ vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::v
     const int64_t n = h->P.n;
     vtm::launch_residual(A, n, nrhs, h->d_b.as<double>(), n, x, n, r, n, h->d_chunkrow.as<int64_t>(),
                          h->d_chunksys.as<int32_t>(), h->nchunks, h->d_syschunk.as<int32_t>(), h->P.nsys,
-                         h->d_part.as<double>(), h->d_relres.as<double>(), h->stream);
+                         h->d_part.as<double>(), h->abort_pending ? h->d_abort.as<int32_t>() : nullptr,
+                         h->d_relres.as<double>(), h->stream);
     rel.resize((size_t)h->P.nsys * nrhs);
-    // The norms go to pinned memory and the host polls the copy's completion: a blocking
-    // synchronisation would add its wake-up latency to every test.
-    if (h->relres_cap < rel.size()) {
+    // The norms (and the persistent sweeps' abort flag after them) go to pinned memory and the host
+    // polls the copy's completion: a blocking synchronisation would add its wake-up latency to every test.
+    const size_t cnt = rel.size() + 1;
+    if (h->relres_cap < cnt) {
         if (h->relres_host) HIP_TRY(hipHostFree(h->relres_host));
         h->relres_host = nullptr;
         h->relres_cap = 0;
-        HIP_TRY(hipHostMalloc((void **)&h->relres_host, sizeof(double) * rel.size(), hipHostMallocDefault));
-        h->relres_cap = rel.size();
+        HIP_TRY(hipHostMalloc((void **)&h->relres_host, sizeof(double) * cnt, hipHostMallocDefault));
+        h->relres_cap = cnt;
     }
     if (!h->ev_test) HIP_TRY(hipEventCreateWithFlags(&h->ev_test, hipEventDisableTiming));
-    HIP_TRY(hipMemcpyAsync(h->relres_host, h->d_relres.p, sizeof(double) * rel.size(), hipMemcpyDeviceToHost,
-                           h->stream));
+    HIP_TRY(hipMemcpyAsync(h->relres_host, h->d_relres.p, sizeof(double) * cnt, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipEventRecord(h->ev_test, h->stream));
     hipError_t q;
     while ((q = hipEventQuery(h->ev_test)) == hipErrorNotReady) {
     }
     HIP_TRY(q);
     std::copy(h->relres_host, h->relres_host + rel.size(), rel.begin());
-    return check_abort(h);
+    return check_abort(h, h->relres_host[rel.size()] != 0.0 ? 1 : 0);
 }
 
 template <typename T>

@@ -1847,7 +1847,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, c
 
 __global__ __launch_bounds__(256) void k_relres(const double *__restrict__ part, int32_t nchunks,
                                                  const int32_t *__restrict__ sys_chunk_ptr, int32_t nsys, int32_t nrhs,
-                                                 double *__restrict__ relres) {
+                                                 const int32_t *__restrict__ flag, double *__restrict__ relres) {
     __shared__ double red[2][256];
     const int c = blockIdx.x / nsys, s = blockIdx.x - c * nsys, tid = threadIdx.x;
     double rr = 0.0, bb = 0.0;
@@ -1863,6 +1863,7 @@ __global__ __launch_bounds__(256) void k_relres(const double *__restrict__ part,
         __syncthreads();
     }
     if (tid == 0) relres[c * nsys + s] = red[1][0] > 0.0 ? sqrt(red[0][0]) / sqrt(red[1][0]) : sqrt(red[0][0]);
+    if (blockIdx.x == 0 && tid == 0) relres[nsys * nrhs] = flag && *flag ? 1.0 : 0.0;  // travels with the norms
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -2103,10 +2104,12 @@ void launch_merge(const DevMaps &M, int64_t n, int64_t nsplit, int32_t nrhs, int
 
 void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, int64_t ldb, const double *x, int64_t ldx,
                      double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *, int32_t nchunks,
-                     const int32_t *sys_chunk_ptr, int32_t nsys, double *part, double *relres, hipStream_t st) {
+                     const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag, double *relres,
+                     hipStream_t st) {
     hipLaunchKernelGGL(k_residual, dim3(nchunks, nrhs), dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr,
                        chunk_row, nchunks, part);
-    hipLaunchKernelGGL(k_relres, dim3(nsys * nrhs), dim3(256), 0, st, part, nchunks, sys_chunk_ptr, nsys, nrhs, relres);
+    hipLaunchKernelGGL(k_relres, dim3(nsys * nrhs), dim3(256), 0, st, part, nchunks, sys_chunk_ptr, nsys, nrhs, flag,
+                       relres);
 }
 
 template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);

@@ -159,10 +159,11 @@ template <typename T>
 void launch_merge(const DevMaps &M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc,
                   const double *base, int64_t ldbase, double *xout, int64_t ldx, hipStream_t st);
 
-// r = b - A x (optional store), per (rhs, system) relative residual into relres[c * nsys + s].
+// r = b - A x (optional store), per (rhs, system) relative residual into relres[c * nsys + s], and
+// relres[nsys * nrhs] = 1 if *flag is set (flag may be null), so that one copy brings both to the host.
 void launch_residual(const DevCsr &A, int64_t n, int32_t nrhs, const double *b, int64_t ldb, const double *x,
                      int64_t ldx, double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *chunk_sys,
-                     int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, double *relres,
-                     hipStream_t st);
+                     int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag,
+                     double *relres, hipStream_t st);
 
 }  // namespace vtm
