@@ -1827,7 +1827,23 @@ __global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, c
     for (int64_t v = r0 + tid; v < r1; v += kThreads) {
         const double bv = b[v + (int64_t)c * ldb];
         double acc = bv;
-        for (int64_t e = A.rp[v]; e < A.rp[v + 1]; ++e) acc -= A.v[e] * x[A.ci[e] + (int64_t)c * ldx];
+        const int64_t e0 = A.rp[v], e1 = A.rp[v + 1];
+        // eight entries a round, their loads issued together (indices past the row clamped to its last
+        // entry, whose product is then weighted by zero: arithmetic, so the loads stay unconditional)
+        for (int64_t eb = e0; eb < e1; eb += 8) {
+            int32_t col[8];
+            double av[8], xv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t e = eb + q < e1 ? eb + q : e1 - 1;
+                col[q] = A.ci[e];
+                av[q] = A.v[e];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xv[q] = x[col[q] + (int64_t)c * ldx];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc -= (double)(eb + q < e1) * av[q] * xv[q];
+        }
         if (r) r[v + (int64_t)c * ldr] = acc;
         rr += acc * acc;
         bb += bv * bv;
