@@ -525,6 +525,18 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
             team_sync<BLK>();
             if (!staged)  // the port front is left zero for the next factorisation
                 for (int i = r; i < f * w; i += n) T[i] = 0.0;
+            if (!Yl && nc * w <= cap) {  // the front is consumed: Y_s over it, so the Gram products read LDS
+                for (int i0 = r; i0 < nc * w; i0 += 8 * n) {
+                    double t[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) t[q] = i0 + q * n < nc * w ? Yg[i0 + q * n] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (i0 + q * n < nc * w) F[i0 + q * n] = t[q];
+                }
+                Yl = F;
+                team_sync<BLK>();
+            }
             for (int it = wv; it < tcn * (tcn + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
                 tri_tile(it, ta, tb);
