@@ -93,6 +93,10 @@ typedef struct {
                               waves take alternate pairs of block columns of G_k, each with its own
                               copy of the products); 0 = two when one wave's LDS would leave fewer than
                               two waves per SIMD */
+    int32_t spin_limit;    /* persistent sweeps: polls of one incoming wave word before the launch gives up
+                              (every other wait then gives up too, the launch ends, and the solve or
+                              vtm_run_sweeps returns VTM_ERR_HIP; the handle stays usable); 0 = 2^20.
+                              A small value forces that path (tests of the failure handling) */
 } vtm_options;
 
 /*

@@ -29,7 +29,8 @@ class Options(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("max_sweeps", C.c_int64), ("rhs_per_block", C.c_int32), ("leaf_size", C.c_int32),
                 ("sweep_threads", C.c_int32), ("graph_mode", C.c_int32), ("sweep_variant", C.c_int32),
-                ("sweep_mode", C.c_int32), ("persistent", C.c_int32), ("sweep_waves", C.c_int32)]
+                ("sweep_mode", C.c_int32), ("persistent", C.c_int32), ("sweep_waves", C.c_int32),
+                ("spin_limit", C.c_int32)]
 
 
 class PartitionSpec(C.Structure):
@@ -129,7 +130,7 @@ class VTM:
     def __init__(self, device: int = 0, precision: int = VTM_FP64, check_every: int = 0, max_sweeps: int = 100000,
                  rhs_per_block: int = 0, leaf_size: int = 0, stream: int | None = None, sweep_threads: int = 0,
                  graph_mode: int = 0, sweep_variant: int = 0, sweep_mode: int = 0, persistent: int = 0,
-                 sweep_waves: int = 0):
+                 sweep_waves: int = 0, spin_limit: int = 0):
         self._h = C.c_void_p()
         o = Options()
         o.device = device
@@ -145,6 +146,7 @@ class VTM:
         o.sweep_mode = sweep_mode
         o.persistent = persistent
         o.sweep_waves = sweep_waves
+        o.spin_limit = spin_limit
         _check(lib().vtm_create(C.byref(o), C.byref(self._h)))
         self.precision = precision
         self.info = None

@@ -736,7 +736,8 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
                     D, h->P.nsub, ng, R, h->max_p, h->max_np, h->npg, h->nports, green_of<float>(h),
                     h->d_goff.as<int64_t>(), h->d_cport.as<float>(), h->d_twin.as<int32_t>(), invz_of<float>(h),
                     h->d_tw.as<unsigned long long>(), h->d_o[0].as<float>(), h->d_o[1].as<float>(), h->tag, nsw,
-                    h->cur, kSpinLimit, h->d_abort.as<int32_t>(), h->stream);
+                    h->cur, h->opt.spin_limit > 0 ? h->opt.spin_limit : kSpinLimit, h->d_abort.as<int32_t>(),
+                    h->stream);
                 if (e != hipSuccess && left == count) {  // not co-resident after all: per-sweep launches
                     (void)hipGetLastError();
                     h->persist_fits = false;
@@ -1329,6 +1330,10 @@ vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
     if (h->opt.sweep_waves < 0 || h->opt.sweep_waves > 2) {
         delete h;
         return fail(VTM_ERR_INVALID, "sweep_waves must be 0, 1 or 2");
+    }
+    if (h->opt.spin_limit < 0) {
+        delete h;
+        return fail(VTM_ERR_INVALID, "spin_limit must be >= 0");
     }
     if (h->opt.device < 0) {  // host-only handle: partition and symbolic analysis, no device work
         *out = h;

@@ -1643,8 +1643,9 @@ __device__ inline unsigned long long await_word(const unsigned long long *w, uns
                                                 int spin_limit, int32_t *abort_flag) {
     int spins = 0;
     while ((int)(v >> 32) != want) {
-        if ((++spins & 63) == 0 &&
-            (spins > spin_limit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        ++spins;
+        if (spins > spin_limit ||
+            ((spins & 63) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
             __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }

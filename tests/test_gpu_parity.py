@@ -334,6 +334,35 @@ def test_persistent_sweeps_match_per_sweep_launches(B, name, nrhs):
         assert _rel(r0["x"][c], r1["x"][c]) <= 1e-6
 
 
+@pytest.mark.parametrize("call", ["solve", "run_sweeps"])
+def test_persistent_wait_timeout_is_reported_and_recoverable(B, call):
+    """A persistent launch whose wave-word waits give up after one re-read (spin_limit=1) ends
+    normally (every other wait gives up too), the call reports VTM_ERR_HIP, and the device flag is
+    cleared: the same handle then fails the same way again, not from a stale flag alone, and a
+    handle with the default limit solves the system."""
+    cfg = gen.make_config("c2", small=True)
+    b = cfg["b"][:1].copy()
+    print(f"[parity] persistent timeout via {call}", flush=True)
+    h, P, z = _setup(B, cfg, precision=1, z_scale=8.0, sweep_mode=2, check_every=10, spin_limit=1)
+    for _ in range(2):
+        with pytest.raises(B.VTMError) as e:
+            if call == "solve":
+                h.solve(b, 1e-8)
+            else:
+                h.run_sweeps(b, 200)
+        assert e.value.code == B.VTM_ERR_HIP and "timed out" in str(e.value), str(e.value)
+        assert h.get_stats()["persistent"] == 1
+        h.reset_waves()
+    h.close()
+    h, P, z = _setup(B, cfg, precision=1, z_scale=8.0, sweep_mode=2, check_every=10)
+    r = h.solve(b, 1e-8)
+    st = h.get_stats()
+    h.close()
+    assert r["status"] == 0 and st["persistent"] == 1
+    A = cfg["A"].to_scipy()
+    assert np.linalg.norm(b[0] - A @ r["x"][0]) <= 1e-8 * np.linalg.norm(b[0]) * 1.01
+
+
 @pytest.mark.parametrize("name,precision", [("c2", 0), ("c1", 0), ("c3", 0), ("c2", 1)])
 def test_test_solve_from_green_columns_matches_substitution(B, name, precision):
     """The convergence test's local solve from the stored Green's columns (y_b + Y w, then the

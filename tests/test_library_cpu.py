@@ -99,7 +99,7 @@ def test_partition_errors():
 
 def test_option_errors():
     """Options outside their documented range are rejected at vtm_create, before any device use."""
-    for bad in (dict(sweep_waves=3), dict(sweep_waves=-1), dict(precision=7)):
+    for bad in (dict(sweep_waves=3), dict(sweep_waves=-1), dict(precision=7), dict(spin_limit=-1)):
         with pytest.raises(B.VTMError) as e:
             B.VTM(device=-1, **bad)
         assert e.value.code == B.VTM_ERR_INVALID
