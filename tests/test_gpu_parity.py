@@ -363,7 +363,7 @@ def test_persistent_wait_timeout_is_reported_and_recoverable(B, call):
     assert np.linalg.norm(b[0] - A @ r["x"][0]) <= 1e-8 * np.linalg.norm(b[0]) * 1.01
 
 
-@pytest.mark.parametrize("name,precision", [("c2", 0), ("c1", 0), ("c3", 0), ("c2", 1)])
+@pytest.mark.parametrize("name,precision", [("c2", 0), ("c1", 0), ("c3", 0), ("c2", 1), ("c3", 1), ("c4", 1), ("c5", 1)])
 def test_test_solve_from_green_columns_matches_substitution(B, name, precision):
     """The convergence test's local solve from the stored Green's columns (y_b + Y w, then the
     backward substitution) gives the iterate of the substitution solve: FP64 solve == run_sweeps
