@@ -1019,7 +1019,8 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
 //   x = K^{-1} (b~ + E w) = L^{-T} (y_b + Y w),  w = Z^{-1} a summed per port vertex,
 // with y_b = L^{-1} b~ stored by the zero-wave solve of the current source.  One parallel phase and
 // the backward substitution replace the level-by-level forward substitution.  Y rows of supernode
-// s live at the plan's workspace offset (after its port front), nc_s x w_s row-major.
+// s (nc_s x w_s, row-major) live in its region of the Green workspace: after its port front in FP64,
+// at y32_pos in the FP32 copy (16-byte rows when w_s >= 4).
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp, const T *__restrict__ Yw,
                                                 int64_t nsplit, int64_t nports, const T *__restrict__ vals,

@@ -64,7 +64,7 @@ struct DevGreen {
     const int32_t *idoff;   // per sorted port: workspace offset of its unit right-side entry
     const uint16_t *perm;   // per sorted port: its port-vertex index in the subgraph
     double *ws;             // port fronts (nc + m) x w followed by Y blocks nc x w; zero on entry
-    float *ws32;            // FP32 copy of the Y blocks at the same offsets, or nullptr
+    float *ws32;            // FP32 copy of the Y blocks (same regions, rows padded to 4 when w >= 4), or nullptr
 };
 
 // Split-vector and merge maps.
