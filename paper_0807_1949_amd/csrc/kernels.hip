@@ -813,7 +813,6 @@ __device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__res
     const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *lev_u = S.lev_u + C.o_lev;
     const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
     const int32_t *urec = S.urec + 2 * (int64_t)C.o_ridx;
-    const uint16_t *ridx = S.ridx + C.o_ridx;
     const int32_t *seg_ptr = S.seg_ptr + C.o_colp, *seg_off = S.seg_off + C.o_seg;
     const uint16_t *seg_c0 = S.seg_c0 + C.o_seg, *seg_nc = S.seg_nc + C.o_seg, *seg_u = S.seg_u + C.o_seg;
     // forward substitution, one level (independent subtrees) at a time
