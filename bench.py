@@ -1,24 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark: VTM on the 1024^2 lognormal-conductance system (32x32 subgraphs).
+"""Benchmark: VTM on the batch of 64 random-geometric-graph systems (7.4M unknowns, 4 RHS each).
 
-One step = the whole hot path on one batch of synthetic input, with the
-partition (host) done once beforehand: vtm_setup (impedances -- for the
-learned rule the network's inference on the GPU --, port augmentation, device
-factorisation of all 1024 local matrices, port Green's functions) + vtm_solve
-to relative residual 1e-8 (sweeps, exchanges, FP64 residual tests,
-refinement).  Inputs are resident in HBM (torch tensors) before the timed
-region.  The per-VTL features of the learned rule depend only on the matrix
-and the partition and are computed with it, in the warm-up step.
+One step = the whole hot path on one batch of synthetic input, with the EVS
+partition (host) done once beforehand and timed on its own: vtm_setup (the
+learned impedance model's inference on the GPU, port augmentation, device
+factorisation of all 14,380 local matrices, port Green's functions) +
+vtm_solve to relative residual 1e-8 in every system and right-hand side
+(FP32 sweeps, exchanges, FP64 residual tests, refinement; a system that has
+converged stops sweeping).  Inputs are resident in HBM (torch tensors) before
+the timed region.
 
-Prints ONE JSON line.  value = unknown-updates per second of the headline
-variant (n * nrhs * sweeps / step time).  Also reported: time to tolerance of
-every variant and the speedup of the headline over plain FP64 VTM, the sweep
-kernel's roofline (algorithmic bytes per sweep over the event-timed sweep
-duration), the roofline of the streaming port-reduced sweep where G comes
-from HBM every sweep (3D Poisson 128^3, 8 RHS), the set-up's matrix-core use
-and the CPU oracle timed on this host.  Measured HBM traffic and matrix-core
-counts come from the rocprofv3 summaries under profiles/ while the kernels'
-source is the one they were taken with.
+Prints ONE JSON line.  value = unknown-updates per second of the headline:
+sum over systems of n_s * nrhs * (sweeps system s ran) / step time.  Beside it:
+time to tolerance with and without the host partition, sweeps, the residual
+re-checked on the host in FP64, the element-wise error against the FP64 oracle
+after a fixed number of sweeps, plain FP64 VTM on the same workload (the
+speed-up), the 3D Poisson and 1024^2 workloads on the same path, the roofline
+of the dominant kernel (the port-reduced sweep k_schur: algorithmic bytes of the
+sweeps of the timed steps over their event-timed duration), the set-up's
+matrix-core use and the CPU oracle timed on this host.  Measured HBM traffic and
+matrix-core counts come from the rocprofv3 summaries under profiles/ while the
+kernels' source is the one they were taken with.
 """
 from __future__ import annotations
 
@@ -32,39 +34,116 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c5": "64 random geometric graph Laplacians + 1e-2 I, n ~ U[20k, 200k] (7,362,043 unknowns), graph EVS into "
+          "14,380 subgraphs, 4 RHS per system",
+    "c3": "3D 7-point Poisson 128^3 (2,097,152 unknowns), seeded RCB into 4096 subgraphs, 8 RHS",
+    "c2": "2D random-conductance Laplacian lognormal(0,1) + 1e-3 I on 1024^2, 1024 subgraphs of 33x33, 1 RHS",
+    "c4": "2D GRF diffusion 512^2, 256 subgraphs, 1 RHS",
+    "c1": "2D Dirichlet Laplacian 64^2, 16 subgraphs, 1 RHS",
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, steps, warmup, check_every, max_sweeps,
-                mode=0, params=None, leaf_size=0):
-    h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps, sweep_mode=mode,
-              leaf_size=leaf_size)
+def parse_variant(B, Zm, v, A, spec):
+    """{ir,fp64}_{lrn,match,diag,aNN}[_sub|_port] -> (precision, z_rule, z, params, sweep_mode)."""
+    parts = v.split("_")
+    prec_s, zr = parts[0], parts[1]
+    mode = {"sub": 1, "port": 2}.get(parts[2], 0) if len(parts) > 2 else 0
+    precision = B.VTM_FP32_IR if prec_s == "ir" else B.VTM_FP64
+    params = None
+    if zr == "diag":
+        z_rule, z = B.VTM_Z_DIAG, None
+    elif zr == "lrn":
+        z_rule, z, params = B.VTM_Z_LEARNED, None, Zm.load()
+    elif zr == "match":
+        z_rule, z = B.VTM_Z_MATCHED, None
+    else:  # uniform multiplier alpha on the diagonal rule, e.g. a64
+        hh = B.VTM(device=-1)
+        hh.evs_partition(A, spec)
+        z_rule, z = B.VTM_Z_USER, float(zr[1:]) * hh.get_partition()["zdiag"]
+        hh.close()
+    return precision, z_rule, z, params, mode
+
+
+def run_variant(B, Zm, torch, cfg, variant, steps, warmup, check_every=0, max_sweeps=200000):
+    """Partition once (timed), then warmup + steps of setup + solve; returns timings, stats and x."""
+    import numpy as np
+
+    A, spec = cfg["A"], cfg["spec"]
+    precision, z_rule, z, params, mode = parse_variant(B, Zm, variant, A, spec)
+    h = B.VTM(device=0, precision=precision, check_every=check_every, max_sweeps=max_sweeps, sweep_mode=mode)
     t0 = time.perf_counter()
-    info = h.evs_partition(A, spec)
+    info = h.evs_partition(A, spec, nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
     part_s = time.perf_counter() - t0
     if params is not None:
         h.zmodel_load(params)
+    b_dev = torch.tensor(cfg["b"], dtype=torch.float64, device="cuda")
     x_dev = torch.empty_like(b_dev)
     times, res = [], None
     for i in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         h.setup(z_rule, z)
-        res = h.solve(b_dev, tol, x_dev)
+        res = h.solve(b_dev, cfg["tol"], x_dev)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if i >= warmup:
             times.append(dt)
-        log(f"  step {i} ({'warmup' if i < warmup else 'timed'}): {dt * 1e3:.2f} ms, status {res['status']}, "
+        log(f"  {variant} step {i} ({'warmup' if i < warmup else 'timed'}): {dt * 1e3:.2f} ms, status {res['status']}, "
             f"sweeps {h.get_stats()['sweeps']}, relres {float(res['relres'].max()):.2e}")
     st = h.get_stats()
-    out = dict(partition_s=part_s, info=info, step_s=sum(times) / len(times), stats=st,
-               relres=float(res["relres"].max()), status=int(res["status"]), x=x_dev.clone(), z=h.get_z())
+    n_s = np.diff(cfg["sys_ptr"])
+    stop = np.where(res["iters"] > 0, res["iters"], st["sweeps"]).max(axis=0)  # sweeps each system ran
+    updates = float((n_s * stop).sum()) * cfg["b"].shape[0]
+    out = dict(partition_s=part_s, info=info, step_s=sum(times) / len(times), stats=st, iters=res["iters"],
+               relres=float(res["relres"].max()), status=int(res["status"]), x=x_dev.cpu().numpy(), z=h.get_z(),
+               updates=updates, sys_sweeps=stop)
     h.close()
+    del b_dev, x_dev
     return out
+
+
+def host_residual(cfg, x):
+    """max over (rhs, system) of ||b - A x|| / ||b|| in FP64 on the host (SciPy)."""
+    import numpy as np
+
+    As = cfg["A"].to_scipy()
+    b, sp = cfg["b"], cfg["sys_ptr"]
+    worst = 0.0
+    for c in range(b.shape[0]):
+        r = b[c] - As @ x[c]
+        for s in range(cfg["nsys"]):
+            lo, hi = sp[s], sp[s + 1]
+            worst = max(worst, float(np.linalg.norm(r[lo:hi]) / np.linalg.norm(b[c, lo:hi])))
+    return worst
+
+
+def oracle_error_fixed_sweeps(B, Zm, torch, cfg, variant, z, nsweeps=20):
+    """Element-wise error of the GPU iterate after nsweeps against the FP64 oracle's with the same
+    impedances (first right-hand side): max |x_gpu - x_oracle| / max |x_oracle|, for the variant's
+    precision and for FP64 sweeps."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    A, spec = cfg["A"], cfg["spec"]
+    b = cfg["b"][:1]
+    P = O.Partition(A, spec)
+    xo = O.Solver(P, z).run(b, nsweeps, 0, 0.0, sys_ptr=cfg["sys_ptr"])["x"][0]
+    out = {}
+    prec_head = B.VTM_FP32_IR if variant.startswith("ir") else B.VTM_FP64
+    for label, prec in (("headline_precision", prec_head), ("fp64", B.VTM_FP64)):
+        h = B.VTM(device=0, precision=prec)
+        h.evs_partition(A, spec, nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+        h.setup(B.VTM_Z_USER, z)
+        xg = h.run_sweeps(b, nsweeps)[0]
+        h.close()
+        out[label] = float(np.max(np.abs(xg - xo)) / np.max(np.abs(xo)))
+    return dict(sweeps=nsweeps, rhs=1, max_abs_err_over_max_abs_x=out)
 
 
 def _profile_fields(name, keys):
@@ -88,39 +167,12 @@ def _profile_fields(name, keys):
     return fields
 
 
-def measured_traffic(kernel, summary="sweep_traffic_c2_lognormal_1024.md"):
-    """HBM bytes per sweep of the sweep kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None."""
-    key = kernel + "-traffic-bytes-per-sweep"
+def measured_traffic(kernel, summary):
+    """HBM bytes per launch of a kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from a committed
+    counter summary, or None."""
+    key = kernel + "-traffic-bytes-per-launch"
     f = _profile_fields(summary, (key,))
     return None if f is None else float(f[key])
-
-
-def streaming_sweep_roofline(B, Zm, torch, nsweeps=48):
-    """The port-reduced sweep where it streams G from HBM: the 3D Poisson 128^3 workload (4096 RCB
-    subgraphs, 8 RHS, FP32 sweeps, learned impedances), one kernel launch per sweep.  Algorithmic
-    bytes per sweep (every packed G_k once, the port constants, the incoming and outgoing waves) over
-    the event-timed duration of the sweep launches."""
-    import gen
-
-    cfg = gen.make_config("c3")
-    h = B.VTM(device=0, precision=B.VTM_FP32_IR, check_every=nsweeps, max_sweeps=nsweeps, sweep_mode=2, persistent=1)
-    info = h.evs_partition(cfg["A"], cfg["spec"])
-    h.zmodel_load(Zm.load())
-    h.setup(B.VTM_Z_LEARNED)
-    b_dev = torch.tensor(cfg["b"], dtype=torch.float64, device="cuda")
-    x_dev = torch.empty_like(b_dev)
-    for _ in range(2):  # the first solve warms up (graph capture)
-        h.reset_waves()
-        h.solve(b_dev, 1e-30, x_dev, raise_on=())
-    st = h.get_stats()
-    h.close()
-    sweep_s = st["sweep_ms"] / 1e3 / max(st["sweeps"], 1)
-    achieved = st["bytes_per_sweep"] / sweep_s / 1e9
-    return dict(kernel="k_schur", workload=cfg["name"] + " (3D 7-point Poisson 128^3, 4096 RCB subgraphs, 8 RHS, FP32)",
-                bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                traffic=measured_traffic("k_schur", "sweep_traffic_c3_poisson_128.md"),
-                bytes_per_sweep=st["bytes_per_sweep"], avg_sweep_us=sweep_s * 1e6, sweeps_timed=int(st["sweeps"]),
-                nsub=int(info["nsub"]))
 
 
 def setup_mfma():
@@ -132,25 +184,76 @@ def setup_mfma():
         return None
     flops, us = float(f[keys[0]]), float(f[keys[1]])
     achieved = flops / (us * 1e-6) / 1e12
-    return dict(kernel="k_factor", bound="latency", mfma_dtype="f64", flops_per_launch=flops, avg_launch_us=us,
-                achieved=achieved, peak=78.6, unit="TFLOP/s", frac=achieved / 78.6)
+    return dict(kernel="k_factor", workload="c2", bound="latency", mfma_dtype="f64", flops_per_launch=flops,
+                avg_launch_us=us, achieved=achieved, peak=78.6, unit="TFLOP/s", frac=achieved / 78.6)
 
 
-def cpu_baseline(O, A, spec, b, z):
-    """Oracle (plain FP64 C, OpenMP) on a bounded sample: a few sweeps of the same system."""
+def host_cpu():
+    """CPU model, logical CPUs available to this process and physical cores of the machine."""
+    model, cores, cur = None, set(), {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if cur:
+                    cores.add((cur.get("physical id"), cur.get("core id")))
+                cur = {}
+                continue
+            k, v = (t.strip() for t in line.split(":", 1))
+            cur[k] = v
+            if k == "model name" and model is None:
+                model = v
+        if cur:
+            cores.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=len(os.sched_getaffinity(0)), physical_cores=len(cores),
+                logical_cpus=os.cpu_count())
+
+
+def cpu_baseline(O, cfg, z, target_s=15.0):
+    """The oracle (plain FP64 C, OpenMP over subgraphs) on a bounded sample of the headline workload:
+    sweeps of the same system, partition and impedances on the first right-hand side, sized to about
+    target_s seconds (its partition and factorisation excluded); unknown-updates/s = n * sweeps / t."""
+    A, spec = cfg["A"], cfg["spec"]
     P = O.Partition(A, spec)
+    t0 = time.perf_counter()
     s = O.Solver(P, z)
-    s.run(b[:1], 2, 0, 0.0)  # first touch of the factors
+    t_setup = time.perf_counter() - t0
+    b = cfg["b"][:1]
+    sp = cfg["sys_ptr"]
+    s.run(b, 2, 0, 0.0, sys_ptr=sp)  # first touch of the factors
     t0 = time.perf_counter()
-    s.run(b[:1], 20, 0, 0.0)
-    t20 = time.perf_counter() - t0
-    nsw = int(max(2, min(50000, 15.0 / max(t20 / 20, 1e-6))))  # about 15 s of oracle work
+    s.run(b, 5, 0, 0.0, sys_ptr=sp)
+    t5 = time.perf_counter() - t0
+    nsw = int(max(2, min(50000, target_s / max(t5 / 5, 1e-6))))
     t0 = time.perf_counter()
-    s.run(b[:1], nsw, 0, 0.0)
+    s.run(b, nsw, 0, 0.0, sys_ptr=sp)
     dt = time.perf_counter() - t0
-    return dict(value=A.n * nsw / dt, unit="unknown-updates/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{nsw} FP64 sweeps of the same system and partition (factorisation excluded), "
-                       f"{dt:.1f} s", time_per_sweep_s=dt / nsw)
+    out = dict(value=A.n * nsw / dt, unit="unknown-updates/s", cores=O.num_threads(), kind="oracle",
+               sample=f"{nsw} FP64 sweeps of {cfg['name']} (all {cfg['nsys']} systems, first right-hand side, "
+                      f"same partition and learned impedances; partition and factorisation excluded), {dt:.1f} s",
+               time_per_sweep_s=dt / nsw, factorisation_s=t_setup)
+    out.update(host_cpu())
+    return out
+
+
+def roofline_of(st, workload):
+    """Roofline of the sweep kernel of a solve from its own statistics: algorithmic bytes of the sweeps
+    it ran over their event-timed duration (HIP events on the library's stream around the sweep
+    launches; in per-sweep launches one sweep is one launch of the kernel)."""
+    kernel = ("k_schur_persist" if st["persistent"] else "k_schur") if st["sweep_mode"] == 2 else "k_sweep"
+    sweep_s = st["sweep_ms"] / 1e3
+    achieved = st["sweep_bytes"] / max(sweep_s, 1e-12) / 1e9
+    summary = f"sweep_traffic_{workload}.md"
+    r = dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+             frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(kernel, summary),
+             bytes_per_launch=st["sweep_bytes"] / max(st["sweeps"], 1), avg_launch_us=sweep_s * 1e6 / max(st["sweeps"], 1),
+             sweeps=int(st["sweeps"]))
+    if st["persistent"]:
+        r["bound"] = "latency"
+        r["note"] = ("one persistent launch per batch of sweeps: G_k read once per launch; the time per sweep is "
+                     "set by the latency of the wave exchange, so the HBM fraction is not its bound")
+    return r
 
 
 def run_configs(names, B, Zm, torch, out_path=None, sweep_mode=0):
@@ -270,17 +373,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--small", action="store_true", help="128^2 version of the workload (quick check)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-streaming-roofline", action="store_true",
-                    help="skip the port-reduced sweep's HBM roofline on the 3D Poisson workload")
-    ap.add_argument("--variants", default="ir_lrn,fp64_diag_sub,ir_diag",
+    ap.add_argument("--workload", default="c5", help="headline workload (c1..c5)")
+    ap.add_argument("--variants", default="ir_lrn,fp64_diag_sub",
                     help="comma list of {ir,fp64}_{lrn,match,diag,aNN}[_sub|_port]: precision, impedance rule "
                          "(learned network, impedance matching, diagonal, or NN times the diagonal), sweep mode (substitution, "
-                         "port-reduced, default chosen by the library); the first is the headline, the "
-                         "second its comparison")
+                         "port-reduced, default chosen by the library); the first is the headline, the others are "
+                         "timed beside it (one step each)")
+    ap.add_argument("--extra", default="c3,c2", help="further workloads timed on the headline variant (one step each; "
+                    "c2 also with plain FP64 VTM)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-error", action="store_true", help="skip the fixed-sweep comparison with the oracle")
     ap.add_argument("--check-every", type=int, default=0, help="0 = adaptive test placement")
-    ap.add_argument("--leaf-size", type=int, default=0, help="nested-dissection leaf size (0 = library default)")
     ap.add_argument("--configs", default="", help="instead of the benchmark line: check these workloads at full "
                     "size (comma list of c1..c5) against the oracle")
     ap.add_argument("--configs-out", default="", help="write the --configs results as JSON to this path")
@@ -315,79 +418,73 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
         del src, dst
-    cfg = gen.make_config("c2", small=args.small)
-    A, spec, tol = cfg["A"], cfg["spec"], cfg["tol"]
-    b_dev = torch.tensor(cfg["b"], dtype=torch.float64, device="cuda")
-    results = {}
     variants = args.variants.split(",")
-    zinfo = {}
-    for v in variants:
-        parts = v.split("_")
-        prec_s, zr = parts[0], parts[1]
-        mode = {"sub": 1, "port": 2}.get(parts[2], 0) if len(parts) > 2 else 0
-        precision = B.VTM_FP32_IR if prec_s == "ir" else B.VTM_FP64
-        params = None
-        if zr == "diag":
-            z_rule, z = B.VTM_Z_DIAG, None
-        elif zr == "lrn":
-            z_rule, z, params = B.VTM_Z_LEARNED, None, Zm.load()
-        elif zr == "match":
-            z_rule, z = B.VTM_Z_MATCHED, None
-        else:  # uniform multiplier alpha on the diagonal rule, e.g. a64
-            alpha = float(zr[1:])
-            hh = B.VTM(device=-1)
-            hh.evs_partition(A, spec)
-            z_rule, z = B.VTM_Z_USER, alpha * hh.get_partition()["zdiag"]
-            hh.close()
-        log(f"variant {v}")
-        results[v] = run_variant(B, torch, A, spec, b_dev, tol, precision, z_rule, z, args.steps, args.warmup,
-                                 args.check_every, 200000, mode, params, args.leaf_size)
-        zinfo[v] = results[v]["z"]
-    head = results[variants[0]]
+    log(f"workload {args.workload}")
+    cfg = gen.make_config(args.workload)
+    head = run_variant(B, Zm, torch, cfg, variants[0], args.steps, args.warmup, args.check_every)
     st = head["stats"]
-    sweeps = st["sweeps"]
-    nrhs = 1
+    others = {v: run_variant(B, Zm, torch, cfg, v, 1, 1, args.check_every) for v in variants[1:]}
+    nrhs = int(cfg["b"].shape[0])
     ms_step = head["step_s"] * 1e3
-    value = A.n * nrhs * sweeps / head["step_s"]
-    sweep_s = st["sweep_ms"] / 1e3 / max(sweeps, 1)
-    achieved = st["bytes_per_sweep"] / sweep_s / 1e9
-    kernel = ("k_schur_persist" if st["persistent"] else "k_schur") if st["sweep_mode"] == 2 else "k_sweep"
+
+    def summary(r, cfg_):
+        s_ = r["stats"]
+        return dict(time_to_tol_s=r["step_s"], time_to_tol_with_partition_s=r["step_s"] + r["partition_s"],
+                    partition_s=r["partition_s"], setup_ms=s_["setup_ms"], solve_ms=s_["solve_ms"],
+                    sweeps=int(s_["sweeps"]), sweeps_per_system_max=int(r["sys_sweeps"].max()),
+                    sweeps_per_system_min=int(r["sys_sweeps"].min()), outer_steps=s_["outer_steps"],
+                    tests=s_["checks"], relres=r["relres"], status=r["status"], sweep_mode=s_["sweep_mode"],
+                    persistent=s_["persistent"], unknown_updates_per_s=r["updates"] / r["step_s"],
+                    sweep_us=s_["sweep_ms"] * 1e3 / max(s_["sweeps"], 1))
+
     line = dict(
         metric="time to rel. residual 1e-8 (s) & unknown-updates/s; learned-Z vs plain VTM",
-        value=value, unit="unknown-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        value=head["updates"] / head["step_s"], unit="unknown-updates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f32+f64" if variants[0].startswith("ir") else "f64", data="synthetic",
-        config=dict(workload=cfg["name"] + " (2D random-conductance Laplacian lognormal(0,1) + 1e-3 I, "
-                    "1024 subgraphs of 33x33, single RHS)", n=A.n, nsub=head["info"]["nsub"], nrhs=nrhs, tol=tol,
-                    variant=variants[0], parallelism="1 GPU, all subgraphs on one device"),
-        time_to_tol_s=head["step_s"], sweeps=sweeps, setup_ms=st["setup_ms"], solve_ms=st["solve_ms"],
-        relres=head["relres"], partition_s=head["partition_s"],
-        variants={v: dict(time_to_tol_s=r["step_s"], sweeps=r["stats"]["sweeps"], setup_ms=r["stats"]["setup_ms"],
-                          sweep_us=r["stats"]["sweep_ms"] * 1e3 / max(r["stats"]["sweeps"], 1),
-                          outer_steps=r["stats"]["outer_steps"], checks=r["stats"]["checks"],
-                          relres=r["relres"], status=r["status"], persistent=r["stats"]["persistent"],
-                          sweep_mode=r["stats"]["sweep_mode"])
-                  for v, r in results.items()},
-        roofline=dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(kernel),
-                      bytes_per_sweep=st["bytes_per_sweep"], avg_sweep_us=sweep_s * 1e6,
-                      note=("one persistent launch per batch of sweeps: G_k read once per launch, the per-sweep "
-                            "time is set by the latency of the wave exchange between neighbouring workgroups, "
-                            "not by bandwidth; achieved and traffic are per sweep") if st["persistent"] else
-                           "one launch per sweep; achieved and traffic are per launch"),
+        config=dict(workload=cfg["name"] + " (" + WORKLOADS[args.workload] + ")", n=int(cfg["A"].n),
+                    nsub=head["info"]["nsub"], nsys=int(cfg["nsys"]), nrhs=nrhs, tol=cfg["tol"], variant=variants[0],
+                    parallelism="1 GPU, all subgraphs of all systems on one device"),
+        time_to_tol_s=head["step_s"], time_to_tol_with_partition_s=head["step_s"] + head["partition_s"],
+        partition_s=head["partition_s"], sweeps=int(st["sweeps"]), setup_ms=st["setup_ms"], solve_ms=st["solve_ms"],
+        relres=head["relres"],
+        value_note="unknown-updates = sum over systems of n_s x nrhs x the sweeps system s ran (it stops at its "
+                   "converged test); port-reduced sweeps update the port unknowns, whose iterates equal those "
+                   "of full local solves, so the count is of equivalent updates; time = setup + solve",
     )
-    if len(variants) > 1:
-        line["speedup_vs_" + variants[1]] = results[variants[1]]["step_s"] / head["step_s"]
+    line["host_relres"] = host_residual(cfg, head["x"])
+    line["variants"] = {variants[0]: summary(head, cfg)}
+    for v, r in others.items():
+        line["variants"][v] = summary(r, cfg)
+        line["speedup_vs_" + v] = r["step_s"] / head["step_s"]
+        line["speedup_vs_" + v + "_with_partition"] = (r["step_s"] + r["partition_s"]) / (head["step_s"] + head["partition_s"])
+    line["roofline"] = roofline_of(st, cfg["name"])
+    if not args.no_oracle_error:
+        log("fixed-sweep error against the oracle")
+        line["oracle_error_20_sweeps"] = oracle_error_fixed_sweeps(B, Zm, torch, cfg, variants[0], head["z"])
+    extra = {}
+    for w in [e for e in args.extra.split(",") if e]:
+        log(f"extra workload {w}")
+        c = gen.make_config(w)
+        r = run_variant(B, Zm, torch, c, variants[0], 1, 1, args.check_every)
+        e = summary(r, c)
+        e.update(workload=c["name"] + " (" + WORKLOADS[w] + ")", host_relres=host_residual(c, r["x"]),
+                 roofline=roofline_of(r["stats"], c["name"]))
+        if not args.no_oracle_error:
+            e["oracle_error_20_sweeps"] = oracle_error_fixed_sweeps(B, Zm, torch, c, variants[0], r["z"])
+        if w == "c2":
+            p = run_variant(B, Zm, torch, c, "fp64_diag_sub", 1, 1, args.check_every)
+            e["fp64_diag_sub"] = summary(p, c)
+            e["speedup_vs_fp64_diag_sub"] = p["step_s"] / r["step_s"]
+        extra[w] = e
+    line["extra_workloads"] = extra
     line["setup_mfma"] = setup_mfma()
-    if not args.no_streaming_roofline:
-        log("streaming sweep roofline (3D Poisson 128^3, 8 RHS)")
-        line["streaming_sweep_roofline"] = streaming_sweep_roofline(B, Zm, torch)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 
-        z = zinfo[variants[0]]
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(O, A, spec, cfg["b"], z)
+        line["cpu_baseline"] = cpu_baseline(O, cfg, head["z"])
+    torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
 
 

@@ -50,7 +50,7 @@ def c3(small: bool = False):
     """3D 7-point Poisson on 128^3, seeded RCB into 4096 boxes, 8 RHS, seed 3."""
     nx, levels = (32, 6) if small else (128, 12)
     A = S.poisson3d_dirichlet(nx)
-    spec = dict(kind="rcb", dims=(nx, nx, nx), levels=levels, seed=3, min_size=200.0, max_size=1100.0)
+    spec = dict(kind="rcb", dims=(nx, nx, nx), levels=levels, seed=3, min_size=300.0, max_size=700.0)
     return _single(A, spec, 8, 3, 1e-8, f"c3_poisson3d_{nx}^3_rcb{2 ** levels}")
 
 

@@ -107,9 +107,10 @@ typedef struct {
  *          covers [I*m, (I+1)*m], the last tile ends at dims-1.  Ids row-major.
  *   RCB  : seeded random recursive coordinate bisection of the vertex grid into
  *          2^levels boxes sharing cut planes; longest axis (ties: lowest) cut at
- *          lo + (len*q + 50)/100, q = 46 + splitmix64(state) mod 9, depth-first
+ *          lo + (len*q + 50)/100, q = 49 + splitmix64(state) mod 3, depth-first
  *          pre-order; accepted iff every box's owned size sum 1/|S(v)| lies in
- *          [min_size, max_size].
+ *          [min_size, max_size], else redrawn from seed + 1, ... (64 seeds; the seed
+ *          used is reported in vtm_partition_info.rcb_seed).
  *   GRAPH: per block of vertices (an independent system), point RCB on coords
  *          into block_parts[b] owners; every cut edge (u,v) with
  *          owner(u) < owner(v) adds owner(v) to S(u).
@@ -154,6 +155,7 @@ typedef struct {
     int32_t max_local;       /* largest |M_j| */
     int32_t nsys;            /* independent systems */
     int64_t factor_entries;  /* stored factor entries over all subgraphs */
+    uint64_t rcb_seed;       /* RCB: the seed actually used (seed, seed + 1, ... until the bounds hold) */
 } vtm_partition_info;
 
 typedef struct {
@@ -169,6 +171,8 @@ typedef struct {
     double flops_per_sweep;  /* substitution: 4 * nrhs * lower-factor entries; port-reduced: 2 * nrhs * G entries */
     int32_t sweep_mode;      /* mode of the last solve or vtm_run_sweeps: 1 substitution, 2 port-reduced */
     int32_t persistent;      /* 1 if the last solve or run ran its sweeps in persistent launches */
+    double sweep_bytes;      /* last solve: algorithmic bytes of all its sweeps, counting only the systems
+                                still sweeping (done mask) and G once per persistent launch */
 } vtm_stats;
 
 /* Create a handle bound to options->device; NULL options = defaults. */
@@ -223,6 +227,27 @@ vtm_status vtm_get_partition(vtm_handle h, int64_t *s_ptr, int32_t *s_idx, int64
 vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl);
 
 /*
+ * Coupled VTLs (Section 7.2, Theorem 7.1): the local preconditioner Z_j of (5.6)-(5.8) is an SPD matrix
+ * over the ports of a subgraph instead of a diagonal one.  Z is given as a symmetric matrix over the
+ * VTLs: diagonal z_vtl[nvtl] (> 0) and the off-diagonal entries Z[vtl_a[e]][vtl_b[e]] = z_ab[e],
+ * e < ncouple, each unordered pair at most once (host arrays).  Coupled VTLs must join the same two
+ * subgraphs; Z is then block diagonal over groups of VTLs between one pair of subgraphs, and both
+ * subgraphs of a group use its block, in their own port order, as their Z_j, so that the twins of
+ * (5.6) see the same matrix.  Every block must be positive definite (Theorem 7.1's condition).
+ * The local matrix of (5.8) gets the block Z_j^{-1} on the group's port vertices (which may add
+ * entries to a local sparsity pattern; the symbolic analysis is redone), every sweep adds
+ * Z_j^{-1} a to the right side, and the outgoing waves stay o = u - Z_j w = 2u - a with
+ * w = Z_j^{-1}(a - u).  Sweeps run as substitution sweeps (no port Green's functions), in the
+ * handle's precision; vtm_solve / vtm_run_sweeps / waves calls work as after vtm_setup.  A later
+ * vtm_setup returns to diagonal impedances (and the original analysis).  vtm_get_partition keeps
+ * returning the EVS pieces.  vtm_batch_solve does not take coupled members.
+ * Errors: VTM_ERR_STATE (no partition), VTM_ERR_INVALID (an entry out of range or non-finite, coupled
+ * VTLs between different subgraph pairs, a block not positive definite), VTM_ERR_NOT_SPD.
+ */
+vtm_status vtm_setup_coupled(vtm_handle h, const double *z_vtl, int64_t ncouple, const int64_t *vtl_a,
+                             const int64_t *vtl_b, const double *z_ab);
+
+/*
  * Definition 7.1: the input impedance of every port, i.e. its potential for a unit inflow current
  * there, with every other port of its subgraph terminated by its current characteristic impedance
  * (as Z grows the terminations vanish and this tends to the definition's value with the other ports
@@ -242,13 +267,34 @@ vtm_status vtm_input_impedance(vtm_handle h, double *r_port);
  * (tested every check_every sweeps).  FP32_IR runs FP32 sweeps on the
  * correction equation and refines x in FP64.
  *   b: n x nrhs (ld >= n), host or device;  x: n x nrhs output (ldx >= n)
- *   iters[nrhs*nsys]: first passing sweep per (rhs, system), -1 if none
- *   relres[nrhs*nsys]: last measured relative residual
+ *   iters[nrhs*nsys]: first passing sweep per (rhs, system), -1 if none; index c * nsys + s
+ *   relres[nrhs*nsys]: relative residual of the returned x
+ * With several systems (vtm_partition_spec.nsys > 1) a system whose right-hand sides all pass
+ * stops sweeping (its x is kept) while the others go on.  Test placement (check_every = 0)
+ * depends on the residual history only, so sweep counts repeat from run to run.
  * Returns VTM_ERR_NOT_CONVERGED (with outputs written) if max_sweeps is hit,
  * VTM_ERR_DIVERGED on NaN or growth.
  */
 vtm_status vtm_solve(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
                      int32_t *iters, double *relres);
+
+/*
+ * Many independent systems (the problem statement of Section 3 for each handle) solved together:
+ * the members' subgraphs run in one launch per sweep, each member's systems keep their own
+ * convergence test (Table 1 step 6), and a system whose right-hand sides all pass stops sweeping
+ * while the others go on (done mask).  Members must be set up, on one device, with one precision;
+ * the batch runs with the options and on the stream of hs[0].  The first call for a list of members
+ * (and the first after any member's vtm_setup) builds the batch: it copies the members'
+ * partitions, analyses and impedances into a context owned by hs[0] and factors them there again
+ * (the members' own factors and waves are not used or changed); later calls reuse it.
+ *   hs[count]; b[i], x[i]: n_i x nrhs blocks (host or device) with leading dimensions ldb[i], ldx[i]
+ *   iters[i], relres[i] (either array or any entry may be NULL): [nrhs * nsys_i] as in vtm_solve
+ * Every member's statistics become those of the batch solve.  Errors as vtm_solve, and
+ * VTM_ERR_INVALID for mixed devices or precisions, VTM_ERR_STATE for a member not set up.
+ */
+vtm_status vtm_batch_solve(vtm_handle *hs, int32_t count, const double *const *b, int32_t nrhs, const int64_t *ldb,
+                           double tol, double *const *x, const int64_t *ldx, int32_t *const *iters,
+                           double *const *relres);
 
 /*
  * Run exactly nsweeps FP64-or-FP32 sweeps (handle precision, no refinement)
@@ -291,8 +337,9 @@ vtm_status vtm_set_waves(vtm_handle h, const double *a, int32_t nrhs);
 
 /* Features of every VTL (host array [nvtl][VTM_NUM_FEATURES]); works on host-only handles. */
 vtm_status vtm_zfeatures(vtm_handle h, float *out);
-/* Load model parameters (host, copied); enables VTM_Z_LEARNED. */
-vtm_status vtm_zmodel_load(vtm_handle h, const float *params);
+/* Load model parameters: weights points to bytes = VTM_ZMODEL_PARAMS * 4 bytes (host, copied), the
+ * float blob above; another size or a non-finite value gives VTM_ERR_INVALID.  Enables VTM_Z_LEARNED. */
+vtm_status vtm_zmodel_load(vtm_handle h, const void *weights, size_t bytes);
 /* Impedance per VTL used by the last vtm_setup (host array [nvtl]). */
 vtm_status vtm_get_z(vtm_handle h, double *z);
 

@@ -43,11 +43,15 @@ def lib():
         L.or_get.argtypes = [P] + [P] * 16
         L.or_setup.restype = C.c_int
         L.or_setup.argtypes = [P, P, C.POINTER(C.c_void_p)]
+        L.or_setup_coupled.restype = C.c_int
+        L.or_setup_coupled.argtypes = [P, P, C.c_int64, P, P, P, C.POINTER(C.c_void_p)]
         L.or_solver_free.argtypes = [P]
         L.or_run.restype = C.c_int64
         L.or_run.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_double, C.c_int32, P, P, P, P, P, C.c_int64]
         L.or_run_local.restype = C.c_int64
         L.or_run_local.argtypes = [P, P, P, C.c_int64, P]
+        L.or_rcb_seed.restype = C.c_int64
+        L.or_rcb_seed.argtypes = [P]
         L.or_num_threads.restype = C.c_int
         L.or_splitmix64_seq.argtypes = [C.c_uint64, C.c_int32, P]
         _lib = L
@@ -103,6 +107,7 @@ class Partition:
         if rc != 0:
             raise OracleError(rc)
         self._h = h
+        self.rcb_seed = int(L.or_rcb_seed(h))
         sz = np.zeros(7, dtype=np.int64)
         L.or_sizes(h, _p(sz))
         n, nsub, nsplit, nloc, nvtl, nports, ns = (int(v) for v in sz)
@@ -147,15 +152,25 @@ class Partition:
 
 
 class Solver:
-    """Port-augmented local factors for a given Z per VTL, and the VTM iteration."""
+    """Port-augmented local factors for a given Z per VTL, and the VTM iteration.
 
-    def __init__(self, part: Partition, z_vtl: np.ndarray):
+    coupling = (l1, l2, zc): off-diagonal entries Z[l1[e]][l2[e]] = zc[e] of a symmetric impedance
+    matrix over the VTLs (coupled VTLs, Section 7.2), z_vtl its diagonal; coupled VTLs join the same
+    two subgraphs."""
+
+    def __init__(self, part: Partition, z_vtl: np.ndarray, coupling=None):
         self.part = part
         z = np.ascontiguousarray(z_vtl, dtype=np.float64)
         if z.shape[0] != part.nvtl:
             raise ValueError("z_vtl must have one value per VTL")
         h = C.c_void_p()
-        rc = lib().or_setup(part._h, _p(z), C.byref(h))
+        if coupling is not None:
+            l1 = np.ascontiguousarray(coupling[0], dtype=np.int64)
+            l2 = np.ascontiguousarray(coupling[1], dtype=np.int64)
+            zc = np.ascontiguousarray(coupling[2], dtype=np.float64)
+            rc = lib().or_setup_coupled(part._h, _p(z), len(l1), _p(l1), _p(l2), _p(zc), C.byref(h))
+        else:
+            rc = lib().or_setup(part._h, _p(z), C.byref(h))
         self._h = h
         if rc != 0:
             raise OracleError(rc)

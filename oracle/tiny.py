@@ -7,6 +7,8 @@ the pieces of the method that the paper works through by hand:
   * the port-augmented local systems (5.4), (5.5) of Example 5.1 and the VTM
     iteration of Table 1,
   * the input impedance of a port (Definition 7.1, Example 7.1),
+  * the iteration with coupled VTLs (Section 7.2), through the unreduced block
+    system (5.7),
   * a brute-force dense Cholesky solve of the whole system.
 """
 from __future__ import annotations
@@ -97,6 +99,53 @@ class SplitSystem:
                 cnt[g] += 1
             hist.append(xbar / cnt)
         return np.array(hist), u, w, xs
+
+
+    def vtm_coupled(self, Zv, sweeps):
+        """VTM with coupled VTLs (Section 7.2): Zv is a symmetric SPD matrix over the VTLs, block diagonal
+        over VTLs that join the same two subgraphs; subgraph k uses Z_k = Zv restricted to its ports'
+        VTLs, in its port order.  Every sweep solves the block system (5.7) of each subgraph as written,
+
+            [ A_k  -E ] [x]   [ b_k                  ]
+            [ E^T  Z_k] [w] = [ u_twin - Z_k w_twin  ],
+
+        with E the unit columns of the port vertices, so Z_k is never inverted.  Returns the merged
+        solution history and the final (u, w) per VTL end."""
+        Zv = np.asarray(Zv, dtype=np.float64)
+        nl = len(self.vtls)
+        u = np.zeros((nl, 2))
+        w = np.zeros((nl, 2))
+        plist = self.ports(np.diag(Zv))
+        hist = []
+        for _ in range(sweeps):
+            un = np.zeros_like(u)
+            wn = np.zeros_like(w)
+            xs = []
+            for k, pc in enumerate(self.pieces):
+                nk, m = pc["A"].shape[0], len(plist[k])
+                ls = [l for _, l, _, _ in plist[k]]
+                Zk = Zv[np.ix_(ls, ls)]
+                E = np.zeros((nk, m))
+                for j, (i, _, _, _) in enumerate(plist[k]):
+                    E[i, j] = 1.0
+                M = np.block([[pc["A"], -E], [E.T, Zk]])
+                ut = np.array([u[l, 1 - side] for _, l, _, side in plist[k]])
+                wt = np.array([w[l, 1 - side] for _, l, _, side in plist[k]])
+                sol = np.linalg.solve(M, np.concatenate([pc["b"], ut - Zk @ wt]))
+                xk, wk = sol[:nk], sol[nk:]
+                xs.append(xk)
+                for j, (i, l, _, side) in enumerate(plist[k]):
+                    un[l, side] = xk[i]
+                    wn[l, side] = wk[j]
+            u, w = un, wn
+            xbar = np.zeros(self.n)
+            cnt = np.zeros(self.n)
+            for k, pc in enumerate(self.pieces):
+                g = np.asarray(pc["glob"])
+                xbar[g] += xs[k]
+                cnt[g] += 1
+            hist.append(xbar / cnt)
+        return np.array(hist), u, w
 
 
 def example_41():

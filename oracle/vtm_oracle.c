@@ -22,6 +22,8 @@
  *      Example 5.1, where both sides use iteration k-1 data).
  *   3. The stopping test of Table 1 step 6, read as the relative residual of
  *      the merged potentials (mean over the children of each vertex).
+ *   4. Coupled VTLs (Section 7.2, Theorem 7.1): Z_j an SPD matrix over the
+ *      ports of a subgraph instead of a diagonal one (or_setup_coupled).
  *
  * Readings where the paper leaves a choice (documented with the design):
  *   - membership rules GRID / RCB / GRAPH / USER and the FACE pairing rule;
@@ -76,7 +78,7 @@ typedef struct {
     int64_t *port_vtl;     /* VTL of each port */
     int32_t *port_lidx;    /* local index of the port vertex in its subdomain */
     double *zdiag;         /* Z = 1/a_vv per VTL */
-    int32_t rcb_seed_used;
+    int64_t rcb_seed_used;
 } or_part;
 
 /* ---------------------------------------------------------------- utilities */
@@ -163,8 +165,10 @@ static int member_grid(or_part *p, const int32_t dims[3], const int32_t parts[3]
 /* Seeded random recursive coordinate bisection of the vertex grid into boxes
  * that share their cut planes.  At each node (depth-first, pre-order) the
  * longest axis (ties: lowest axis) with length len = hi - lo is cut at
- * c = lo + (len * q + 50) / 100, q = 46 + (splitmix64 mod 9) percent; both
- * children contain plane c.  Leaves are numbered in visiting order. */
+ * c = lo + (len * q + 50) / 100, q = 49 + (splitmix64 mod 3) percent; both
+ * children contain plane c.  Leaves are numbered in visiting order.  The
+ * partition is accepted when every box's owned size lies in the bounds;
+ * otherwise it is drawn again from seed + 1, seed + 2, ... (64 seeds). */
 typedef struct { int32_t lo[3], hi[3]; } or_box;
 
 static int rcb_rec(or_box b, int depth, int levels, uint64_t *st, or_box *leaves, int32_t *nleaf) {
@@ -174,7 +178,7 @@ static int rcb_rec(or_box b, int depth, int levels, uint64_t *st, or_box *leaves
     int32_t len = b.hi[ax] - b.lo[ax];
     if (len < 2) return OR_ERR_PARTITION;
     uint64_t z = splitmix64(st);
-    int32_t q = 46 + (int32_t)(z % 9);
+    int32_t q = 49 + (int32_t)(z % 3);
     int32_t c = b.lo[ax] + (int32_t)(((int64_t)len * q + 50) / 100);
     or_box l = b, r = b;
     l.hi[ax] = c;
@@ -184,7 +188,8 @@ static int rcb_rec(or_box b, int depth, int levels, uint64_t *st, or_box *leaves
     return rcb_rec(r, depth + 1, levels, st, leaves, nleaf);
 }
 
-static int member_rcb(or_part *p, const int32_t dims[3], int levels, uint64_t seed, double min_size, double max_size) {
+static int member_rcb_seed(or_part *p, const int32_t dims[3], int levels, uint64_t seed, double min_size,
+                           double max_size) {
     int64_t nv = (int64_t)dims[0] * dims[1] * dims[2];
     if (nv != p->n || levels < 0 || levels > 20) return OR_ERR_INVALID;
     int32_t nleaf = 0;
@@ -229,6 +234,17 @@ static int member_rcb(or_part *p, const int32_t dims[3], int levels, uint64_t se
     free(cnt);
     free(leaves);
     return rc;
+}
+
+static int member_rcb(or_part *p, const int32_t dims[3], int levels, uint64_t seed, double min_size, double max_size) {
+    for (int t = 0; t < 64; t++) {
+        int rc = member_rcb_seed(p, dims, levels, seed + (uint64_t)t, min_size, max_size);
+        if (rc == OR_OK) { p->rcb_seed_used = (int64_t)(seed + (uint64_t)t); return OR_OK; }
+        free(p->s_ptr); p->s_ptr = NULL;
+        free(p->s_idx); p->s_idx = NULL;
+        if (rc != OR_ERR_PARTITION) return rc;
+    }
+    return OR_ERR_PARTITION;
 }
 
 /* ----------------------------------------------------- membership: GRAPH */
@@ -353,7 +369,7 @@ int or_partition(int64_t n, const int64_t *rowptr, const int32_t *col, const dou
 
     switch (kind) {
         case OR_GRID: rc = member_grid(p, dims, parts); break;
-        case OR_RCB: rc = member_rcb(p, dims, levels, seed, min_size, max_size); p->rcb_seed_used = (int32_t)seed; break;
+        case OR_RCB: rc = member_rcb(p, dims, levels, seed, min_size, max_size); break;
         case OR_GRAPH: rc = member_graph(p, coords, dim, nblocks, bstart, bcount, bparts); break;
         case OR_USER:
             p->nsub = user_nsub;
@@ -594,6 +610,9 @@ int or_partition(int64_t n, const int64_t *rowptr, const int32_t *col, const dou
     return OR_OK;
 }
 
+/* RCB: the seed whose boxes met the owned-size bounds (0 for other membership rules). */
+int64_t or_rcb_seed(const or_part *p) { return p->rcb_seed_used; }
+
 /* sizes: n, nsub, n_split, local nnz, nvtl, nports, s_idx size */
 void or_sizes(const or_part *p, int64_t *out) {
     out[0] = p->n;
@@ -639,7 +658,14 @@ typedef struct {
     double *env;
 } or_factor;
 
-static int factor_local(const or_part *p, int32_t k, const double *zport, or_factor *F) {
+/* Coupled VTLs (Section 7.2): per port p, the ports q of the same subgraph whose VTLs are coupled
+ * with p's (p itself included), with (Z_j^{-1})_pq and (Z_j)_pq; cptr == NULL when Z is diagonal. */
+typedef struct {
+    int64_t *cptr, *cq;
+    double *cy, *cz;
+} or_coupling;
+
+static int factor_local(const or_part *p, int32_t k, const double *zport, const or_coupling *cp, or_factor *F) {
     int64_t base = p->loc_ptr[k], nk = p->loc_ptr[k + 1] - base;
     F->nk = nk;
     F->fnz = malloc(sizeof(int64_t) * nk);
@@ -649,6 +675,12 @@ static int factor_local(const or_part *p, int32_t k, const double *zport, or_fac
         for (int64_t e = p->lrp[base + i]; e < p->lrp[base + i + 1]; e++) if (p->lcol[e] < f) f = p->lcol[e];
         F->fnz[i] = f;
     }
+    if (cp->cptr)  /* the dense port blocks Z_j^{-1} widen the envelope */
+        for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++)
+            for (int64_t e = cp->cptr[q]; e < cp->cptr[q + 1]; e++) {
+                int64_t i = p->port_lidx[q], j = p->port_lidx[cp->cq[e]];
+                if (j < F->fnz[i]) F->fnz[i] = j;
+            }
     F->eptr[0] = 0;
     for (int64_t i = 0; i < nk; i++) F->eptr[i + 1] = F->eptr[i] + (i - F->fnz[i] + 1);
     F->env = calloc(F->eptr[nk], sizeof(double));
@@ -659,9 +691,17 @@ static int factor_local(const or_part *p, int32_t k, const double *zport, or_fac
             int64_t j = p->lcol[e];
             if (j <= i) F->env[F->eptr[i] + (j - F->fnz[i])] = p->lval[e];
         }
-    for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) {
-        int64_t i = p->port_lidx[q];
-        F->env[F->eptr[i] + (i - F->fnz[i])] += 1.0 / zport[q];
+    if (cp->cptr) {  /* K_k = A~_k + R^T Z_j^{-1} R: the whole port block, lower part */
+        for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++)
+            for (int64_t e = cp->cptr[q]; e < cp->cptr[q + 1]; e++) {
+                int64_t i = p->port_lidx[q], j = p->port_lidx[cp->cq[e]];
+                if (j <= i) F->env[F->eptr[i] + (j - F->fnz[i])] += cp->cy[e];
+            }
+    } else {
+        for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) {
+            int64_t i = p->port_lidx[q];
+            F->env[F->eptr[i] + (i - F->fnz[i])] += 1.0 / zport[q];
+        }
     }
     /* row-by-row Cholesky inside the envelope */
     for (int64_t i = 0; i < nk; i++) {
@@ -704,7 +744,23 @@ typedef struct {
     or_part *p;
     or_factor *f;
     double *zport;  /* Z at each port (equal at both ends of a VTL) */
+    or_coupling c;  /* coupled VTLs, or all NULL */
 } or_solver;
+
+static int factor_all(or_solver *s) {
+    int rc = OR_OK;
+    const or_part *p = s->p;
+    s->f = calloc(p->nsub, sizeof(or_factor));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t k = 0; k < p->nsub; k++) {
+        int r = factor_local(p, k, s->zport, &s->c, &s->f[k]);
+        if (r) {
+#pragma omp critical
+            rc = r;
+        }
+    }
+    return rc;
+}
 
 int or_setup(or_part *p, const double *z_vtl, or_solver **out) {
     *out = NULL;
@@ -714,25 +770,135 @@ int or_setup(or_part *p, const double *z_vtl, or_solver **out) {
     s->p = p;
     s->zport = malloc(sizeof(double) * (np + 1));
     for (int64_t q = 0; q < np; q++) s->zport[q] = z_vtl[p->port_vtl[q]];
-    s->f = calloc(p->nsub, sizeof(or_factor));
-    int rc = OR_OK;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t k = 0; k < p->nsub; k++) {
-        int r = factor_local(p, k, s->zport, &s->f[k]);
-        if (r) {
-#pragma omp critical
-            rc = r;
-        }
+    int rc = factor_all(s);
+    *out = s;
+    return rc;
+}
+
+/* Union-find root with path halving. */
+static int64_t uf_root(int64_t *par, int64_t x) {
+    while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+    return x;
+}
+
+/*
+ * Coupled VTLs (Section 7.2, Theorem 7.1): the impedance is a symmetric matrix Z over the VTLs with
+ * diagonal z_vtl and the off-diagonal entries Z[l1[e]][l2[e]] = Z[l2[e]][l1[e]] = zc[e] (each pair
+ * given once).  Coupled VTLs must join the same two subgraphs; Z is then block diagonal over the
+ * groups of coupled VTLs, and both subgraphs of a group use the group's block as their Z_j (in the
+ * order of their own ports, so that the twins see the same matrix).  Every block must be SPD.  The
+ * blocks are inverted here by a plain Cholesky factorisation and unit solves.
+ */
+int or_setup_coupled(or_part *p, const double *z_vtl, int64_t ncpl, const int64_t *l1, const int64_t *l2,
+                     const double *zc, or_solver **out) {
+    *out = NULL;
+    const int64_t nl = p->nvtl, np = 2 * nl;
+    for (int64_t l = 0; l < nl; l++) if (!(z_vtl[l] > 0.0) || !isfinite(z_vtl[l])) return OR_ERR_INVALID;
+    for (int64_t e = 0; e < ncpl; e++) {
+        if (l1[e] < 0 || l1[e] >= nl || l2[e] < 0 || l2[e] >= nl || l1[e] == l2[e] || !isfinite(zc[e]))
+            return OR_ERR_INVALID;
+        if (p->vtl_k[l1[e]] != p->vtl_k[l2[e]] || p->vtl_k2[l1[e]] != p->vtl_k2[l2[e]]) return OR_ERR_INVALID;
     }
+    /* groups of coupled VTLs; member lists in ascending VTL order */
+    int64_t *par = malloc(sizeof(int64_t) * (nl + 1));
+    for (int64_t l = 0; l < nl; l++) par[l] = l;
+    for (int64_t e = 0; e < ncpl; e++) {
+        int64_t a = uf_root(par, l1[e]), b = uf_root(par, l2[e]);
+        if (a != b) par[a < b ? b : a] = a < b ? a : b;
+    }
+    int64_t *root = malloc(sizeof(int64_t) * (nl + 1)), *gsz = calloc(nl + 1, sizeof(int64_t));
+    int64_t *gpos = malloc(sizeof(int64_t) * (nl + 1));  /* index of a VTL inside its group */
+    for (int64_t l = 0; l < nl; l++) { root[l] = uf_root(par, l); gpos[l] = gsz[root[l]]++; }
+    int64_t *gptr = calloc(nl + 1, sizeof(int64_t)), *gmem = malloc(sizeof(int64_t) * (nl + 1));
+    for (int64_t l = 0; l < nl; l++) gptr[l + 1] = gptr[l] + gsz[l];
+    for (int64_t l = 0; l < nl; l++) gmem[gptr[root[l]] + gpos[l]] = l;
+    /* the two ports of every VTL: end 0 in vtl_k, end 1 in vtl_k2 */
+    int64_t *vport = malloc(sizeof(int64_t) * (np + 1));
+    for (int32_t k = 0; k < p->nsub; k++)
+        for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) {
+            int64_t l = p->port_vtl[q];
+            vport[2 * l + (k == p->vtl_k[l] ? 0 : 1)] = q;
+        }
+    /* dense Z and Y = Z^{-1} per group (groups indexed by their root), entries kept per VTL pair */
+    int64_t *yoff = calloc(nl + 1, sizeof(int64_t));
+    int64_t tot = 0;
+    for (int64_t r = 0; r < nl; r++) { yoff[r] = tot; tot += gsz[r] * gsz[r]; }
+    double *Zd = calloc(tot + 1, sizeof(double)), *Yd = calloc(tot + 1, sizeof(double));
+    for (int64_t l = 0; l < nl; l++) Zd[yoff[root[l]] + gpos[l] * gsz[root[l]] + gpos[l]] = z_vtl[l];
+    for (int64_t e = 0; e < ncpl; e++) {
+        int64_t r = root[l1[e]], m = gsz[r], i = gpos[l1[e]], j = gpos[l2[e]];
+        Zd[yoff[r] + i * m + j] = zc[e];
+        Zd[yoff[r] + j * m + i] = zc[e];
+    }
+    int rc = OR_OK;
+    for (int64_t r = 0; r < nl && rc == OR_OK; r++) {
+        int64_t m = gsz[r];
+        if (m == 0) continue;
+        double *Zg = Zd + yoff[r], *Yg = Yd + yoff[r];
+        double *L = calloc(m * m, sizeof(double)), *col = malloc(sizeof(double) * m);
+        for (int64_t i = 0; i < m && rc == OR_OK; i++)  /* Z = L L^T */
+            for (int64_t j = 0; j <= i; j++) {
+                double acc = Zg[i * m + j];
+                for (int64_t t = 0; t < j; t++) acc -= L[i * m + t] * L[j * m + t];
+                if (i == j) {
+                    if (!(acc > 0.0)) { rc = OR_ERR_INVALID; break; }
+                    L[i * m + i] = sqrt(acc);
+                } else {
+                    L[i * m + j] = acc / L[j * m + j];
+                }
+            }
+        for (int64_t c = 0; c < m && rc == OR_OK; c++) {  /* column c of Z^{-1}: L L^T y = e_c */
+            for (int64_t i = 0; i < m; i++) {
+                double acc = i == c ? 1.0 : 0.0;
+                for (int64_t t = 0; t < i; t++) acc -= L[i * m + t] * col[t];
+                col[i] = acc / L[i * m + i];
+            }
+            for (int64_t i = m - 1; i >= 0; i--) {
+                double acc = col[i];
+                for (int64_t t = i + 1; t < m; t++) acc -= L[t * m + i] * col[t];
+                col[i] = acc / L[i * m + i];
+            }
+            for (int64_t i = 0; i < m; i++) Yg[i * m + c] = col[i];
+        }
+        free(L);
+        free(col);
+    }
+    or_solver *s = NULL;
+    if (rc == OR_OK) {
+        s = calloc(1, sizeof(or_solver));
+        s->p = p;
+        s->zport = malloc(sizeof(double) * (np + 1));
+        for (int64_t q = 0; q < np; q++) s->zport[q] = z_vtl[p->port_vtl[q]];
+        /* per port: the ports of its own subgraph on the VTLs of its group, in group order */
+        s->c.cptr = calloc(np + 1, sizeof(int64_t));
+        for (int64_t q = 0; q < np; q++) s->c.cptr[q + 1] = s->c.cptr[q] + gsz[root[p->port_vtl[q]]];
+        s->c.cq = malloc(sizeof(int64_t) * (s->c.cptr[np] + 1));
+        s->c.cy = malloc(sizeof(double) * (s->c.cptr[np] + 1));
+        s->c.cz = malloc(sizeof(double) * (s->c.cptr[np] + 1));
+        for (int64_t q = 0; q < np; q++) {
+            int64_t l = p->port_vtl[q], r = root[l], m = gsz[r], i = gpos[l];
+            int end = vport[2 * l] == q ? 0 : 1;
+            for (int64_t j = 0; j < m; j++) {
+                int64_t e = s->c.cptr[q] + j, lj = gmem[gptr[r] + j];
+                s->c.cq[e] = vport[2 * lj + end];
+                s->c.cy[e] = Yd[yoff[r] + i * m + j];
+                s->c.cz[e] = Zd[yoff[r] + i * m + j];
+            }
+        }
+        rc = factor_all(s);
+    }
+    free(par); free(root); free(gsz); free(gpos); free(gptr); free(gmem); free(vport); free(yoff); free(Zd); free(Yd);
     *out = s;
     return rc;
 }
 
 void or_solver_free(or_solver *s) {
     if (!s) return;
-    for (int32_t k = 0; k < s->p->nsub; k++) { free(s->f[k].fnz); free(s->f[k].eptr); free(s->f[k].env); }
+    if (s->f)
+        for (int32_t k = 0; k < s->p->nsub; k++) { free(s->f[k].fnz); free(s->f[k].eptr); free(s->f[k].env); }
     free(s->f);
     free(s->zport);
+    free(s->c.cptr); free(s->c.cq); free(s->c.cy); free(s->c.cz);
     free(s);
 }
 
@@ -757,6 +923,47 @@ static void merged_residual(const or_part *p, const double *xloc, const double *
         }
         relres[s] = sqrt(rr) / sqrt(bb);
     }
+}
+
+/* One subgraph's part of a sweep: right side of (5.8), local solve, port currents and outgoing
+ * waves (right side of (5.6)).  Diagonal Z:
+ *   rhs += (a_p / Z_p) e_v(p);  w_p = (a_p - u_p) / Z_p;  o_p = u_p - Z_p w_p
+ * coupled VTLs (Z_j a matrix over the subgraph's ports):
+ *   rhs += R^T Z_j^{-1} a;  w = Z_j^{-1} (a - u);  o = u - Z_j w */
+static void sweep_local(const or_solver *s, int32_t k, const double *b, const double *a, double *xk, double *o) {
+    const or_part *p = s->p;
+    int64_t base = p->loc_ptr[k], nk = p->loc_ptr[k + 1] - base;
+    for (int64_t i = 0; i < nk; i++) {
+        int64_t v = p->loc_vtx[base + i];
+        xk[i] = b[v] / (double)(p->s_ptr[v + 1] - p->s_ptr[v]);  /* source split */
+    }
+    const int64_t q0 = p->port_ptr[k], q1 = p->port_ptr[k + 1];
+    if (!s->c.cptr) {
+        for (int64_t q = q0; q < q1; q++) xk[p->port_lidx[q]] += a[q] / s->zport[q];
+        solve_local(&s->f[k], xk);
+        for (int64_t q = q0; q < q1; q++) {
+            double u = xk[p->port_lidx[q]];
+            double w = (a[q] - u) / s->zport[q];
+            o[q] = u - s->zport[q] * w;
+        }
+        return;
+    }
+    const or_coupling *c = &s->c;
+    for (int64_t q = q0; q < q1; q++)
+        for (int64_t e = c->cptr[q]; e < c->cptr[q + 1]; e++) xk[p->port_lidx[q]] += c->cy[e] * a[c->cq[e]];
+    solve_local(&s->f[k], xk);
+    double *w = malloc(sizeof(double) * (q1 - q0 + 1));
+    for (int64_t q = q0; q < q1; q++) {
+        double acc = 0.0;
+        for (int64_t e = c->cptr[q]; e < c->cptr[q + 1]; e++) acc += c->cy[e] * (a[c->cq[e]] - xk[p->port_lidx[c->cq[e]]]);
+        w[q - q0] = acc;
+    }
+    for (int64_t q = q0; q < q1; q++) {
+        double acc = xk[p->port_lidx[q]];
+        for (int64_t e = c->cptr[q]; e < c->cptr[q + 1]; e++) acc -= c->cz[e] * w[c->cq[e] - q0];
+        o[q] = acc;
+    }
+    free(w);
 }
 
 /*
@@ -786,21 +993,7 @@ int64_t or_run(or_solver *s, const double *b, double *a, int64_t max_sweeps, int
     while (sweep < max_sweeps) {
         sweep++;
 #pragma omp parallel for schedule(dynamic, 1)
-        for (int32_t k = 0; k < p->nsub; k++) {
-            int64_t base = p->loc_ptr[k], nk = p->loc_ptr[k + 1] - base;
-            double *xk = xloc + base;
-            for (int64_t i = 0; i < nk; i++) {
-                int64_t v = p->loc_vtx[base + i];
-                xk[i] = b[v] / (double)(p->s_ptr[v + 1] - p->s_ptr[v]);  /* source split */
-            }
-            for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) xk[p->port_lidx[q]] += a[q] / s->zport[q];
-            solve_local(&s->f[k], xk);
-            for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) {
-                double u = xk[p->port_lidx[q]];
-                double w = (a[q] - u) / s->zport[q];
-                o[q] = u - s->zport[q] * w;
-            }
-        }
+        for (int32_t k = 0; k < p->nsub; k++) sweep_local(s, k, b, a, xloc + p->loc_ptr[k], o);
         for (int64_t q = 0; q < np; q++) a[q] = o[p->port_twin[q]];
         if (check_every > 0 && (sweep % check_every == 0 || sweep == max_sweeps)) {
             merged_residual(p, xloc, b, x, nsys, sys_ptr, rr);
@@ -831,21 +1024,7 @@ int64_t or_run_local(or_solver *s, const double *b, double *a, int64_t nsweeps, 
     double *o = calloc(np + 1, sizeof(double));
     for (int64_t sweep = 0; sweep < nsweeps; sweep++) {
 #pragma omp parallel for schedule(dynamic, 1)
-        for (int32_t k = 0; k < p->nsub; k++) {
-            int64_t base = p->loc_ptr[k], nk = p->loc_ptr[k + 1] - base;
-            double *xk = xloc_out + base;
-            for (int64_t i = 0; i < nk; i++) {
-                int64_t v = p->loc_vtx[base + i];
-                xk[i] = b[v] / (double)(p->s_ptr[v + 1] - p->s_ptr[v]);
-            }
-            for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) xk[p->port_lidx[q]] += a[q] / s->zport[q];
-            solve_local(&s->f[k], xk);
-            for (int64_t q = p->port_ptr[k]; q < p->port_ptr[k + 1]; q++) {
-                double u = xk[p->port_lidx[q]];
-                double w = (a[q] - u) / s->zport[q];
-                o[q] = u - s->zport[q] * w;
-            }
-        }
+        for (int32_t k = 0; k < p->nsub; k++) sweep_local(s, k, b, a, xloc_out + p->loc_ptr[k], o);
         for (int64_t q = 0; q < np; q++) a[q] = o[p->port_twin[q]];
     }
     free(o);

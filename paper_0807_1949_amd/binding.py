@@ -45,14 +45,14 @@ class PartitionSpec(C.Structure):
 class PartitionInfo(C.Structure):
     _fields_ = [("nsub", C.c_int32), ("nclass", C.c_int32), ("n_split", C.c_int64), ("nvtl", C.c_int64),
                 ("nports", C.c_int64), ("max_local", C.c_int32), ("nsys", C.c_int32),
-                ("factor_entries", C.c_int64)]
+                ("factor_entries", C.c_int64), ("rcb_seed", C.c_uint64)]
 
 
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int64), ("outer_steps", C.c_int32), ("checks", C.c_int32),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("bytes_per_sweep", C.c_double), ("flops_per_sweep", C.c_double), ("sweep_mode", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("persistent", C.c_int32), ("sweep_bytes", C.c_double)]
 
 
 class VTMError(RuntimeError):
@@ -68,7 +68,8 @@ EXPORTS = ("vtm_create", "vtm_destroy", "vtm_last_error", "vtm_evs_partition", "
            "vtm_solve", "vtm_run_sweeps", "vtm_reset_waves", "vtm_get_waves", "vtm_set_waves", "vtm_get_stats",
            "vtm_debug_class", "vtm_zfeatures", "vtm_zmodel_load", "vtm_get_z", "vtm_input_impedance", "vtm_trainer_create",
            "vtm_trainer_destroy", "vtm_trainer_set_data", "vtm_trainer_grad", "vtm_trainer_epoch",
-           "vtm_trainer_predict", "vtm_trainer_get_params", "vtm_autotune")
+           "vtm_trainer_predict", "vtm_trainer_get_params", "vtm_autotune", "vtm_batch_solve",
+           "vtm_setup_coupled")
 NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 12, 5081, 5057
 
 
@@ -85,6 +86,7 @@ def lib():
         L.vtm_evs_partition.argtypes = [P, C.c_int64, P, P, P, C.POINTER(PartitionSpec), C.POINTER(PartitionInfo)]
         L.vtm_get_partition.argtypes = [P] + [P] * 15
         L.vtm_setup.argtypes = [P, C.c_int32, P]
+        L.vtm_setup_coupled.argtypes = [P, P, C.c_int64, P, P, P]
         L.vtm_solve.argtypes = [P, P, C.c_int32, C.c_int64, C.c_double, P, C.c_int64, P, P]
         L.vtm_run_sweeps.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, P, C.c_int64]
         L.vtm_reset_waves.argtypes = [P]
@@ -93,7 +95,8 @@ def lib():
         L.vtm_get_stats.argtypes = [P, C.POINTER(Stats)]
         L.vtm_debug_class.argtypes = [P, C.c_int32, P, P, P, P, P, P, P]
         L.vtm_zfeatures.argtypes = [P, P]
-        L.vtm_zmodel_load.argtypes = [P, P]
+        L.vtm_zmodel_load.argtypes = [P, P, C.c_size_t]
+        L.vtm_batch_solve.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_double, P, P, P, P]
         L.vtm_get_z.argtypes = [P, P]
         L.vtm_input_impedance.argtypes = [P, P]
         L.vtm_trainer_create.argtypes = [C.c_int32, P, C.POINTER(C.c_void_p)]
@@ -252,6 +255,14 @@ class VTM:
         z = None if z_vtl is None else np.ascontiguousarray(z_vtl, dtype=np.float64)
         _check(lib().vtm_setup(self._h, z_rule, _np_ptr(z)))
 
+    def setup_coupled(self, z_vtl, vtl_a=(), vtl_b=(), z_ab=()):
+        """Coupled VTLs: symmetric Z over the VTLs with diagonal z_vtl and Z[vtl_a[e]][vtl_b[e]] = z_ab[e]."""
+        z = np.ascontiguousarray(z_vtl, dtype=np.float64)
+        la = np.ascontiguousarray(vtl_a, dtype=np.int64)
+        lb = np.ascontiguousarray(vtl_b, dtype=np.int64)
+        zc = np.ascontiguousarray(z_ab, dtype=np.float64)
+        _check(lib().vtm_setup_coupled(self._h, _np_ptr(z), len(la), _np_ptr(la), _np_ptr(lb), _np_ptr(zc)))
+
     # ------------------------------------------------------------------ solve
     def _vec(self, b):
         """(pointer, nrhs, ld, keepalive) of an (nrhs, n) block, numpy (host) or torch (device)."""
@@ -325,8 +336,7 @@ class VTM:
 
     def zmodel_load(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
-        assert p.shape == (ZMODEL_PARAMS,)
-        _check(lib().vtm_zmodel_load(self._h, _np_ptr(p)))
+        _check(lib().vtm_zmodel_load(self._h, _np_ptr(p), p.nbytes))
 
     def input_impedance(self) -> np.ndarray:
         """Input impedance of every port (Definition 7.1) with the other ports terminated by their Z."""
@@ -343,6 +353,37 @@ class VTM:
         s = Stats()
         _check(lib().vtm_get_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def batch_solve(handles, bs, tol: float, xs=None, raise_on=(VTM_ERR_DIVERGED,)):
+    """vtm_batch_solve over independent handles: bs[i] is an (nrhs, n_i) block (numpy or torch)."""
+    count = len(handles)
+    hv = (C.c_void_p * count)(*[h._h.value for h in handles])
+    bp, xp, keep, xk = (C.c_void_p * count)(), (C.c_void_p * count)(), [], []
+    ldb = np.zeros(count, np.int64)
+    ldx = np.zeros(count, np.int64)
+    nrhs = None
+    its, rels = [], []
+    ip, rp = (C.c_void_p * count)(), (C.c_void_p * count)()
+    for i, h in enumerate(handles):
+        pb, nr, ld, bk = h._vec(bs[i])
+        nrhs = nr if nrhs is None else nrhs
+        if nr != nrhs:
+            raise ValueError("every member needs the same number of right-hand sides")
+        x = h._out_like(bk, nr) if xs is None else xs[i]
+        px, _, lx, xkk = h._vec(x)
+        bp[i], xp[i], ldb[i], ldx[i] = pb, px, ld, lx
+        keep += [bk, xkk]
+        xk.append(xkk)
+        nsys = h.info["nsys"]
+        its.append(np.zeros(nr * nsys, np.int32))
+        rels.append(np.zeros(nr * nsys, np.float64))
+        ip[i], rp[i] = its[-1].ctypes.data, rels[-1].ctypes.data
+    code = lib().vtm_batch_solve(hv, count, bp, nrhs, _np_ptr(ldb), tol, xp, _np_ptr(ldx), ip, rp)
+    if code != VTM_OK and (code in raise_on or code not in (VTM_ERR_NOT_CONVERGED, VTM_ERR_DIVERGED)):
+        _check(code)
+    return [dict(x=xk[i], iters=its[i].reshape(nrhs, -1), relres=rels[i].reshape(nrhs, -1), status=code)
+            for i in range(count)]
 
 
 class Trainer:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -44,6 +45,10 @@ vtm_status fail(vtm_status code, const std::string &msg) {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;
@@ -51,6 +56,23 @@ struct DevBuf {
     }
     template <typename T>
     T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// HIP events released on every return path.
+struct Events {
+    hipEvent_t e[5] = {};
+    int n = 0;
+    hipError_t create(int count) {
+        for (; n < count; ++n) {
+            hipError_t r = hipEventCreate(&e[n]);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    hipEvent_t operator[](int i) const { return e[i]; }
+    ~Events() {
+        for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+    }
 };
 
 }  // namespace
@@ -71,6 +93,8 @@ struct vtm_ctx {
     // port-reduced sweeps
     DevBuf d_goff, d_G64, d_G32, d_cport, d_gorder, d_portpg;
     int32_t max_p = 0, npg = 0, max_np = 0;
+    // per system: packed G entries, port vertices, ports, stored factor entries, split entries
+    std::vector<double> sys_g, sys_pg, sys_ports, sys_lower, sys_split;
     int32_t persist_R = -1, persist_ng = -1;
     bool persist_fits = false;
     int64_t total_g = 0;   // stored entries of all packed G_k
@@ -93,7 +117,19 @@ struct vtm_ctx {
     DevBuf d_subcls, d_subval, d_subx, d_subaval, d_subws, d_pgptr, d_pgpos, d_pgbeg, d_pgcnt, d_portptr;
     // maps, matrix, ports
     DevBuf d_fvtx, d_fmul, d_cpptr, d_cpidx, d_rp, d_ci, d_v, d_aval, d_twin, d_portvtl, d_chunkrow, d_chunksys,
-        d_syschunk;
+        d_syschunk, d_subsys, d_active;
+    bool mask_on = false;          // sweeps and test solves skip converged systems (batched solves)
+    int32_t *active_host = nullptr;  // pinned per-system flags of the done mask
+    size_t active_cap = 0;
+    uint64_t setup_id = 0;         // unique id of the last vtm_setup (batch solves rebuild when one changes)
+    vtm_ctx *batch = nullptr;      // concatenation of handles for vtm_batch_solve (owned)
+    std::vector<uint64_t> batch_key;
+    // coupled VTLs: the local pieces carry the off-diagonal entries of Z_j^{-1}; the EVS pieces are kept
+    bool coupled = false;
+    std::vector<int64_t> lrp0;
+    std::vector<int32_t> lcol0;
+    std::vector<double> lval0;
+    DevBuf d_cplptr, d_cpltw, d_cply64, d_cply32;
     int32_t nchunks = 0;
     // setup products
     DevBuf d_z, d_invz64, d_invz32, d_vals64, d_vals32, d_status;
@@ -112,7 +148,7 @@ struct vtm_ctx {
         hipGraphExec_t exec = nullptr;
         int64_t count = 0;
         int32_t R = 0, ng = 0, threads = 0, variant = 0;
-        const void *ptrs[7] = {};
+        const void *ptrs[8] = {};
     } graphs[2];
     void drop_graphs() {
         for (auto &g : graphs) {
@@ -136,7 +172,7 @@ struct vtm_ctx {
                           &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr,
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
-                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_z, &d_invz64, &d_invz32,
+                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
                           &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gorder, &d_portpg, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
@@ -147,7 +183,9 @@ struct vtm_ctx {
         (void)hipSetDevice(opt.device);
         drop_graphs();
         for (DevBuf *b : all) b->release();
+        delete batch;
         if (relres_host) (void)hipHostFree(relres_host);
+        if (active_host) (void)hipHostFree(active_host);
         if (ev_test) (void)hipEventDestroy(ev_test);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -227,6 +265,12 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     d.port_ptr = h->d_portptr.as<int32_t>();
     d.port_pg = h->d_portpg.as<uint16_t>();
     d.gorder = h->d_gorder.as<int32_t>();
+    d.sub_sys = h->d_subsys.as<int32_t>();
+    d.active = h->mask_on ? h->d_active.as<int32_t>() : nullptr;
+    d.cpl_ptr = h->coupled ? h->d_cplptr.as<int32_t>() : nullptr;
+    d.cpl_tw = h->d_cpltw.as<int32_t>();
+    d.cpl_y64 = h->d_cply64.as<double>();
+    d.cpl_y32 = h->d_cply32.as<float>();
     return d;
 }
 
@@ -491,6 +535,19 @@ vtm_status upload_partition(vtm_ctx *h) {
         }
         h->total_g = goff[nsub];
         h->npg = pgptr[nsub];
+        h->sys_g.assign(P.nsys, 0.0);
+        h->sys_pg.assign(P.nsys, 0.0);
+        h->sys_ports.assign(P.nsys, 0.0);
+        h->sys_lower.assign(P.nsys, 0.0);
+        h->sys_split.assign(P.nsys, 0.0);
+        for (int32_t k = 0; k < nsub; ++k) {
+            const int32_t y = P.sub_sys[k];
+            h->sys_g[y] += (double)(goff[k + 1] - goff[k]);
+            h->sys_pg[y] += (double)(pgptr[k + 1] - pgptr[k]);
+            h->sys_ports[y] += (double)(P.port_ptr[k + 1] - P.port_ptr[k]);
+            h->sys_lower[y] += (double)S.classes[S.sub_class[k]].nlower;
+            h->sys_split[y] += (double)(P.loc_ptr[k + 1] - P.loc_ptr[k]);
+        }
         HIP_TRY(upload(h->d_goff, goff, st));
         // launch order of the port-reduced sweep: largest G_k first (ties by subgraph id)
         std::vector<int32_t> gorder(nsub);
@@ -555,7 +612,7 @@ vtm_status upload_partition(vtm_ctx *h) {
     UP(d_fvtx, fvtx); UP(d_fmul, fmul); UP(d_cpptr, P.s_ptr); UP(d_cpidx, cpidx);
     UP(d_rp, h->A.rp); UP(d_ci, h->A.ci); UP(d_v, h->A.v); UP(d_aval, afront);
     UP(d_twin, twin); UP(d_portvtl, portvtl); UP(d_chunkrow, chunkrow); UP(d_chunksys, chunksys);
-    UP(d_syschunk, syschunk);
+    UP(d_syschunk, syschunk); UP(d_subsys, P.sub_sys);
 #undef UP
     HIP_TRY(hipStreamSynchronize(st));
     return VTM_OK;
@@ -664,7 +721,7 @@ T *invz_of(vtm_ctx *h) {
 constexpr double kGreenRatio = 8.0;
 
 bool use_schur(vtm_ctx *h) {
-    if (!h->have_green) return false;
+    if (!h->have_green || h->coupled) return false;
     // the port vectors of a workgroup (R right-hand sides) must fit in LDS
     if (vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, std::max(1, h->wave_R), h->opt.sweep_waves) > vtm::kMaxLds) return false;
     if (h->opt.sweep_mode == 2) return true;
@@ -777,12 +834,12 @@ per_sweep:
     const int64_t nrep = h->opt.graph_mode == 0 ? (count - 1) / kGraphBatch : 0;
     if (nrep > 0) {
         auto &g = h->graphs[h->cur];
-        const void *ptrs[7] = {schur ? (const void *)green_of<T>(h) : (const void *)vals_of<T>(h),
+        const void *ptrs[8] = {schur ? (const void *)green_of<T>(h) : (const void *)vals_of<T>(h),
                                schur ? h->d_cport.p : h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p,
-                               h->d_o[1].p, h->d_xloc.p};
+                               h->d_o[1].p, h->d_xloc.p, h->mask_on ? h->d_active.p : nullptr};
         bool same = g.exec && g.count == kGraphBatch && g.R == R && g.ng == ng && g.threads == nt &&
                     g.variant == sweep_variant(h) + (schur ? 10 : 0);
-        for (int i = 0; i < 7 && same; ++i) same = g.ptrs[i] == ptrs[i];
+        for (int i = 0; i < 8 && same; ++i) same = g.ptrs[i] == ptrs[i];
         if (!same) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             g = vtm_ctx::SweepGraph();
@@ -802,7 +859,7 @@ per_sweep:
             g.ng = ng;
             g.threads = nt;
             g.variant = sweep_variant(h) + (schur ? 10 : 0);
-            for (int i = 0; i < 7; ++i) g.ptrs[i] = ptrs[i];
+            for (int i = 0; i < 8; ++i) g.ptrs[i] = ptrs[i];
         }
         for (int64_t r = 0; r < nrep; ++r) HIP_TRY(hipGraphLaunch(g.exec, h->stream));
     }
@@ -917,39 +974,82 @@ vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::v
     return check_abort(h, h->relres_host[rel.size()] != 0.0 ? 1 : 0);
 }
 
+// Cost of one convergence test in sweeps, from a fixed model: algorithmic bytes over a nominal
+// stream bandwidth, plus launch latencies (a persistent sweep is bound by the latency of its wave
+// exchange, a launched one by the launch).  The test placement uses it instead of measured timings,
+// so the placement -- and every reported sweep count -- depends on the iteration alone.
+double test_cost_sweeps(vtm_ctx *h, int32_t nrhs, bool schur, bool persistent) {
+    constexpr double kBw = 5e12, kSweepPersist = 4e-6, kSweepLaunch = 12e-6, kTestLatency = 60e-6;
+    const double s = (double)h->tsize(), r = (double)nrhs;
+    const double sweep_bytes = schur ? s * ((persistent ? 0.0 : (double)h->total_g) + (double)h->npg * r +
+                                            2.0 * (double)h->nports * r)
+                                     : s * ((double)h->total_lower + (double)h->nsplit * r + 2.0 * (double)h->nports * r);
+    const double t_sweep = std::max(sweep_bytes / kBw, persistent ? kSweepPersist : kSweepLaunch);
+    const double nnz = (double)h->A.rp[h->P.n], n = (double)h->P.n;
+    double test_bytes = r * (12.0 * nnz + 24.0 * n) + r * (double)h->nsplit * (s + 8.0);  // residual, merge
+    test_bytes += schur ? s * ((double)h->gws_total + 2.0 * (double)h->nsplit * r)       // Y blocks, y_b, x
+                        : s * ((double)h->total_lower + 2.0 * (double)h->nsplit * r);    // substitution
+    return (test_bytes / kBw + kTestLatency) / t_sweep;
+}
+
+// Per-system done mask of a solve over several independent systems: all systems active.
+vtm_status mask_begin(vtm_ctx *h) {
+    h->mask_on = false;
+    const int32_t nsys = h->P.nsys;
+    if (nsys <= 1) return VTM_OK;
+    if (h->active_cap < (size_t)nsys) {
+        if (h->active_host) HIP_TRY(hipHostFree(h->active_host));
+        h->active_host = nullptr;
+        h->active_cap = 0;
+        HIP_TRY(hipHostMalloc((void **)&h->active_host, sizeof(int32_t) * nsys, hipHostMallocDefault));
+        h->active_cap = nsys;
+    }
+    HIP_TRY(ensure(h->d_active, sizeof(int32_t) * nsys));
+    std::fill(h->active_host, h->active_host + nsys, 1);
+    HIP_TRY(hipMemcpyAsync(h->d_active.p, h->active_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice, h->stream));
+    h->mask_on = true;
+    return VTM_OK;
+}
+
+// The VTM solve (Table 1 steps 3-6) on the right sides staged in d_b (waves and buffers ready).
+// it[c * nsys + s]: first passing sweep; rel: the relative residuals of the returned x, *xfinal.
 template <typename T>
-vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
-                      int32_t *iters, double *relres) {
+vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t> &it, std::vector<double> &rel_x,
+                      const double **xfinal) {
     vtm_status rc;
     h->stats.persistent = 0;
     h->persist_launches = 0;
-    if ((rc = ensure_waves<T>(h, nrhs))) return rc;
-    if ((rc = alloc_solve<T>(h, nrhs))) return rc;
-    if ((rc = stage_b(h, b, nrhs, ldb))) return rc;
     const int64_t n = h->P.n;
-    const int32_t nsys = h->P.nsys, R = h->wave_R;
+    const int32_t nsys = h->P.nsys, R = h->wave_R, ng = (nrhs + R - 1) / R;
     const vtm::DevMaps M = dev_maps(h);
     // fixed cadence, or (check_every == 0) the next test is placed where the observed contraction
     // rate predicts the target (between 5 and 200 sweeps later), past it by a margin of half the
-    // prediction, at most the test's measured cost in sweeps: the rate measured early is faster than
-    // the asymptotic one, and a test that falls short costs a further test.  A refinement restart
-    // keeps the rate (the operator is the same) and is taken once the inner solve has gained a third
-    // of its factor eta.
+    // prediction, at most the modelled cost of a test in sweeps: the rate measured early is faster
+    // than the asymptotic one, and a test that falls short costs a further test.  A refinement
+    // restart keeps the rate (the operator is the same).
     const bool adaptive = h->opt.check_every <= 0;
     int64_t cadence = adaptive ? 10 : h->opt.check_every;
     const int64_t maxsw = h->opt.max_sweeps > 0 ? h->opt.max_sweeps : 100000;
     const bool refine = sizeof(T) == 4;
+    const size_t nq = (size_t)nsys * nrhs;
     std::vector<double> rel;
-    std::vector<int32_t> it((size_t)nsys * nrhs, -1);
-    std::vector<double> last((size_t)nsys * nrhs, 1.0);
-    hipEvent_t e0, e1, s0, s1, c1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventCreate(&s0));
-    HIP_TRY(hipEventCreate(&s1));
-    HIP_TRY(hipEventCreate(&c1));
+    it.assign(nq, -1);
+    std::vector<double> acc_rel(nq, 1.0);  // residuals of the accepted x (x = 0 at the start: r = b)
+    std::vector<double> cand_rel;          // residuals of the candidate left in xtr (refinement)
+    double cand_worst = 1e300;
+    std::vector<char> sys_done(nsys, 0);
+    Events ev;
+    HIP_TRY(ev.create(5));
+    const hipEvent_t e0 = ev[0], e1 = ev[1], s0 = ev[2], s1 = ev[3];
     HIP_TRY(hipEventRecord(e0, h->stream));
-    double sweep_ms = 0.0;
+    if ((rc = mask_begin(h))) return rc;
+    struct MaskOff {  // the mask applies to this solve only
+        vtm_ctx *h;
+        ~MaskOff() { h->mask_on = false; }
+    } mask_off{h};
+    const int64_t *chunkrow = h->d_chunkrow.as<int64_t>();
+    const int32_t *chunksys = h->d_chunksys.as<int32_t>();
+    double sweep_ms = 0.0, sweep_bytes = 0.0;
     int64_t sweeps = 0;
     int32_t outer = 1, checks = 0;
     bool done = false, diverged = false;
@@ -962,44 +1062,55 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
     if ((rc = zero_waves<T>(h))) return rc;
     if ((rc = port_constants<T>(h))) return rc;
     const bool schur = use_schur(h);
+    const double test_sweeps = test_cost_sweeps(h, nrhs, schur, schur && persistent_ok(h, R, ng));
     double rel_outer = 1.0, rel_prev = 1e300;
     const double eta = 1e-5;
     constexpr double kMargin = 0.5;
     double rate_ref = -1.0;  // worst residual at the previous test of the current inner solve
     double lr_known = 0.0;   // last measured log contraction per sweep (< 0 when known)
-    double test_sweeps = 0.0;  // cost of one test in sweeps (measured)
     int inner_checks = 0;
-    double last_worst = 1e300;
     while (!done && sweeps < maxsw) {
         const int64_t cnt = std::min(cadence, maxsw - sweeps);
         HIP_TRY(hipEventRecord(s0, h->stream));
+        const int64_t launches_before = h->persist_launches;
         if ((rc = run_sweeps_dev<T>(h, cnt))) return rc;
         HIP_TRY(hipEventRecord(s1, h->stream));
+        {  // algorithmic bytes of these sweeps over the systems still sweeping
+            const double ts = (double)sizeof(T), r = (double)nrhs;
+            const double g_reads = h->persist_launches > launches_before
+                                       ? (double)(h->persist_launches - launches_before) : (double)cnt;
+            for (int32_t y = 0; y < nsys; ++y) {
+                if (h->mask_on && !h->active_host[y]) continue;
+                sweep_bytes += schur ? ts * (h->sys_g[y] * g_reads + (double)cnt * r * (h->sys_pg[y] + 2.0 * h->sys_ports[y]))
+                                     : ts * (double)cnt * (h->sys_lower[y] + r * (h->sys_split[y] + 2.0 * h->sys_ports[y]));
+            }
+        }
         sweeps += cnt;
         ++checks;
         ++inner_checks;
         if (schur && (rc = test_solve<T>(h))) return rc;  // interior potentials of the last sweep
         // merged potentials (plus the refined x in FP32_IR), FP64 residual
-        vtm::launch_merge<T>(M, n, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, h->stream);
-        HIP_TRY(hipEventRecord(c1, h->stream));
+        vtm::launch_merge<T>(M, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, chunkrow,
+                             chunksys, h->nchunks, h->mask_on ? h->d_active.as<int32_t>() : nullptr, h->stream);
         if ((rc = residual(h, nrhs, xtr, refine ? rtr : nullptr, rel))) return rc;
-        float ms = 0.f, cms = 0.f;
+        float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, s0, s1));
-        HIP_TRY(hipEventElapsedTime(&cms, s1, c1));
         sweep_ms += ms;
-        if (ms > 0.f) test_sweeps = (double)cms / ((double)ms / (double)cnt);
         double worst = 0.0;
         bool all = true;
-        for (size_t q = 0; q < rel.size(); ++q) {
+        for (size_t q = 0; q < nq; ++q) {
             if (!std::isfinite(rel[q])) diverged = true;
             if (it[q] < 0 && rel[q] <= tol) it[q] = (int32_t)sweeps;
             all = all && rel[q] <= tol;
             worst = std::max(worst, rel[q]);
-            last[q] = rel[q];
         }
         if (first < 0) first = worst;
         if (worst > 1e3 * std::max(first, 1.0)) diverged = true;
-        if (diverged) break;
+        if (diverged) {
+            cand_rel = rel;
+            cand_worst = worst;
+            break;
+        }
         if (adaptive) {
             int64_t next = 2 * cnt;
             if (rate_ref > 0.0 && worst < rate_ref) lr_known = std::log(worst / rate_ref) / (double)cnt;
@@ -1014,20 +1125,47 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         }
         if (all) {
             std::swap(xcur, xtr);
+            acc_rel = rel;
             done = true;
             break;
         }
+        // done mask: a system whose every right side passes stops sweeping; its candidate x goes into
+        // both x buffers, which the merges of later tests leave alone
+        if (h->mask_on) {
+            bool changed = false;
+            for (int32_t sy = 0; sy < nsys; ++sy) {
+                if (sys_done[sy]) continue;
+                bool ok = true;
+                for (int32_t c = 0; c < nrhs && ok; ++c) ok = rel[(size_t)c * nsys + sy] <= tol;
+                if (!ok) continue;
+                sys_done[sy] = 1;
+                h->active_host[sy] = 0;
+                changed = true;
+                const int64_t lo = h->P.sys_ptr[sy], len = h->P.sys_ptr[sy + 1] - lo;
+                HIP_TRY(hipMemcpy2DAsync(xcur + lo, sizeof(double) * n, xtr + lo, sizeof(double) * n,
+                                         sizeof(double) * len, nrhs, hipMemcpyDeviceToDevice, h->stream));
+                for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + sy] = rel[(size_t)c * nsys + sy];
+            }
+            if (changed)
+                HIP_TRY(hipMemcpyAsync(h->d_active.p, h->active_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice,
+                                       h->stream));
+        }
         if (!refine) {
             std::swap(xcur, xtr);
+            acc_rel = rel;
             continue;
         }
         // FP32 inner solve: restart on the new residual once it has gained a factor eta or stalls
         const bool gained = worst <= 3.0 * eta * rel_outer;
         const bool stalled = inner_checks >= 2 && worst > 0.995 * rel_prev;
         rel_prev = worst;
+        cand_rel = rel;
+        cand_worst = worst;
         if ((gained || stalled) && worst < rel_outer) {
             std::swap(xcur, xtr);
             std::swap(rcur, rtr);
+            acc_rel = rel;
+            cand_worst = 1e300;  // xtr now holds an older x
             rel_outer = worst;
             rel_prev = 1e300;
             inner_checks = 0;
@@ -1042,28 +1180,26 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
             vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
             if ((rc = zero_waves<T>(h))) return rc;
             if ((rc = port_constants<T>(h))) return rc;
-            last_worst = 1e300;
             continue;
-        } else if (stalled) {
-            break;  // no further progress possible; keep the last accepted x
         }
-        last_worst = worst;
+        if (stalled) break;  // no further progress possible
     }
-    if (refine && !done && !diverged && last_worst < rel_outer) std::swap(xcur, xtr);
+    // refinement without convergence: return the better of the accepted x and the last candidate
+    if (refine && !done && !diverged && cand_worst < rel_outer) {
+        std::swap(xcur, xtr);
+        acc_rel = cand_rel;
+    }
+    if (diverged) acc_rel = cand_rel;
     HIP_TRY(hipEventRecord(e1, h->stream));
     HIP_TRY(hipEventSynchronize(e1));
     float total = 0.f;
     HIP_TRY(hipEventElapsedTime(&total, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(s0);
-    (void)hipEventDestroy(s1);
-    (void)hipEventDestroy(c1);
     h->stats.sweeps = sweeps;
     h->stats.outer_steps = outer;
     h->stats.checks = checks;
     h->stats.solve_ms = total;
     h->stats.sweep_ms = sweep_ms;
+    h->stats.sweep_bytes = sweep_bytes;
     if (schur) {
         // G_k is read once per launch: every sweep in per-sweep launches, once per batch in persistent ones
         const double g_reads = h->stats.persistent ? (double)h->persist_launches / (double)std::max<int64_t>(1, sweeps) : 1.0;
@@ -1076,12 +1212,31 @@ vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, do
         h->stats.flops_per_sweep = 4.0 * nrhs * (double)h->total_lower;
     }
     h->stats.sweep_mode = schur ? 2 : 1;
-    if ((rc = write_x(h, xcur, x, nrhs, ldx))) return rc;
-    if (iters) std::copy(it.begin(), it.end(), iters);
-    if (relres) std::copy(last.begin(), last.end(), relres);
+    rel_x = acc_rel;
+    *xfinal = xcur;
     if (diverged) return fail(VTM_ERR_DIVERGED, "VTM diverged (non-finite or growing residual)");
     if (!done) return fail(VTM_ERR_NOT_CONVERGED, "tolerance not reached within max_sweeps");
     return VTM_OK;
+}
+
+template <typename T>
+vtm_status solve_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, double tol, double *x, int64_t ldx,
+                      int32_t *iters, double *relres) {
+    vtm_status rc;
+    if ((rc = ensure_waves<T>(h, nrhs))) return rc;
+    if ((rc = alloc_solve<T>(h, nrhs))) return rc;
+    if ((rc = stage_b(h, b, nrhs, ldb))) return rc;
+    std::vector<int32_t> it;
+    std::vector<double> rel;
+    const double *xf = nullptr;
+    const vtm_status st = solve_core<T>(h, nrhs, tol, it, rel, &xf);
+    if (st != VTM_OK && st != VTM_ERR_NOT_CONVERGED && st != VTM_ERR_DIVERGED) return st;
+    const std::string msg = vtm::last_error_ref();
+    if ((rc = write_x(h, xf, x, nrhs, ldx))) return rc;
+    if (iters) std::copy(it.begin(), it.end(), iters);
+    if (relres) std::copy(rel.begin(), rel.end(), relres);
+    if (st != VTM_OK) vtm::last_error_ref() = msg;
+    return st;
 }
 
 template <typename T>
@@ -1100,8 +1255,8 @@ vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int6
         if ((rc = port_constants<T>(h))) return rc;
         if ((rc = run_sweeps_dev<T>(h, nsweeps))) return rc;
         if (use_schur(h)) local_solve<T>(h, false);
-        vtm::launch_merge<T>(M, n, h->nsplit, nrhs, h->wave_R, h->d_xloc.as<T>(), nullptr, n, h->d_x.as<double>(), n,
-                             h->stream);
+        vtm::launch_merge<T>(M, h->nsplit, nrhs, h->wave_R, h->d_xloc.as<T>(), nullptr, n, h->d_x.as<double>(), n,
+                             h->d_chunkrow.as<int64_t>(), h->d_chunksys.as<int32_t>(), h->nchunks, nullptr, h->stream);
     } else {
         HIP_TRY(hipMemsetAsync(h->d_x.p, 0, sizeof(double) * n * nrhs, h->stream));
     }
@@ -1165,7 +1320,8 @@ vtm_status learned_z(vtm_ctx *h) {
 }
 
 // Impedances set, augmentation, factorisation and (when wanted or forced) the port Green's functions.
-vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, bool force_green) {
+vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, bool force_green,
+                      const std::vector<double> *invz_port = nullptr) {
     const vtm::Partition &P = h->P;
     hipStream_t st = h->stream;
     if (z_rule == VTM_Z_LEARNED) {
@@ -1181,7 +1337,7 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     DevBuf &ws = h->d_ws;
     HIP_TRY(ensure(ws, sizeof(double) * (h->total_ws + 1)));
     // port Green's functions for port-reduced sweeps (skipped when forced off or too large)
-    const bool want_green = h->max_p > 0 && h->max_p <= 2048 &&
+    const bool want_green = !h->coupled && h->max_p > 0 && h->max_p <= 2048 &&
                             (force_green || (h->opt.sweep_mode != 1 && (h->opt.sweep_mode == 2 ||
                                              (double)h->total_g <= kGreenRatio * (double)h->total_lower)));
     if (want_green && h->plan_state == 0) {
@@ -1193,12 +1349,19 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
         HIP_TRY(ensure(h->d_gws, sizeof(double) * (h->gws_total + 2)));
         if (h->d_gws.p != before) h->gws_clean = false;
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    Events ev;
+    HIP_TRY(ev.create(2));
+    const hipEvent_t e0 = ev[0], e1 = ev[1];
     HIP_TRY(hipEventRecord(e0, st));
-    vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
-                     h->d_invz32.as<float>(), h->nports, st);
+    if (invz_port) {  // coupled VTLs: the diagonal of Z_j^{-1} at every port, from the host
+        std::vector<float> i32(invz_port->begin(), invz_port->end());
+        HIP_TRY(upload(h->d_invz64, *invz_port, st));
+        HIP_TRY(upload(h->d_invz32, i32, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        vtm::launch_invz(h->d_z.as<double>(), h->d_portvtl.as<int32_t>(), h->d_invz64.as<double>(),
+                         h->d_invz32.as<float>(), h->nports, st);
+    }
     const bool fused = want_green && h->plan_state == 1;
     h->have_y = h->have_y32 = h->yb_ok = false;
     if (fused && h->fp32()) {
@@ -1242,8 +1405,6 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
     if (fused) h->gws_clean = true;  // the factorisation ran to its end
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     h->stats.setup_ms = ms;
     for (int32_t k = 0; k < P.nsub; ++k)
         if (status[k]) {
@@ -1251,7 +1412,9 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
             return fail(VTM_ERR_NOT_SPD, "non-positive pivot in subgraph " + std::to_string(k) + " (supernode " +
                                              std::to_string(status[k] - 1) + ")");
         }
+    static std::atomic<uint64_t> next_setup_id{1};
     h->set_up = true;
+    h->setup_id = next_setup_id++;
     h->wave_nrhs = 0;  // fresh zero waves on the next solve
     h->drop_graphs();
     return VTM_OK;
@@ -1309,6 +1472,324 @@ vtm_status matched_setup(vtm_ctx *h) {
     vtm_status rc = setup_core(h, VTM_Z_USER, z, false);
     h->stats.setup_ms += total_ms;
     return rc;
+}
+
+
+// The EVS pieces back in the partition after a coupled set-up, with their own symbolic analysis.
+vtm_status restore_pieces(vtm_ctx *h) {
+    if (!h->coupled) return VTM_OK;
+    h->P.lrp.swap(h->lrp0);
+    h->P.lcol.swap(h->lcol0);
+    h->P.lval.swap(h->lval0);
+    h->lrp0.clear();
+    h->lcol0.clear();
+    h->lval0.clear();
+    h->coupled = false;
+    h->set_up = false;
+    std::string err;
+    const int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : 16;
+    int rc = vtm::build_symbolic(h->P, leaf, h->S, err);
+    if (rc) return fail(rc, err);
+    return upload_partition(h);
+}
+
+// Coupled VTLs (Section 7.2, Theorem 7.1).  Z is a symmetric matrix over the VTLs: diagonal z_vtl,
+// off-diagonal entries zab[e] at (la[e], lb[e]); coupled VTLs must join the same two subgraphs, so
+// that Z is block diagonal over groups of VTLs between one pair of subgraphs and both subgraphs of a
+// group use its block, in their own port order, as their Z_j (the twins then see one matrix).  Each
+// block is factored Z = L L^T (failure: not SPD) and inverted as L^{-T} L^{-1}.  The local matrix
+// of (5.8) gets the block Z_j^{-1} on the group's port vertices: its diagonal through the port
+// diagonal, its other entries as added entries of the local pieces (which may widen their sparsity,
+// so the symbolic analysis is redone); each sweep adds sum_q (Z_j^{-1})_pq a_q to the right side.
+vtm_status coupled_setup(vtm_ctx *h, const double *z_vtl, int64_t ncpl, const int64_t *la, const int64_t *lb,
+                         const double *zab) {
+    vtm::Partition &P = h->P;
+    const int64_t nvtl = (int64_t)P.vtl_v.size(), np = (int64_t)P.port_v.size();
+    std::vector<double> z(z_vtl, z_vtl + nvtl);
+    for (int64_t l = 0; l < nvtl; ++l)
+        if (!(z[l] > 0.0) || !std::isfinite(z[l])) return fail(VTM_ERR_INVALID, "Z must be finite and > 0");
+    for (int64_t e = 0; e < ncpl; ++e) {
+        if (la[e] < 0 || la[e] >= nvtl || lb[e] < 0 || lb[e] >= nvtl || la[e] == lb[e] || !std::isfinite(zab[e]))
+            return fail(VTM_ERR_INVALID, "coupling entry " + std::to_string(e) + " invalid");
+        if (P.vtl_k[la[e]] != P.vtl_k[lb[e]] || P.vtl_k2[la[e]] != P.vtl_k2[lb[e]])
+            return fail(VTM_ERR_INVALID, "coupled VTLs " + std::to_string(la[e]) + ", " + std::to_string(lb[e]) +
+                                             " do not join the same two subgraphs");
+    }
+    // groups: connected components of the coupling graph (labels = smallest member)
+    std::vector<int64_t> lab(nvtl);
+    for (int64_t l = 0; l < nvtl; ++l) lab[l] = l;
+    auto find = [&](int64_t x) {
+        while (lab[x] != x) x = lab[x] = lab[lab[x]];
+        return x;
+    };
+    for (int64_t e = 0; e < ncpl; ++e) {
+        const int64_t a = find(la[e]), b = find(lb[e]);
+        if (a != b) lab[std::max(a, b)] = std::min(a, b);
+    }
+    std::vector<std::vector<int64_t>> members(nvtl);
+    std::vector<int32_t> slot(nvtl);
+    for (int64_t l = 0; l < nvtl; ++l) {
+        const int64_t g = find(l);
+        slot[l] = (int32_t)members[g].size();
+        members[g].push_back(l);
+    }
+    std::vector<std::vector<double>> Y(nvtl);  // per group root: Z^{-1}, m x m row-major
+    {
+        std::vector<std::vector<double>> Zg(nvtl);
+        for (int64_t g = 0; g < nvtl; ++g) {
+            const size_t m = members[g].size();
+            if (!m) continue;
+            Zg[g].assign(m * m, 0.0);
+            for (size_t i = 0; i < m; ++i) Zg[g][i * m + i] = z[members[g][i]];
+        }
+        for (int64_t e = 0; e < ncpl; ++e) {
+            const int64_t g = find(la[e]);
+            const size_t m = members[g].size(), i = slot[la[e]], j = slot[lb[e]];
+            Zg[g][i * m + j] = zab[e];
+            Zg[g][j * m + i] = zab[e];
+        }
+        for (int64_t g = 0; g < nvtl; ++g) {
+            const size_t m = members[g].size();
+            if (!m) continue;
+            std::vector<double> L(m * m, 0.0), Li(m * m, 0.0);
+            for (size_t j = 0; j < m; ++j) {  // column-oriented Cholesky
+                double d = Zg[g][j * m + j];
+                for (size_t t = 0; t < j; ++t) d -= L[j * m + t] * L[j * m + t];
+                if (!(d > 0.0) || !std::isfinite(d))
+                    return fail(VTM_ERR_INVALID, "coupled impedance block of VTL " + std::to_string(members[g][0]) +
+                                                     " is not positive definite");
+                L[j * m + j] = std::sqrt(d);
+                for (size_t i = j + 1; i < m; ++i) {
+                    double v = Zg[g][i * m + j];
+                    for (size_t t = 0; t < j; ++t) v -= L[i * m + t] * L[j * m + t];
+                    L[i * m + j] = v / L[j * m + j];
+                }
+            }
+            for (size_t j = 0; j < m; ++j) {  // Li = L^{-1}, lower triangular
+                Li[j * m + j] = 1.0 / L[j * m + j];
+                for (size_t i = j + 1; i < m; ++i) {
+                    double v = 0.0;
+                    for (size_t t = j; t < i; ++t) v -= L[i * m + t] * Li[t * m + j];
+                    Li[i * m + j] = v / L[i * m + i];
+                }
+            }
+            Y[g].assign(m * m, 0.0);  // Z^{-1} = Li^T Li
+            for (size_t i = 0; i < m; ++i)
+                for (size_t j = 0; j < m; ++j) {
+                    double v = 0.0;
+                    for (size_t t = std::max(i, j); t < m; ++t) v += Li[t * m + i] * Li[t * m + j];
+                    Y[g][i * m + j] = v;
+                }
+        }
+    }
+    // the two ports of every VTL (end 0 in vtl_k, end 1 in vtl_k2) and the subgraph of every port
+    std::vector<int64_t> vport(2 * nvtl);
+    std::vector<int32_t> sub_of(np);
+    for (int32_t k = 0; k < P.nsub; ++k)
+        for (int64_t q = P.port_ptr[k]; q < P.port_ptr[k + 1]; ++q) {
+            const int64_t l = P.port_vtl[q];
+            vport[2 * l + (k == P.vtl_k[l] ? 0 : 1)] = q;
+            sub_of[q] = k;
+        }
+    std::vector<double> invz(np);
+    std::vector<int32_t> cptr(np + 1, 0), ctw;
+    std::vector<double> cy;
+    // additions to the local pieces: (subgraph, local row, local column, value), off-diagonal only
+    struct Add {
+        int32_t k, i, j;
+        double v;
+    };
+    std::vector<Add> adds;
+    for (int64_t q = 0; q < np; ++q) {
+        const int64_t l = P.port_vtl[q], g = find(l);
+        const int end = vport[2 * l] == q ? 0 : 1;
+        const size_t m = members[g].size(), i = slot[l];
+        invz[q] = Y[g][i * m + i];
+        for (size_t j = 0; j < m; ++j) {
+            if (j == i) continue;
+            const int64_t qo = vport[2 * members[g][j] + end];
+            ctw.push_back((int32_t)P.port_twin[qo]);
+            cy.push_back(Y[g][i * m + j]);
+            adds.push_back(Add{sub_of[q], P.port_lidx[q], P.port_lidx[qo], Y[g][i * m + j]});
+        }
+        cptr[q + 1] = (int32_t)ctw.size();
+    }
+    // the EVS pieces with the added entries (kept aside: vtm_get_partition returns the pieces)
+    vtm_status rc = restore_pieces(h);
+    if (rc) return rc;
+    std::sort(adds.begin(), adds.end(), [](const Add &a, const Add &b) {
+        return a.k != b.k ? a.k < b.k : a.i != b.i ? a.i < b.i : a.j < b.j;
+    });
+    std::vector<int64_t> lrp(P.lrp.size());
+    std::vector<int32_t> lcol;
+    std::vector<double> lval;
+    lcol.reserve(P.lcol.size() + adds.size());
+    lval.reserve(P.lcol.size() + adds.size());
+    size_t ai = 0;
+    lrp[0] = 0;
+    for (int32_t k = 0; k < P.nsub; ++k)
+        for (int64_t r = P.loc_ptr[k]; r < P.loc_ptr[k + 1]; ++r) {
+            const int32_t i = (int32_t)(r - P.loc_ptr[k]);
+            int64_t e = P.lrp[r];
+            const int64_t e1 = P.lrp[r + 1];
+            while (e < e1 || (ai < adds.size() && adds[ai].k == k && adds[ai].i == i)) {
+                const bool take_add = ai < adds.size() && adds[ai].k == k && adds[ai].i == i &&
+                                      (e >= e1 || adds[ai].j <= P.lcol[e]);
+                if (take_add) {
+                    const Add &a = adds[ai++];
+                    if (e < e1 && a.j == P.lcol[e]) {
+                        lcol.push_back(P.lcol[e]);
+                        lval.push_back(P.lval[e] + a.v);
+                        ++e;
+                    } else if (!lcol.empty() && (int64_t)lcol.size() > lrp[r] && lcol.back() == a.j) {
+                        lval.back() += a.v;
+                    } else {
+                        lcol.push_back(a.j);
+                        lval.push_back(a.v);
+                    }
+                } else {
+                    lcol.push_back(P.lcol[e]);
+                    lval.push_back(P.lval[e]);
+                    ++e;
+                }
+            }
+            lrp[r + 1] = (int64_t)lcol.size();
+        }
+    h->lrp0.swap(P.lrp);
+    h->lcol0.swap(P.lcol);
+    h->lval0.swap(P.lval);
+    P.lrp.swap(lrp);
+    P.lcol.swap(lcol);
+    P.lval.swap(lval);
+    h->coupled = true;
+    std::string err;
+    const int leaf = h->opt.leaf_size > 0 ? h->opt.leaf_size : 16;
+    int r2 = vtm::build_symbolic(P, leaf, h->S, err);
+    if (r2) return fail(r2, err);
+    if ((rc = upload_partition(h))) return rc;
+    std::vector<float> cy32(cy.begin(), cy.end());
+    HIP_TRY(upload(h->d_cplptr, cptr, h->stream));
+    HIP_TRY(upload(h->d_cpltw, ctw, h->stream));
+    HIP_TRY(upload(h->d_cply64, cy, h->stream));
+    HIP_TRY(upload(h->d_cply32, cy32, h->stream));
+    return setup_core(h, VTM_Z_USER, z, false, &invz);
+}
+
+// vtm_batch_solve: the members' systems as one block-diagonal set of independent systems (each
+// member's systems stay systems of the batch), in a context of its own that holds copies of their
+// partitions, symbolic analyses and impedances and factors them again, all in one launch.
+vtm_status build_batch(vtm_ctx *const *hs, int32_t count, vtm_ctx *B) {
+    vtm::Csr &A = B->A;
+    vtm::Partition &P = B->P;
+    vtm::Symbolic &S = B->S;
+    A = vtm::Csr();
+    P = vtm::Partition();
+    S = vtm::Symbolic();
+    A.rp.assign(1, 0);
+    P.s_ptr.assign(1, 0);
+    P.loc_ptr.assign(1, 0);
+    P.lrp.assign(1, 0);
+    P.port_ptr.assign(1, 0);
+    P.sys_ptr.assign(1, 0);
+    P.nsys = 0;
+    std::vector<double> z;
+    for (int32_t i = 0; i < count; ++i) {
+        const vtm_ctx *h = hs[i];
+        const vtm::Csr &a = h->A;
+        const vtm::Partition &p = h->P;
+        const int64_t vo = A.n, eo = (int64_t)A.ci.size(), so = (int64_t)P.s_idx.size(), xo = (int64_t)P.loc_vtx.size(),
+                      lo = (int64_t)P.lcol.size(), to = (int64_t)P.vtl_v.size(), po = (int64_t)P.port_v.size();
+        const int32_t ko = P.nsub, co = (int32_t)S.classes.size(), yo = P.nsys;
+        for (int64_t v = 0; v < a.n; ++v) A.rp.push_back(a.rp[v + 1] + eo);
+        for (const int32_t c : a.ci) A.ci.push_back((int32_t)(c + vo));
+        A.v.insert(A.v.end(), a.v.begin(), a.v.end());
+        for (int64_t v = 0; v < p.n; ++v) P.s_ptr.push_back(p.s_ptr[v + 1] + so);
+        for (const int32_t k : p.s_idx) P.s_idx.push_back(k + ko);
+        for (int32_t k = 0; k < p.nsub; ++k) P.loc_ptr.push_back(p.loc_ptr[k + 1] + xo);
+        for (const int64_t v : p.loc_vtx) P.loc_vtx.push_back(v + vo);
+        for (size_t e = 1; e < p.lrp.size(); ++e) P.lrp.push_back(p.lrp[e] + lo);
+        P.lcol.insert(P.lcol.end(), p.lcol.begin(), p.lcol.end());
+        P.lval.insert(P.lval.end(), p.lval.begin(), p.lval.end());
+        for (const int64_t v : p.vtl_v) P.vtl_v.push_back(v + vo);
+        for (const int32_t k : p.vtl_k) P.vtl_k.push_back(k + ko);
+        for (const int32_t k : p.vtl_k2) P.vtl_k2.push_back(k + ko);
+        for (int32_t k = 0; k < p.nsub; ++k) P.port_ptr.push_back(p.port_ptr[k + 1] + po);
+        for (const int64_t v : p.port_v) P.port_v.push_back(v + vo);
+        for (const int64_t t : p.port_twin) P.port_twin.push_back(t + po);
+        for (const int64_t l : p.port_vtl) P.port_vtl.push_back(l + to);
+        for (const int32_t k : p.port_other) P.port_other.push_back(k + ko);
+        P.port_lidx.insert(P.port_lidx.end(), p.port_lidx.begin(), p.port_lidx.end());
+        P.adiag.insert(P.adiag.end(), p.adiag.begin(), p.adiag.end());
+        P.zdiag.insert(P.zdiag.end(), p.zdiag.begin(), p.zdiag.end());
+        for (int32_t y = 0; y < p.nsys; ++y) P.sys_ptr.push_back(p.sys_ptr[y + 1] + vo);
+        for (const int32_t y : p.sub_sys) P.sub_sys.push_back(y + yo);
+        for (const int32_t c : h->S.sub_class) S.sub_class.push_back(c + co);
+        S.classes.insert(S.classes.end(), h->S.classes.begin(), h->S.classes.end());
+        A.n += a.n;
+        P.n += p.n;
+        P.nsub += p.nsub;
+        P.nsys += p.nsys;
+        std::vector<double> zi(p.vtl_v.size());
+        if (!zi.empty())
+            HIP_TRY(hipMemcpy(zi.data(), h->d_z.p, sizeof(double) * zi.size(), hipMemcpyDeviceToHost));
+        z.insert(z.end(), zi.begin(), zi.end());
+    }
+    vtm_status rc = upload_partition(B);
+    if (rc) return rc;
+    B->partitioned = true;
+    return setup_core(B, VTM_Z_USER, z, false);
+}
+
+// Device or host copy direction for a 2D copy between a user pointer and the device.
+hipMemcpyKind user_kind(const void *user, bool to_device) {
+    if (is_device_ptr(user)) return hipMemcpyDeviceToDevice;
+    return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+}
+
+template <typename T>
+vtm_status batch_impl(vtm_ctx *B, vtm_ctx *const *hs, int32_t count, const double *const *b, int32_t nrhs,
+                      const int64_t *ldb, double tol, double *const *x, const int64_t *ldx, int32_t *const *iters,
+                      double *const *relres) {
+    vtm_status rc;
+    if ((rc = ensure_waves<T>(B, nrhs))) return rc;
+    if ((rc = alloc_solve<T>(B, nrhs))) return rc;
+    const int64_t N = B->P.n;
+    HIP_TRY(ensure(B->d_b, sizeof(double) * (size_t)N * nrhs));
+    int64_t vo = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t ni = hs[i]->P.n;
+        HIP_TRY(hipMemcpy2DAsync(B->d_b.as<double>() + vo, sizeof(double) * N, b[i], sizeof(double) * ldb[i],
+                                 sizeof(double) * ni, nrhs, user_kind(b[i], true), B->stream));
+        vo += ni;
+    }
+    std::vector<int32_t> it;
+    std::vector<double> rel;
+    const double *xf = nullptr;
+    const vtm_status st = solve_core<T>(B, nrhs, tol, it, rel, &xf);
+    if (st != VTM_OK && st != VTM_ERR_NOT_CONVERGED && st != VTM_ERR_DIVERGED) return st;
+    const std::string msg = vtm::last_error_ref();
+    vo = 0;
+    int32_t yo = 0;
+    const int32_t NS = B->P.nsys;
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t ni = hs[i]->P.n;
+        const int32_t nsi = hs[i]->P.nsys;
+        HIP_TRY(hipMemcpy2DAsync(x[i], sizeof(double) * ldx[i], xf + vo, sizeof(double) * N, sizeof(double) * ni, nrhs,
+                                 user_kind(x[i], false), B->stream));
+        for (int32_t c = 0; c < nrhs; ++c)
+            for (int32_t y = 0; y < nsi; ++y) {
+                const size_t q = (size_t)c * NS + yo + y, qi = (size_t)c * nsi + y;
+                if (iters && iters[i]) iters[i][qi] = it[q];
+                if (relres && relres[i]) relres[i][qi] = rel[q];
+            }
+        vo += ni;
+        yo += nsi;
+    }
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    if ((rc = check_abort(B))) return rc;
+    for (int32_t i = 0; i < count; ++i) hs[i]->stats = B->stats;
+    if (st != VTM_OK) vtm::last_error_ref() = msg;
+    return st;
 }
 
 }  // namespace
@@ -1377,6 +1858,7 @@ vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, con
     if (!h->host_only()) HIP_TRY(hipSetDevice(h->opt.device));
     h->partitioned = h->set_up = false;
     h->feats_ready = h->feats_on_dev = false;
+    h->coupled = false;
     h->A.n = n;
     h->A.rp.assign(rowptr, rowptr + n + 1);
     h->A.ci.assign(col, col + rowptr[n]);
@@ -1400,6 +1882,7 @@ vtm_status vtm_evs_partition(vtm_handle h, int64_t n, const int64_t *rowptr, con
         info->max_local = h->max_nk;
         info->nsys = h->P.nsys;
         info->factor_entries = h->total_lower;
+        info->rcb_seed = h->P.rcb_seed;
     }
     return VTM_OK;
 }
@@ -1414,8 +1897,10 @@ vtm_status vtm_get_partition(vtm_handle h, int64_t *s_ptr, int32_t *s_idx, int64
     auto cp = [](auto *dst, const auto &src) {
         if (dst) std::copy(src.begin(), src.end(), dst);
     };
-    cp(s_ptr, P.s_ptr); cp(s_idx, P.s_idx); cp(loc_ptr, P.loc_ptr); cp(loc_vtx, P.loc_vtx); cp(lrp, P.lrp);
-    cp(lcol, P.lcol); cp(lval, P.lval); cp(vtl_v, P.vtl_v); cp(vtl_k, P.vtl_k); cp(vtl_k2, P.vtl_k2);
+    cp(s_ptr, P.s_ptr); cp(s_idx, P.s_idx); cp(loc_ptr, P.loc_ptr); cp(loc_vtx, P.loc_vtx);
+    cp(lrp, h->coupled ? h->lrp0 : P.lrp);  // the EVS pieces, also while a coupled set-up holds the handle
+    cp(lcol, h->coupled ? h->lcol0 : P.lcol);
+    cp(lval, h->coupled ? h->lval0 : P.lval); cp(vtl_v, P.vtl_v); cp(vtl_k, P.vtl_k); cp(vtl_k2, P.vtl_k2);
     cp(port_ptr, P.port_ptr); cp(port_v, P.port_v); cp(port_other, P.port_other); cp(port_twin, P.port_twin);
     cp(zdiag, P.zdiag);
     return VTM_OK;
@@ -1426,6 +1911,10 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
     if (h->host_only()) return fail(VTM_ERR_STATE, "host-only handle (device < 0) cannot set up");
     if (!h->partitioned) return fail(VTM_ERR_STATE, "vtm_setup before vtm_evs_partition");
     HIP_TRY(hipSetDevice(h->opt.device));
+    if (h->coupled) {  // back to the EVS pieces of the partition
+        vtm_status rc = restore_pieces(h);
+        if (rc) return rc;
+    }
     const vtm::Partition &P = h->P;
     const int64_t nvtl = (int64_t)P.vtl_v.size();
     std::vector<double> z;
@@ -1443,6 +1932,17 @@ vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl) {
         return fail(VTM_ERR_INVALID, "unknown z_rule");
     }
     return setup_core(h, z_rule, z, false);
+}
+
+vtm_status vtm_setup_coupled(vtm_handle h, const double *z_vtl, int64_t ncouple, const int64_t *vtl_a,
+                             const int64_t *vtl_b, const double *z_ab) {
+    if (!h || (!z_vtl && h->P.vtl_v.size()) || ncouple < 0 || (ncouple > 0 && (!vtl_a || !vtl_b || !z_ab)))
+        return fail(VTM_ERR_INVALID, "bad argument");
+    if (h->host_only()) return fail(VTM_ERR_STATE, "host-only handle (device < 0) cannot set up");
+    if (!h->partitioned) return fail(VTM_ERR_STATE, "vtm_setup_coupled before vtm_evs_partition");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    h->set_up = false;
+    return coupled_setup(h, z_vtl, ncouple, vtl_a, vtl_b, z_ab);
 }
 
 vtm_status vtm_input_impedance(vtm_handle h, double *r_port) {
@@ -1465,6 +1965,47 @@ vtm_status vtm_solve(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, d
     HIP_TRY(hipSetDevice(h->opt.device));
     return h->fp32() ? solve_impl<float>(h, b, nrhs, ldb, tol, x, ldx, iters, relres)
                      : solve_impl<double>(h, b, nrhs, ldb, tol, x, ldx, iters, relres);
+}
+
+vtm_status vtm_batch_solve(vtm_handle *hs, int32_t count, const double *const *b, int32_t nrhs, const int64_t *ldb,
+                           double tol, double *const *x, const int64_t *ldx, int32_t *const *iters,
+                           double *const *relres) {
+    if (!hs || count < 1 || !b || !x || !ldb || !ldx || nrhs < 1) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!(tol > 0.0)) return fail(VTM_ERR_INVALID, "tol <= 0");
+    vtm_ctx *h0 = hs[0];
+    for (int32_t i = 0; i < count; ++i) {
+        vtm_ctx *h = hs[i];
+        if (!h || !b[i] || !x[i]) return fail(VTM_ERR_INVALID, "null handle or vector in the batch");
+        if (!h->set_up) return fail(VTM_ERR_STATE, "vtm_batch_solve: member " + std::to_string(i) + " is not set up");
+        if (h->coupled) return fail(VTM_ERR_INVALID, "vtm_batch_solve: member " + std::to_string(i) + " has coupled VTLs");
+        if (h->opt.device != h0->opt.device || h->opt.precision != h0->opt.precision)
+            return fail(VTM_ERR_INVALID, "batch members must share the device and the precision");
+        if (ldb[i] < h->P.n || ldx[i] < h->P.n) return fail(VTM_ERR_INVALID, "leading dimension < n");
+    }
+    HIP_TRY(hipSetDevice(h0->opt.device));
+    std::vector<uint64_t> key(count);
+    for (int32_t i = 0; i < count; ++i) key[i] = hs[i]->setup_id;
+    if (!h0->batch || h0->batch_key != key) {
+        delete h0->batch;
+        h0->batch = nullptr;
+        h0->batch_key.clear();
+        vtm_ctx *B = new (std::nothrow) vtm_ctx();
+        if (!B) return fail(VTM_ERR_OOM, "batch context allocation failed");
+        B->opt = h0->opt;
+        B->opt.stream = h0->stream;
+        B->stream = h0->stream;
+        B->own_stream = false;
+        vtm_status rc = build_batch(hs, count, B);
+        if (rc) {
+            delete B;
+            return rc;
+        }
+        h0->batch = B;
+        h0->batch_key = key;
+    }
+    vtm_ctx *B = h0->batch;
+    return B->fp32() ? batch_impl<float>(B, hs, count, b, nrhs, ldb, tol, x, ldx, iters, relres)
+                     : batch_impl<double>(B, hs, count, b, nrhs, ldb, tol, x, ldx, iters, relres);
 }
 
 vtm_status vtm_run_sweeps(vtm_handle h, const double *b, int32_t nrhs, int64_t ldb, int64_t nsweeps, double *x,
@@ -1534,9 +2075,9 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
     const vtm_options saved = h->opt;
     double best = 1e300;
     vtm_options bestopt = saved;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    Events ev;
+    HIP_TRY(ev.create(2));
+    const hipEvent_t e0 = ev[0], e1 = ev[1];
     struct Cand { int32_t mode, var, nt; };
     std::vector<Cand> cands;
     for (int32_t var = 1; var <= 2; ++var)
@@ -1576,8 +2117,6 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
                 bestopt = h->opt;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     h->opt = saved;
     h->opt.rhs_per_block = bestopt.rhs_per_block;
     h->opt.sweep_threads = bestopt.sweep_threads;
@@ -1596,13 +2135,20 @@ vtm_status vtm_autotune(vtm_handle h, int32_t nrhs, int32_t *chosen) {
 vtm_status vtm_zfeatures(vtm_handle h, float *out) {
     if (!h || !out) return fail(VTM_ERR_INVALID, "bad argument");
     if (!h->partitioned) return fail(VTM_ERR_STATE, "no partition");
+    if (h->coupled && !h->feats_ready) return fail(VTM_ERR_STATE, "features need the EVS pieces: vtm_setup first");
     ensure_features(h);
     std::copy(h->feats.begin(), h->feats.end(), out);
     return VTM_OK;
 }
 
-vtm_status vtm_zmodel_load(vtm_handle h, const float *params) {
-    if (!h || !params) return fail(VTM_ERR_INVALID, "bad argument");
+vtm_status vtm_zmodel_load(vtm_handle h, const void *weights, size_t bytes) {
+    if (!h || !weights) return fail(VTM_ERR_INVALID, "bad argument");
+    if (bytes != sizeof(float) * (size_t)vtm::kParams)
+        return fail(VTM_ERR_INVALID, "model blob has " + std::to_string(bytes) + " bytes, expected " +
+                                         std::to_string(sizeof(float) * (size_t)vtm::kParams));
+    std::vector<float> blob(vtm::kParams);
+    std::memcpy(blob.data(), weights, bytes);  // the caller's blob need not be aligned
+    const float *params = blob.data();
     if (h->host_only()) return fail(VTM_ERR_STATE, "host-only handle");
     for (int i = 0; i < vtm::kParams; ++i)
         if (!std::isfinite(params[i])) return fail(VTM_ERR_INVALID, "non-finite model parameter");

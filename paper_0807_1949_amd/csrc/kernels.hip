@@ -947,6 +947,13 @@ __device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict
     backward_subst<T, R>(C, S, Vk, vec, tmp);
 }
 
+template <typename T>
+__device__ inline T cpl_y(const DevSub &D, int e);
+template <>
+__device__ inline double cpl_y<double>(const DevSub &D, int e) { return D.cpl_y64[e]; }
+template <>
+__device__ inline float cpl_y<float>(const DevSub &D, int e) { return D.cpl_y32[e]; }
+
 // One VTM sweep.  flags: kWriteX stores the local solutions; kNoWaves leaves o_next untouched
 // (a read-only solve with the current incoming waves); kZeroWaves ignores o_prev (a = 0); kWriteY
 // stores the forward result y = L^{-1} (right side) in yout (layout of the local solutions).
@@ -958,6 +965,7 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
                                                T *__restrict__ xloc, T *__restrict__ yout, int flags) {
     extern __shared__ char smraw[];
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    if (sub_inactive(D, k)) return;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
     T *vec = reinterpret_cast<T *>(smraw);  // right side, then y (forward result)
@@ -969,7 +977,8 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
     const int64_t wo = (int64_t)g * nports * R;
     const bool zero_waves = flags & kZeroWaves;
 
-    // right side of (5.8): split source + Z^{-1} * incoming wave at every port
+    // right side of (5.8): split source + Z^{-1} * incoming wave at every port (with coupled VTLs the
+    // off-diagonal entries of Z_j^{-1} add the incoming waves of the coupled ports)
     for (int i = tid; i < nk * R; i += nt) vec[i] = bs[i];
     __syncthreads();
     const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
@@ -984,6 +993,13 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
                 const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
 #pragma unroll
                 for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
+                if (D.cpl_ptr)
+                    for (int e = D.cpl_ptr[pb + j]; e < D.cpl_ptr[pb + j + 1]; ++e) {
+                        const T y = cpl_y<T>(D, e);
+                        const T *aq = o_prev + wo + (int64_t)D.cpl_tw[e] * R;
+#pragma unroll
+                        for (int c = 0; c < R; ++c) acc[c] += aq[c] * y;
+                    }
             }
 #pragma unroll
             for (int c = 0; c < R; ++c) vec[pos * R + c] = acc[c];
@@ -1028,6 +1044,7 @@ __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp,
                                                 T *__restrict__ xloc) {
     extern __shared__ char smraw[];
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    if (sub_inactive(D, k)) return;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
     T *vec = reinterpret_cast<T *>(smraw);  // y
@@ -1155,6 +1172,7 @@ template <typename T>
 __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
                                T *__restrict__ cport) {
     const int k = blockIdx.x, g = blockIdx.y;
+    if (sub_inactive(D, k)) return;
     const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
     const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
     for (int idx = threadIdx.x; idx < (pg1 - pg0) * R; idx += blockDim.x) {
@@ -1324,6 +1342,7 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
     constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
     typedef typename Mma<T>::acc Acc;
     const int k = D.gorder[blockIdx.x], g = blockIdx.y, tid = threadIdx.x, nt = 64 * W;
+    if (sub_inactive(D, k)) return;
     const int lane = tid & 63, m = lane & 15, q = lane >> 4;
     const int wv = W == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
@@ -1673,6 +1692,8 @@ __global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg,
                                                           int32_t cur0, int32_t spin_limit, int32_t *abort_flag) {
     extern __shared__ __attribute__((aligned(16))) char smraw[];
     const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    // a converged system's workgroups leave at once: their twins are in the same system
+    if (sub_inactive(D, k)) return;
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
     const int nb = (p + 15) >> 4;
     const int64_t wo = (int64_t)g * nports * R, bstride = (int64_t)gridDim.y * nports * R;
@@ -1814,10 +1835,14 @@ __global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg,
 // current waves with tag t0, the other buffer tag t0 - 1 (never the tag a reader waits for).
 // ------------------------------------------------------------------ merge, residual
 template <typename T>
-__global__ void k_merge(DevMaps M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *__restrict__ xloc,
-                        const double *__restrict__ base, int64_t ldbase, double *__restrict__ xout, int64_t ldx) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+__global__ void k_merge(DevMaps M, int64_t nsplit, int32_t nrhs, int32_t R, const T *__restrict__ xloc,
+                        const double *__restrict__ base, int64_t ldbase, double *__restrict__ xout, int64_t ldx,
+                        const int64_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_sys,
+                        const int32_t *__restrict__ active) {
+    const int ch = blockIdx.x;
+    if (active && !active[chunk_sys[ch]]) return;  // a converged system keeps its x
+    const int64_t v = chunk_row[ch] + threadIdx.x;
+    if (v >= chunk_row[ch + 1]) return;
     const int64_t p0 = M.cp_ptr[v], p1 = M.cp_ptr[v + 1];
     const double m = (double)(p1 - p0);
     for (int c = 0; c < nrhs; ++c) {
@@ -2125,10 +2150,12 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
 }
 
 template <typename T>
-void launch_merge(const DevMaps &M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc,
-                  const double *base, int64_t ldbase, double *xout, int64_t ldx, hipStream_t st) {
-    hipLaunchKernelGGL(k_merge<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, M, n, nsplit, nrhs, R, xloc, base, ldbase,
-                       xout, ldx);
+void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc, const double *base,
+                  int64_t ldbase, double *xout, int64_t ldx, const int64_t *chunk_row, const int32_t *chunk_sys,
+                  int32_t nchunks, const int32_t *active, hipStream_t st) {
+    // one workgroup per residual chunk (at most kThreads rows)
+    hipLaunchKernelGGL(k_merge<T>, dim3(nchunks), dim3(kThreads), 0, st, M, nsplit, nrhs, R, xloc, base, ldbase,
+                       xout, ldx, chunk_row, chunk_sys, active);
 }
 
 void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, int64_t ldb, const double *x, int64_t ldx,
@@ -2171,9 +2198,11 @@ template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int
                                   const int64_t *, const float *, const int32_t *, const float *, const float *,
                                   float *, hipStream_t);
 template hipError_t prepare_sweep<float>(int32_t, int32_t, int32_t, int32_t);
-template void launch_merge<double>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const double *, const double *,
-                                   int64_t, double *, int64_t, hipStream_t);
-template void launch_merge<float>(const DevMaps &, int64_t, int64_t, int32_t, int32_t, const float *, const double *,
-                                  int64_t, double *, int64_t, hipStream_t);
+template void launch_merge<double>(const DevMaps &, int64_t, int32_t, int32_t, const double *, const double *, int64_t,
+                                   double *, int64_t, const int64_t *, const int32_t *, int32_t, const int32_t *,
+                                   hipStream_t);
+template void launch_merge<float>(const DevMaps &, int64_t, int32_t, int32_t, const float *, const double *, int64_t,
+                                  double *, int64_t, const int64_t *, const int32_t *, int32_t, const int32_t *,
+                                  hipStream_t);
 
 }  // namespace vtm

@@ -51,7 +51,19 @@ struct DevSub {
     const int32_t *port_ptr; // first port of each subgraph (nsub + 1)
     const uint16_t *port_pg; // port -> index of its port vertex (group) in its subgraph
     const int32_t *gorder;   // subgraphs by decreasing size of G_k (launch order of the port-reduced sweep)
+    const int32_t *sub_sys;  // independent system of each subgraph
+    const int32_t *active;   // per system: 0 once it has converged (its subgraphs skip sweeps and test
+                             // solves); nullptr = every system active
+    // coupled VTLs: per port p, entries [cpl_ptr[p], cpl_ptr[p + 1]) name the twin of each other port q
+    // of its subgraph coupled with it and (Z_j^{-1})_pq; cpl_ptr == nullptr when Z is diagonal
+    const int32_t *cpl_ptr;
+    const int32_t *cpl_tw;
+    const double *cpl_y64;
+    const float *cpl_y32;
 };
+
+// Skip the workgroups of converged systems (done mask of a batched solve).
+__device__ inline bool sub_inactive(const DevSub &D, int k) { return D.active && !D.active[D.sub_sys[k]]; }
 
 // Column plan of the port Green's functions computed inside the factorisation.  Ports of a subgraph
 // are sorted by the postorder of their supernode, so the ports below supernode s form one column
@@ -154,10 +166,13 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
                                 float *plain0, float *plain1, int32_t t0, int32_t nsw, int32_t cur0,
                                 int32_t spin_limit, int32_t *abort_flag, hipStream_t st);
 
-// xout[v + c*ldx] = (base ? base[v + c*ldb] : 0) + mean over the children of v of xloc.
+// xout[v + c*ldx] = (base ? base[v + c*ldbase] : 0) + mean over the children of v of xloc, by residual
+// chunks (chunk_row[nchunks + 1]: row ranges of at most 256 rows inside one system, chunk_sys: their
+// systems); the rows of a system with active[s] == 0 are left as they are (active may be null).
 template <typename T>
-void launch_merge(const DevMaps &M, int64_t n, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc,
-                  const double *base, int64_t ldbase, double *xout, int64_t ldx, hipStream_t st);
+void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc, const double *base,
+                  int64_t ldbase, double *xout, int64_t ldx, const int64_t *chunk_row, const int32_t *chunk_sys,
+                  int32_t nchunks, const int32_t *active, hipStream_t st);
 
 // r = b - A x (optional store), per (rhs, system) relative residual into relres[c * nsys + s], and
 // relres[nsys * nrhs] = 1 if *flag is set (flag may be null), so that one copy brings both to the host.

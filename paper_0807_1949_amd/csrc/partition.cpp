@@ -63,16 +63,12 @@ int grid_membership(const vtm_partition_spec &sp, Partition &P, std::string &err
     return VTM_OK;
 }
 
-int rcb_membership(const vtm_partition_spec &sp, Partition &P, std::string &err) {
-    const int32_t *d = sp.dims;
-    if ((int64_t)d[0] * d[1] * d[2] != P.n || sp.levels < 0 || sp.levels > 20) {
-        err = "RCB dims/levels invalid";
-        return VTM_ERR_INVALID;
-    }
-    std::vector<Box> leaves;
-    leaves.reserve((size_t)1 << sp.levels);
-    SplitMix64 rng{sp.seed};
-    // explicit depth-first pre-order: a stack of (box, depth); right child pushed first
+// Leaf boxes of the seeded RCB of the vertex grid d (depth-first pre-order, explicit stack with
+// the right child pushed first).  The cut percent is q = 49 + (splitmix64 mod 3).
+int rcb_leaves(const int32_t *d, int levels, uint64_t seed, std::vector<Box> &leaves, std::string &err) {
+    leaves.clear();
+    leaves.reserve((size_t)1 << levels);
+    SplitMix64 rng{seed};
     std::vector<std::pair<Box, int>> stack;
     Box root;
     for (int a = 0; a < 3; ++a) { root.lo[a] = 0; root.hi[a] = d[a] - 1; }
@@ -80,13 +76,13 @@ int rcb_membership(const vtm_partition_spec &sp, Partition &P, std::string &err)
     while (!stack.empty()) {
         auto [b, depth] = stack.back();
         stack.pop_back();
-        if (depth == sp.levels) { leaves.push_back(b); continue; }
+        if (depth == levels) { leaves.push_back(b); continue; }
         int ax = 0;
         for (int a = 1; a < 3; ++a)
             if (b.hi[a] - b.lo[a] > b.hi[ax] - b.lo[ax]) ax = a;
         int32_t len = b.hi[ax] - b.lo[ax];
         if (len < 2) { err = "RCB box too thin to cut"; return VTM_ERR_PARTITION; }
-        int32_t q = 46 + (int32_t)(rng.next() % 9);
+        int32_t q = 49 + (int32_t)(rng.next() % 3);
         int32_t c = b.lo[ax] + (int32_t)(((int64_t)len * q + 50) / 100);
         Box l = b, r = b;
         l.hi[ax] = c;
@@ -94,7 +90,18 @@ int rcb_membership(const vtm_partition_spec &sp, Partition &P, std::string &err)
         stack.push_back({r, depth + 1});
         stack.push_back({l, depth + 1});
     }
-    P.nsub = (int32_t)leaves.size();
+    return VTM_OK;
+}
+
+constexpr int kRcbTries = 64;  // seeds seed, seed + 1, ... tried until every owned size is in bounds
+
+int rcb_membership(const vtm_partition_spec &sp, Partition &P, std::string &err) {
+    const int32_t *d = sp.dims;
+    if ((int64_t)d[0] * d[1] * d[2] != P.n || sp.levels < 0 || sp.levels > 20) {
+        err = "RCB dims/levels invalid";
+        return VTM_ERR_INVALID;
+    }
+    std::vector<Box> leaves;
     std::vector<int32_t> cnt(P.n, 0);
     auto each = [&](const Box &b, auto &&fn) {
         for (int32_t z = b.lo[2]; z <= b.hi[2]; ++z)
@@ -103,21 +110,34 @@ int rcb_membership(const vtm_partition_spec &sp, Partition &P, std::string &err)
                 for (int32_t x = b.lo[0]; x <= b.hi[0]; ++x) fn(row + x);
             }
     };
-    for (const Box &b : leaves) each(b, [&](int64_t v) { cnt[v]++; });
-    P.s_ptr.assign(P.n + 1, 0);
-    for (int64_t v = 0; v < P.n; ++v) P.s_ptr[v + 1] = P.s_ptr[v] + cnt[v];
-    P.s_idx.assign(P.s_ptr[P.n], 0);
-    std::fill(cnt.begin(), cnt.end(), 0);
-    for (int32_t k = 0; k < P.nsub; ++k) each(leaves[k], [&](int64_t v) { P.s_idx[P.s_ptr[v] + cnt[v]++] = k; });
-    for (int32_t k = 0; k < P.nsub; ++k) {
-        double own = 0.0;  // ascending vertex order
-        each(leaves[k], [&](int64_t v) { own += 1.0 / (double)(P.s_ptr[v + 1] - P.s_ptr[v]); });
-        if (own < sp.min_size || own > sp.max_size) {
-            err = "RCB box " + std::to_string(k) + " owned size " + std::to_string(own) + " outside bounds";
-            return VTM_ERR_PARTITION;
+    std::string last;
+    for (int t = 0; t < kRcbTries; ++t) {
+        const uint64_t seed = sp.seed + (uint64_t)t;
+        int rc = rcb_leaves(d, sp.levels, seed, leaves, err);
+        if (rc) return rc;
+        P.nsub = (int32_t)leaves.size();
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (const Box &b : leaves) each(b, [&](int64_t v) { cnt[v]++; });
+        P.s_ptr.assign(P.n + 1, 0);
+        for (int64_t v = 0; v < P.n; ++v) P.s_ptr[v + 1] = P.s_ptr[v] + cnt[v];
+        bool ok = true;
+        for (int32_t k = 0; k < P.nsub && ok; ++k) {
+            double own = 0.0;  // ascending vertex order
+            each(leaves[k], [&](int64_t v) { own += 1.0 / (double)(P.s_ptr[v + 1] - P.s_ptr[v]); });
+            if (own < sp.min_size || own > sp.max_size) {
+                ok = false;
+                last = "RCB box " + std::to_string(k) + " owned size " + std::to_string(own) + " outside bounds";
+            }
         }
+        if (!ok) continue;
+        P.s_idx.assign(P.s_ptr[P.n], 0);
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int32_t k = 0; k < P.nsub; ++k) each(leaves[k], [&](int64_t v) { P.s_idx[P.s_ptr[v] + cnt[v]++] = k; });
+        P.rcb_seed = seed;
+        return VTM_OK;
     }
-    return VTM_OK;
+    err = last + " for seeds " + std::to_string(sp.seed) + " .. " + std::to_string(sp.seed + kRcbTries - 1);
+    return VTM_ERR_PARTITION;
 }
 
 int graph_membership(const vtm_partition_spec &sp, const Csr &A, Partition &P, std::string &err) {

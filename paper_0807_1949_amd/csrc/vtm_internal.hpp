@@ -39,6 +39,7 @@ struct Partition {
     int32_t nsys = 1;
     std::vector<int64_t> sys_ptr;           // vertex ranges of independent systems
     std::vector<int32_t> sub_sys;           // system of each subgraph
+    uint64_t rcb_seed = 0;                  // RCB: the seed whose boxes met the owned-size bounds
 };
 
 int build_partition(const Csr &A, const vtm_partition_spec &spec, Partition &P, std::string &err);

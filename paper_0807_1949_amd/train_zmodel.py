@@ -129,7 +129,7 @@ def main(argv=None):
     summ = {}
     for fam in sorted(set(r["family"] for r in rows)):
         rr = [r for r in rows if r["family"] == fam]
-        summ[fam] = {k: dict(sweeps=float(np.mean([r[k]["sweeps"] for r in rr])),
+        summ[fam] = {k: dict(sweeps=float(np.mean([r[k]["sweeps"] or r[k]["sweeps_run"] for r in rr])),
                              time_s=float(np.mean([r[k]["time_s"] for r in rr]))) for k in ("diag", "uniform", "learned")}
     log("summary " + json.dumps(summ))
     if args.report:

@@ -96,3 +96,51 @@ def test_learned_z_setup_and_solve(B):
     ro = O.Solver(Po, z).run(cfg["b"], 100000, 10, 1e-8)
     assert int(ro["iters"][0, 0]) == int(r["iters"][0, 0])
     assert np.linalg.norm(r["x"][0] - ro["x"][0]) <= 1e-8 * np.linalg.norm(ro["x"][0])
+
+
+def test_zmodel_load_checks_blob_size(B):
+    import gen
+
+    cfg = gen.make_config("c1")
+    h = B.VTM(device=0)
+    h.evs_partition(cfg["A"], cfg["spec"])
+    with pytest.raises(B.VTMError) as e:
+        h.zmodel_load(np.zeros(M.NPARAMS - 1, np.float32))
+    assert e.value.code == B.VTM_ERR_INVALID
+    with pytest.raises(B.VTMError) as e:
+        h.setup(B.VTM_Z_LEARNED)
+    assert e.value.code == B.VTM_ERR_STATE
+
+
+@pytest.mark.parametrize("seed", [4200, 4201])
+def test_trained_model_beats_diagonal_rule_on_held_out_systems(B, seed):
+    """The committed trained network (zmodel_weights.json) on held-out systems of the learned-Z workload
+    (512^2 GRF diffusion, 16 x 16 tiles, evaluation seeds never used in training): sweeps to 1e-8 on
+    the FP32 + FP64-refinement path with a fixed test cadence, against the diagonal rule Z = 1/a_vv and
+    uniform multipliers alpha / a_vv of the label grid (reported beside it)."""
+    import gen
+    from paper_0807_1949_amd import zmodel as Zm
+
+    cfg = gen.configs.c4(seed=seed)
+    print(f"[learned-Z] c4 seed {seed}", flush=True)
+
+    def sweeps(rule, z=None, cap=60000):
+        h = B.VTM(device=0, precision=B.VTM_FP32_IR, check_every=20, max_sweeps=cap)
+        h.evs_partition(cfg["A"], cfg["spec"])
+        if rule == B.VTM_Z_LEARNED:
+            h.zmodel_load(Zm.load())
+        h.setup(rule, z)
+        r = h.solve(cfg["b"], 1e-8)
+        st = h.get_stats()
+        zz = h.get_z()
+        h.close()
+        return (int(r["iters"].max()) if r["status"] == 0 else None), int(st["sweeps"]), zz
+
+    n_lrn, _, _ = sweeps(B.VTM_Z_LEARNED)
+    n_diag, tot_diag, z0 = sweeps(B.VTM_Z_DIAG)
+    uni = {a: sweeps(B.VTM_Z_USER, a * z0, cap=20000)[0] for a in (16.0, 32.0, 64.0, 128.0)}
+    best = min((v, a) for a, v in uni.items() if v is not None)
+    print(f"    sweeps to 1e-8: learned {n_lrn}, diagonal rule {n_diag if n_diag else '> %d' % tot_diag}, "
+          f"uniform {uni} (best alpha {best[1]:g}: {best[0]})", flush=True)
+    assert n_lrn is not None
+    assert n_diag is None or n_lrn * 10 <= n_diag

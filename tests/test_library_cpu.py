@@ -61,14 +61,20 @@ def test_partition_bit_exact_rules(split, topo):
     _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"], split=split, topology=topo))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c3", "c5"])
 def test_partition_bit_exact_full(name):
+    """Every workload at full size, including the 3D RCB (4096 boxes) and the 64-system graph batch."""
     cfg = gen.make_config(name)
     h = _host_handle()
-    info = h.evs_partition(cfg["A"], cfg["spec"])
-    _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"]))
+    info = h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+    op = O.Partition(cfg["A"], cfg["spec"])
+    _assert_partition_equal(h.get_partition(), op)
     if name == "c2":
         assert info["nsub"] == 1024 and info["n_split"] == 1113025 and info["nvtl"] == 65410
+    if name == "c3":
+        assert info["nsub"] == 4096 and info["rcb_seed"] == op.rcb_seed
+    if name == "c5":
+        assert info["nsys"] == 64 and info["nsub"] == sum(b[2] for b in cfg["spec"]["blocks"])
 
 
 def test_partition_errors():

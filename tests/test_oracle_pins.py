@@ -317,3 +317,177 @@ def test_graph_partition_covers_edges():
     for k in range(P.nsub):
         lv = P.loc_vtx[P.loc_ptr[k]:P.loc_ptr[k + 1]]
         assert np.searchsorted(sp, lv.min(), "right") == np.searchsorted(sp, lv.max(), "right")
+
+
+@pytest.mark.parametrize("name", ["c2", "c5"])
+def test_oracle_relres_is_the_true_residual(name):
+    """The relative residual that the oracle reports (Table 1 step 6, per system) equals
+    ||b - A x||_2 / ||b||_2 recomputed from its returned x with SciPy's sparse product."""
+    cfg = gen.make_config(name, small=True)
+    P = O.Partition(cfg["A"], cfg["spec"])
+    sp = cfg["sys_ptr"]
+    A = cfg["A"].to_scipy()
+    for sweeps in (1, 17):
+        r = O.Solver(P, 8.0 * P.zdiag).run(cfg["b"][:2], sweeps, 0, 0.0, sys_ptr=sp)
+        for c in range(r["x"].shape[0]):
+            res = cfg["b"][c] - A @ r["x"][c]
+            for s in range(cfg["nsys"]):
+                lo, hi = sp[s], sp[s + 1]
+                want = np.linalg.norm(res[lo:hi]) / np.linalg.norm(cfg["b"][c, lo:hi])
+                assert abs(r["relres"][c, s] - want) <= 1e-12 * want, (c, s, r["relres"][c, s], want)
+
+
+def test_face_pairing_3d_eight_way_point():
+    """Fig. 7 in 3D: a 9^3 grid in 2 x 2 x 2 tiles.  The centre vertex has 8 children joined as the edges
+    of a cube (12 VTLs, 3 ports per child, only tiles that differ in one tile index); vertices on a
+    tile edge have 4 children with 2 ports each; face vertices 2 children with 1 port each."""
+    A = gen.poisson3d_dirichlet(9)
+    P = O.Partition(A, dict(kind="grid", dims=(9, 9, 9), parts=(2, 2, 2)))
+    mult = P.multiplicity()
+    centre = (4 * 9 + 4) * 9 + 4
+    assert mult[centre] == 8 and (mult == 8).sum() == 1
+    at = P.vtl_v == centre
+    assert at.sum() == 12
+    for k, k2 in zip(P.vtl_k[at], P.vtl_k2[at]):
+        ti = np.array([k % 2, (k // 2) % 2, k // 4])
+        tj = np.array([k2 % 2, (k2 // 2) % 2, k2 // 4])
+        assert np.abs(ti - tj).sum() == 1
+    kp = np.repeat(np.arange(P.nsub), np.diff(P.port_ptr))
+    for want_mult, ports_per_child in ((8, 3), (4, 2), (2, 1)):
+        vs = np.nonzero(mult == want_mult)[0]
+        assert len(vs) > 0
+        sel = np.isin(P.port_v, vs)
+        _, cnt = np.unique(P.port_v[sel] * P.nsub + kp[sel], return_counts=True)
+        assert (cnt == ports_per_child).all(), want_mult
+    # the twin of a twin is the port itself, and twins sit at the same vertex in the other tile
+    assert np.array_equal(P.port_twin[P.port_twin], np.arange(P.nports))
+    assert np.array_equal(P.port_v[P.port_twin], P.port_v)
+    assert np.array_equal(P.port_other, kp[P.port_twin])
+
+
+def test_rcb_owned_sizes_within_bounds_3d_workload():
+    """The 3D workload's RCB: 4096 boxes, every owned size sum 1/|S(v)| in [300, 700] (recomputed here
+    from the membership), the sizes summing to n, and the seed actually used reported."""
+    cfg = gen.make_config("c3")
+    P = O.Partition(cfg["A"], cfg["spec"])
+    assert P.nsub == 4096 and P.rcb_seed >= cfg["spec"]["seed"]
+    inv = 1.0 / P.multiplicity()
+    own = np.add.reduceat(inv[P.loc_vtx], P.loc_ptr[:-1])
+    assert own.min() >= 300.0 and own.max() <= 700.0, (own.min(), own.max())
+    assert abs(own.sum() - cfg["A"].n) <= 1e-6 * cfg["A"].n
+
+
+# ------------------------------------------------------------ coupled VTLs (Section 7.2)
+
+def _interface_coupling(P, z, beta):
+    """Tridiagonal coupling along every interface: consecutive VTLs (by vertex) that join the same two
+    subgraphs get Z_lm = beta sqrt(Z_l Z_m); with |beta| < 1/2 every block is SPD."""
+    key = P.vtl_k.astype(np.int64) * P.nsub + P.vtl_k2
+    order = np.lexsort((P.vtl_v, key))
+    l1, l2 = [], []
+    for a, b in zip(order[:-1], order[1:]):
+        if key[a] == key[b]:
+            l1.append(a), l2.append(b)
+    l1, l2 = np.array(l1, np.int64), np.array(l2, np.int64)
+    return l1, l2, beta * np.sqrt(z[l1] * z[l2])
+
+
+def _z_matrix(nvtl, z, coupling):
+    Z = np.diag(z)
+    l1, l2, zc = coupling
+    Z[l1, l2] = zc
+    Z[l2, l1] = zc
+    return Z
+
+
+def test_coupled_example_51_theorem_71(golden):
+    """Example 5.1 with T3 and T4 coupled by an SPD 2 x 2 Z, iterated through (5.7) itself: it converges
+    to the solution of (3.2) (Theorem 7.1), twins agree and their currents cancel; with the coupling
+    set to zero the (5.7) iterates equal those of (5.8) with Z = (1, 0.5)."""
+    A = np.array(golden["system_3_2"]["A"], float)
+    xs = np.linalg.solve(A, np.array(golden["system_3_2"]["b"], float))
+    S = T.example_41()
+    hist, u, w = S.vtm_coupled(np.array([[1.0, 0.3], [0.3, 0.5]]), 120)
+    assert np.abs(hist[-1] - xs).max() < 1e-13
+    assert np.abs(u[:, 0] - u[:, 1]).max() < 1e-13 and np.abs(w[:, 0] + w[:, 1]).max() < 1e-13
+    h57, _, _ = S.vtm_coupled(np.diag(golden["example_5_1"]["Z"]), 10)
+    h58 = S.vtm(golden["example_5_1"]["Z"], 10)[0]
+    assert np.abs(h57 - h58).max() < 1e-14
+
+
+@pytest.mark.parametrize("seed,nparts", [(0, 2), (1, 3), (2, 4)])
+def test_coupled_oracle_matches_dense_57(seed, nparts):
+    """The C oracle with coupled VTLs (Z_j^{-1} in the port block of (5.8), w = Z_j^{-1}(a - u),
+    o = u - Z_j w) equals the unreduced (5.7) iteration sweep by sweep, on tiny random systems with a
+    random dense SPD block per pair of subgraphs."""
+    A, csr, spec = _tiny_random_system(26 + 4 * seed, 20 + seed, nparts)
+    b = np.random.default_rng(30 + seed).uniform(-1, 1, A.shape[0])
+    P = O.Partition(csr, spec)
+    rng = np.random.default_rng(40 + seed)
+    z = rng.uniform(0.5, 2.0, P.nvtl) * P.zdiag
+    key = P.vtl_k.astype(np.int64) * P.nsub + P.vtl_k2
+    l1, l2, zc = [], [], []
+    for kk in np.unique(key):
+        ls = np.nonzero(key == kk)[0]
+        m = len(ls)
+        if m < 2:
+            continue
+        M = rng.standard_normal((m, m))
+        C = M @ M.T / m * np.sqrt(np.outer(z[ls], z[ls])) * 0.3
+        for i in range(m):
+            for j in range(i + 1, m):
+                l1.append(ls[i]), l2.append(ls[j]), zc.append(C[i, j])
+        z[ls] += np.diag(C)
+    cpl = (np.array(l1, np.int64), np.array(l2, np.int64), np.array(zc))
+    assert len(cpl[0]) > 0
+    Zv = _z_matrix(P.nvtl, z, cpl)
+    assert np.linalg.eigvalsh(Zv).min() > 0
+    hist, _, _ = T.from_oracle_partition(P, b).vtm_coupled(Zv, 15)
+    s = O.Solver(P, z, coupling=cpl)
+    for k in (1, 2, 6, 15):
+        r = s.run(b, k, 0, 0.0)
+        assert np.abs(r["x"][0] - hist[k - 1]).max() <= 1e-13 * np.abs(hist[k - 1]).max(), k
+
+
+def test_coupled_diagonal_reproduces_uncoupled():
+    """A coupled set-up with no off-diagonal entries reproduces the diagonal-Z iterates (to rounding:
+    the diagonal block is inverted through its Cholesky factor)."""
+    cfg = gen.make_config("c2", small=True)
+    P = O.Partition(cfg["A"], cfg["spec"])
+    z = 8.0 * P.zdiag
+    e = np.zeros(0, np.int64)
+    x0 = O.Solver(P, z).run(cfg["b"], 30, 0, 0.0)["x"][0]
+    x1 = O.Solver(P, z, coupling=(e, e, np.zeros(0))).run(cfg["b"], 30, 0, 0.0)["x"][0]
+    assert np.abs(x1 - x0).max() <= 1e-13 * np.abs(x0).max()
+
+
+@pytest.mark.parametrize("beta", [-0.3, 0.3])
+def test_coupled_converges_and_is_nonexpansive(beta):
+    """Theorem 7.1 on a 2D grid in 3 x 3 tiles with SPD tridiagonal coupling along every interface: the
+    iteration reaches the dense Cholesky solution, and the wave error measured in the norm
+    e^T Zhat^{-1} e (Zhat: the block-diagonal port impedance, twin-symmetric) never grows (the
+    argument of Appendix 3 with Z_j a matrix: one sweep maps the scaled error by J(2W - I))."""
+    A = gen.lognormal_conductance_2d(25, seed=7, shift=1e-2)
+    spec = dict(kind="grid", dims=(25, 25, 1), parts=(3, 3, 1))
+    P = O.Partition(A, spec)
+    z = 8.0 * P.zdiag
+    cpl = _interface_coupling(P, z, beta)
+    b = np.random.default_rng(3).uniform(-1, 1, A.n)
+    s = O.Solver(P, z, coupling=cpl)
+    r = s.run(b, 50000, 1, 1e-13)
+    xref = T.dense_cholesky_solve(A.to_dense(), b)
+    assert r["iters"][0, 0] > 0 and np.abs(r["x"][0] - xref).max() <= 1e-10 * np.abs(xref).max()
+    # the port-level inverse impedance: Zhat^{-1} restricted to each subgraph's ports of one group
+    Zv = _z_matrix(P.nvtl, z, cpl)
+    Y = np.linalg.inv(Zv)  # block diagonal like Zv
+    kp = np.repeat(np.arange(P.nsub), np.diff(P.port_ptr))
+    same = kp[:, None] == kp[None, :]
+    Yp = Y[np.ix_(P.port_vtl, P.port_vtl)] * same
+    assert np.allclose(Yp[np.ix_(P.port_twin, P.port_twin)], Yp, rtol=0, atol=1e-14 * np.abs(Yp).max())
+    a_star = s.run(b, 6000, 0, 0.0)["waves"][0]
+    prev = np.inf
+    for k in range(1, 60):
+        e = s.run(b, k, 0, 0.0)["waves"][0] - a_star
+        nrm = float(e @ Yp @ e)
+        assert nrm <= prev * (1 + 1e-9) + 1e-28, (k, nrm, prev)
+        prev = nrm
