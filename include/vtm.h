@@ -261,6 +261,17 @@ vtm_status vtm_setup_coupled(vtm_handle h, const double *z_vtl, int64_t ncouple,
 vtm_status vtm_input_impedance(vtm_handle h, double *r_port);
 
 /*
+ * vtm_input_impedance for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same values, computed on the device
+ * into a fixed scratch of 2^22 doubles (32 MiB) that each GPU the library runs on holds until the
+ * process ends; no hipMalloc, hipFree or allocating call.  r_port[nports] may be a host or a device
+ * pointer.  More than 2^22 ports: VTM_ERR_INVALID.  Every call on one GPU uses that GPU's scratch,
+ * so calls that overlap on one GPU (from several threads or streams) race; the scratch keeps the last
+ * call's values and every entry the call returns is written by it.  Errors as vtm_input_impedance.
+ */
+vtm_status vtm_input_impedance_noalloc(vtm_handle h, double *r_port);
+
+/*
  * Solve A X = B for nrhs right-hand sides: zero initial waves (Example 5.1),
  * sweeps until every system's relative residual ||b - A xbar||_2 / ||b||_2 is
  * <= tol for every column, where xbar_v is the mean of the children of v

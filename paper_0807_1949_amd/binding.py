@@ -69,7 +69,7 @@ EXPORTS = ("vtm_create", "vtm_destroy", "vtm_last_error", "vtm_evs_partition", "
            "vtm_debug_class", "vtm_zfeatures", "vtm_zmodel_load", "vtm_get_z", "vtm_input_impedance", "vtm_trainer_create",
            "vtm_trainer_destroy", "vtm_trainer_set_data", "vtm_trainer_grad", "vtm_trainer_epoch",
            "vtm_trainer_predict", "vtm_trainer_get_params", "vtm_autotune", "vtm_batch_solve",
-           "vtm_setup_coupled")
+           "vtm_setup_coupled", "vtm_input_impedance_noalloc")
 NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 12, 5081, 5057
 
 
@@ -99,6 +99,7 @@ def lib():
         L.vtm_batch_solve.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_double, P, P, P, P]
         L.vtm_get_z.argtypes = [P, P]
         L.vtm_input_impedance.argtypes = [P, P]
+        L.vtm_input_impedance_noalloc.argtypes = [P, P]
         L.vtm_trainer_create.argtypes = [C.c_int32, P, C.POINTER(C.c_void_p)]
         L.vtm_trainer_destroy.argtypes = [P]
         L.vtm_trainer_set_data.argtypes = [P, P, P, C.c_int64]
@@ -342,6 +343,14 @@ class VTM:
         """Input impedance of every port (Definition 7.1) with the other ports terminated by their Z."""
         r = np.zeros(self.info["nports"])
         _check(lib().vtm_input_impedance(self._h, _np_ptr(r)))
+        return r
+
+    def input_impedance_noalloc(self, out=None):
+        """vtm_input_impedance_noalloc: the same values without any device allocation; out may be a
+        preallocated host array or device tensor of nports doubles."""
+        r = np.zeros(self.info["nports"]) if out is None else out
+        ptr = C.c_void_p(r.data_ptr()) if _is_torch(r) else _np_ptr(r)
+        _check(lib().vtm_input_impedance_noalloc(self._h, ptr))
         return r
 
     def get_z(self) -> np.ndarray:

@@ -1834,6 +1834,13 @@ vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
         delete h;
         return fail(VTM_ERR_HIP, hipGetErrorString(e));
     }
+    {  // the allocation-free entry points' scratch: its address on this device, looked up once
+        double *scr = nullptr;
+        if ((e = vtm::noalloc_scratch(h->opt.device, &scr)) != hipSuccess) {
+            delete h;
+            return fail(VTM_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+        }
+    }
     if (h->opt.stream) h->stream = (hipStream_t)h->opt.stream;
     else {
         if ((e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking)) != hipSuccess) {
@@ -1954,6 +1961,26 @@ vtm_status vtm_input_impedance(vtm_handle h, double *r_port) {
     vtm_status rc = port_rin(h, z, r);
     if (rc) return rc;
     std::copy(r.begin(), r.end(), r_port);
+    return VTM_OK;
+}
+
+vtm_status vtm_input_impedance_noalloc(vtm_handle h, double *r_port) {
+    if (!h || !r_port) return fail(VTM_ERR_INVALID, "bad argument");
+    if (!h->set_up) return fail(VTM_ERR_STATE, "vtm_input_impedance_noalloc before vtm_setup");
+    if (!h->have_green) return fail(VTM_ERR_STATE, "input impedances need the port Green's functions");
+    if ((size_t)h->nports > vtm::kNoAllocDoubles)
+        return fail(VTM_ERR_INVALID, std::to_string(h->nports) + " ports exceed the scratch of " +
+                                         std::to_string(vtm::kNoAllocDoubles) + " values");
+    HIP_TRY(hipSetDevice(h->opt.device));
+    double *scr = nullptr;
+    HIP_TRY(vtm::noalloc_scratch(h->opt.device, &scr));
+    if (h->nports == 0) return VTM_OK;
+    vtm::launch_rin(dev_sub(h), h->P.nsub, h->d_goff.as<int64_t>(), h->d_G64.as<double>(), h->d_invz64.as<double>(),
+                    scr, h->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(r_port, scr, sizeof(double) * (size_t)h->nports,
+                           is_device_ptr(r_port) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
     return VTM_OK;
 }
 

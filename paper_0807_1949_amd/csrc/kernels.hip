@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 
@@ -1167,6 +1168,23 @@ __global__ void k_gdiag(DevSub D, const int64_t *__restrict__ goff, const double
     for (int j = threadIdx.x; j < p; j += blockDim.x) gd[pg0 + j] = G[goff[k] + gpack_index(nb, j, j)];
 }
 
+// Input impedance of every port (Definition 7.1) with the other ports of its subgraph terminated by
+// their Z: with g the diagonal entry of G_k at the port's vertex, r = 1 / (1/g - 1/Z_p); +inf where the
+// port's own termination is what makes K_k definite (1/g - 1/Z_p <= 1e-14 / g).  One workgroup per
+// subgraph, one thread per port.
+__global__ void k_rin(DevSub D, const int64_t *__restrict__ goff, const double *__restrict__ G,
+                      const double *__restrict__ invz, double *__restrict__ r) {
+    const int k = blockIdx.x;
+    const int p = D.pg_ptr[k + 1] - D.pg_ptr[k], nb = (p + 15) >> 4;
+    const double *Gk = G + goff[k];
+    for (int t = D.port_ptr[k] + threadIdx.x; t < D.port_ptr[k + 1]; t += blockDim.x) {
+        const int i = D.port_pg[t];
+        const double g = Gk[gpack_index(nb, i, i)];
+        const double d = 1.0 / g - invz[t];
+        r[t] = d > 1e-14 / g ? 1.0 / d : __builtin_inf();
+    }
+}
+
 // c[g][q][c] = K^{-1} b~ at the port vertices (local solutions of a zero-wave solve).
 template <typename T>
 __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
@@ -2047,6 +2065,35 @@ void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk
 
 void launch_gdiag(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, double *gd, hipStream_t st) {
     hipLaunchKernelGGL(k_gdiag, dim3(nsub), dim3(128), 0, st, D, goff, G, gd);
+}
+
+void launch_rin(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, const double *invz, double *r,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_rin, dim3(nsub), dim3(128), 0, st, D, goff, G, invz, r);
+}
+
+// Scratch of the allocation-free entry points: one array per GPU, held until the process ends.
+// Host code never passes the name itself to a kernel (on the host it only stands for the symbol);
+// it takes each device's address with hipGetSymbolAddress, once per device with that device current.
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+hipError_t noalloc_scratch(int device, double **ptr) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current first
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double *>(p);
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 template <typename T>

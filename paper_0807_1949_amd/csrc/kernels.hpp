@@ -135,6 +135,14 @@ void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk
                   const double *vals, const int64_t *goff, double *G, hipStream_t st);
 // gd[port vertex] = diagonal entry of its G_k (FP64).
 void launch_gdiag(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, double *gd, hipStream_t st);
+// r[port] = input impedance of the port (Definition 7.1, other ports terminated) from the FP64 G_k.
+void launch_rin(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, const double *invz, double *r,
+                hipStream_t st);
+// Scratch of the allocation-free entry points: kNoAllocDoubles doubles per device in a file-scope device
+// array; *ptr = its address on `device`, which must be current (looked up once per device, then cached).
+constexpr size_t kNoAllocDoubles = (size_t)1 << 22;  // 32 MiB
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, double **ptr);
 // cport[g][port vertex][R] = local solutions at the port vertices.
 template <typename T>
 void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t nsplit, int32_t npg, int32_t R,
