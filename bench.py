@@ -175,16 +175,16 @@ def measured_traffic(kernel, summary):
     return None if f is None else float(f[key])
 
 
-def setup_mfma():
+def setup_mfma(workload):
     """Matrix-core use of the factorisation kernel from its counters (FP64 MFMA FLOPs per launch over
     the launch's duration), or None when the kernels have changed since."""
     keys = ("k_factor-mfma-flops-per-launch", "k_factor-duration-us")
-    f = _profile_fields("setup_mfma_c2_lognormal_1024.md", keys)
+    f = _profile_fields(f"setup_mfma_{workload}.md", keys)
     if f is None:
         return None
     flops, us = float(f[keys[0]]), float(f[keys[1]])
     achieved = flops / (us * 1e-6) / 1e12
-    return dict(kernel="k_factor", workload="c2", bound="latency", mfma_dtype="f64", flops_per_launch=flops,
+    return dict(kernel="k_factor", workload=workload, bound="latency", mfma_dtype="f64", flops_per_launch=flops,
                 avg_launch_us=us, achieved=achieved, peak=78.6, unit="TFLOP/s", frac=achieved / 78.6)
 
 
@@ -478,7 +478,7 @@ def main():
             e["speedup_vs_fp64_diag_sub"] = p["step_s"] / r["step_s"]
         extra[w] = e
     line["extra_workloads"] = extra
-    line["setup_mfma"] = setup_mfma()
+    line["setup_mfma"] = setup_mfma(cfg["name"])
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 

@@ -119,6 +119,9 @@ struct vtm_ctx {
     DevBuf d_fvtx, d_fmul, d_cpptr, d_cpidx, d_rp, d_ci, d_v, d_aval, d_twin, d_portvtl, d_chunkrow, d_chunksys,
         d_syschunk, d_subsys, d_active;
     bool mask_on = false;          // sweeps and test solves skip converged systems (batched solves)
+    DevBuf d_sublist;              // subgraphs of the systems still sweeping, largest G_k first
+    std::vector<int32_t> h_gorder, h_sublist;
+    bool list_on = false;          // launches cover d_sublist only (h_sublist.size() workgroups)
     int32_t *active_host = nullptr;  // pinned per-system flags of the done mask
     size_t active_cap = 0;
     uint64_t setup_id = 0;         // unique id of the last vtm_setup (batch solves rebuild when one changes)
@@ -149,6 +152,7 @@ struct vtm_ctx {
         int64_t count = 0;
         int32_t R = 0, ng = 0, threads = 0, variant = 0;
         const void *ptrs[8] = {};
+        int32_t nlaunch = 0;
     } graphs[2];
     void drop_graphs() {
         for (auto &g : graphs) {
@@ -172,7 +176,7 @@ struct vtm_ctx {
                           &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr,
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
-                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
+                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_sublist, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
                           &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gorder, &d_portpg, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
@@ -271,7 +275,13 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     d.cpl_tw = h->d_cpltw.as<int32_t>();
     d.cpl_y64 = h->d_cply64.as<double>();
     d.cpl_y32 = h->d_cply32.as<float>();
+    d.sub_list = h->mask_on && h->list_on ? h->d_sublist.as<int32_t>() : nullptr;
     return d;
+}
+
+// Workgroups of a launch over the subgraphs: the active list under the done mask, else all.
+int32_t nsub_launch(const vtm_ctx *h) {
+    return h->mask_on && h->list_on ? (int32_t)h->h_sublist.size() : h->P.nsub;
 }
 
 // Column plan of the port Green's functions (computed inside k_factor).  Ports are sorted by the
@@ -556,6 +566,7 @@ vtm_status upload_partition(vtm_ctx *h) {
             return goff[a + 1] - goff[a] > goff[b + 1] - goff[b];
         });
         HIP_TRY(upload(h->d_gorder, gorder, st));
+        h->h_gorder = gorder;
     }
     h->nsplit = P.loc_ptr[nsub];
     h->nports = (int64_t)P.port_v.size();
@@ -819,11 +830,11 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
 per_sweep:
     auto launch = [&](int cur, bool last) {
         if (schur)
-            vtm::launch_schur<T>(D, h->P.nsub, ng, R, h->opt.sweep_waves, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
+            vtm::launch_schur<T>(D, nsub_launch(h), ng, R, h->opt.sweep_waves, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
                                  h->d_goff.as<int64_t>(), h->d_cport.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h),
                                  h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->stream);
         else
-            vtm::launch_sweep<T>(S, D, h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R, nt, h->nsplit,
+            vtm::launch_sweep<T>(S, D, nsub_launch(h), h->max_nk, h->max_nu, sweep_variant(h), ng, R, nt, h->nsplit,
                                  h->nports, vals_of<T>(h), h->d_bsplit.as<T>(), h->d_twin.as<int32_t>(),
                                  invz_of<T>(h), h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->d_xloc.as<T>(),
                                  nullptr, last ? vtm::kSweepWriteX : 0, h->stream);
@@ -838,7 +849,7 @@ per_sweep:
                                schur ? h->d_cport.p : h->d_bsplit.p, h->d_twin.p, invz_of<T>(h), h->d_o[0].p,
                                h->d_o[1].p, h->d_xloc.p, h->mask_on ? h->d_active.p : nullptr};
         bool same = g.exec && g.count == kGraphBatch && g.R == R && g.ng == ng && g.threads == nt &&
-                    g.variant == sweep_variant(h) + (schur ? 10 : 0);
+                    g.variant == sweep_variant(h) + (schur ? 10 : 0) && g.nlaunch == nsub_launch(h);
         for (int i = 0; i < 8 && same; ++i) same = g.ptrs[i] == ptrs[i];
         if (!same) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -860,6 +871,7 @@ per_sweep:
             g.threads = nt;
             g.variant = sweep_variant(h) + (schur ? 10 : 0);
             for (int i = 0; i < 8; ++i) g.ptrs[i] = ptrs[i];
+            g.nlaunch = nsub_launch(h);
         }
         for (int64_t r = 0; r < nrep; ++r) HIP_TRY(hipGraphLaunch(g.exec, h->stream));
     }
@@ -876,7 +888,7 @@ per_sweep:
 template <typename T>
 void local_solve(vtm_ctx *h, bool zero_waves, bool write_y = false) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
-    vtm::launch_sweep<T>(dev_sym(h), dev_sub(h), h->P.nsub, h->max_nk, h->max_nu, sweep_variant(h), ng, R,
+    vtm::launch_sweep<T>(dev_sym(h), dev_sub(h), nsub_launch(h), h->max_nk, h->max_nu, sweep_variant(h), ng, R,
                          sweep_threads(h), h->nsplit, h->nports, vals_of<T>(h), h->d_bsplit.as<T>(),
                          h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur ^ 1].as<T>(), h->d_o[h->cur].as<T>(),
                          h->d_xloc.as<T>(), write_y ? h->d_yb.as<T>() : nullptr,
@@ -899,7 +911,7 @@ template <typename T>
 vtm_status test_solve(vtm_ctx *h) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
     if (h->have_y && h->yb_ok && vtm::prepare_ysolve<T>(h->max_nk, h->max_p, R) == hipSuccess) {
-        vtm::launch_ysolve<T>(dev_sym(h), dev_sub(h), dev_green(h, true), yblocks_of<T>(h), h->P.nsub, h->max_nk,
+        vtm::launch_ysolve<T>(dev_sym(h), dev_sub(h), dev_green(h, true), yblocks_of<T>(h), nsub_launch(h), h->max_nk,
                               h->max_p, ng, R, h->nsplit, h->nports, vals_of<T>(h), h->d_yb.as<T>(),
                               h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur ^ 1].as<T>(), h->d_xloc.as<T>(),
                               h->stream);
@@ -924,7 +936,7 @@ vtm_status port_constants(vtm_ctx *h) {
         h->yb_ok = true;
     }
     local_solve<T>(h, true, h->yb_ok);
-    vtm::launch_gather_ports<T>(dev_sub(h), h->P.nsub, ng, h->nsplit, h->npg, R, h->d_xloc.as<T>(),
+    vtm::launch_gather_ports<T>(dev_sub(h), nsub_launch(h), ng, h->nsplit, h->npg, R, h->d_xloc.as<T>(),
                                 h->d_cport.as<T>(), h->stream);
     return VTM_OK;
 }
@@ -949,7 +961,7 @@ vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::v
     vtm::DevCsr A{h->d_rp.as<int64_t>(), h->d_ci.as<int32_t>(), h->d_v.as<double>()};
     const int64_t n = h->P.n;
     vtm::launch_residual(A, n, nrhs, h->d_b.as<double>(), n, x, n, r, n, h->d_chunkrow.as<int64_t>(),
-                         h->d_chunksys.as<int32_t>(), h->nchunks, h->d_syschunk.as<int32_t>(), h->P.nsys,
+                         h->d_chunksys.as<int32_t>(), h->mask_on ? h->d_active.as<int32_t>() : nullptr, h->nchunks, h->d_syschunk.as<int32_t>(), h->P.nsys,
                          h->d_part.as<double>(), h->abort_pending ? h->d_abort.as<int32_t>() : nullptr,
                          h->d_relres.as<double>(), h->stream);
     rel.resize((size_t)h->P.nsys * nrhs);
@@ -1008,6 +1020,24 @@ vtm_status mask_begin(vtm_ctx *h) {
     std::fill(h->active_host, h->active_host + nsys, 1);
     HIP_TRY(hipMemcpyAsync(h->d_active.p, h->active_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice, h->stream));
     h->mask_on = true;
+    h->list_on = false;
+    return VTM_OK;
+}
+
+// After systems have converged: the launch list = the subgraphs of the systems still sweeping, in
+// launch order (largest G_k first).  The host list stays unchanged until the next rebuild, which
+// comes after a synchronisation (a test), so the asynchronous copy from it is safe.
+vtm_status mask_relist(vtm_ctx *h) {
+    h->h_sublist.clear();
+    for (const int32_t k : h->h_gorder)
+        if (h->active_host[h->P.sub_sys[k]]) h->h_sublist.push_back(k);
+    // sized for every subgraph, so that its address (captured in sweep graphs) never changes
+    HIP_TRY(ensure(h->d_sublist, sizeof(int32_t) * std::max<size_t>(h->P.nsub, 1)));
+    if (h->h_sublist.empty()) return VTM_OK;  // every system has converged: no further launch
+    if (!h->h_sublist.empty())
+        HIP_TRY(hipMemcpyAsync(h->d_sublist.p, h->h_sublist.data(), sizeof(int32_t) * h->h_sublist.size(),
+                               hipMemcpyHostToDevice, h->stream));
+    h->list_on = true;
     return VTM_OK;
 }
 
@@ -1045,7 +1075,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     if ((rc = mask_begin(h))) return rc;
     struct MaskOff {  // the mask applies to this solve only
         vtm_ctx *h;
-        ~MaskOff() { h->mask_on = false; }
+        ~MaskOff() { h->mask_on = h->list_on = false; }
     } mask_off{h};
     const int64_t *chunkrow = h->d_chunkrow.as<int64_t>();
     const int32_t *chunksys = h->d_chunksys.as<int32_t>();
@@ -1146,9 +1176,11 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
                                          sizeof(double) * len, nrhs, hipMemcpyDeviceToDevice, h->stream));
                 for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + sy] = rel[(size_t)c * nsys + sy];
             }
-            if (changed)
+            if (changed) {
                 HIP_TRY(hipMemcpyAsync(h->d_active.p, h->active_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice,
                                        h->stream));
+                if ((rc = mask_relist(h))) return rc;
+            }
         }
         if (!refine) {
             std::swap(xcur, xtr);

@@ -161,6 +161,15 @@ __device__ inline int64_t gpack_index(int nb, int i, int j) {
     return ((int64_t)J * nb - (int64_t)J * (J - 1) / 2 + (I - J)) * 256 + gblk_pos(i & 15, j & 15);
 }
 
+// Stored factor of a supernode with nc columns and f = nc + m rows: V = [Linv; W] (Linv = L11^{-1}
+// lower triangular, W = L21 L11^{-1}), only its lower trapezoid, column by column: column j holds rows
+// j .. f - 1 contiguously (Linv rows j .. nc - 1, then the m rows of W), so V[i][j], i >= j, sits at
+// vpos(f, i, j).  nc (nc + 1) / 2 + m nc values.  The forward substitution reads each column once as
+// an axpy (lanes over rows), the backward one each column once as a dot product (lanes over the
+// column's rows); both reads are coalesced.
+__host__ __device__ inline int vcol(int f, int j) { return j * f - j * (j - 1) / 2; }
+__host__ __device__ inline int vpos(int f, int i, int j) { return vcol(f, j) + (i - j); }
+
 struct FactorArgs {
     const double *A;       // assembly values of the subgraph (scatter order)
     double *V;             // factor values of the subgraph (FP64), or nullptr
@@ -408,16 +417,18 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
             team_sync<BLK>();
         }
     }
-    // 3. outputs: Linv and W (f x nc, row-major), the update matrix (packed lower triangle)
+    // 3. outputs: [Linv; W] (f x nc, lower trapezoid, packed by columns: see vpos), the update matrix
+    //    (packed lower triangle)
     {
         double *Vs = X.V ? X.V + X.sn_val[s] : nullptr;
         float *Vs32 = X.V32 ? X.V32 + X.sn_val[s] : nullptr;
         const Cover cv = cover(nc, r, n);
         for (int j = cv.c; j < nc; j += cv.cw)
             for (int i = cv.r0; i < f; i += cv.rs) {
-                const double v = i < nc ? (j <= i ? F[j * f + i] : 0.0) : -F[j * f + i];
-                if (Vs) Vs[i * nc + j] = v;
-                if (Vs32) Vs32[i * nc + j] = (float)v;
+                if (i < j) continue;
+                const double v = i < nc ? F[j * f + i] : -F[j * f + i];
+                if (Vs) Vs[vpos(f, i, j)] = v;
+                if (Vs32) Vs32[vpos(f, i, j)] = (float)v;
             }
     }
     if (m > 0) {
@@ -640,16 +651,17 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
     float *Vs32 = X.V32 ? X.V32 + X.sn_val[s] : nullptr;
     for (int idx = r; idx < nc * nc; idx += n) {
         const int i = idx / nc, j = idx - i * nc;
-        const double v = j > i ? 0.0 : (j == i ? 1.0 / F[i * f + i] : F[j * f + i]);
-        if (Vs) Vs[idx] = v;
-        if (Vs32) Vs32[idx] = (float)v;
+        if (j > i) continue;
+        const double v = j == i ? 1.0 / F[i * f + i] : F[j * f + i];
+        if (Vs) Vs[vpos(f, i, j)] = v;
+        if (Vs32) Vs32[vpos(f, i, j)] = (float)v;
     }
     for (int idx = r; idx < m * nc; idx += n) {  // W[q][j] = sum_{t >= j} L21[q][t] Linv[t][j]
         const int q = idx / nc, j = idx - q * nc;
         double acc = F[j * f + nc + q] / F[j * f + j];
         for (int t = j + 1; t < nc; ++t) acc += F[t * f + nc + q] * F[j * f + t];
-        if (Vs) Vs[nc * nc + idx] = acc;
-        if (Vs32) Vs32[nc * nc + idx] = (float)acc;
+        if (Vs) Vs[vpos(f, nc + q, j)] = acc;
+        if (Vs32) Vs32[vpos(f, nc + q, j)] = (float)acc;
     }
     double *Us = X.W + X.sn_uoff[s];
     const int tm = (m + 15) >> 4, kr = lane >> 4;
@@ -788,6 +800,53 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
         }
 }
 
+// Lane moves by DPP (quad permutations and row rotations); a double moves as its two halves.
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// Value of lane m ^ X (X = 8, 1, 2 or 4) within each 16-lane DPP row: row_ror:8 for 8, quad
+// permutations for 1 and 2, and for 4 a shift left by 4 into banks 0 and 2 plus a shift right by 4
+// into banks 1 and 3.
+template <int X>
+__device__ inline int lane_xor(int v) {
+    if constexpr (X == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+    if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    if constexpr (X == 4) {
+        const int lo = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);
+        return __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xF, 0xA, false);
+    }
+    return v;
+}
+template <int X>
+__device__ inline float lane_xor(float v) {
+    return __builtin_bit_cast(float, lane_xor<X>(__builtin_bit_cast(int, v)));
+}
+template <int X>
+__device__ inline double lane_xor(double v) {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = lane_xor<X>((int)x), hi = lane_xor<X>((int)(x >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum of v over the 16 lanes of each DPP row, left in every lane of the row.
+template <typename T>
+__device__ inline T row16_sum(T v) {
+    v += lane_xor<8>(v);
+    v += lane_xor<4>(v);
+    v += lane_xor<2>(v);
+    v += lane_xor<1>(v);
+    return v;
+}
+
 // ------------------------------------------------------------------------ sweep
 //
 // Factor layout per supernode s (nc columns, m off-diagonal rows R_s): Linv_s = L11^{-1}
@@ -807,83 +866,62 @@ __device__ inline int hi16(int32_t w) { return (int)((uint32_t)w >> 16); }
 __device__ inline int lo16(int32_t w) { return (int)((uint32_t)w & 0xFFFFu); }
 
 // Forward substitution of one subgraph, R right-hand sides interleaved in LDS.
-// In: vec = right side.  Out: vec = y = L^{-1} (right side) (tmp, ubuf: scratch).  Ends with a barrier.
-template <typename T, int R, int V>
+// In: vec = right side.  Out: vec = y = L^{-1} (right side); tmp, ubuf: scratch.  Level by level,
+// leaves first:
+//   (a) t_i = vec_i minus the update entries that descendant supernodes left for row i (one thread
+//       per column of the level, summed in a fixed order);
+//   (b) [y_s; u_s] = V_s t_s for every supernode s of the level, one thread per row of V_s: the
+//       level's columns (rows of Linv, results y_i to vec) and then its update entries (rows of W,
+//       results u to the update slots), all rows of the level dealt to the threads at once.  A thread
+//       runs over the columns j of its supernode; threads on consecutive rows of one supernode read
+//       consecutive entries of column j (V_s is stored by columns), so the loads are coalesced.
+// Ends with a barrier.
+template <typename T, int R>
 __device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, T *vec, T *tmp, T *ubuf) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *lev_u = S.lev_u + C.o_lev;
-    const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
-    const int32_t *urec = S.urec + 2 * (int64_t)C.o_ridx;
-    const int32_t *seg_ptr = S.seg_ptr + C.o_colp, *seg_off = S.seg_off + C.o_seg;
-    const uint16_t *seg_c0 = S.seg_c0 + C.o_seg, *seg_nc = S.seg_nc + C.o_seg, *seg_u = S.seg_u + C.o_seg;
-    // forward substitution, one level (independent subtrees) at a time
+    const int32_t *seg_ptr = S.seg_ptr + C.o_colp;
+    const uint16_t *seg_u = S.seg_u + C.o_seg;
+    const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col, *urec = S.urec + 4 * (int64_t)C.o_ridx;
     for (int lv = 0; lv < C.nlev; ++lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
         for (int i = cb + tid; i < ce; i += nt) {
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = vec[i * R + c];
-            const int s0 = seg_ptr[i], s1 = seg_ptr[i + 1];
-            if (V == 0) {
-                // pull: W_d[q, :] . t_d of every descendant supernode d with R_d[q] = i
-                for (int s = s0; s < s1; ++s) {
-                    const T *w = Vk + seg_off[s];
-                    const T *t = tmp + seg_c0[s] * R;
-                    const int n = seg_nc[s];
-                    for (int j = 0; j < n; ++j) {
-                        const T wj = w[j];
+            for (int q = seg_ptr[i]; q < seg_ptr[i + 1]; ++q) {
+                const T *u = ubuf + seg_u[q] * R;
 #pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] -= wj * t[j * R + c];
-                    }
-                }
-            } else {
-                for (int s = s0; s < s1; ++s) {
-                    const T *u = ubuf + seg_u[s] * R;
-#pragma unroll
-                    for (int c = 0; c < R; ++c) acc[c] -= u[c];
-                }
+                for (int c = 0; c < R; ++c) acc[c] -= u[c];
             }
 #pragma unroll
             for (int c = 0; c < R; ++c) tmp[i * R + c] = acc[c];
         }
         __syncthreads();
-        // y = Linv t for this level's columns and (variant 1) u = W t for its update entries
-        const int nrow = ce - cb;
-        const int nu = V == 1 ? lev_u[lv + 1] - lev_u[lv] : 0;
-        for (int task = tid; task < nrow + nu; task += nt) {
-            const T *l;
-            const T *t;
-            int n;
-            T *out;
-            if (task < nrow) {
-                const int i = cb + task;
-                const ColRec r = load_col(colrec, i);
-                const int nc = lo16(r.c0nc), jj = hi16(r.jjm);
-                l = Vk + r.off + jj * nc;
-                t = tmp + hi16(r.c0nc) * R;
-                n = jj + 1;
-                out = vec + i * R;
-            } else {
-                const int e = lev_u[lv] + task - nrow;
-                const int2 u = reinterpret_cast<const int2 *>(urec)[e];
-                l = Vk + u.x;
-                t = tmp + hi16(u.y) * R;
-                n = lo16(u.y);
-                out = ubuf + e * R;
-            }
+        const int ub = lev_u[lv], ncol = ce - cb, nrow = ncol + (lev_u[lv + 1] - ub);
+        for (int task = tid; task < nrow; task += nt) {
+            // one record per row: {block offset, c0<<16|nc, row<<16|m, ridx offset}
+            const ColRec r = load_col(task < ncol ? colrec : urec, task < ncol ? cb + task : ub + task - ncol);
+            const int nc = lo16(r.c0nc), i = hi16(r.jjm), f = nc + lo16(r.jjm), jn = i < nc ? i + 1 : nc;
+            const T *Vs = Vk + r.off;
+            const T *t = tmp + hi16(r.c0nc) * R;
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int j0 = 0; j0 < n; j0 += 8) {  // loads of eight entries in flight together
-                T lv[8];
+            for (int j0 = 0; j0 < jn; j0 += 8) {  // eight loads in flight together
+                T v[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) lv[q] = j0 + q < n ? l[j0 + q] : (T)0;
+                for (int q = 0; q < 8; ++q) {
+                    const int j = j0 + q < jn ? j0 + q : jn - 1;
+                    v[q] = Vs[vcol(f, j) + (i - j)];
+                }
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    if (j0 + q < n)
+                    if (j0 + q < jn)
 #pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] += lv[q] * t[(j0 + q) * R + c];
+                        for (int c = 0; c < R; ++c) acc[c] += v[q] * t[(j0 + q) * R + c];
             }
+            T *out = task < ncol ? vec + (cb + task) * R : ubuf + (ub + task - ncol) * R;
 #pragma unroll
             for (int c = 0; c < R; ++c) out[c] = acc[c];
         }
@@ -891,60 +929,61 @@ __device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__res
     }
 }
 
-// Backward substitution of one subgraph: x_s = Linv^T y_s - W^T x_R, root level first.
-// In: vec = y.  Out: tmp = x.  Ends with a barrier.
+// Backward substitution of one subgraph, root level first: x_s = Linv^T y_s - W^T x_{R_s}, i.e. for
+// every column j of s, x_j = (column j of V_s) . [y_s; -x_{R_s}] over its rows j .. f - 1.  One
+// thread per column of the level; the column's entries are contiguous (V_s is stored by columns) and
+// read eight at a time.  In: vec = y.  Out: tmp = x.  Ends with a barrier.
 template <typename T, int R>
 __device__ void backward_subst(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, const T *vec, T *tmp) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int32_t *lev_c0 = S.lev_c0 + C.o_lev;
-    const int32_t *colrec = S.colrec + 4 * (int64_t)C.o_col;
+    const int32_t *lev_c0 = S.lev_c0 + C.o_lev, *colrec = S.colrec + 4 * (int64_t)C.o_col;
     const uint16_t *ridx = S.ridx + C.o_ridx;
     for (int lv = C.nlev - 1; lv >= 0; --lv) {
         const int cb = lev_c0[lv], ce = lev_c0[lv + 1];
-        for (int j = cb + tid; j < ce; j += nt) {
-            const ColRec r = load_col(colrec, j);
-            const int c0 = hi16(r.c0nc), nc = lo16(r.c0nc), jj = hi16(r.jjm), m = lo16(r.jjm);
-            const T *lcol = Vk + r.off + jj;
-            const T *wcol = Vk + r.off + nc * nc + jj;
+        for (int jg = cb + tid; jg < ce; jg += nt) {
+            const ColRec r = load_col(colrec, jg);
+            const int c0 = hi16(r.c0nc), nc = lo16(r.c0nc), j = hi16(r.jjm), m = lo16(r.jjm);
+            const T *lcol = Vk + r.off + vcol(nc + m, j);  // Linv[j .. nc)[j], then W[0 .. m)[j]
+            const T *wcol = lcol + (nc - j);
             const uint16_t *rr = ridx + r.ridx;
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int i0 = jj; i0 < nc; i0 += 8) {  // loads of eight entries in flight together
-                T lv[8];
+            for (int k0 = 0; k0 < nc - j; k0 += 8) {  // Linv^T y: eight loads in flight
+                T v[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) lv[q] = i0 + q < nc ? lcol[(i0 + q) * nc] : (T)0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (i0 + q < nc)
-#pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] += lv[q] * vec[(c0 + i0 + q) * R + c];
-            }
-            for (int q0 = 0; q0 < m; q0 += 8) {
-                T wv[8];
-                int ri[8];
+                for (int q = 0; q < 8; ++q) v[q] = k0 + q < nc - j ? lcol[k0 + q] : (T)0;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    wv[q] = q0 + q < m ? wcol[(q0 + q) * nc] : (T)0;
-                    ri[q] = q0 + q < m ? rr[q0 + q] : 0;
+                    const int row = k0 + q < nc - j ? c0 + j + k0 + q : c0 + j;
+#pragma unroll
+                    for (int c = 0; c < R; ++c) acc[c] += v[q] * vec[row * R + c];
+                }
+            }
+            for (int q0 = 0; q0 < m; q0 += 8) {  // - W^T x_R
+                T v[8];
+                int ri[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {  // past m: a zero weight on a row that holds a finished x
+                    v[q] = q0 + q < m ? wcol[q0 + q] : (T)0;
+                    ri[q] = rr[q0 + q < m ? q0 + q : m - 1];
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    if (q0 + q < m)
 #pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] -= wv[q] * tmp[ri[q] * R + c];
+                    for (int c = 0; c < R; ++c) acc[c] -= v[q] * tmp[ri[q] * R + c];
             }
 #pragma unroll
-            for (int c = 0; c < R; ++c) tmp[j * R + c] = acc[c];
+            for (int c = 0; c < R; ++c) tmp[jg * R + c] = acc[c];
         }
         __syncthreads();
     }
 }
 
 // Forward and backward substitution.  In: vec = right side.  Out: tmp = x, vec = y.
-template <typename T, int R, int V>
+template <typename T, int R>
 __device__ void trisolve(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, T *vec, T *tmp, T *ubuf) {
-    forward_subst<T, R, V>(C, S, Vk, vec, tmp, ubuf);
+    forward_subst<T, R>(C, S, Vk, vec, tmp, ubuf);
     backward_subst<T, R>(C, S, Vk, vec, tmp);
 }
 
@@ -958,56 +997,62 @@ __device__ inline float cpl_y<float>(const DevSub &D, int e) { return D.cpl_y32[
 // One VTM sweep.  flags: kWriteX stores the local solutions; kNoWaves leaves o_next untouched
 // (a read-only solve with the current incoming waves); kZeroWaves ignores o_prev (a = 0); kWriteY
 // stores the forward result y = L^{-1} (right side) in yout (layout of the local solutions).
-template <typename T, int R, int V>
+// Vectors are laid out in groups of R right-hand sides; a workgroup takes RS of them (the RS-wide
+// block rb of group g), so that its LDS -- right side / y, t / x and the update slots, RS values each
+// per entry -- fits the CU when the subgraphs are large.
+template <typename T, int R, int RS>
 __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nsplit, int64_t nports,
                                                const T *__restrict__ vals, const T *__restrict__ bsplit,
                                                const int32_t *__restrict__ twin, const T *__restrict__ invz,
                                                const T *__restrict__ o_prev, T *__restrict__ o_next,
                                                T *__restrict__ xloc, T *__restrict__ yout, int flags) {
+    static_assert(RS <= R && R % RS == 0, "right-hand-side block");
+    constexpr int NB = R / RS;
     extern __shared__ char smraw[];
-    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const int k = sub_of_block(D, blockIdx.x), g = blockIdx.y / NB, rb = (blockIdx.y % NB) * RS, tid = threadIdx.x,
+              nt = blockDim.x;
     if (sub_inactive(D, k)) return;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
     T *vec = reinterpret_cast<T *>(smraw);  // right side, then y (forward result)
-    T *tmp = vec + (size_t)nk * R;          // t during the forward pass, x during the backward pass
-    T *ubuf = tmp + (size_t)nk * R;         // variant 1: update entries W_s t_s of every R_s row
+    T *tmp = vec + (size_t)nk * RS;         // t during the forward pass, x during the backward pass
+    T *ubuf = tmp + (size_t)nk * RS;        // update entries W_s t_s of every R_s row
     const T *Vk = vals + D.val[k];
-    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
+    const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R + rb;
     const T *bs = bsplit + xo;
-    const int64_t wo = (int64_t)g * nports * R;
+    const int64_t wo = (int64_t)g * nports * R + rb;
     const bool zero_waves = flags & kZeroWaves;
 
     // right side of (5.8): split source + Z^{-1} * incoming wave at every port (with coupled VTLs the
     // off-diagonal entries of Z_j^{-1} add the incoming waves of the coupled ports)
-    for (int i = tid; i < nk * R; i += nt) vec[i] = bs[i];
+    for (int i = tid; i < nk * RS; i += nt) vec[i] = bs[(i / RS) * R + i % RS];
     __syncthreads();
     const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
     if (!zero_waves) {
         for (int q = pg0 + tid; q < pg1; q += nt) {
             const int pos = D.pg_pos[q], pb = D.pg_beg[q], pc = D.pg_cnt[q];
-            T acc[R];
+            T acc[RS];
 #pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] = vec[pos * R + c];
+            for (int c = 0; c < RS; ++c) acc[c] = vec[pos * RS + c];
             for (int j = 0; j < pc; ++j) {
                 const T iz = invz[pb + j];
                 const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += a[c] * iz;
+                for (int c = 0; c < RS; ++c) acc[c] += a[c] * iz;
                 if (D.cpl_ptr)
                     for (int e = D.cpl_ptr[pb + j]; e < D.cpl_ptr[pb + j + 1]; ++e) {
                         const T y = cpl_y<T>(D, e);
                         const T *aq = o_prev + wo + (int64_t)D.cpl_tw[e] * R;
 #pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] += aq[c] * y;
+                        for (int c = 0; c < RS; ++c) acc[c] += aq[c] * y;
                     }
             }
 #pragma unroll
-            for (int c = 0; c < R; ++c) vec[pos * R + c] = acc[c];
+            for (int c = 0; c < RS; ++c) vec[pos * RS + c] = acc[c];
         }
     }
     __syncthreads();
-    trisolve<T, R, V>(C, S, Vk, vec, tmp, ubuf);
+    trisolve<T, RS>(C, S, Vk, vec, tmp, ubuf);
     // outgoing waves o_p = 2 u_p - a_p
     if (!(flags & kNoWaves)) {
         for (int q = pg0 + tid; q < pg1; q += nt) {
@@ -1016,17 +1061,17 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
                 const T *a = o_prev + wo + (int64_t)twin[pb + j] * R;
                 T *o = o_next + wo + (int64_t)(pb + j) * R;
 #pragma unroll
-                for (int c = 0; c < R; ++c) o[c] = (T)2 * tmp[pos * R + c] - (zero_waves ? (T)0 : a[c]);
+                for (int c = 0; c < RS; ++c) o[c] = (T)2 * tmp[pos * RS + c] - (zero_waves ? (T)0 : a[c]);
             }
         }
     }
     if (flags & kWriteX) {
         T *xo_ = xloc + xo;
-        for (int i = tid; i < nk * R; i += nt) xo_[i] = tmp[i];
+        for (int i = tid; i < nk * RS; i += nt) xo_[(i / RS) * R + i % RS] = tmp[i];
     }
     if (flags & kWriteY) {
         T *yo_ = yout + xo;
-        for (int i = tid; i < nk * R; i += nt) yo_[i] = vec[i];
+        for (int i = tid; i < nk * RS; i += nt) yo_[(i / RS) * R + i % RS] = vec[i];
     }
 }
 
@@ -1044,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp,
                                                 const T *__restrict__ invz, const T *__restrict__ o_in,
                                                 T *__restrict__ xloc) {
     extern __shared__ char smraw[];
-    const int k = blockIdx.x, g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
+    const int k = sub_of_block(D, blockIdx.x), g = blockIdx.y, tid = threadIdx.x, nt = blockDim.x;
     if (sub_inactive(D, k)) return;
     const ClassDev C = S.cls[D.cls[k]];
     const int nk = C.nk;
@@ -1130,10 +1175,9 @@ __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp,
 
 // Port Green's functions G_k = R_k K_k^{-1} R_k^T (R_k selects the port vertices), FP64:
 // column j of G_k is the port part of K_k^{-1} e_{v(j)}; blockIdx.y picks RHS columns j.
-template <int V>
+template <int R>
 __global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double *__restrict__ vals,
                                                const int64_t *__restrict__ goff, double *__restrict__ G) {
-    constexpr int R = 4;
     extern __shared__ char smraw[];
     const int k = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const ClassDev C = S.cls[D.cls[k]];
@@ -1148,7 +1192,7 @@ __global__ __launch_bounds__(256) void k_green(DevSym S, DevSub D, const double 
     __syncthreads();
     if (tid < R && j0 + tid < p) vec[D.pg_pos[pg0 + j0 + tid] * R + tid] = 1.0;
     __syncthreads();
-    trisolve<double, R, V>(C, S, vals + D.val[k], vec, tmp, ubuf);
+    trisolve<double, R>(C, S, vals + D.val[k], vec, tmp, ubuf);
     double *Gk = G + goff[k];
     const int nb = (p + 15) >> 4;
     for (int idx = tid; idx < R * p; idx += nt) {
@@ -1189,7 +1233,7 @@ __global__ void k_rin(DevSub D, const int64_t *__restrict__ goff, const double *
 template <typename T>
 __global__ void k_gather_ports(DevSub D, int64_t nsplit, int32_t npg, int32_t R, const T *__restrict__ xloc,
                                T *__restrict__ cport) {
-    const int k = blockIdx.x, g = blockIdx.y;
+    const int k = sub_of_block(D, blockIdx.x), g = blockIdx.y;
     if (sub_inactive(D, k)) return;
     const int pg0 = D.pg_ptr[k], pg1 = D.pg_ptr[k + 1];
     const int64_t xo = ((int64_t)g * nsplit + D.x[k]) * R;
@@ -1228,43 +1272,6 @@ template <> struct Quad<double> {
     }
     __device__ double operator[](int i) const { return i == 0 ? a.x : i == 1 ? a.y : i == 2 ? b.x : b.y; }
 };
-
-// Lane moves by DPP (quad permutations and row rotations); a double moves as its two halves.
-template <int CTRL>
-__device__ inline float dpp_mov(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ inline double dpp_mov(double v) {
-    const long long x = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-// Value of lane m ^ X (X = 8, 1, 2 or 4) within each 16-lane DPP row: row_ror:8 for 8, quad
-// permutations for 1 and 2, and for 4 a shift left by 4 into banks 0 and 2 plus a shift right by 4
-// into banks 1 and 3.
-template <int X>
-__device__ inline int lane_xor(int v) {
-    if constexpr (X == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
-    if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
-    if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
-    if constexpr (X == 4) {
-        const int lo = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0x5, false);
-        return __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xF, 0xA, false);
-    }
-    return v;
-}
-template <int X>
-__device__ inline float lane_xor(float v) {
-    return __builtin_bit_cast(float, lane_xor<X>(__builtin_bit_cast(int, v)));
-}
-template <int X>
-__device__ inline double lane_xor(double v) {
-    const long long x = __builtin_bit_cast(long long, v);
-    const int lo = lane_xor<X>((int)x), hi = lane_xor<X>((int)(x >> 32));
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
 // Sum of v[0 .. N) over the 16 lanes of each DPP row, scattered: level by level (lane bits 3, 0, 1,
 // 2) a lane keeps the lower or upper half of its values, by its bit, and adds the partner's copy of
@@ -1359,7 +1366,7 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
     constexpr int U = 4;                          // ports per lane whose loads are issued together
     constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
     typedef typename Mma<T>::acc Acc;
-    const int k = D.gorder[blockIdx.x], g = blockIdx.y, tid = threadIdx.x, nt = 64 * W;
+    const int k = D.sub_list ? D.sub_list[blockIdx.x] : D.gorder[blockIdx.x], g = blockIdx.y, tid = threadIdx.x, nt = 64 * W;
     if (sub_inactive(D, k)) return;
     const int lane = tid & 63, m = lane & 15, q = lane >> 4;
     const int wv = W == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1872,48 +1879,74 @@ __global__ void k_merge(DevMaps M, int64_t nsplit, int32_t nrhs, int32_t R, cons
     }
 }
 
+// r = b - A x for NR right-hand sides (block y: columns NR y .. NR y + NR - 1) in one pass over A:
+// each row's entries are read once for all of them.  One workgroup per chunk of rows (inside one
+// system); a chunk of a converged system (active[s] == 0) is skipped and keeps its partial sums.
+template <int NR>
 __global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
                                                        const double *__restrict__ x, int64_t ldx, double *__restrict__ r,
                                                        int64_t ldr, const int64_t *__restrict__ chunk_row,
-                                                       int32_t nchunks, double *__restrict__ part) {
+                                                       const int32_t *__restrict__ chunk_sys,
+                                                       const int32_t *__restrict__ active, int32_t nchunks,
+                                                       double *__restrict__ part) {
     __shared__ double red[2][kThreads];
-    const int ch = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const int ch = blockIdx.x, c0 = blockIdx.y * NR, tid = threadIdx.x;
+    if (active && !active[chunk_sys[ch]]) return;
     const int64_t r0 = chunk_row[ch], r1 = chunk_row[ch + 1];
-    double rr = 0.0, bb = 0.0;
+    double rr[NR], bb[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) rr[c] = bb[c] = 0.0;
     for (int64_t v = r0 + tid; v < r1; v += kThreads) {
-        const double bv = b[v + (int64_t)c * ldb];
-        double acc = bv;
+        double acc[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            const int cc = c0 + c < nrhs ? c0 + c : nrhs - 1;
+            acc[c] = b[v + (int64_t)cc * ldb];
+            bb[c] += c0 + c < nrhs ? acc[c] * acc[c] : 0.0;
+        }
         const int64_t e0 = A.rp[v], e1 = A.rp[v + 1];
         // eight entries a round, their loads issued together (indices past the row clamped to its last
         // entry, whose product is then weighted by zero: arithmetic, so the loads stay unconditional)
         for (int64_t eb = e0; eb < e1; eb += 8) {
             int32_t col[8];
-            double av[8], xv[8];
+            double av[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int64_t e = eb + q < e1 ? eb + q : e1 - 1;
                 col[q] = A.ci[e];
-                av[q] = A.v[e];
+                av[q] = eb + q < e1 ? A.v[e] : 0.0;
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) xv[q] = x[col[q] + (int64_t)c * ldx];
+            for (int c = 0; c < NR; ++c) {
+                const int cc = c0 + c < nrhs ? c0 + c : nrhs - 1;
+                double xv[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc -= (double)(eb + q < e1) * av[q] * xv[q];
+                for (int q = 0; q < 8; ++q) xv[q] = x[col[q] + (int64_t)cc * ldx];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[c] -= av[q] * xv[q];
+            }
         }
-        if (r) r[v + (int64_t)c * ldr] = acc;
-        rr += acc * acc;
-        bb += bv * bv;
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+            if (c0 + c < nrhs) {
+                if (r) r[v + (int64_t)(c0 + c) * ldr] = acc[c];
+                rr[c] += acc[c] * acc[c];
+            }
     }
-    red[0][tid] = rr;
-    red[1][tid] = bb;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) { red[0][tid] += red[0][tid + s]; red[1][tid] += red[1][tid + s]; }
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        red[0][tid] = rr[c];
+        red[1][tid] = bb[c];
         __syncthreads();
-    }
-    if (tid == 0) {
-        part[((int64_t)c * nchunks + ch) * 2 + 0] = red[0][0];
-        part[((int64_t)c * nchunks + ch) * 2 + 1] = red[1][0];
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
+            __syncthreads();
+        }
+        if (tid == 0 && c0 + c < nrhs) {
+            part[((int64_t)(c0 + c) * nchunks + ch) * 2 + 0] = red[0][0];
+            part[((int64_t)(c0 + c) * nchunks + ch) * 2 + 1] = red[1][0];
+        }
+        __syncthreads();
     }
 }
 
@@ -1975,35 +2008,44 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
     hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, ldb, R, bsplit);
 }
 
-template <typename T, int V>
-static const void *sweep_fn_v(int32_t R) {
-    return R == 1 ? (const void *)k_sweep<T, 1, V> : R == 2 ? (const void *)k_sweep<T, 2, V>
-         : R == 4 ? (const void *)k_sweep<T, 4, V> : (const void *)k_sweep<T, 8, V>;
+// Right-hand sides per workgroup of the substitution sweep: the largest RS <= R whose LDS is at
+// most 96 KiB (two workgroups per CU), else the largest that fits the CU at all (0: none fits).
+template <typename T>
+static int32_t sweep_rs(int32_t max_nk, int32_t max_nu, int32_t R) {
+    auto need = [&](int32_t rs) { return sizeof(T) * (size_t)rs * (2 * (size_t)max_nk + (size_t)max_nu); };
+    int32_t rs = R;
+    while (rs > 1 && need(rs) > 96 * 1024) rs /= 2;
+    return need(rs) <= kMaxLds ? rs : 0;
+}
+
+template <typename T, int R>
+static const void *sweep_fn_r(int32_t rs) {
+    if constexpr (R == 1) return (const void *)k_sweep<T, 1, 1>;
+    else if constexpr (R == 2) return rs == 2 ? (const void *)k_sweep<T, 2, 2> : (const void *)k_sweep<T, 2, 1>;
+    else if constexpr (R == 4)
+        return rs == 4 ? (const void *)k_sweep<T, 4, 4> : rs == 2 ? (const void *)k_sweep<T, 4, 2> : (const void *)k_sweep<T, 4, 1>;
+    else
+        return rs == 8 ? (const void *)k_sweep<T, 8, 8> : rs == 4 ? (const void *)k_sweep<T, 8, 4>
+             : rs == 2 ? (const void *)k_sweep<T, 8, 2> : (const void *)k_sweep<T, 8, 1>;
+}
+template <typename T>
+static const void *sweep_fn(int32_t R, int32_t rs) {
+    return R == 1 ? sweep_fn_r<T, 1>(rs) : R == 2 ? sweep_fn_r<T, 2>(rs) : R == 4 ? sweep_fn_r<T, 4>(rs) : sweep_fn_r<T, 8>(rs);
 }
 
 template <typename T>
-size_t sweep_shm(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R) {
-    return sizeof(T) * (size_t)R * (2 * (size_t)max_nk + (variant == 1 ? (size_t)max_nu : 0));
+size_t sweep_shm(int32_t max_nk, int32_t max_nu, int32_t, int32_t R) {
+    const int32_t rs = sweep_rs<T>(max_nk, max_nu, R);
+    return sizeof(T) * (size_t)(rs ? rs : 1) * (2 * (size_t)max_nk + (size_t)max_nu);
 }
 
 template <typename T>
 hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R) {
+    const int32_t rs = sweep_rs<T>(max_nk, max_nu, R);
+    if (!rs) return hipErrorInvalidValue;  // a subgraph too large for the CU's LDS
     const size_t shm = sweep_shm<T>(max_nk, max_nu, variant, R);
     if (shm <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute(variant == 1 ? sweep_fn_v<T, 1>(R) : sweep_fn_v<T, 0>(R),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-}
-
-template <typename T, int V>
-static void launch_sweep_v(const DevSym &S, const DevSub &D, dim3 grid, dim3 block, size_t shm, int32_t R,
-                           int64_t nsplit, int64_t nports, const T *vals, const T *bsplit, const int32_t *twin,
-                           const T *invz, const T *o_prev, T *o_next, T *xloc, T *yout, int flags, hipStream_t st) {
-    switch (R) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, 1, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, 2, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, 4, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
-        default: hipLaunchKernelGGL((k_sweep<T, 8, V>), grid, block, shm, st, S, D, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags); break;
-    }
+    return hipFuncSetAttribute(sweep_fn<T>(R, rs), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
 template <typename T>
@@ -2011,12 +2053,13 @@ void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk
                   int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports, const T *vals,
                   const T *bsplit, const int32_t *twin, const T *invz, const T *o_prev, T *o_next, T *xloc,
                   T *yout, int flags, hipStream_t st) {
+    const int32_t rs = sweep_rs<T>(max_nk, max_nu, R);
+    if (!rs) return;  // prepare_sweep reported it
     const size_t shm = sweep_shm<T>(max_nk, max_nu, variant, R);
-    const dim3 grid(nsub, ngroups), block(threads);
-    if (variant == 1)
-        launch_sweep_v<T, 1>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags, st);
-    else
-        launch_sweep_v<T, 0>(S, D, grid, block, shm, R, nsplit, nports, vals, bsplit, twin, invz, o_prev, o_next, xloc, yout, flags, st);
+    const dim3 grid(nsub, ngroups * (R / rs)), block(threads);
+    void *args[] = {(void *)&S, (void *)&D, &nsplit, &nports, &vals, &bsplit, &twin, &invz, &o_prev, &o_next,
+                    &xloc, &yout, &flags};
+    (void)hipLaunchKernel(sweep_fn<T>(R, rs), grid, block, args, shm, st);
 }
 
 template <typename T>
@@ -2054,13 +2097,15 @@ void launch_ysolve(const DevSym &S, const DevSub &D, const DevGreen &Gp, const T
 
 void launch_green(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t max_p,
                   const double *vals, const int64_t *goff, double *G, hipStream_t st) {
-    const int V = 2 * (size_t)max_nk + max_nu <= 96 * 1024 / (8 * 4) ? 1 : 0;
-    const size_t shm = sizeof(double) * 4 * (2 * (size_t)max_nk + (V ? (size_t)max_nu : 0));
-    const void *fn = V ? (const void *)k_green<1> : (const void *)k_green<0>;
+    // four port columns per workgroup when their LDS fits the CU, else one
+    const size_t per = sizeof(double) * (2 * (size_t)max_nk + (size_t)max_nu);
+    const int R = 4 * per <= kMaxLds ? 4 : 1;
+    const size_t shm = R * per;
+    const void *fn = R == 4 ? (const void *)k_green<4> : (const void *)k_green<1>;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    const dim3 grid(nsub, (max_p + 3) / 4);
-    if (V) hipLaunchKernelGGL(k_green<1>, grid, dim3(256), shm, st, S, D, vals, goff, G);
-    else hipLaunchKernelGGL(k_green<0>, grid, dim3(256), shm, st, S, D, vals, goff, G);
+    const dim3 grid(nsub, (max_p + R - 1) / R);
+    if (R == 4) hipLaunchKernelGGL(k_green<4>, grid, dim3(256), shm, st, S, D, vals, goff, G);
+    else hipLaunchKernelGGL(k_green<1>, grid, dim3(256), shm, st, S, D, vals, goff, G);
 }
 
 void launch_gdiag(const DevSub &D, int32_t nsub, const int64_t *goff, const double *G, double *gd, hipStream_t st) {
@@ -2191,6 +2236,7 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
                                 int32_t spin_limit, int32_t *abort_flag, hipStream_t st) {
     const size_t shm = persist_lds_bytes(max_p, max_np, R);
     DevSub d = D;
+    d.sub_list = nullptr;  // one workgroup per subgraph: every wave of every twin is resident
     void *args[] = {&d, &npg, &nports, &max_np, &G, &goff, &cport, &twin, &invz, &tw, &plain0, &plain1,
                     &t0, &nsw, &cur0, &spin_limit, &abort_flag};
     return hipLaunchCooperativeKernel(persist_fn(R), dim3(nsub, ngroups), dim3(256), args, (unsigned)shm, st);
@@ -2206,11 +2252,17 @@ void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t R, con
 }
 
 void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, int64_t ldb, const double *x, int64_t ldx,
-                     double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *, int32_t nchunks,
-                     const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag, double *relres,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(k_residual, dim3(nchunks, nrhs), dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr,
-                       chunk_row, nchunks, part);
+                     double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *chunk_sys, const int32_t *active,
+                     int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag,
+                     double *relres, hipStream_t st) {
+    const int NR = nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    const dim3 grid(nchunks, (nrhs + NR - 1) / NR);
+    switch (NR) {
+        case 1: hipLaunchKernelGGL(k_residual<1>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
+        case 2: hipLaunchKernelGGL(k_residual<2>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
+        case 4: hipLaunchKernelGGL(k_residual<4>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
+        default: hipLaunchKernelGGL(k_residual<8>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
+    }
     hipLaunchKernelGGL(k_relres, dim3(nsys * nrhs), dim3(256), 0, st, part, nchunks, sys_chunk_ptr, nsys, nrhs, flag,
                        relres);
 }

@@ -33,7 +33,7 @@ struct DevSym {
     const int32_t *seg_ptr, *seg_off;
     const uint16_t *seg_c0, *seg_nc;
     const uint16_t *seg_u, *u_sn;   // update-entry lists (variant 1 of the sweep)
-    const int32_t *colrec, *urec;   // packed per-column and per-update-entry records
+    const int32_t *colrec, *urec;   // per column and per update entry: {block offset, c0<<16|nc, row<<16|m, ridx offset}
     const int32_t *lev_u;           // update-entry range per level (lev offsets)
     const int32_t *sc_ptr, *sc_dst;
 };
@@ -60,7 +60,13 @@ struct DevSub {
     const int32_t *cpl_tw;
     const double *cpl_y64;
     const float *cpl_y32;
+    // the subgraphs a launch covers (done mask: those of the systems still sweeping, largest G_k first),
+    // one per workgroup; nullptr = every subgraph (gorder for the port-reduced sweep, else by id)
+    const int32_t *sub_list;
 };
+
+// Subgraph of workgroup b: from the launch list, else in the given default order.
+__device__ inline int sub_of_block(const DevSub &D, int b) { return D.sub_list ? D.sub_list[b] : b; }
 
 // Skip the workgroups of converged systems (done mask of a batched solve).
 __device__ inline bool sub_inactive(const DevSub &D, int k) { return D.active && !D.active[D.sub_sys[k]]; }
@@ -184,8 +190,11 @@ void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t R, con
 
 // r = b - A x (optional store), per (rhs, system) relative residual into relres[c * nsys + s], and
 // relres[nsys * nrhs] = 1 if *flag is set (flag may be null), so that one copy brings both to the host.
+// Rows of the chunks of a system with active[s] == 0 (active may be null) are skipped; their partial
+// sums keep the values of the last pass over them.
 void launch_residual(const DevCsr &A, int64_t n, int32_t nrhs, const double *b, int64_t ldb, const double *x,
                      int64_t ldx, double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *chunk_sys,
+                     const int32_t *active,
                      int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag,
                      double *relres, hipStream_t st);
 

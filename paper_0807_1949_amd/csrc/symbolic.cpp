@@ -254,7 +254,7 @@ int analyse(const Partition &P, int32_t k, int leaf, ClassSym &C, std::string &e
         C.sn_val[t] = (int32_t)val;
         C.sn_ridx[t] = (int32_t)ri;
         C.sn_uoff[t] = (int32_t)uo;
-        val += nc * nc + m * nc;
+        val += nc * (nc + 1) / 2 + m * nc;  // packed: column j holds rows j .. nc + m - 1
         ri += m;
         uo += m * m;
         C.nlower += nc * (nc + 1) / 2 + m * nc;
@@ -315,11 +315,14 @@ int analyse(const Partition &P, int32_t k, int leaf, ClassSym &C, std::string &e
             r[2] = (int32_t)(((uint32_t)q << 16) | (uint32_t)C.sn_m[t]);
             r[3] = C.sn_ridx[t];
         }
-    C.urec.resize(2 * (size_t)ri);
+    C.urec.resize(4 * (size_t)ri);  // the colrec layout for row nc + q of the supernode (an update entry)
     for (int32_t t = 0; t < nb; ++t)
         for (int32_t q = 0; q < C.sn_m[t]; ++q) {
-            C.urec[2 * (size_t)(C.sn_ridx[t] + q)] = C.sn_val[t] + C.sn_nc[t] * C.sn_nc[t] + q * C.sn_nc[t];
-            C.urec[2 * (size_t)(C.sn_ridx[t] + q) + 1] = (int32_t)(((uint32_t)C.sn_c0[t] << 16) | (uint32_t)C.sn_nc[t]);
+            int32_t *r = &C.urec[4 * (size_t)(C.sn_ridx[t] + q)];
+            r[0] = C.sn_val[t];
+            r[1] = (int32_t)(((uint32_t)C.sn_c0[t] << 16) | (uint32_t)C.sn_nc[t]);
+            r[2] = (int32_t)(((uint32_t)(C.sn_nc[t] + q) << 16) | (uint32_t)C.sn_m[t]);
+            r[3] = C.sn_ridx[t];
         }
     C.lev_u.assign(C.nlev + 1, (int32_t)ri);
     for (int32_t t = nb - 1; t >= 0; --t) C.lev_u[C.sn_level[t]] = C.sn_ridx[t];

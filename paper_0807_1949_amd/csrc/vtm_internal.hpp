@@ -64,7 +64,7 @@ struct ClassSym {
     std::vector<uint16_t> rel;       // position of each R_s row inside the parent's front
     std::vector<int32_t> ch_ptr, ch_idx;  // children of each supernode
     std::vector<int32_t> colrec;     // per factor column: {block offset, c0<<16|nc, jj<<16|m, ridx offset}
-    std::vector<int32_t> urec;       // per update entry: {W row offset, c0<<16|nc}
+    std::vector<int32_t> urec;       // per update entry (row nc + q of its supernode): same four fields
     std::vector<uint16_t> u_sn;      // supernode of every update entry (one per R_s row, ridx order)
     std::vector<uint16_t> seg_u;     // update entries summed into each factor row (CSR by seg_ptr)
     std::vector<int32_t> lev_u;      // update-entry range of each level (nlev + 1)
