@@ -179,7 +179,7 @@ def setup_mfma(workload):
     """Matrix-core use of the factorisation kernel from its counters (FP64 MFMA FLOPs per launch over
     the launch's duration), or None when the kernels have changed since."""
     keys = ("k_factor-mfma-flops-per-launch", "k_factor-duration-us")
-    f = _profile_fields(f"setup_mfma_{workload}.md", keys)
+    f = _profile_fields(f"setup_mfma_{workload.replace('^', '')}.md", keys)
     if f is None:
         return None
     flops, us = float(f[keys[0]]), float(f[keys[1]])
@@ -244,7 +244,7 @@ def roofline_of(st, workload):
     kernel = ("k_schur_persist" if st["persistent"] else "k_schur") if st["sweep_mode"] == 2 else "k_sweep"
     sweep_s = st["sweep_ms"] / 1e3
     achieved = st["sweep_bytes"] / max(sweep_s, 1e-12) / 1e9
-    summary = f"sweep_traffic_{workload}.md"
+    summary = f"sweep_traffic_{workload.replace('^', '')}.md"
     r = dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
              frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(kernel, summary),
              bytes_per_launch=st["sweep_bytes"] / max(st["sweeps"], 1), avg_launch_us=sweep_s * 1e6 / max(st["sweeps"], 1),
@@ -381,6 +381,7 @@ def main():
                          "timed beside it (one step each)")
     ap.add_argument("--extra", default="c3,c2", help="further workloads timed on the headline variant (one step each; "
                     "c2 also with plain FP64 VTM)")
+    ap.add_argument("--no-extra-plain", action="store_true", help="skip plain FP64 VTM on the extra 1024^2 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-error", action="store_true", help="skip the fixed-sweep comparison with the oracle")
     ap.add_argument("--check-every", type=int, default=0, help="0 = adaptive test placement")
@@ -472,7 +473,7 @@ def main():
                  roofline=roofline_of(r["stats"], c["name"]))
         if not args.no_oracle_error:
             e["oracle_error_20_sweeps"] = oracle_error_fixed_sweeps(B, Zm, torch, c, variants[0], r["z"])
-        if w == "c2":
+        if w == "c2" and not args.no_extra_plain:
             p = run_variant(B, Zm, torch, c, "fp64_diag_sub", 1, 1, args.check_every)
             e["fp64_diag_sub"] = summary(p, c)
             e["speedup_vs_fp64_diag_sub"] = p["step_s"] / r["step_s"]
