@@ -160,7 +160,7 @@ typedef struct {
 
 typedef struct {
     int64_t sweeps;          /* sweeps of the last solve (all outer steps) */
-    int32_t outer_steps;     /* refinement steps of the last solve (FP32_IR), 1 in FP64 */
+    int32_t outer_steps;     /* refinement steps of the last solve (FP32_IR; the most any one system took), 1 in FP64 */
     int32_t checks;          /* convergence tests of the last solve */
     double setup_ms;         /* last vtm_setup: Z, augmentation and factorisation (device time) */
     double solve_ms;         /* last solve, wall time on the stream (events) */
@@ -281,8 +281,10 @@ vtm_status vtm_input_impedance_noalloc(vtm_handle h, double *r_port);
  *   iters[nrhs*nsys]: first passing sweep per (rhs, system), -1 if none; index c * nsys + s
  *   relres[nrhs*nsys]: relative residual of the returned x
  * With several systems (vtm_partition_spec.nsys > 1) a system whose right-hand sides all pass
- * stops sweeping (its x is kept) while the others go on.  Test placement (check_every = 0)
- * depends on the residual history only, so sweep counts repeat from run to run.
+ * stops sweeping (its x is kept) while the others go on; in FP32_IR each system also restarts its
+ * inner solve on its own new residual (after a gain of 1e-5 or a stall; a system that stalls
+ * without improving stops, and the call then returns VTM_ERR_NOT_CONVERGED).  Test placement
+ * (check_every = 0) depends on the residual history only, so sweep counts repeat from run to run.
  * Returns VTM_ERR_NOT_CONVERGED (with outputs written) if max_sweeps is hit,
  * VTM_ERR_DIVERGED on NaN or growth.
  */

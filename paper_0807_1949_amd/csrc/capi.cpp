@@ -7,6 +7,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -122,6 +124,9 @@ struct vtm_ctx {
     DevBuf d_sublist;              // subgraphs of the systems still sweeping, largest G_k first
     std::vector<int32_t> h_gorder, h_sublist;
     bool list_on = false;          // launches cover d_sublist only (h_sublist.size() workgroups)
+    DevBuf d_rlist;                // subgraphs of the systems whose refinement restarts at this test
+    std::vector<int32_t> h_rlist;
+    bool rl_on = false;            // launches cover d_rlist only (restart of some systems)
     int32_t *active_host = nullptr;  // pinned per-system flags of the done mask
     size_t active_cap = 0;
     uint64_t setup_id = 0;         // unique id of the last vtm_setup (batch solves rebuild when one changes)
@@ -170,13 +175,14 @@ struct vtm_ctx {
     hipEvent_t ev_test = nullptr;   // completion of a test's residual copy (polled)
     bool abort_pending = false;
     vtm_stats stats{};
+    bool trace = false;  // VTM_TRACE set: one line per convergence test on stderr
 
     vtm_ctx() {
         DevBuf *list[] = {&d_cls, &d_lev, &d_colsn, &d_snc0, &d_snnc, &d_snm, &d_snval, &d_snridx, &d_snuoff, &d_ridx,
                           &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr,
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
-                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_sublist, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
+                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_sublist, &d_rlist, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
                           &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gorder, &d_portpg, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
@@ -275,13 +281,14 @@ vtm::DevSub dev_sub(vtm_ctx *h) {
     d.cpl_tw = h->d_cpltw.as<int32_t>();
     d.cpl_y64 = h->d_cply64.as<double>();
     d.cpl_y32 = h->d_cply32.as<float>();
-    d.sub_list = h->mask_on && h->list_on ? h->d_sublist.as<int32_t>() : nullptr;
+    d.sub_list = h->rl_on ? h->d_rlist.as<int32_t>() : h->mask_on && h->list_on ? h->d_sublist.as<int32_t>() : nullptr;
     return d;
 }
 
-// Workgroups of a launch over the subgraphs: the active list under the done mask, else all.
+// Workgroups of a launch over the subgraphs: the restart list, the active list under the done mask,
+// else all.
 int32_t nsub_launch(const vtm_ctx *h) {
-    return h->mask_on && h->list_on ? (int32_t)h->h_sublist.size() : h->P.nsub;
+    return h->rl_on ? (int32_t)h->h_rlist.size() : h->mask_on && h->list_on ? (int32_t)h->h_sublist.size() : h->P.nsub;
 }
 
 // Column plan of the port Green's functions (computed inside k_factor).  Ports are sorted by the
@@ -1041,8 +1048,37 @@ vtm_status mask_relist(vtm_ctx *h) {
     return VTM_OK;
 }
 
+// Restart the refinement of the systems in sys on their new residuals (rows of r): source split and
+// zero waves on their subgraphs, then their port constants, while the other systems go on with their
+// current inner solves.  Like the launch list, the host list stays unchanged until the next test's
+// synchronisation, so the asynchronous copy from it is safe.
+template <typename T>
+vtm_status restart_systems(vtm_ctx *h, const std::vector<int32_t> &sys, const double *r, int32_t nrhs) {
+    std::vector<char> on(h->P.nsys, 0);
+    for (const int32_t s : sys) on[s] = 1;
+    h->h_rlist.clear();
+    for (const int32_t k : h->h_gorder)
+        if (on[h->P.sub_sys[k]]) h->h_rlist.push_back(k);
+    if (h->h_rlist.empty()) return VTM_OK;
+    HIP_TRY(ensure(h->d_rlist, sizeof(int32_t) * std::max<size_t>(h->P.nsub, 1)));
+    HIP_TRY(hipMemcpyAsync(h->d_rlist.p, h->h_rlist.data(), sizeof(int32_t) * h->h_rlist.size(),
+                           hipMemcpyHostToDevice, h->stream));
+    h->rl_on = true;
+    struct ListOff {
+        vtm_ctx *h;
+        ~ListOff() { h->rl_on = false; }
+    } list_off{h};
+    vtm::launch_restart<T>(dev_sub(h), dev_maps(h), h->P.nsub, (int32_t)h->h_rlist.size(), h->nsplit, h->nports, r,
+                           nrhs, h->P.n, h->wave_R, h->d_bsplit.as<T>(), h->d_o[h->cur].as<T>(), h->stream);
+    return port_constants<T>(h);
+}
+
 // The VTM solve (Table 1 steps 3-6) on the right sides staged in d_b (waves and buffers ready).
 // it[c * nsys + s]: first passing sweep; rel: the relative residuals of the returned x, *xfinal.
+//
+// Every independent system runs its own course: it stops sweeping once all its right sides pass (done
+// mask), and in FP32_IR its inner solve restarts on its new residual once the residual has fallen by
+// a factor eta since its last restart, or stalls (then the system stops if it has not improved).
 template <typename T>
 vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t> &it, std::vector<double> &rel_x,
                       const double **xfinal) {
@@ -1052,11 +1088,13 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     const int64_t n = h->P.n;
     const int32_t nsys = h->P.nsys, R = h->wave_R, ng = (nrhs + R - 1) / R;
     const vtm::DevMaps M = dev_maps(h);
-    // fixed cadence, or (check_every == 0) the next test is placed where the observed contraction
-    // rate predicts the target (between 5 and 200 sweeps later), past it by a margin of half the
-    // prediction, at most the modelled cost of a test in sweeps: the rate measured early is faster
-    // than the asymptotic one, and a test that falls short costs a further test.  A refinement
-    // restart keeps the rate (the operator is the same).
+    // Test placement: a fixed cadence, or (check_every == 0) from the contraction rate each system
+    // showed between its last tests.  Its next event (converged, or refinement step due) is predicted
+    // that many sweeps ahead, plus a margin of half the prediction but at most the modelled cost of a
+    // test (the rate measured early is faster than the asymptotic one, and a test that falls short
+    // costs another).  The next test comes at the earliest event, or at a later one while the sweeps
+    // the systems with earlier events would spend waiting cost less than one more test; between 5 and
+    // 200 sweeps.  A restart keeps the system's rate (the operator is the same).
     const bool adaptive = h->opt.check_every <= 0;
     int64_t cadence = adaptive ? 10 : h->opt.check_every;
     const int64_t maxsw = h->opt.max_sweeps > 0 ? h->opt.max_sweeps : 100000;
@@ -1064,10 +1102,20 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     const size_t nq = (size_t)nsys * nrhs;
     std::vector<double> rel;
     it.assign(nq, -1);
-    std::vector<double> acc_rel(nq, 1.0);  // residuals of the accepted x (x = 0 at the start: r = b)
-    std::vector<double> cand_rel;          // residuals of the candidate left in xtr (refinement)
-    double cand_worst = 1e300;
-    std::vector<char> sys_done(nsys, 0);
+    std::vector<double> acc_rel(nq, 1.0);     // residuals of the accepted x (x = 0 at the start: r = b)
+    std::vector<double> cand_rel(nq, 1e300);  // residuals of the candidate left in xtr (refinement)
+    // per system: 0 sweeping, 1 converged, 2 refinement stalled above the tolerance
+    std::vector<char> state(nsys, 0);
+    struct SysCourse {
+        double outer = 1.0;  // worst residual when the current inner solve started
+        double prev = 1e300; // worst residual at the previous test of the current inner solve
+        double ref = -1.0;   // same, for the rate (not set on the first test after a restart)
+        double lr = 0.0;     // last measured log contraction per sweep (< 0 when known)
+        int32_t checks = 0;  // tests of the current inner solve
+        int32_t steps = 1;   // refinement steps so far
+    };
+    std::vector<SysCourse> sc(nsys);
+    int32_t nactive = nsys;
     Events ev;
     HIP_TRY(ev.create(5));
     const hipEvent_t e0 = ev[0], e1 = ev[1], s0 = ev[2], s1 = ev[3];
@@ -1081,25 +1129,33 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     const int32_t *chunksys = h->d_chunksys.as<int32_t>();
     double sweep_ms = 0.0, sweep_bytes = 0.0;
     int64_t sweeps = 0;
-    int32_t outer = 1, checks = 0;
-    bool done = false, diverged = false;
+    int32_t checks = 0;
+    bool diverged = false;
     double first = -1.0;
     // x = 0, r = b for the refinement; the FP64 path solves b directly
     double *xcur = h->d_x.as<double>(), *xtr = h->d_xt.as<double>();
     double *rcur = h->d_r.as<double>(), *rtr = h->d_rt.as<double>();
+    auto copy_rows = [&](double *dst, const double *src, int32_t s) {
+        const int64_t lo = h->P.sys_ptr[s], len = h->P.sys_ptr[s + 1] - lo;
+        return hipMemcpy2DAsync(dst + lo, sizeof(double) * n, src + lo, sizeof(double) * n, sizeof(double) * len,
+                                nrhs, hipMemcpyDeviceToDevice, h->stream);
+    };
     HIP_TRY(hipMemsetAsync(xcur, 0, sizeof(double) * n * nrhs, h->stream));
     vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
     if ((rc = zero_waves<T>(h))) return rc;
     if ((rc = port_constants<T>(h))) return rc;
     const bool schur = use_schur(h);
     const double test_sweeps = test_cost_sweeps(h, nrhs, schur, schur && persistent_ok(h, R, ng));
-    double rel_outer = 1.0, rel_prev = 1e300;
     const double eta = 1e-5;
     constexpr double kMargin = 0.5;
-    double rate_ref = -1.0;  // worst residual at the previous test of the current inner solve
-    double lr_known = 0.0;   // last measured log contraction per sweep (< 0 when known)
-    int inner_checks = 0;
-    while (!done && sweeps < maxsw) {
+    // algorithmic bytes of one sweep of each system (the weights of the test placement)
+    std::vector<double> wsys(nsys);
+    for (int32_t y = 0; y < nsys; ++y)
+        wsys[y] = schur ? h->sys_g[y] + nrhs * (h->sys_pg[y] + 2.0 * h->sys_ports[y])
+                        : h->sys_lower[y] + nrhs * (h->sys_split[y] + 2.0 * h->sys_ports[y]);
+    std::vector<int32_t> restart;
+    std::vector<std::pair<double, double>> events;
+    while (nactive > 0 && sweeps < maxsw) {
         const int64_t cnt = std::min(cadence, maxsw - sweeps);
         HIP_TRY(hipEventRecord(s0, h->stream));
         const int64_t launches_before = h->persist_launches;
@@ -1110,14 +1166,13 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
             const double g_reads = h->persist_launches > launches_before
                                        ? (double)(h->persist_launches - launches_before) : (double)cnt;
             for (int32_t y = 0; y < nsys; ++y) {
-                if (h->mask_on && !h->active_host[y]) continue;
+                if (state[y]) continue;
                 sweep_bytes += schur ? ts * (h->sys_g[y] * g_reads + (double)cnt * r * (h->sys_pg[y] + 2.0 * h->sys_ports[y]))
                                      : ts * (double)cnt * (h->sys_lower[y] + r * (h->sys_split[y] + 2.0 * h->sys_ports[y]));
             }
         }
         sweeps += cnt;
         ++checks;
-        ++inner_checks;
         if (schur && (rc = test_solve<T>(h))) return rc;  // interior potentials of the last sweep
         // merged potentials (plus the refined x in FP32_IR), FP64 residual
         vtm::launch_merge<T>(M, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, chunkrow,
@@ -1126,102 +1181,148 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, s0, s1));
         sweep_ms += ms;
+        // the residuals of systems that have stopped are stale: only the sweeping ones count
         double worst = 0.0;
-        bool all = true;
-        for (size_t q = 0; q < nq; ++q) {
-            if (!std::isfinite(rel[q])) diverged = true;
-            if (it[q] < 0 && rel[q] <= tol) it[q] = (int32_t)sweeps;
-            all = all && rel[q] <= tol;
-            worst = std::max(worst, rel[q]);
+        for (int32_t s = 0; s < nsys; ++s) {
+            if (state[s]) continue;
+            for (int32_t c = 0; c < nrhs; ++c) {
+                const size_t q = (size_t)c * nsys + s;
+                if (!std::isfinite(rel[q])) diverged = true;
+                if (it[q] < 0 && rel[q] <= tol) it[q] = (int32_t)sweeps;
+                worst = std::max(worst, rel[q]);
+            }
         }
         if (first < 0) first = worst;
         if (worst > 1e3 * std::max(first, 1.0)) diverged = true;
         if (diverged) {
             cand_rel = rel;
-            cand_worst = worst;
             break;
         }
-        if (adaptive) {
-            int64_t next = 2 * cnt;
-            if (rate_ref > 0.0 && worst < rate_ref) lr_known = std::log(worst / rate_ref) / (double)cnt;
-            if (lr_known < 0.0) {
-                const double target = refine ? std::max(tol, eta * rel_outer) : tol;
-                const double need = std::log(target / worst) / lr_known;
-                const double margin = std::min(kMargin * need, test_sweeps);
-                next = need > 0 ? (int64_t)std::ceil(need + std::max(0.0, margin)) : 5;
+        restart.clear();
+        bool changed = false;  // the done mask changed
+        for (int32_t s = 0; s < nsys; ++s) {
+            if (state[s]) continue;
+            double ws = 0.0;
+            bool ok = true;
+            for (int32_t c = 0; c < nrhs; ++c) {
+                ws = std::max(ws, rel[(size_t)c * nsys + s]);
+                ok = ok && rel[(size_t)c * nsys + s] <= tol;
             }
-            cadence = std::max<int64_t>(5, std::min<int64_t>(200, next));
-            rate_ref = worst;
-        }
-        if (all) {
-            std::swap(xcur, xtr);
-            acc_rel = rel;
-            done = true;
-            break;
-        }
-        // done mask: a system whose every right side passes stops sweeping; its candidate x goes into
-        // both x buffers, which the merges of later tests leave alone
-        if (h->mask_on) {
-            bool changed = false;
-            for (int32_t sy = 0; sy < nsys; ++sy) {
-                if (sys_done[sy]) continue;
-                bool ok = true;
-                for (int32_t c = 0; c < nrhs && ok; ++c) ok = rel[(size_t)c * nsys + sy] <= tol;
-                if (!ok) continue;
-                sys_done[sy] = 1;
-                h->active_host[sy] = 0;
+            SysCourse &y = sc[s];
+            if (y.ref > 0.0 && ws < y.ref) y.lr = std::log(ws / y.ref) / (double)cnt;
+            y.ref = ws;
+            ++y.checks;
+            if (ok) {  // converged: the candidate is the result, and both x buffers hold it from now on
+                state[s] = 1;
+                --nactive;
+                HIP_TRY(copy_rows(xcur, xtr, s));
+                for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + s] = rel[(size_t)c * nsys + s];
                 changed = true;
-                const int64_t lo = h->P.sys_ptr[sy], len = h->P.sys_ptr[sy + 1] - lo;
-                HIP_TRY(hipMemcpy2DAsync(xcur + lo, sizeof(double) * n, xtr + lo, sizeof(double) * n,
-                                         sizeof(double) * len, nrhs, hipMemcpyDeviceToDevice, h->stream));
-                for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + sy] = rel[(size_t)c * nsys + sy];
+                continue;
             }
-            if (changed) {
-                HIP_TRY(hipMemcpyAsync(h->d_active.p, h->active_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice,
-                                       h->stream));
-                if ((rc = mask_relist(h))) return rc;
+            if (!refine) continue;
+            const bool gained = ws <= 3.0 * eta * y.outer;
+            const bool stalled = y.checks >= 2 && ws > 0.995 * y.prev;
+            y.prev = ws;
+            for (int32_t c = 0; c < nrhs; ++c) cand_rel[(size_t)c * nsys + s] = rel[(size_t)c * nsys + s];
+            if ((gained || stalled) && ws < y.outer) {  // accept the candidate, restart on its residual
+                restart.push_back(s);
+                for (int32_t c = 0; c < nrhs; ++c) {
+                    acc_rel[(size_t)c * nsys + s] = rel[(size_t)c * nsys + s];
+                    cand_rel[(size_t)c * nsys + s] = 1e300;  // xtr is about to hold an older x
+                }
+                y.outer = ws;
+                y.prev = 1e300;
+                y.ref = -1.0;
+                y.checks = 0;
+                ++y.steps;
+            } else if (stalled) {  // no further progress: keep the accepted x (the better one) in both buffers
+                state[s] = 2;
+                --nactive;
+                HIP_TRY(copy_rows(xtr, xcur, s));
+                changed = true;
             }
+        }
+        if (h->mask_on && changed) {
+            for (int32_t s = 0; s < nsys; ++s) h->active_host[s] = state[s] == 0;
+            HIP_TRY(hipMemcpyAsync(h->d_active.p, h->active_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice,
+                                   h->stream));
+            if ((rc = mask_relist(h))) return rc;
         }
         if (!refine) {
             std::swap(xcur, xtr);
-            acc_rel = rel;
-            continue;
-        }
-        // FP32 inner solve: restart on the new residual once it has gained a factor eta or stalls
-        const bool gained = worst <= 3.0 * eta * rel_outer;
-        const bool stalled = inner_checks >= 2 && worst > 0.995 * rel_prev;
-        rel_prev = worst;
-        cand_rel = rel;
-        cand_worst = worst;
-        if ((gained || stalled) && worst < rel_outer) {
-            std::swap(xcur, xtr);
-            std::swap(rcur, rtr);
-            acc_rel = rel;
-            cand_worst = 1e300;  // xtr now holds an older x
-            rel_outer = worst;
-            rel_prev = 1e300;
-            inner_checks = 0;
-            rate_ref = -1.0;
-            if (adaptive) {  // first test of the new inner solve from the known rate
-                const double target = std::max(tol, eta * rel_outer);
-                const double need = lr_known < 0.0 ? std::log(target / rel_outer) / lr_known : 10.0;
-                const double margin = std::min(kMargin * need, test_sweeps);
-                cadence = std::max<int64_t>(5, std::min<int64_t>(200, (int64_t)std::ceil(need + margin)));
+            for (int32_t s = 0; s < nsys; ++s)
+                if (!state[s])
+                    for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + s] = rel[(size_t)c * nsys + s];
+        } else if (!restart.empty()) {
+            if ((int32_t)restart.size() == nactive) {
+                // every system still sweeping restarts (the stopped ones hold the same rows in both buffers)
+                std::swap(xcur, xtr);
+                std::swap(rcur, rtr);
+                vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
+                if ((rc = zero_waves<T>(h))) return rc;
+                if ((rc = port_constants<T>(h))) return rc;
+            } else {
+                for (const int32_t s : restart) {
+                    HIP_TRY(copy_rows(xcur, xtr, s));
+                    HIP_TRY(copy_rows(rcur, rtr, s));
+                }
+                if ((rc = restart_systems<T>(h, restart, rcur, nrhs))) return rc;
             }
-            ++outer;
-            vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
-            if ((rc = zero_waves<T>(h))) return rc;
-            if ((rc = port_constants<T>(h))) return rc;
-            continue;
         }
-        if (stalled) break;  // no further progress possible
+        if (h->trace) {
+            std::fprintf(stderr, "vtm test %d: sweeps %lld, sweeping %d, restarts %zu |", checks, (long long)sweeps,
+                         nactive, restart.size());
+            for (int32_t s = 0; s < nsys; ++s) {
+                double ws = 0.0;
+                for (int32_t c = 0; c < nrhs; ++c) ws = std::max(ws, rel[(size_t)c * nsys + s]);
+                std::fprintf(stderr, " %c%.1e", "s+x"[state[s]], ws);
+            }
+            std::fprintf(stderr, "\n");
+        }
+        if (adaptive && nactive > 0) {
+            events.clear();
+            double wtot = 0.0;
+            for (int32_t s = 0; s < nsys; ++s) {
+                if (state[s]) continue;
+                const SysCourse &y = sc[s];
+                const double target = refine ? std::max(tol, eta * y.outer) : tol;
+                const double now = y.ref > 0.0 ? y.ref : y.outer;
+                double t = y.ref > 0.0 ? 2.0 * (double)cnt : 10.0;  // rate not known yet
+                if (y.lr < 0.0) {
+                    const double need = std::log(target / now) / y.lr;
+                    t = need > 0.0 ? std::ceil(need + std::min(kMargin * need, test_sweeps)) : 5.0;
+                }
+                events.emplace_back(t, wsys[s]);
+                wtot += wsys[s];
+            }
+            std::sort(events.begin(), events.end());
+            double t_next = events[0].first, w_past = 0.0, waiting = 0.0;
+            for (size_t i = 1; i < events.size(); ++i) {
+                w_past += events[i - 1].second;
+                waiting += w_past * (events[i].first - events[i - 1].first);
+                if (waiting > test_sweeps * wtot) break;
+                t_next = events[i].first;
+            }
+            cadence = std::max<int64_t>(5, std::min<int64_t>(200, (int64_t)t_next));
+        }
     }
-    // refinement without convergence: return the better of the accepted x and the last candidate
-    if (refine && !done && !diverged && cand_worst < rel_outer) {
-        std::swap(xcur, xtr);
-        acc_rel = cand_rel;
-    }
+    // refinement stopped by max_sweeps: per system, the better of the accepted x and the last candidate
+    if (refine && !diverged)
+        for (int32_t s = 0; s < nsys; ++s) {
+            if (state[s]) continue;
+            double cw = 0.0;
+            for (int32_t c = 0; c < nrhs; ++c) cw = std::max(cw, cand_rel[(size_t)c * nsys + s]);
+            if (cw < sc[s].outer) {
+                HIP_TRY(copy_rows(xcur, xtr, s));
+                for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + s] = cand_rel[(size_t)c * nsys + s];
+            }
+        }
     if (diverged) acc_rel = cand_rel;
+    bool done = !diverged;
+    for (int32_t s = 0; s < nsys; ++s) done = done && state[s] == 1;
+    int32_t outer = 1;
+    for (int32_t s = 0; s < nsys; ++s) outer = std::max(outer, sc[s].steps);
     HIP_TRY(hipEventRecord(e1, h->stream));
     HIP_TRY(hipEventSynchronize(e1));
     float total = 0.f;
@@ -1836,6 +1937,7 @@ vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
     vtm_ctx *h = new (std::nothrow) vtm_ctx();
     if (!h) return fail(VTM_ERR_OOM, "handle allocation failed");
     if (options) h->opt = *options;
+    h->trace = std::getenv("VTM_TRACE") != nullptr;
     if (h->opt.precision != VTM_FP64 && h->opt.precision != VTM_FP32_IR) {
         delete h;
         return fail(VTM_ERR_INVALID, "unknown precision");

@@ -800,6 +800,31 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
         }
 }
 
+// Restart of the listed subgraphs: split of the new right side over their entries, zero waves on
+// their ports (for every RHS group).  Entries of subgraph k end where those of k + 1 begin.
+template <typename T>
+__global__ void k_restart(DevSub D, DevMaps M, int32_t nsub, int64_t nsplit, int64_t nports,
+                          const double *__restrict__ b, int32_t nrhs, int64_t ldb, int32_t R, T *__restrict__ out,
+                          T *__restrict__ o) {
+    const int k = sub_of_block(D, blockIdx.x);
+    const int64_t e0 = D.x[k], e1 = k + 1 < nsub ? D.x[k + 1] : nsplit;
+    const int ng = (nrhs + R - 1) / R;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int32_t v = M.fvtx[e];
+        const double m = (double)M.fmul[e];
+        for (int g = 0; g < ng; ++g)
+            for (int cc = 0; cc < R; ++cc) {
+                const int c = g * R + cc;
+                out[((int64_t)g * nsplit + e) * R + cc] = c < nrhs ? (T)(b[v + (int64_t)c * ldb] / m) : (T)0;
+            }
+    }
+    const int p0 = D.port_ptr[k], np = D.port_ptr[k + 1] - p0;
+    for (int i = threadIdx.x; i < np * R * ng; i += blockDim.x) {
+        const int g = i / (np * R), j = i - g * np * R;
+        o[((int64_t)g * nports + p0) * R + j] = (T)0;
+    }
+}
+
 // Lane moves by DPP (quad permutations and row rotations); a double moves as its two halves.
 template <int CTRL>
 __device__ inline float dpp_mov(float v) {
@@ -2008,6 +2033,14 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
     hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, ldb, R, bsplit);
 }
 
+template <typename T>
+void launch_restart(const DevSub &D, const DevMaps &M, int32_t nsub, int32_t nlist, int64_t nsplit, int64_t nports,
+                    const double *b, int32_t nrhs, int64_t ldb, int32_t R, T *bsplit, T *o, hipStream_t st) {
+    if (nlist <= 0) return;
+    hipLaunchKernelGGL(k_restart<T>, dim3(nlist), dim3(256), 0, st, D, M, nsub, nsplit, nports, b, nrhs, ldb, R,
+                       bsplit, o);
+}
+
 // Right-hand sides per workgroup of the substitution sweep: the largest RS <= R whose LDS is at
 // most 96 KiB (two workgroups per CU), else the largest that fits the CU at all (0: none fits).
 template <typename T>
@@ -2269,6 +2302,10 @@ void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, in
 
 template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);
 template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, float *, hipStream_t);
+template void launch_restart<double>(const DevSub &, const DevMaps &, int32_t, int32_t, int64_t, int64_t, const double *, int32_t,
+                                     int64_t, int32_t, double *, double *, hipStream_t);
+template void launch_restart<float>(const DevSub &, const DevMaps &, int32_t, int32_t, int64_t, int64_t, const double *, int32_t,
+                                    int64_t, int32_t, float *, float *, hipStream_t);
 template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
                                    int32_t, int64_t, int64_t, const double *, const double *, const int32_t *,
                                    const double *, const double *, double *, double *, double *, int, hipStream_t);

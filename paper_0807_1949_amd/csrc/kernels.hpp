@@ -115,6 +115,13 @@ template <typename T>
 void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int64_t ldb, int32_t R,
                   T *bsplit, hipStream_t st);
 
+// Restart of the inner solves of some systems (iterative refinement, one system at a time): for the
+// nlist subgraphs of D.sub_list (of nsub), the source split of the new right side b and zero outgoing waves on
+// their ports in o (the buffer the next sweep reads).
+template <typename T>
+void launch_restart(const DevSub &D, const DevMaps &M, int32_t nsub, int32_t nlist, int64_t nsplit, int64_t nports,
+                    const double *b, int32_t nrhs, int64_t ldb, int32_t R, T *bsplit, T *o, hipStream_t st);
+
 // One VTM sweep over all subgraphs and right-hand-side groups (grid = subgraphs x RHS groups).
 template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,
