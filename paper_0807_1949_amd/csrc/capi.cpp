@@ -676,17 +676,41 @@ vtm_status zero_waves(vtm_ctx *h) {
     return VTM_OK;
 }
 
-// Stage b (host or device) into the handle's FP64 device copy.
+// A caller's column-major n x nrhs block (host or device, leading dimension ld) into row-interleaved
+// device rows (stride vec_stride(nrhs)); a host block passes through the device buffer staging
+// (column-major, at least n x nrhs), which the stream order keeps until the conversion has read it.
+vtm_status to_rows(vtm_ctx *h, const double *src, int64_t ld, int64_t n, int32_t nrhs, double *dst, double *staging) {
+    const int32_t S = vtm::vec_stride(nrhs);
+    if (!is_device_ptr(src)) {
+        HIP_TRY(hipMemcpy2DAsync(staging, sizeof(double) * n, src, sizeof(double) * ld, sizeof(double) * n, nrhs,
+                                 hipMemcpyHostToDevice, h->stream));
+        src = staging;
+        ld = n;
+    }
+    vtm::launch_to_rows(src, ld, n, nrhs, S, dst, h->stream);
+    return VTM_OK;
+}
+
+// Row-interleaved device rows into a caller's column-major block (host or device), through staging
+// for a host destination.
+vtm_status from_rows(vtm_ctx *h, const double *src, int64_t n, int32_t nrhs, double *dst, int64_t ld, double *staging) {
+    const int32_t S = vtm::vec_stride(nrhs);
+    if (is_device_ptr(dst)) {
+        vtm::launch_from_rows(src, S, n, nrhs, dst, ld, h->stream);
+        return VTM_OK;
+    }
+    vtm::launch_from_rows(src, S, n, nrhs, staging, n, h->stream);
+    HIP_TRY(hipMemcpy2DAsync(dst, sizeof(double) * ld, staging, sizeof(double) * n, sizeof(double) * n, nrhs,
+                             hipMemcpyDeviceToHost, h->stream));
+    return VTM_OK;
+}
+
+// Stage b (host or device) into the handle's FP64 device copy (row-interleaved; after alloc_solve, whose
+// residual buffer stages a host b).
 vtm_status stage_b(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb) {
     const int64_t n = h->P.n;
-    HIP_TRY(ensure(h->d_b, sizeof(double) * (size_t)n * nrhs));
-    if (is_device_ptr(b))
-        HIP_TRY(hipMemcpy2DAsync(h->d_b.p, sizeof(double) * n, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
-                                 hipMemcpyDeviceToDevice, h->stream));
-    else
-        HIP_TRY(hipMemcpy2DAsync(h->d_b.p, sizeof(double) * n, b, sizeof(double) * ldb, sizeof(double) * n, nrhs,
-                                 hipMemcpyHostToDevice, h->stream));
-    return VTM_OK;
+    HIP_TRY(ensure(h->d_b, sizeof(double) * (size_t)n * vtm::vec_stride(nrhs)));
+    return to_rows(h, b, ldb, n, nrhs, h->d_b.as<double>(), h->d_rt.as<double>());
 }
 
 // After a stream synchronisation: did a persistent launch since the last check give up on a wait?
@@ -707,11 +731,11 @@ vtm_status check_abort(vtm_ctx *h, int fetched = -1) {
     return VTM_OK;
 }
 
+// x (row-interleaved src, one of the two iterate buffers) to the caller; the residual buffer stages a
+// host destination.
 vtm_status write_x(vtm_ctx *h, const double *src, double *x, int32_t nrhs, int64_t ldx) {
-    const int64_t n = h->P.n;
-    hipMemcpyKind kind = is_device_ptr(x) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    HIP_TRY(hipMemcpy2DAsync(x, sizeof(double) * ldx, src, sizeof(double) * n, sizeof(double) * n, nrhs, kind,
-                             h->stream));
+    vtm_status rc;
+    if ((rc = from_rows(h, src, h->P.n, nrhs, x, ldx, h->d_r.as<double>()))) return rc;
     HIP_TRY(hipStreamSynchronize(h->stream));
     return check_abort(h);
 }
@@ -951,13 +975,13 @@ vtm_status port_constants(vtm_ctx *h) {
 template <typename T>
 vtm_status alloc_solve(vtm_ctx *h, int32_t nrhs) {
     const int32_t R = h->wave_R, ng = (nrhs + R - 1) / R;
-    const int64_t n = h->P.n;
+    const int64_t n = h->P.n, S = vtm::vec_stride(nrhs);
     HIP_TRY(ensure(h->d_bsplit, sizeof(T) * (size_t)ng * h->nsplit * R));
     HIP_TRY(ensure(h->d_xloc, sizeof(T) * (size_t)ng * h->nsplit * R));
-    HIP_TRY(ensure(h->d_x, sizeof(double) * (size_t)n * nrhs));
-    HIP_TRY(ensure(h->d_xt, sizeof(double) * (size_t)n * nrhs));
-    HIP_TRY(ensure(h->d_r, sizeof(double) * (size_t)n * nrhs));
-    HIP_TRY(ensure(h->d_rt, sizeof(double) * (size_t)n * nrhs));
+    HIP_TRY(ensure(h->d_x, sizeof(double) * (size_t)n * S));
+    HIP_TRY(ensure(h->d_xt, sizeof(double) * (size_t)n * S));
+    HIP_TRY(ensure(h->d_r, sizeof(double) * (size_t)n * S));
+    HIP_TRY(ensure(h->d_rt, sizeof(double) * (size_t)n * S));
     HIP_TRY(ensure(h->d_part, sizeof(double) * 2 * (size_t)h->nchunks * nrhs));
     HIP_TRY(ensure(h->d_relres, sizeof(double) * ((size_t)h->P.nsys * nrhs + 1)));
     return VTM_OK;
@@ -967,7 +991,7 @@ vtm_status alloc_solve(vtm_ctx *h, int32_t nrhs) {
 vtm_status residual(vtm_ctx *h, int32_t nrhs, const double *x, double *r, std::vector<double> &rel) {
     vtm::DevCsr A{h->d_rp.as<int64_t>(), h->d_ci.as<int32_t>(), h->d_v.as<double>()};
     const int64_t n = h->P.n;
-    vtm::launch_residual(A, n, nrhs, h->d_b.as<double>(), n, x, n, r, n, h->d_chunkrow.as<int64_t>(),
+    vtm::launch_residual(A, n, nrhs, vtm::vec_stride(nrhs), h->d_b.as<double>(), x, r, h->d_chunkrow.as<int64_t>(),
                          h->d_chunksys.as<int32_t>(), h->mask_on ? h->d_active.as<int32_t>() : nullptr, h->nchunks, h->d_syschunk.as<int32_t>(), h->P.nsys,
                          h->d_part.as<double>(), h->abort_pending ? h->d_abort.as<int32_t>() : nullptr,
                          h->d_relres.as<double>(), h->stream);
@@ -1069,7 +1093,8 @@ vtm_status restart_systems(vtm_ctx *h, const std::vector<int32_t> &sys, const do
         ~ListOff() { h->rl_on = false; }
     } list_off{h};
     vtm::launch_restart<T>(dev_sub(h), dev_maps(h), h->P.nsub, (int32_t)h->h_rlist.size(), h->nsplit, h->nports, r,
-                           nrhs, h->P.n, h->wave_R, h->d_bsplit.as<T>(), h->d_o[h->cur].as<T>(), h->stream);
+                           nrhs, vtm::vec_stride(nrhs), h->wave_R, h->d_bsplit.as<T>(), h->d_o[h->cur].as<T>(),
+                           h->stream);
     return port_constants<T>(h);
 }
 
@@ -1086,7 +1111,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     h->stats.persistent = 0;
     h->persist_launches = 0;
     const int64_t n = h->P.n;
-    const int32_t nsys = h->P.nsys, R = h->wave_R, ng = (nrhs + R - 1) / R;
+    const int32_t nsys = h->P.nsys, R = h->wave_R, ng = (nrhs + R - 1) / R, S = vtm::vec_stride(nrhs);
     const vtm::DevMaps M = dev_maps(h);
     // Test placement: a fixed cadence, or (check_every == 0) from the contraction rate each system
     // showed between its last tests.  Its next event (converged, or refinement step due) is predicted
@@ -1135,13 +1160,13 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     // x = 0, r = b for the refinement; the FP64 path solves b directly
     double *xcur = h->d_x.as<double>(), *xtr = h->d_xt.as<double>();
     double *rcur = h->d_r.as<double>(), *rtr = h->d_rt.as<double>();
-    auto copy_rows = [&](double *dst, const double *src, int32_t s) {
+    auto copy_rows = [&](double *dst, const double *src, int32_t s) {  // the rows of system s
         const int64_t lo = h->P.sys_ptr[s], len = h->P.sys_ptr[s + 1] - lo;
-        return hipMemcpy2DAsync(dst + lo, sizeof(double) * n, src + lo, sizeof(double) * n, sizeof(double) * len,
-                                nrhs, hipMemcpyDeviceToDevice, h->stream);
+        return hipMemcpyAsync(dst + lo * S, src + lo * S, sizeof(double) * len * S, hipMemcpyDeviceToDevice,
+                              h->stream);
     };
-    HIP_TRY(hipMemsetAsync(xcur, 0, sizeof(double) * n * nrhs, h->stream));
-    vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
+    HIP_TRY(hipMemsetAsync(xcur, 0, sizeof(double) * n * S, h->stream));
+    vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, S, R, h->d_bsplit.as<T>(), h->stream);
     if ((rc = zero_waves<T>(h))) return rc;
     if ((rc = port_constants<T>(h))) return rc;
     const bool schur = use_schur(h);
@@ -1175,7 +1200,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
         ++checks;
         if (schur && (rc = test_solve<T>(h))) return rc;  // interior potentials of the last sweep
         // merged potentials (plus the refined x in FP32_IR), FP64 residual
-        vtm::launch_merge<T>(M, h->nsplit, nrhs, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, n, xtr, n, chunkrow,
+        vtm::launch_merge<T>(M, h->nsplit, nrhs, S, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, xtr, chunkrow,
                              chunksys, h->nchunks, h->mask_on ? h->d_active.as<int32_t>() : nullptr, h->stream);
         if ((rc = residual(h, nrhs, xtr, refine ? rtr : nullptr, rel))) return rc;
         float ms = 0.f;
@@ -1259,7 +1284,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
                 // every system still sweeping restarts (the stopped ones hold the same rows in both buffers)
                 std::swap(xcur, xtr);
                 std::swap(rcur, rtr);
-                vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, n, R, h->d_bsplit.as<T>(), h->stream);
+                vtm::launch_split<T>(M, h->nsplit, rcur, nrhs, S, R, h->d_bsplit.as<T>(), h->stream);
                 if ((rc = zero_waves<T>(h))) return rc;
                 if ((rc = port_constants<T>(h))) return rc;
             } else {
@@ -1382,16 +1407,17 @@ vtm_status run_impl(vtm_ctx *h, const double *b, int32_t nrhs, int64_t ldb, int6
     if ((rc = stage_b(h, b, nrhs, ldb))) return rc;
     const int64_t n = h->P.n;
     const vtm::DevMaps M = dev_maps(h);
-    vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, n, h->wave_R, h->d_bsplit.as<T>(), h->stream);
+    const int32_t S = vtm::vec_stride(nrhs);
+    vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, S, h->wave_R, h->d_bsplit.as<T>(), h->stream);
     h->stats.sweep_mode = use_schur(h) ? 2 : 1;
     if (nsweeps > 0) {
         if ((rc = port_constants<T>(h))) return rc;
         if ((rc = run_sweeps_dev<T>(h, nsweeps))) return rc;
         if (use_schur(h)) local_solve<T>(h, false);
-        vtm::launch_merge<T>(M, h->nsplit, nrhs, h->wave_R, h->d_xloc.as<T>(), nullptr, n, h->d_x.as<double>(), n,
+        vtm::launch_merge<T>(M, h->nsplit, nrhs, S, h->wave_R, h->d_xloc.as<T>(), nullptr, h->d_x.as<double>(),
                              h->d_chunkrow.as<int64_t>(), h->d_chunksys.as<int32_t>(), h->nchunks, nullptr, h->stream);
     } else {
-        HIP_TRY(hipMemsetAsync(h->d_x.p, 0, sizeof(double) * n * nrhs, h->stream));
+        HIP_TRY(hipMemsetAsync(h->d_x.p, 0, sizeof(double) * n * S, h->stream));
     }
     return write_x(h, h->d_x.as<double>(), x, nrhs, ldx);
 }
@@ -1873,12 +1899,6 @@ vtm_status build_batch(vtm_ctx *const *hs, int32_t count, vtm_ctx *B) {
     return setup_core(B, VTM_Z_USER, z, false);
 }
 
-// Device or host copy direction for a 2D copy between a user pointer and the device.
-hipMemcpyKind user_kind(const void *user, bool to_device) {
-    if (is_device_ptr(user)) return hipMemcpyDeviceToDevice;
-    return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
-}
-
 template <typename T>
 vtm_status batch_impl(vtm_ctx *B, vtm_ctx *const *hs, int32_t count, const double *const *b, int32_t nrhs,
                       const int64_t *ldb, double tol, double *const *x, const int64_t *ldx, int32_t *const *iters,
@@ -1886,13 +1906,12 @@ vtm_status batch_impl(vtm_ctx *B, vtm_ctx *const *hs, int32_t count, const doubl
     vtm_status rc;
     if ((rc = ensure_waves<T>(B, nrhs))) return rc;
     if ((rc = alloc_solve<T>(B, nrhs))) return rc;
-    const int64_t N = B->P.n;
-    HIP_TRY(ensure(B->d_b, sizeof(double) * (size_t)N * nrhs));
+    const int64_t N = B->P.n, S = vtm::vec_stride(nrhs);
+    HIP_TRY(ensure(B->d_b, sizeof(double) * (size_t)N * S));
     int64_t vo = 0;
-    for (int32_t i = 0; i < count; ++i) {
+    for (int32_t i = 0; i < count; ++i) {  // the members' rows one after the other
         const int64_t ni = hs[i]->P.n;
-        HIP_TRY(hipMemcpy2DAsync(B->d_b.as<double>() + vo, sizeof(double) * N, b[i], sizeof(double) * ldb[i],
-                                 sizeof(double) * ni, nrhs, user_kind(b[i], true), B->stream));
+        if ((rc = to_rows(B, b[i], ldb[i], ni, nrhs, B->d_b.as<double>() + vo * S, B->d_rt.as<double>()))) return rc;
         vo += ni;
     }
     std::vector<int32_t> it;
@@ -1907,8 +1926,7 @@ vtm_status batch_impl(vtm_ctx *B, vtm_ctx *const *hs, int32_t count, const doubl
     for (int32_t i = 0; i < count; ++i) {
         const int64_t ni = hs[i]->P.n;
         const int32_t nsi = hs[i]->P.nsys;
-        HIP_TRY(hipMemcpy2DAsync(x[i], sizeof(double) * ldx[i], xf + vo, sizeof(double) * N, sizeof(double) * ni, nrhs,
-                                 user_kind(x[i], false), B->stream));
+        if ((rc = from_rows(B, xf + vo * S, ni, nrhs, x[i], ldx[i], B->d_r.as<double>()))) return rc;
         for (int32_t c = 0; c < nrhs; ++c)
             for (int32_t y = 0; y < nsi; ++y) {
                 const size_t q = (size_t)c * NS + yo + y, qi = (size_t)c * nsi + y;

@@ -188,13 +188,11 @@ struct FactorArgs {
     int nb;  // 16 x 16 blocks per row of the packed G_k
 };
 
-// Position of Y_s[row][a] in the FP32 copy of the Y blocks.  A supernode's region of the Green
-// workspace starts on a multiple of 4 entries and holds (2 nc + m) w of them; the FP32 copy needs no
-// port front, so for w >= 4 its rows start at the region's start with a stride of w rounded up to 4
-// (16-byte rows for vector loads; nc (w + 3) <= (2 nc + m) w), and for w < 4 they stay where the FP64
-// Y block is.
-__host__ __device__ inline int64_t y32_pos(int64_t region, int f, int w, int row, int a) {
-    return w >= 4 ? region + (int64_t)row * ((w + 3) & ~3) + a : region + (int64_t)f * w + (int64_t)row * w + a;
+// Position of Y_s[row][a] in the FP32 copy of the Y blocks: column-major from the start of the
+// supernode's region of the Green workspace (which holds (2 nc + m) w >= nc w entries), so that the
+// threads of a test solve, one per row, read consecutive entries for every port column a.
+__host__ __device__ inline int64_t y32_pos(int64_t region, int nc, int row, int a) {
+    return region + (int64_t)a * nc + row;
 }
 
 // G[ports a, b of s] += acc for the lower part of tile (ta, tb) of Y_s^T Y_s; port(x) is the port
@@ -527,7 +525,7 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                         if (row < nc) {
                             Yg[row * w + a] = v;
                             if (Yl) Yl[row * w + a] = v;
-                            if (X.gws32) X.gws32[y32_pos(e.x, f, w, row, a)] = (float)v;
+                            if (X.gws32) X.gws32[y32_pos(e.x, nc, row, a)] = (float)v;
                         } else {
                             X.gws[e.z + (int64_t)prow[jj] * pw + a + (pc0 - ppc0)] = v;
                         }
@@ -690,7 +688,7 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
                 double acc = T[i * w + a] / F[i * f + i];
                 for (int t = 0; t < i; ++t) acc += F[t * f + i] * T[t * w + a];
                 Y[idx] = acc;
-                if (X.gws32) X.gws32[y32_pos(e.x, f, w, i, a)] = (float)acc;
+                if (X.gws32) X.gws32[y32_pos(e.x, nc, i, a)] = (float)acc;
             }
             __syncthreads();
             for (int idx = r; idx < m * w; idx += n) {  // T[nc:] - L21 Y into the parent's port front
@@ -786,7 +784,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, cons
 
 // ------------------------------------------------------------------------ split
 template <typename T>
-__global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b, int32_t nrhs, int64_t ldb, int32_t R,
+__global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b, int32_t nrhs, int32_t S, int32_t R,
                         T *__restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nsplit) return;
@@ -796,7 +794,7 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
     for (int g = 0; g < ng; ++g)
         for (int cc = 0; cc < R; ++cc) {
             const int c = g * R + cc;
-            out[((int64_t)g * nsplit + e) * R + cc] = c < nrhs ? (T)(b[v + (int64_t)c * ldb] / m) : (T)0;
+            out[((int64_t)g * nsplit + e) * R + cc] = c < nrhs ? (T)(b[(int64_t)v * S + c] / m) : (T)0;
         }
 }
 
@@ -804,7 +802,7 @@ __global__ void k_split(DevMaps M, int64_t nsplit, const double *__restrict__ b,
 // their ports (for every RHS group).  Entries of subgraph k end where those of k + 1 begin.
 template <typename T>
 __global__ void k_restart(DevSub D, DevMaps M, int32_t nsub, int64_t nsplit, int64_t nports,
-                          const double *__restrict__ b, int32_t nrhs, int64_t ldb, int32_t R, T *__restrict__ out,
+                          const double *__restrict__ b, int32_t nrhs, int32_t S, int32_t R, T *__restrict__ out,
                           T *__restrict__ o) {
     const int k = sub_of_block(D, blockIdx.x);
     const int64_t e0 = D.x[k], e1 = k + 1 < nsub ? D.x[k + 1] : nsplit;
@@ -815,7 +813,7 @@ __global__ void k_restart(DevSub D, DevMaps M, int32_t nsub, int64_t nsplit, int
         for (int g = 0; g < ng; ++g)
             for (int cc = 0; cc < R; ++cc) {
                 const int c = g * R + cc;
-                out[((int64_t)g * nsplit + e) * R + cc] = c < nrhs ? (T)(b[v + (int64_t)c * ldb] / m) : (T)0;
+                out[((int64_t)g * nsplit + e) * R + cc] = c < nrhs ? (T)(b[(int64_t)v * S + c] / m) : (T)0;
             }
     }
     const int p0 = D.port_ptr[k], np = D.port_ptr[k + 1] - p0;
@@ -1106,7 +1104,7 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
 // with y_b = L^{-1} b~ stored by the zero-wave solve of the current source.  One parallel phase and
 // the backward substitution replace the level-by-level forward substitution.  Y rows of supernode
 // s (nc_s x w_s, row-major) live in its region of the Green workspace: after its port front in FP64,
-// at y32_pos in the FP32 copy (16-byte rows when w_s >= 4).
+// column-major at y32_pos in the FP32 copy.
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp, const T *__restrict__ Yw,
                                                 int64_t nsplit, int64_t nports, const T *__restrict__ vals,
@@ -1155,29 +1153,24 @@ __global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp,
         T acc[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) acc[c] = 0;
-        if (sizeof(T) == 4 && w >= 4) {
-            // FP32 rows of 16 bytes (y32_pos): four entries per load, sixteen in flight, the padding
-            // past w dropped (its weight index clamped into the supernode's range)
-            const f32x4 *y4 = reinterpret_cast<const f32x4 *>(Yk + y32_pos(e.x, f, w, row, 0));
-            const int n4 = (w + 3) >> 2;
-            for (int b0 = 0; b0 < n4; b0 += 4) {
-                f32x4 yv[4];
+        if (sizeof(T) == 4) {
+            // FP32 columns (y32_pos): the lanes of a supernode read consecutive rows of each column
+            // (coalesced), eight columns in flight; the weights are LDS broadcasts
+            const T *yc = Yk + y32_pos(e.x, sn_nc[s], row, 0);
+            const int ldc = sn_nc[s];
+            for (int a0 = 0; a0 < w; a0 += 8) {
+                T yv[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) yv[q] = y4[b0 + q < n4 ? b0 + q : n4 - 1];
+                for (int q = 0; q < 8; ++q) yv[q] = a0 + q < w ? yc[(int64_t)(a0 + q) * ldc] : (T)0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 8; ++q) {
+                    const T *wa = wr + (size_t)(a0 + q < w ? a0 + q : w - 1) * R;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int a = 4 * (b0 + q) + j;
-                        const T v = b0 + q < n4 && a < w ? (T)yv[q][j] : (T)0;
-                        const T *wa = wr + (size_t)(a < w ? a : w - 1) * R;
-#pragma unroll
-                        for (int c = 0; c < R; ++c) acc[c] += v * wa[c];
-                    }
+                    for (int c = 0; c < R; ++c) acc[c] += yv[q] * wa[c];
+                }
             }
         } else {
-            const T *yr = sizeof(T) == 4 ? Yk + y32_pos(e.x, f, w, row, 0)
-                                         : Yk + e.x + (int64_t)f * w + (int64_t)row * w;
+            const T *yr = Yk + e.x + (int64_t)f * w + (int64_t)row * w;
             for (int a0 = 0; a0 < w; a0 += 16) {  // sixteen loads in flight before the first product
                 T yv[16];
 #pragma unroll
@@ -1884,9 +1877,29 @@ __global__ __launch_bounds__(256, 4) void k_schur_persist(DevSub D, int32_t npg,
 // Tagged wave buffers for a persistent launch starting at sweep tag t0: buffer t0 & 1 holds the
 // current waves with tag t0, the other buffer tag t0 - 1 (never the tag a reader waits for).
 // ------------------------------------------------------------------ merge, residual
-template <typename T>
-__global__ void k_merge(DevMaps M, int64_t nsplit, int32_t nrhs, int32_t R, const T *__restrict__ xloc,
-                        const double *__restrict__ base, int64_t ldbase, double *__restrict__ xout, int64_t ldx,
+// Row of NR values of a row-interleaved vector (32-byte aligned for NR >= 4, 16-byte for NR = 2).
+template <int NR>
+__device__ inline void load_row(const double *__restrict__ p, double (&v)[NR]) {
+    if constexpr (NR >= 4) {
+#pragma unroll
+        for (int h = 0; h < NR / 4; ++h) {
+            const f64x4 t = *reinterpret_cast<const f64x4 *>(p + 4 * h);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[4 * h + j] = t[j];
+        }
+    } else if constexpr (NR == 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = p[0];
+    }
+}
+
+// Merged potentials (mean over the children) plus the base, written as whole rows (padding zero).
+template <typename T, int R>
+__global__ void k_merge(DevMaps M, int64_t nsplit, int32_t nrhs, int32_t S, const T *__restrict__ xloc,
+                        const double *__restrict__ base, double *__restrict__ xout,
                         const int64_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_sys,
                         const int32_t *__restrict__ active) {
     const int ch = blockIdx.x;
@@ -1895,84 +1908,138 @@ __global__ void k_merge(DevMaps M, int64_t nsplit, int32_t nrhs, int32_t R, cons
     if (v >= chunk_row[ch + 1]) return;
     const int64_t p0 = M.cp_ptr[v], p1 = M.cp_ptr[v + 1];
     const double m = (double)(p1 - p0);
-    for (int c = 0; c < nrhs; ++c) {
-        const int g = c / R, cc = c - g * R;
-        double acc = 0.0;
-        for (int64_t p = p0; p < p1; ++p) acc += (double)xloc[((int64_t)g * nsplit + M.cp_idx[p]) * R + cc];
-        const double xb = acc / m;
-        xout[v + (int64_t)c * ldx] = base ? base[v + (int64_t)c * ldbase] + xb : xb;
+    const int ng = (nrhs + R - 1) / R;
+    double *xo = xout + v * S;
+    const double *bo = base ? base + v * S : nullptr;
+    for (int g = 0; g < ng; ++g) {
+        double acc[R];
+#pragma unroll
+        for (int cc = 0; cc < R; ++cc) acc[cc] = 0.0;
+        for (int64_t p = p0; p < p1; ++p) {
+            const T *src = xloc + ((int64_t)g * nsplit + M.cp_idx[p]) * R;
+#pragma unroll
+            for (int cc = 0; cc < R; ++cc) acc[cc] += (double)src[cc];
+        }
+#pragma unroll
+        for (int cc = 0; cc < R; ++cc) {
+            const int c = g * R + cc;
+            if (c < nrhs) xo[c] = bo ? bo[c] + acc[cc] / m : acc[cc] / m;
+        }
     }
+    for (int c = nrhs; c < S; ++c) xo[c] = 0.0;
 }
 
-// r = b - A x for NR right-hand sides (block y: columns NR y .. NR y + NR - 1) in one pass over A:
-// each row's entries are read once for all of them.  One workgroup per chunk of rows (inside one
-// system); a chunk of a converged system (active[s] == 0) is skipped and keeps its partial sums.
+// Sum over a wave of 64 lanes (butterfly), the result in every lane.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// r = b - A x for NR right-hand sides (block y: columns NR y .. NR y + NR - 1 of the row-interleaved
+// vectors, row stride S) in one pass over A: each row's entries are read once for all of them, and x
+// and b as whole rows.  One workgroup per chunk of at most 256 rows (inside one system); its entries
+// are first staged in LDS by coalesced loads when they fit (else read from memory by the row's
+// thread).  A chunk of a converged system (active[s] == 0) is skipped and keeps its partial sums.
+constexpr int kResStage = 2560;  // matrix entries of a chunk staged in LDS (30 KiB)
 template <int NR>
-__global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
-                                                       const double *__restrict__ x, int64_t ldx, double *__restrict__ r,
-                                                       int64_t ldr, const int64_t *__restrict__ chunk_row,
+__global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, int32_t S, const double *__restrict__ b,
+                                                       const double *__restrict__ x, double *__restrict__ r,
+                                                       const int64_t *__restrict__ chunk_row,
                                                        const int32_t *__restrict__ chunk_sys,
                                                        const int32_t *__restrict__ active, int32_t nchunks,
                                                        double *__restrict__ part) {
-    __shared__ double red[2][kThreads];
+    __shared__ int32_t scol[kResStage];
+    __shared__ double sval[kResStage];
+    __shared__ double red[kThreads / 64][2 * NR];
     const int ch = blockIdx.x, c0 = blockIdx.y * NR, tid = threadIdx.x;
     if (active && !active[chunk_sys[ch]]) return;
     const int64_t r0 = chunk_row[ch], r1 = chunk_row[ch + 1];
+    const int64_t eb = A.rp[r0], ee = A.rp[r1];
+    const bool staged = ee - eb <= kResStage;
+    if (staged) {
+        for (int i = tid; i < (int)(ee - eb); i += kThreads) {
+            scol[i] = A.ci[eb + i];
+            sval[i] = A.v[eb + i];
+        }
+        __syncthreads();
+    }
     double rr[NR], bb[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) rr[c] = bb[c] = 0.0;
     for (int64_t v = r0 + tid; v < r1; v += kThreads) {
         double acc[NR];
+        load_row<NR>(b + v * S + c0, acc);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) bb[c] += c0 + c < nrhs ? acc[c] * acc[c] : 0.0;
+        const int64_t e0 = A.rp[v], e1 = A.rp[v + 1];
+        // four entries a round, their rows of x loaded together (indices past the row clamped to its
+        // last entry, whose product is then weighted by zero: the loads stay unconditional)
+        for (int64_t e = e0; e < e1; e += 4) {
+            int32_t col[4];
+            double av[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t ei = e + q < e1 ? e + q : e1 - 1;
+                col[q] = staged ? scol[ei - eb] : A.ci[ei];
+                const double a = staged ? sval[ei - eb] : A.v[ei];
+                av[q] = e + q < e1 ? a : 0.0;
+            }
+            double xv[4][NR];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) load_row<NR>(x + (int64_t)col[q] * S + c0, xv[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[c] -= av[q] * xv[q][c];
+        }
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            const int cc = c0 + c < nrhs ? c0 + c : nrhs - 1;
-            acc[c] = b[v + (int64_t)cc * ldb];
-            bb[c] += c0 + c < nrhs ? acc[c] * acc[c] : 0.0;
+            if (c0 + c >= nrhs) acc[c] = 0.0;  // padding columns
+            rr[c] += acc[c] * acc[c];
         }
-        const int64_t e0 = A.rp[v], e1 = A.rp[v + 1];
-        // eight entries a round, their loads issued together (indices past the row clamped to its last
-        // entry, whose product is then weighted by zero: arithmetic, so the loads stay unconditional)
-        for (int64_t eb = e0; eb < e1; eb += 8) {
-            int32_t col[8];
-            double av[8];
+        if (r) {
+            double *ro = r + v * S + c0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int64_t e = eb + q < e1 ? eb + q : e1 - 1;
-                col[q] = A.ci[e];
-                av[q] = eb + q < e1 ? A.v[e] : 0.0;
-            }
-#pragma unroll
-            for (int c = 0; c < NR; ++c) {
-                const int cc = c0 + c < nrhs ? c0 + c : nrhs - 1;
-                double xv[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) xv[q] = x[col[q] + (int64_t)cc * ldx];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) acc[c] -= av[q] * xv[q];
-            }
+            for (int c = 0; c < NR; ++c) ro[c] = acc[c];
         }
-#pragma unroll
-        for (int c = 0; c < NR; ++c)
-            if (c0 + c < nrhs) {
-                if (r) r[v + (int64_t)(c0 + c) * ldr] = acc[c];
-                rr[c] += acc[c] * acc[c];
-            }
     }
+    // per column: wave sums, then the four waves' partial sums added in a fixed order
+    const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-        red[0][tid] = rr[c];
-        red[1][tid] = bb[c];
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (tid < w) { red[0][tid] += red[0][tid + w]; red[1][tid] += red[1][tid + w]; }
-            __syncthreads();
+        const double sr = wave_sum(rr[c]), sb = wave_sum(bb[c]);
+        if (lane == 0) {
+            red[wave][2 * c] = sr;
+            red[wave][2 * c + 1] = sb;
         }
-        if (tid == 0 && c0 + c < nrhs) {
-            part[((int64_t)(c0 + c) * nchunks + ch) * 2 + 0] = red[0][0];
-            part[((int64_t)(c0 + c) * nchunks + ch) * 2 + 1] = red[1][0];
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    if (tid < NR && c0 + tid < nrhs) {
+        double sr = 0.0, sb = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            sr += red[w][2 * tid];
+            sb += red[w][2 * tid + 1];
+        }
+        part[((int64_t)(c0 + tid) * nchunks + ch) * 2 + 0] = sr;
+        part[((int64_t)(c0 + tid) * nchunks + ch) * 2 + 1] = sb;
+    }
+}
+
+// Column-major n x nrhs (leading dimension ld) to row-interleaved rows of stride S (padding zero), and back.
+__global__ void k_to_rows(const double *__restrict__ src, int64_t ld, int64_t n, int32_t nrhs, int32_t S,
+                          double *__restrict__ dst) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    for (int c = 0; c < S; ++c) dst[v * S + c] = c < nrhs ? src[v + (int64_t)c * ld] : 0.0;
+}
+
+__global__ void k_from_rows(const double *__restrict__ src, int32_t S, int64_t n, int32_t nrhs,
+                            double *__restrict__ dst, int64_t ld) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    for (int c = 0; c < nrhs; ++c) dst[v + (int64_t)c * ld] = src[v * S + c];
 }
 
 __global__ __launch_bounds__(256) void k_relres(const double *__restrict__ part, int32_t nchunks,
@@ -2028,16 +2095,24 @@ void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {
 }
 
 template <typename T>
-void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int64_t ldb, int32_t R, T *bsplit,
+void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int32_t S, int32_t R, T *bsplit,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, ldb, R, bsplit);
+    hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, S, R, bsplit);
+}
+
+void launch_to_rows(const double *src, int64_t ld, int64_t n, int32_t nrhs, int32_t S, double *dst, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_to_rows, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, ld, n, nrhs, S, dst);
+}
+
+void launch_from_rows(const double *src, int32_t S, int64_t n, int32_t nrhs, double *dst, int64_t ld, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_from_rows, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, S, n, nrhs, dst, ld);
 }
 
 template <typename T>
 void launch_restart(const DevSub &D, const DevMaps &M, int32_t nsub, int32_t nlist, int64_t nsplit, int64_t nports,
-                    const double *b, int32_t nrhs, int64_t ldb, int32_t R, T *bsplit, T *o, hipStream_t st) {
+                    const double *b, int32_t nrhs, int32_t S, int32_t R, T *bsplit, T *o, hipStream_t st) {
     if (nlist <= 0) return;
-    hipLaunchKernelGGL(k_restart<T>, dim3(nlist), dim3(256), 0, st, D, M, nsub, nsplit, nports, b, nrhs, ldb, R,
+    hipLaunchKernelGGL(k_restart<T>, dim3(nlist), dim3(256), 0, st, D, M, nsub, nsplit, nports, b, nrhs, S, R,
                        bsplit, o);
 }
 
@@ -2276,36 +2351,41 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
 }
 
 template <typename T>
-void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc, const double *base,
-                  int64_t ldbase, double *xout, int64_t ldx, const int64_t *chunk_row, const int32_t *chunk_sys,
-                  int32_t nchunks, const int32_t *active, hipStream_t st) {
+void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t S, int32_t R, const T *xloc, const double *base,
+                  double *xout, const int64_t *chunk_row, const int32_t *chunk_sys, int32_t nchunks,
+                  const int32_t *active, hipStream_t st) {
     // one workgroup per residual chunk (at most kThreads rows)
-    hipLaunchKernelGGL(k_merge<T>, dim3(nchunks), dim3(kThreads), 0, st, M, nsplit, nrhs, R, xloc, base, ldbase,
-                       xout, ldx, chunk_row, chunk_sys, active);
+    const dim3 grid(nchunks), block(kThreads);
+    switch (R) {
+        case 1: hipLaunchKernelGGL((k_merge<T, 1>), grid, block, 0, st, M, nsplit, nrhs, S, xloc, base, xout, chunk_row, chunk_sys, active); break;
+        case 2: hipLaunchKernelGGL((k_merge<T, 2>), grid, block, 0, st, M, nsplit, nrhs, S, xloc, base, xout, chunk_row, chunk_sys, active); break;
+        case 4: hipLaunchKernelGGL((k_merge<T, 4>), grid, block, 0, st, M, nsplit, nrhs, S, xloc, base, xout, chunk_row, chunk_sys, active); break;
+        default: hipLaunchKernelGGL((k_merge<T, 8>), grid, block, 0, st, M, nsplit, nrhs, S, xloc, base, xout, chunk_row, chunk_sys, active); break;
+    }
 }
 
-void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, const double *b, int64_t ldb, const double *x, int64_t ldx,
-                     double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *chunk_sys, const int32_t *active,
-                     int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag,
-                     double *relres, hipStream_t st) {
-    const int NR = nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
-    const dim3 grid(nchunks, (nrhs + NR - 1) / NR);
+void launch_residual(const DevCsr &A, int64_t, int32_t nrhs, int32_t S, const double *b, const double *x, double *r,
+                     const int64_t *chunk_row, const int32_t *chunk_sys, const int32_t *active, int32_t nchunks,
+                     const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag, double *relres,
+                     hipStream_t st) {
+    const int NR = res_group(S);
+    const dim3 grid(nchunks, S / NR), block(kThreads);
     switch (NR) {
-        case 1: hipLaunchKernelGGL(k_residual<1>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
-        case 2: hipLaunchKernelGGL(k_residual<2>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
-        case 4: hipLaunchKernelGGL(k_residual<4>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
-        default: hipLaunchKernelGGL(k_residual<8>, grid, dim3(kThreads), 0, st, A, nrhs, b, ldb, x, ldx, r, ldr, chunk_row, chunk_sys, active, nchunks, part); break;
+        case 1: hipLaunchKernelGGL(k_residual<1>, grid, block, 0, st, A, nrhs, S, b, x, r, chunk_row, chunk_sys, active, nchunks, part); break;
+        case 2: hipLaunchKernelGGL(k_residual<2>, grid, block, 0, st, A, nrhs, S, b, x, r, chunk_row, chunk_sys, active, nchunks, part); break;
+        case 4: hipLaunchKernelGGL(k_residual<4>, grid, block, 0, st, A, nrhs, S, b, x, r, chunk_row, chunk_sys, active, nchunks, part); break;
+        default: hipLaunchKernelGGL(k_residual<8>, grid, block, 0, st, A, nrhs, S, b, x, r, chunk_row, chunk_sys, active, nchunks, part); break;
     }
     hipLaunchKernelGGL(k_relres, dim3(nsys * nrhs), dim3(256), 0, st, part, nchunks, sys_chunk_ptr, nsys, nrhs, flag,
                        relres);
 }
 
-template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, double *, hipStream_t);
-template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int64_t, int32_t, float *, hipStream_t);
+template void launch_split<double>(const DevMaps &, int64_t, const double *, int32_t, int32_t, int32_t, double *, hipStream_t);
+template void launch_split<float>(const DevMaps &, int64_t, const double *, int32_t, int32_t, int32_t, float *, hipStream_t);
 template void launch_restart<double>(const DevSub &, const DevMaps &, int32_t, int32_t, int64_t, int64_t, const double *, int32_t,
-                                     int64_t, int32_t, double *, double *, hipStream_t);
+                                     int32_t, int32_t, double *, double *, hipStream_t);
 template void launch_restart<float>(const DevSub &, const DevMaps &, int32_t, int32_t, int64_t, int64_t, const double *, int32_t,
-                                    int64_t, int32_t, float *, float *, hipStream_t);
+                                    int32_t, int32_t, float *, float *, hipStream_t);
 template void launch_sweep<double>(const DevSym &, const DevSub &, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t,
                                    int32_t, int64_t, int64_t, const double *, const double *, const int32_t *,
                                    const double *, const double *, double *, double *, double *, int, hipStream_t);
@@ -2334,11 +2414,9 @@ template void launch_schur<float>(const DevSub &, int32_t, int32_t, int32_t, int
                                   const int64_t *, const float *, const int32_t *, const float *, const float *,
                                   float *, hipStream_t);
 template hipError_t prepare_sweep<float>(int32_t, int32_t, int32_t, int32_t);
-template void launch_merge<double>(const DevMaps &, int64_t, int32_t, int32_t, const double *, const double *, int64_t,
-                                   double *, int64_t, const int64_t *, const int32_t *, int32_t, const int32_t *,
-                                   hipStream_t);
-template void launch_merge<float>(const DevMaps &, int64_t, int32_t, int32_t, const float *, const double *, int64_t,
-                                  double *, int64_t, const int64_t *, const int32_t *, int32_t, const int32_t *,
-                                  hipStream_t);
+template void launch_merge<double>(const DevMaps &, int64_t, int32_t, int32_t, int32_t, const double *, const double *,
+                                   double *, const int64_t *, const int32_t *, int32_t, const int32_t *, hipStream_t);
+template void launch_merge<float>(const DevMaps &, int64_t, int32_t, int32_t, int32_t, const float *, const double *,
+                                  double *, const int64_t *, const int32_t *, int32_t, const int32_t *, hipStream_t);
 
 }  // namespace vtm

@@ -111,8 +111,20 @@ void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_f
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 
+// The solver's FP64 n-vectors (right sides, iterates, residuals) are row-interleaved: the nrhs values
+// of vertex v at v * S .. v * S + nrhs, with the row stride S padded to a multiple of four beyond two
+// (whole 32-byte rows for the residual's loads), padding zero.  The residual takes res_group(S)
+// columns per pass.
+inline int32_t vec_stride(int32_t nrhs) { return nrhs <= 2 ? nrhs : (nrhs + 3) & ~3; }
+inline int32_t res_group(int32_t S) { return S <= 2 ? S : S % 8 == 0 ? 8 : 4; }
+
+// Column-major n x nrhs (leading dimension ld) to row-interleaved rows of stride S, and back.
+void launch_to_rows(const double *src, int64_t ld, int64_t n, int32_t nrhs, int32_t S, double *dst, hipStream_t st);
+void launch_from_rows(const double *src, int32_t S, int64_t n, int32_t nrhs, double *dst, int64_t ld, hipStream_t st);
+
+// bsplit[g][e][cc] = b[fvtx[e]][g R + cc] / |S(v)| (source split; b row-interleaved, stride S).
 template <typename T>
-void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int64_t ldb, int32_t R,
+void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int32_t S, int32_t R,
                   T *bsplit, hipStream_t st);
 
 // Restart of the inner solves of some systems (iterative refinement, one system at a time): for the
@@ -120,7 +132,7 @@ void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrh
 // their ports in o (the buffer the next sweep reads).
 template <typename T>
 void launch_restart(const DevSub &D, const DevMaps &M, int32_t nsub, int32_t nlist, int64_t nsplit, int64_t nports,
-                    const double *b, int32_t nrhs, int64_t ldb, int32_t R, T *bsplit, T *o, hipStream_t st);
+                    const double *b, int32_t nrhs, int32_t S, int32_t R, T *bsplit, T *o, hipStream_t st);
 
 // One VTM sweep over all subgraphs and right-hand-side groups (grid = subgraphs x RHS groups).
 template <typename T>
@@ -187,22 +199,23 @@ hipError_t launch_schur_persist(const DevSub &D, int32_t nsub, int32_t ngroups, 
                                 float *plain0, float *plain1, int32_t t0, int32_t nsw, int32_t cur0,
                                 int32_t spin_limit, int32_t *abort_flag, hipStream_t st);
 
-// xout[v + c*ldx] = (base ? base[v + c*ldbase] : 0) + mean over the children of v of xloc, by residual
-// chunks (chunk_row[nchunks + 1]: row ranges of at most 256 rows inside one system, chunk_sys: their
-// systems); the rows of a system with active[s] == 0 are left as they are (active may be null).
+// xout[v][c] = (base ? base[v][c] : 0) + mean over the children of v of xloc (row-interleaved, stride
+// S), by residual chunks (chunk_row[nchunks + 1]: row ranges of at most 256 rows inside one system,
+// chunk_sys: their systems); the rows of a system with active[s] == 0 are left as they are (active may
+// be null).
 template <typename T>
-void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t R, const T *xloc, const double *base,
-                  int64_t ldbase, double *xout, int64_t ldx, const int64_t *chunk_row, const int32_t *chunk_sys,
+void launch_merge(const DevMaps &M, int64_t nsplit, int32_t nrhs, int32_t S, int32_t R, const T *xloc,
+                  const double *base, double *xout, const int64_t *chunk_row, const int32_t *chunk_sys,
                   int32_t nchunks, const int32_t *active, hipStream_t st);
 
-// r = b - A x (optional store), per (rhs, system) relative residual into relres[c * nsys + s], and
+// r = b - A x (b, x, r row-interleaved, stride S; optional store of r), per (rhs, system) relative
+// residual into relres[c * nsys + s], and
 // relres[nsys * nrhs] = 1 if *flag is set (flag may be null), so that one copy brings both to the host.
 // Rows of the chunks of a system with active[s] == 0 (active may be null) are skipped; their partial
 // sums keep the values of the last pass over them.
-void launch_residual(const DevCsr &A, int64_t n, int32_t nrhs, const double *b, int64_t ldb, const double *x,
-                     int64_t ldx, double *r, int64_t ldr, const int64_t *chunk_row, const int32_t *chunk_sys,
-                     const int32_t *active,
-                     int32_t nchunks, const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag,
-                     double *relres, hipStream_t st);
+void launch_residual(const DevCsr &A, int64_t n, int32_t nrhs, int32_t S, const double *b, const double *x, double *r,
+                     const int64_t *chunk_row, const int32_t *chunk_sys, const int32_t *active, int32_t nchunks,
+                     const int32_t *sys_chunk_ptr, int32_t nsys, double *part, const int32_t *flag, double *relres,
+                     hipStream_t st);
 
 }  // namespace vtm
