@@ -59,7 +59,7 @@ enum {
 enum { VTM_FP64 = 0, VTM_FP32_IR = 1 };
 enum { VTM_PART_GRID = 0, VTM_PART_RCB = 1, VTM_PART_GRAPH = 2, VTM_PART_USER = 3 };
 enum { VTM_SPLIT_BRANCH = 0, VTM_SPLIT_EQUAL = 1 };
-enum { VTM_TOPO_FACE = 0, VTM_TOPO_COMPLETE = 1 };
+enum { VTM_TOPO_FACE = 0, VTM_TOPO_COMPLETE = 1, VTM_TOPO_TREE = 2 };
 enum { VTM_Z_DIAG = 0, VTM_Z_USER = 1, VTM_Z_LEARNED = 2, VTM_Z_MATCHED = 3 };
 
 typedef struct vtm_ctx *vtm_handle;
@@ -122,7 +122,9 @@ typedef struct {
  * Sources are split b_v / |S(v)|.  Multilevel splitting (Fig. 7): topology FACE
  * joins two children of v by a VTL iff their subgraphs share a vertex of
  * multiplicity 2 somewhere (all pairs if that leaves S(v) disconnected);
- * COMPLETE joins all pairs.
+ * COMPLETE joins all pairs; TREE keeps of the FACE pairs, taken in (k, k') order, those
+ * that join two children not yet connected -- the |S(v)| - 1 VTLs of splitting v again and
+ * again into two (no cycle of VTLs at one vertex, around which waves could circulate).
  */
 typedef struct {
     int32_t kind;
@@ -336,17 +338,18 @@ vtm_status vtm_set_waves(vtm_handle h, const double *a, int32_t nrhs);
 
 /*
  * Learned impedance (an addition to the paper's impedance matching, Section
- * 7.1): an MLP 12 -> 64 -> 64 -> 1 with ReLU predicts delta = ln(Z a_vv) for
- * every VTL from VTM_NUM_FEATURES scale-free features of its two ends; setup
+ * 7.1): an MLP 13 -> 64 -> 64 -> 1 with ReLU predicts delta = ln(Z a_vv) for
+ * every VTL from VTM_NUM_FEATURES scale-free features (twelve of its two ends,
+ * and the number of subgraphs of its system as the global scale); setup
  * with VTM_Z_LEARNED uses Z = exp(clamp(delta, ln 1/4, ln 256)) / a_vv.
  * Inference and training run on the matrix cores with BF16 operands and FP32
  * accumulation.  Parameter blob (float, VTM_ZMODEL_PARAMS):
- *   mu[12], sigma[12] (input standardisation), W1[64][12], b1[64],
+ *   mu[13], sigma[13] (input standardisation), W1[64][13], b1[64],
  *   W2[64][64], b2[64], w3[64], b3.
  */
-#define VTM_NUM_FEATURES 12
-#define VTM_ZMODEL_PARAMS 5081
-#define VTM_ZMODEL_TRAIN 5057
+#define VTM_NUM_FEATURES 13
+#define VTM_ZMODEL_PARAMS 5147
+#define VTM_ZMODEL_TRAIN 5121
 
 /* Features of every VTL (host array [nvtl][VTM_NUM_FEATURES]); works on host-only handles. */
 vtm_status vtm_zfeatures(vtm_handle h, float *out);
@@ -364,7 +367,7 @@ vtm_status vtm_get_z(vtm_handle h, double *z);
 typedef struct vtm_trainer_ctx *vtm_trainer;
 vtm_status vtm_trainer_create(int32_t device, const float *params, vtm_trainer *out);
 vtm_status vtm_trainer_destroy(vtm_trainer t);
-/* Copy n rows of features [n][12] and labels [n] (host) to the device. */
+/* Copy n rows of features [n][VTM_NUM_FEATURES] and labels [n] (host) to the device. */
 vtm_status vtm_trainer_set_data(vtm_trainer t, const float *feats, const float *labels, int64_t n);
 /* Gradient (host [VTM_ZMODEL_TRAIN], parameter layout without mu/sigma) and loss of rows [row0, row0+nrows). */
 vtm_status vtm_trainer_grad(vtm_trainer t, int64_t row0, int64_t nrows, float *grad, float *loss);

@@ -1,4 +1,4 @@
-"""FP64 NumPy reference of the learned-impedance MLP (12 -> 64 -> 64 -> 1, ReLU).
+"""FP64 NumPy reference of the learned-impedance MLP (13 -> 64 -> 64 -> 1, ReLU).
 
 TEST INFRASTRUCTURE ONLY.  Forward pass and the gradient of the mean squared
 error written out layer by layer.  With ``bf16=True`` the values that the GPU
@@ -6,14 +6,14 @@ kernels feed to the matrix cores are rounded to BF16 (round to nearest even)
 at the same points: standardised inputs, W1, W2, the post-ReLU first hidden
 layer, and the back-propagated dH2 and dH1.  Everything else is FP64.
 
-Parameter layout (float32 blob of 5081): mu[12], sigma[12], W1[64][12],
+Parameter layout (float32 blob of 5147): mu[13], sigma[13], W1[64][13],
 b1[64], W2[64][64], b2[64], w3[64], b3.
 """
 from __future__ import annotations
 
 import numpy as np
 
-NF, NH = 12, 64
+NF, NH = 13, 64
 NTRAIN = NH * NF + NH + NH * NH + NH + NH + 1
 NPARAMS = 2 * NF + NTRAIN
 

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "PARTITION", 3: "NOT_SPD", 4: "NOT_CON
 VTM_FP64, VTM_FP32_IR = 0, 1
 KIND = {"grid": 0, "rcb": 1, "graph": 2, "user": 3}
 SPLIT = {"branch": 0, "equal": 1}
-TOPO = {"face": 0, "complete": 1}
+TOPO = {"face": 0, "complete": 1, "tree": 2}
 VTM_Z_DIAG, VTM_Z_USER, VTM_Z_LEARNED, VTM_Z_MATCHED = 0, 1, 2, 3
 
 
@@ -70,7 +70,7 @@ EXPORTS = ("vtm_create", "vtm_destroy", "vtm_last_error", "vtm_evs_partition", "
            "vtm_trainer_destroy", "vtm_trainer_set_data", "vtm_trainer_grad", "vtm_trainer_epoch",
            "vtm_trainer_predict", "vtm_trainer_get_params", "vtm_autotune", "vtm_batch_solve",
            "vtm_setup_coupled", "vtm_input_impedance_noalloc")
-NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 12, 5081, 5057
+NUM_FEATURES, ZMODEL_PARAMS, ZMODEL_TRAIN = 13, 5147, 5121
 
 
 def lib():
@@ -206,7 +206,7 @@ class VTM:
             keep += [sp, si]
             s.s_ptr, s.s_idx, s.user_nsub = sp.ctypes.data, si.ctypes.data, int(spec["nsub"])
         s.split_rule = SPLIT[split]
-        s.topology = TOPO[topology]
+        s.topology = TOPO[spec.get("topology", topology)]  # a spec may name its own
         if nsys > 1:
             sptr = np.ascontiguousarray(sys_ptr, np.int64)
             keep.append(sptr)

@@ -2322,6 +2322,8 @@ vtm_status vtm_zfeatures(vtm_handle h, float *out) {
 
 vtm_status vtm_zmodel_load(vtm_handle h, const void *weights, size_t bytes) {
     if (!h || !weights) return fail(VTM_ERR_INVALID, "bad argument");
+    static_assert(vtm::kParams == VTM_ZMODEL_PARAMS && vtm::kTrain == VTM_ZMODEL_TRAIN &&
+                      vtm::kNumFeatures == VTM_NUM_FEATURES, "model sizes in vtm.h");
     if (bytes != sizeof(float) * (size_t)vtm::kParams)
         return fail(VTM_ERR_INVALID, "model blob has " + std::to_string(bytes) + " bytes, expected " +
                                          std::to_string(sizeof(float) * (size_t)vtm::kParams));

@@ -12,6 +12,8 @@
 //   9    ln |S(v)|                            children of v
 //   10   ln(mean |a_uw| / a_vv)               over the edges within one hop of v's neighbours
 //   11   ln(max |a_uw| / min |a_uw|)          same edges
+//   12   ln(#subgraphs of v's system)         global scale: the best impedances grow with the number
+//                                             of subgraphs information has to cross
 // Every feature is invariant under scaling A by a positive constant.
 #include <algorithm>
 #include <cmath>
@@ -23,8 +25,11 @@ namespace vtm {
 void compute_features(const Csr &A, const Partition &P, std::vector<float> &out) {
     const int64_t nvtl = (int64_t)P.vtl_v.size();
     out.assign(nvtl * kNumFeatures, 0.f);
-    std::vector<int64_t> nports(P.nsub);
-    for (int32_t k = 0; k < P.nsub; ++k) nports[k] = P.port_ptr[k + 1] - P.port_ptr[k];
+    std::vector<int64_t> nports(P.nsub), nsub_sys(std::max(P.nsys, 1), 0);
+    for (int32_t k = 0; k < P.nsub; ++k) {
+        nports[k] = P.port_ptr[k + 1] - P.port_ptr[k];
+        ++nsub_sys[P.sub_sys.empty() ? 0 : P.sub_sys[k]];
+    }
     auto nS = [&](int64_t v) { return P.s_ptr[v + 1] - P.s_ptr[v]; };
     auto end_stats = [&](int32_t k, int64_t v, double &dk, double &inner) {
         const int64_t *lv = P.loc_vtx.data() + P.loc_ptr[k];
@@ -80,6 +85,7 @@ void compute_features(const Csr &A, const Partition &P, std::vector<float> &out)
         o[9] = (float)std::log((double)nS(v));
         o[10] = wcnt ? (float)std::log(wsum / wcnt / avv) : 0.f;
         o[11] = wcnt ? (float)std::log(wmax / wmin) : 0.f;
+        o[12] = (float)std::log((double)nsub_sys[P.sub_sys.empty() ? 0 : P.sub_sys[ka]]);
     }
 }
 

@@ -1,10 +1,10 @@
-// Learned impedance model on gfx950: MLP 12 -> 64 -> 64 -> 1 (ReLU), BF16
+// Learned impedance model on gfx950: MLP 13 -> 64 -> 64 -> 1 (ReLU), BF16
 // operands on the matrix cores (v_mfma_f32_16x16x16_bf16), FP32 accumulation,
 // FP32 master weights and Adam.
 //
 // Parameter blob (FP32), kParams floats:
-//   mu[12], sigma[12]          input standardisation (not trained)
-//   W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3[1]
+//   mu[13], sigma[13]          input standardisation (not trained)
+//   W1[64][13], b1[64], W2[64][64], b2[64], w3[64], b3[1]
 // Gradients use the same layout without mu/sigma (kTrain floats).
 //
 // Rounding points (the CPU check follows them): standardised inputs, W1, W2,
@@ -23,7 +23,7 @@ namespace {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int F = kNumFeatures;  // 12 inputs, padded to 16 on the matrix cores
+constexpr int F = kNumFeatures;  // 13 inputs, padded to 16 on the matrix cores
 constexpr int H = 64;
 constexpr int kWaves = 4;
 

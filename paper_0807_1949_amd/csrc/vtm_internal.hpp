@@ -44,7 +44,7 @@ struct Partition {
 
 int build_partition(const Csr &A, const vtm_partition_spec &spec, Partition &P, std::string &err);
 
-constexpr int kNumFeatures = 12;
+constexpr int kNumFeatures = 13;
 // Per-VTL features of the learned impedance model, [nvtl][kNumFeatures].
 void compute_features(const Csr &A, const Partition &P, std::vector<float> &out);
 

@@ -51,7 +51,9 @@ def test_gradient_matches_reference(B, n):
     g, loss = tr.grad()
     go, lo = M.grad(P, X, t, bf=True)
     assert abs(loss - lo) <= 1e-4 * max(lo, 1e-6)
-    blocks = [(0, 768), (768, 832), (832, 4928), (4928, 4992), (4992, 5056), (5056, 5057)]
+    o1 = M.NH * M.NF
+    blocks = [(0, o1), (o1, o1 + 64), (o1 + 64, o1 + 4160), (o1 + 4160, o1 + 4224), (o1 + 4224, o1 + 4288),
+              (o1 + 4288, o1 + 4289)]
     for a, b in blocks:
         ref = go[a:b]
         assert np.linalg.norm(g[a:b] - ref) <= 2e-3 * max(np.linalg.norm(ref), 1e-6), (a, b)

@@ -34,5 +34,21 @@ def test_features_are_scale_free():
     h2 = B.VTM(device=-1)
     h2.evs_partition(A2, cfg["spec"])
     f2 = h2.zfeatures()
-    assert f1.shape == (h1.info["nvtl"], 12) and np.isfinite(f1).all()
+    assert f1.shape == (h1.info["nvtl"], B.NUM_FEATURES) and np.isfinite(f1).all()
     assert np.allclose(f1, f2, atol=1e-5)
+
+
+def test_global_scale_feature_counts_the_systems_subgraphs():
+    """Feature 12 is ln of the number of subgraphs of the VTL's own system (batched systems with
+    different part counts), counted here from the partition's vertex lists and the system ranges."""
+    cfg = gen.make_config("c5", small=True)
+    h = B.VTM(device=-1)
+    info = h.evs_partition(cfg["A"], cfg["spec"], nsys=cfg["nsys"], sys_ptr=cfg["sys_ptr"])
+    p = h.get_partition()
+    f = h.zfeatures()
+    sys_of_sub = np.searchsorted(cfg["sys_ptr"], p["loc_vtx"][p["loc_ptr"][:-1]], side="right") - 1
+    per_sys = np.bincount(sys_of_sub, minlength=cfg["nsys"])
+    assert len(np.unique(per_sys)) > 1  # the systems differ in size
+    expect = np.log(per_sys[sys_of_sub[p["vtl_k"]]])
+    assert np.allclose(f[:, 12], expect, atol=1e-6)
+    assert np.array_equal(sys_of_sub[p["vtl_k"]], sys_of_sub[p["vtl_k2"]])
