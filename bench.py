@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
-    "c5": "64 random geometric graph Laplacians + 1e-2 I, n ~ U[20k, 200k] (7,362,043 unknowns), graph EVS into "
+    "c5": "64 random geometric graph Laplacians + 1e-2 I, n ~ U[20k, 200k] (7,362,043 unknowns), graph EVS (tree VTLs) into "
           "14,380 subgraphs, 4 RHS per system",
     "c3": "3D 7-point Poisson 128^3 (2,097,152 unknowns), seeded RCB into 4096 subgraphs, 8 RHS",
     "c2": "2D random-conductance Laplacian lognormal(0,1) + 1e-3 I on 1024^2, 1024 subgraphs of 33x33, 1 RHS",

@@ -74,7 +74,8 @@ C4_EVAL_SEEDS = tuple(range(4200, 4210))
 
 
 def c5(small: bool = False, nsys: int | None = None):
-    """Batch of random geometric graph Laplacians + 1e-2 I, n ~ U{20k..200k}, 4 RHS each."""
+    """Batch of random geometric graph Laplacians + 1e-2 I, n ~ U{20k..200k}, 4 RHS each; graph EVS
+    with tree VTLs."""
     if nsys is None:
         nsys = 4 if small else 64
     lo, hi = (2000, 8000) if small else (20000, 200000)
@@ -86,7 +87,8 @@ def c5(small: bool = False, nsys: int | None = None):
     for s in syss:
         blocks.append((start, s.n, max(1, (s.n + 256) // 512)))
         start += s.n
-    spec = dict(kind="graph", coords=coords, blocks=blocks)
+    # graph partitions split vertices three ways around triangles of subgraphs: tree VTLs
+    spec = dict(kind="graph", coords=coords, blocks=blocks, topology="tree")
     b = np.concatenate([S.random_rhs(s.n, 4, 5000 + i) for i, s in enumerate(syss)], axis=1)
     sys_ptr = np.array([0] + list(np.cumsum(sizes)), dtype=np.int64)
     return dict(A=A, spec=spec, b=b, tol=1e-8, nsys=nsys, sys_ptr=sys_ptr,

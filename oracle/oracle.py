@@ -17,7 +17,7 @@ _lib = None
 
 KIND = {"grid": 0, "rcb": 1, "graph": 2, "user": 3}
 SPLIT = {"branch": 0, "equal": 1}
-TOPO = {"face": 0, "complete": 1}
+TOPO = {"face": 0, "complete": 1, "tree": 2}
 ERR = {0: "ok", -1: "invalid", -2: "partition", -3: "not_spd", -4: "oom"}
 
 
@@ -103,7 +103,7 @@ class Partition:
         h = C.c_void_p()
         rc = L.or_partition(A.n, _p(rowptr), _p(col), _p(val), KIND[kind], _p(dims), _p(parts), levels, seed, mn, mx,
                             _p(coords), dim, len(blocks), _p(bstart), _p(bcount), _p(bparts), _p(usp), _p(usi), unsub,
-                            SPLIT[split], TOPO[topology], C.byref(h))
+                            SPLIT[split], TOPO[spec.get("topology", topology)], C.byref(h))
         if rc != 0:
             raise OracleError(rc)
         self._h = h

@@ -48,7 +48,7 @@
 enum { OR_OK = 0, OR_ERR_INVALID = -1, OR_ERR_PARTITION = -2, OR_ERR_NOT_SPD = -3, OR_ERR_OOM = -4 };
 enum { OR_GRID = 0, OR_RCB = 1, OR_GRAPH = 2, OR_USER = 3 };
 enum { OR_SPLIT_BRANCH = 0, OR_SPLIT_EQUAL = 1 };
-enum { OR_TOPO_FACE = 0, OR_TOPO_COMPLETE = 1 };
+enum { OR_TOPO_FACE = 0, OR_TOPO_COMPLETE = 1, OR_TOPO_TREE = 2 };
 
 typedef struct {
     /* input copy */
@@ -508,7 +508,7 @@ int or_partition(int64_t n, const int64_t *rowptr, const int32_t *col, const dou
         int npair = m * (m - 1) / 2;
         char *use = calloc(npair, 1);
         int nuse = 0;
-        if (topology == OR_TOPO_FACE) {
+        if (topology == OR_TOPO_FACE || topology == OR_TOPO_TREE) {
             int q = 0;
             for (int a = 0; a < m; a++)
                 for (int b = a + 1; b < m; b++, q++) {
@@ -539,6 +539,22 @@ int or_partition(int64_t n, const int64_t *rowptr, const int32_t *col, const dou
         } else {
             memset(use, 1, npair);
             nuse = npair;
+        }
+        if (topology == OR_TOPO_TREE) {
+            /* repeated binary splitting: each further split of a child adds one VTL, so the VTLs of v
+               form a tree.  Keep the FACE pairs, taken in (a, b) order, that join two children not yet
+               connected (a spanning tree of the FACE pairs, which connect S(v)). */
+            int *lab = malloc(sizeof(int) * m);
+            for (int a = 0; a < m; a++) lab[a] = a;
+            int q2 = 0;
+            for (int a = 0; a < m; a++)
+                for (int b = a + 1; b < m; b++, q2++) {
+                    if (!use[q2]) continue;
+                    if (lab[a] == lab[b]) { use[q2] = 0; nuse--; continue; }
+                    const int gone = lab[b], into = lab[a];
+                    for (int c = 0; c < m; c++) if (lab[c] == gone) lab[c] = into;
+                }
+            free(lab);
         }
         int q = 0;
         for (int a = 0; a < m; a++)

@@ -368,6 +368,21 @@ int build_partition(const Csr &A, const vtm_partition_spec &sp, Partition &P, st
             for (int a = 1; a < m; ++a) connected &= find(a) == find(0);
             if (!connected) pairs = all;
         }
+        if (sp.topology == VTM_TOPO_TREE) {
+            // repeated binary splits: one VTL per split, a spanning tree of the pairs above (greedy in
+            // (k, k') order), so that no cycle of VTLs meets at v
+            std::vector<int> root(m);
+            std::iota(root.begin(), root.end(), 0);
+            auto top = [&](int x) { while (root[x] != x) x = root[x] = root[root[x]]; return x; };
+            std::vector<std::pair<int, int>> tree;
+            for (auto &pr : pairs) {
+                const int ra = top(pr.first), rb = top(pr.second);
+                if (ra == rb) continue;
+                root[rb] = ra;
+                tree.push_back(pr);
+            }
+            pairs.swap(tree);
+        }
         for (auto &pr : pairs) {
             P.vtl_v.push_back(v);
             P.vtl_k.push_back(sv[pr.first]);

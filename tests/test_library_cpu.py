@@ -53,7 +53,7 @@ def test_partition_bit_exact_small(name):
     _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"]))
 
 
-@pytest.mark.parametrize("split,topo", [("equal", "face"), ("branch", "complete")])
+@pytest.mark.parametrize("split,topo", [("equal", "face"), ("branch", "complete"), ("branch", "tree")])
 def test_partition_bit_exact_rules(split, topo):
     cfg = gen.make_config("c3", small=True)
     h = _host_handle()

@@ -491,3 +491,38 @@ def test_coupled_converges_and_is_nonexpansive(beta):
         nrm = float(e @ Yp @ e)
         assert nrm <= prev * (1 + 1e-9) + 1e-28, (k, nrm, prev)
         prev = nrm
+
+
+def test_tree_topology_is_a_spanning_tree_of_the_face_pairs():
+    """TREE (repeated binary splitting): at every split vertex the VTLs are |S(v)| - 1 pairs of the FACE
+    topology that connect all children of v, so no cycle of VTLs meets at one vertex.  Checked on a 3D
+    RCB partition, whose corner vertices have up to eight children and FACE cycles."""
+    import gen
+    from oracle import oracle as O
+    cfg = gen.make_config("c3", small=True)
+    face = O.Partition(cfg["A"], cfg["spec"], topology="face")
+    tree = O.Partition(cfg["A"], cfg["spec"], topology="tree")
+    assert np.array_equal(face.s_ptr, tree.s_ptr) and np.array_equal(face.s_idx, tree.s_idx)
+    fset = set(zip(face.vtl_v.tolist(), face.vtl_k.tolist(), face.vtl_k2.tolist()))
+    tv = tree.vtl_v
+    mult = np.diff(tree.s_ptr)
+    assert np.array_equal(np.bincount(tv, minlength=tree.n), np.maximum(mult - 1, 0))
+    cycles = 0
+    for v in np.nonzero(mult >= 3)[0]:
+        sel = tv == v
+        kids = tree.s_idx[tree.s_ptr[v]:tree.s_ptr[v + 1]].tolist()
+        par = {k: k for k in kids}
+
+        def root(k):
+            while par[k] != k:
+                k = par[k]
+            return k
+        for k1, k2 in zip(tree.vtl_k[sel].tolist(), tree.vtl_k2[sel].tolist()):
+            assert (int(v), k1, k2) in fset
+            assert root(k1) != root(k2)  # adding it closes no cycle
+            par[root(k1)] = root(k2)
+        assert len({root(k) for k in kids}) == 1
+        cycles += int((face.vtl_v == v).sum()) - (len(kids) - 1)
+    assert cycles > 0  # FACE had cycles here that the tree drops
+    # ports and twins follow the VTLs: two ports per VTL, each the other's twin
+    assert len(tree.port_v) == 2 * tree.nvtl and np.array_equal(tree.port_twin[tree.port_twin], np.arange(2 * tree.nvtl))
