@@ -2076,11 +2076,15 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
                    const double *invz, double *vals, float *vals32, double *ws, int32_t *status,
                    const DevGreen &Gp, const int64_t *goff, double *G, hipStream_t st) {
-    // 40 KiB of fronts per workgroup keeps four workgroups on a CU; larger fronts get the room they
-    // need up to the CU's LDS, beyond that they stay in the workspace
+    // 40 KiB of fronts per workgroup keeps four workgroups on a CU.  Larger fronts get the room they
+    // need, up to the CU's LDS, only when every workgroup is resident even at one per CU; otherwise
+    // they stay in the workspace and the CUs keep four subgraphs each in flight
     int lds_doubles = kFactorLds;
     const int need = max_front * max_front + pivot_len(max_front, true);
-    if (need > lds_doubles && need <= (int)((kMaxLds - 1024) / sizeof(double))) lds_doubles = need;
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    if (need > lds_doubles && need <= (int)((kMaxLds - 1024) / sizeof(double)) && nsub <= ncu) lds_doubles = need;
     const size_t shm = sizeof(double) * (size_t)lds_doubles;
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, vals32, ws, lds_doubles,
