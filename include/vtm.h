@@ -92,7 +92,8 @@ typedef struct {
     int32_t sweep_waves;   /* port-reduced sweeps in per-sweep launches: waves per subgraph, 1 or 2 (two
                               waves take alternate pairs of block columns of G_k, each with its own
                               copy of the products); 0 = two when one wave's LDS would leave fewer than
-                              two waves per SIMD */
+                              two waves per SIMD, or when the subgraphs still sweeping (done mask) are
+                              fewer than two per compute unit */
     int32_t spin_limit;    /* persistent sweeps: polls of one incoming wave word before the launch gives up
                               (every other wait then gives up too, the launch ends, and the solve or
                               vtm_run_sweeps returns VTM_ERR_HIP; the handle stays usable); 0 = 2^20.

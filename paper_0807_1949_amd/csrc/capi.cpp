@@ -129,6 +129,9 @@ struct vtm_ctx {
     bool rl_on = false;            // launches cover d_rlist only (restart of some systems)
     int32_t *active_host = nullptr;  // pinned per-system flags of the done mask
     size_t active_cap = 0;
+    int32_t *rowflag_host = nullptr;  // pinned per-system row moves of a test (see launch_sys_rows)
+    size_t rowflag_cap = 0;
+    DevBuf d_rowflag;
     uint64_t setup_id = 0;         // unique id of the last vtm_setup (batch solves rebuild when one changes)
     vtm_ctx *batch = nullptr;      // concatenation of handles for vtm_batch_solve (owned)
     std::vector<uint64_t> batch_key;
@@ -176,13 +179,14 @@ struct vtm_ctx {
     bool abort_pending = false;
     vtm_stats stats{};
     bool trace = false;  // VTM_TRACE set: one line per convergence test on stderr
+    int32_t ncu = 0;     // compute units of the device
 
     vtm_ctx() {
         DevBuf *list[] = {&d_cls, &d_lev, &d_colsn, &d_snc0, &d_snnc, &d_snm, &d_snval, &d_snridx, &d_snuoff, &d_ridx,
                           &d_rel, &d_chptr, &d_chidx, &d_segptr, &d_segoff, &d_segc0, &d_segnc, &d_scptr,
                           &d_scdst, &d_subcls, &d_subval, &d_subx, &d_subaval, &d_subws, &d_pgptr, &d_pgpos,
                           &d_pgbeg, &d_pgcnt, &d_portptr, &d_fvtx, &d_fmul, &d_cpptr, &d_cpidx, &d_rp, &d_ci, &d_v, &d_aval,
-                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_sublist, &d_rlist, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
+                          &d_twin, &d_portvtl, &d_chunkrow, &d_chunksys, &d_syschunk, &d_subsys, &d_active, &d_sublist, &d_rlist, &d_rowflag, &d_cplptr, &d_cpltw, &d_cply64, &d_cply32, &d_z, &d_invz64, &d_invz32,
                           &d_vals64, &d_vals32, &d_status, &d_segu, &d_usn, &d_levu, &d_colrec, &d_urec, &d_goff, &d_G64, &d_G32, &d_cport, &d_gorder, &d_portpg, &d_gsn, &d_gbase, &d_gwso, &d_gidoff, &d_gperm, &d_gws, &d_levmaxf, &d_tw, &d_abort, &d_zparams, &d_feat, &d_avvl, &d_pred, &d_ws, &d_gws32, &d_yb, &d_o[0], &d_o[1], &d_bsplit, &d_xloc, &d_x, &d_xt, &d_r,
                           &d_rt, &d_b, &d_part, &d_relres};
         for (DevBuf *b : list) all.push_back(b);
@@ -196,6 +200,7 @@ struct vtm_ctx {
         delete batch;
         if (relres_host) (void)hipHostFree(relres_host);
         if (active_host) (void)hipHostFree(active_host);
+        if (rowflag_host) (void)hipHostFree(rowflag_host);
         if (ev_test) (void)hipEventDestroy(ev_test);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -815,7 +820,13 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R, nt = sweep_threads(h);
     HIP_TRY(vtm::prepare_sweep<T>(h->max_nk, h->max_nu, sweep_variant(h), R));
     const bool schur = use_schur(h);
-    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, h->max_np, R, h->opt.sweep_waves));
+    // waves per subgraph of the streaming sweep: the option, else two when the subgraphs still
+    // sweeping would leave most CUs idle (the tail of a batch), so that each G_k streams on two waves
+    int32_t W = h->opt.sweep_waves;
+    if (schur && W == 0 && h->ncu > 0 && (int64_t)nsub_launch(h) * ng < 2 * (int64_t)h->ncu &&
+        vtm::schur_lds_bytes(h->tsize(), h->max_p, h->max_np, R, 2) <= vtm::kMaxLds)
+        W = 2;
+    if (schur) HIP_TRY(vtm::prepare_schur<T>(h->max_p, h->max_np, R, W));
     if constexpr (std::is_same<T, float>::value) {
         if (schur && persistent_ok(h, R, ng)) {
             const int64_t nw = (int64_t)ng * h->nports * R;
@@ -861,7 +872,7 @@ vtm_status run_sweeps_dev(vtm_ctx *h, int64_t count) {
 per_sweep:
     auto launch = [&](int cur, bool last) {
         if (schur)
-            vtm::launch_schur<T>(D, nsub_launch(h), ng, R, h->opt.sweep_waves, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
+            vtm::launch_schur<T>(D, nsub_launch(h), ng, R, W, h->max_p, h->max_np, h->npg, h->nports, green_of<T>(h),
                                  h->d_goff.as<int64_t>(), h->d_cport.as<T>(), h->d_twin.as<int32_t>(), invz_of<T>(h),
                                  h->d_o[cur].as<T>(), h->d_o[1 - cur].as<T>(), h->stream);
         else
@@ -1160,10 +1171,42 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
     // x = 0, r = b for the refinement; the FP64 path solves b directly
     double *xcur = h->d_x.as<double>(), *xtr = h->d_xt.as<double>();
     double *rcur = h->d_r.as<double>(), *rtr = h->d_rt.as<double>();
-    auto copy_rows = [&](double *dst, const double *src, int32_t s) {  // the rows of system s
-        const int64_t lo = h->P.sys_ptr[s], len = h->P.sys_ptr[s + 1] - lo;
-        return hipMemcpyAsync(dst + lo * S, src + lo * S, sizeof(double) * len * S, hipMemcpyDeviceToDevice,
-                              h->stream);
+    // Row moves of a test, per system (1: x from xtr to xcur; 2: also r from rtr to rcur; 3: x from xcur
+    // to xtr), done together by one kernel over the residual chunks (one copy per buffer for a single
+    // system).  The pinned flag array is rewritten only after the previous upload has completed.
+    std::vector<int32_t> rowflag(nsys, 0);
+    bool rowflag_pending = false;  // an upload of the flags may still be in flight
+    auto flush_rows = [&]() -> vtm_status {
+        bool any = false;
+        for (const int32_t f : rowflag) any = any || f != 0;
+        if (!any) return VTM_OK;
+        if (nsys == 1) {
+            const size_t bytes = sizeof(double) * (size_t)n * S;
+            const int32_t f = rowflag[0];
+            HIP_TRY(hipMemcpyAsync(f == 3 ? xtr : xcur, f == 3 ? xcur : xtr, bytes, hipMemcpyDeviceToDevice, h->stream));
+            if (f == 2) HIP_TRY(hipMemcpyAsync(rcur, rtr, bytes, hipMemcpyDeviceToDevice, h->stream));
+            rowflag[0] = 0;
+            return VTM_OK;
+        }
+        if (h->rowflag_cap < (size_t)nsys) {
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            if (h->rowflag_host) HIP_TRY(hipHostFree(h->rowflag_host));
+            h->rowflag_host = nullptr;
+            h->rowflag_cap = 0;
+            HIP_TRY(hipHostMalloc((void **)&h->rowflag_host, sizeof(int32_t) * nsys, hipHostMallocDefault));
+            h->rowflag_cap = nsys;
+            rowflag_pending = false;
+        }
+        if (rowflag_pending) HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(ensure(h->d_rowflag, sizeof(int32_t) * nsys));
+        std::copy(rowflag.begin(), rowflag.end(), h->rowflag_host);
+        HIP_TRY(hipMemcpyAsync(h->d_rowflag.p, h->rowflag_host, sizeof(int32_t) * nsys, hipMemcpyHostToDevice,
+                               h->stream));
+        rowflag_pending = true;
+        vtm::launch_sys_rows(chunkrow, chunksys, h->nchunks, h->d_rowflag.as<int32_t>(), S, xcur, xtr, rcur, rtr,
+                             h->stream);
+        std::fill(rowflag.begin(), rowflag.end(), 0);
+        return VTM_OK;
     };
     HIP_TRY(hipMemsetAsync(xcur, 0, sizeof(double) * n * S, h->stream));
     vtm::launch_split<T>(M, h->nsplit, h->d_b.as<double>(), nrhs, S, R, h->d_bsplit.as<T>(), h->stream);
@@ -1203,6 +1246,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
         vtm::launch_merge<T>(M, h->nsplit, nrhs, S, R, h->d_xloc.as<T>(), refine ? xcur : nullptr, xtr, chunkrow,
                              chunksys, h->nchunks, h->mask_on ? h->d_active.as<int32_t>() : nullptr, h->stream);
         if ((rc = residual(h, nrhs, xtr, refine ? rtr : nullptr, rel))) return rc;
+        rowflag_pending = false;  // the residual's copy to the host has completed: so have earlier uploads
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, s0, s1));
         sweep_ms += ms;
@@ -1240,7 +1284,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
             if (ok) {  // converged: the candidate is the result, and both x buffers hold it from now on
                 state[s] = 1;
                 --nactive;
-                HIP_TRY(copy_rows(xcur, xtr, s));
+                rowflag[s] = 1;
                 for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + s] = rel[(size_t)c * nsys + s];
                 changed = true;
                 continue;
@@ -1264,7 +1308,7 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
             } else if (stalled) {  // no further progress: keep the accepted x (the better one) in both buffers
                 state[s] = 2;
                 --nactive;
-                HIP_TRY(copy_rows(xtr, xcur, s));
+                rowflag[s] = 3;
                 changed = true;
             }
         }
@@ -1274,13 +1318,18 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
                                    h->stream));
             if ((rc = mask_relist(h))) return rc;
         }
+        // the row moves go before any swap of the buffers; a partial restart moves its systems' x and r
+        const bool swap_restart = refine && !restart.empty() && (int32_t)restart.size() == nactive;
+        if (refine && !swap_restart)
+            for (const int32_t s : restart) rowflag[s] = 2;
+        if ((rc = flush_rows())) return rc;
         if (!refine) {
             std::swap(xcur, xtr);
             for (int32_t s = 0; s < nsys; ++s)
                 if (!state[s])
                     for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + s] = rel[(size_t)c * nsys + s];
         } else if (!restart.empty()) {
-            if ((int32_t)restart.size() == nactive) {
+            if (swap_restart) {
                 // every system still sweeping restarts (the stopped ones hold the same rows in both buffers)
                 std::swap(xcur, xtr);
                 std::swap(rcur, rtr);
@@ -1288,10 +1337,6 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
                 if ((rc = zero_waves<T>(h))) return rc;
                 if ((rc = port_constants<T>(h))) return rc;
             } else {
-                for (const int32_t s : restart) {
-                    HIP_TRY(copy_rows(xcur, xtr, s));
-                    HIP_TRY(copy_rows(rcur, rtr, s));
-                }
                 if ((rc = restart_systems<T>(h, restart, rcur, nrhs))) return rc;
             }
         }
@@ -1339,10 +1384,11 @@ vtm_status solve_core(vtm_ctx *h, int32_t nrhs, double tol, std::vector<int32_t>
             double cw = 0.0;
             for (int32_t c = 0; c < nrhs; ++c) cw = std::max(cw, cand_rel[(size_t)c * nsys + s]);
             if (cw < sc[s].outer) {
-                HIP_TRY(copy_rows(xcur, xtr, s));
+                rowflag[s] = 1;
                 for (int32_t c = 0; c < nrhs; ++c) acc_rel[(size_t)c * nsys + s] = cand_rel[(size_t)c * nsys + s];
             }
         }
+    if ((rc = flush_rows())) return rc;
     if (diverged) acc_rel = cand_rel;
     bool done = !diverged;
     for (int32_t s = 0; s < nsys; ++s) done = done && state[s] == 1;
@@ -1986,6 +2032,7 @@ vtm_status vtm_create(const vtm_options *options, vtm_handle *out) {
         delete h;
         return fail(VTM_ERR_HIP, hipGetErrorString(e));
     }
+    if (hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->opt.device) != hipSuccess) h->ncu = 0;
     {  // the allocation-free entry points' scratch: its address on this device, looked up once
         double *scr = nullptr;
         if ((e = vtm::noalloc_scratch(h->opt.device, &scr)) != hipSuccess) {

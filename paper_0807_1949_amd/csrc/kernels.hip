@@ -2027,6 +2027,21 @@ __global__ __launch_bounds__(kThreads) void k_residual(DevCsr A, int32_t nrhs, i
     }
 }
 
+// Rows of flagged systems between the two iterate (and residual) buffers, one workgroup per chunk.
+__global__ void k_sys_rows(const int64_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_sys,
+                           const int32_t *__restrict__ flag, int32_t S, double *__restrict__ xa,
+                           double *__restrict__ xb, double *__restrict__ ra, const double *__restrict__ rb) {
+    const int ch = blockIdx.x;
+    const int f = flag[chunk_sys[ch]];
+    if (f == 0) return;
+    const int64_t lo = chunk_row[ch] * S, hi = chunk_row[ch + 1] * S;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        if (f == 3) xb[i] = xa[i];
+        else xa[i] = xb[i];
+        if (f == 2) ra[i] = rb[i];
+    }
+}
+
 // Column-major n x nrhs (leading dimension ld) to row-interleaved rows of stride S (padding zero), and back.
 __global__ void k_to_rows(const double *__restrict__ src, int64_t ld, int64_t n, int32_t nrhs, int32_t S,
                           double *__restrict__ dst) {
@@ -2102,6 +2117,12 @@ template <typename T>
 void launch_split(const DevMaps &M, int64_t nsplit, const double *b, int32_t nrhs, int32_t S, int32_t R, T *bsplit,
                   hipStream_t st) {
     hipLaunchKernelGGL(k_split<T>, dim3(blocks_for(nsplit, 256)), dim3(256), 0, st, M, nsplit, b, nrhs, S, R, bsplit);
+}
+
+void launch_sys_rows(const int64_t *chunk_row, const int32_t *chunk_sys, int32_t nchunks, const int32_t *flag,
+                     int32_t S, double *xa, double *xb, double *ra, const double *rb, hipStream_t st) {
+    if (nchunks > 0)
+        hipLaunchKernelGGL(k_sys_rows, dim3(nchunks), dim3(256), 0, st, chunk_row, chunk_sys, flag, S, xa, xb, ra, rb);
 }
 
 void launch_to_rows(const double *src, int64_t ld, int64_t n, int32_t nrhs, int32_t S, double *dst, hipStream_t st) {

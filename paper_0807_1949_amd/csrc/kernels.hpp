@@ -118,6 +118,11 @@ void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 inline int32_t vec_stride(int32_t nrhs) { return nrhs <= 2 ? nrhs : (nrhs + 3) & ~3; }
 inline int32_t res_group(int32_t S) { return S <= 2 ? S : S % 8 == 0 ? 8 : 4; }
 
+// Rows of the systems flagged in flag[] (per system) moved between the solve's two iterate buffers,
+// by residual chunks: 1 copies x from xb to xa, 2 also r from rb to ra, 3 copies x from xa to xb.
+void launch_sys_rows(const int64_t *chunk_row, const int32_t *chunk_sys, int32_t nchunks, const int32_t *flag,
+                     int32_t S, double *xa, double *xb, double *ra, const double *rb, hipStream_t st);
+
 // Column-major n x nrhs (leading dimension ld) to row-interleaved rows of stride S, and back.
 void launch_to_rows(const double *src, int64_t ld, int64_t n, int32_t nrhs, int32_t S, double *dst, hipStream_t st);
 void launch_from_rows(const double *src, int32_t S, int64_t n, int32_t nrhs, double *dst, int64_t ld, hipStream_t st);
