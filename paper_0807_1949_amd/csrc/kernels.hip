@@ -1374,18 +1374,30 @@ __device__ inline void lds_put4(double *p, const double (&v)[4]) {
 }
 
 template <typename T, int R, int W>
-__global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t nports, const T *__restrict__ G,
-                                              const int64_t *__restrict__ goff, const T *__restrict__ cport,
-                                              const int32_t *__restrict__ twin, const T *__restrict__ invz,
-                                              const T *__restrict__ o_prev, T *__restrict__ o_next) {
+__global__ __launch_bounds__(W == 1 ? 256 : 64 * W, W == 1 && sizeof(T) == 4 && R <= 4 ? 6 : 1) void k_schur(DevSub D, int32_t nslots, int32_t team_bytes, int32_t npg,
+                                                              int64_t nports, const T *__restrict__ G,
+                                                              const int64_t *__restrict__ goff, const T *__restrict__ cport,
+                                                              const int32_t *__restrict__ twin, const T *__restrict__ invz,
+                                                              const T *__restrict__ o_prev, T *__restrict__ o_next) {
     static_assert(R == 1 || R == 2 || R == 4 || R == 8, "right-hand sides per wave");
-    extern __shared__ char smraw[];
+    extern __shared__ char smem_all[];
     constexpr int PF = 4;                         // blocks in flight (4 KB FP32, 8 KB FP64)
     constexpr int U = 4;                          // ports per lane whose loads are issued together
     constexpr int NV = 4 * R;                     // column partial sums per lane, index c * 4 + kk
     typedef typename Mma<T>::acc Acc;
-    const int k = D.sub_list ? D.sub_list[blockIdx.x] : D.gorder[blockIdx.x], g = blockIdx.y, tid = threadIdx.x, nt = 64 * W;
+    // A team of W waves sweeps one subgraph.  With one wave per team, a workgroup holds several
+    // independent teams (blockDim.x / 64 of them, each with its own LDS), so that a CU is not limited
+    // by the number of workgroups it can hold; their syncs are wave-level.
+    const int nt = 64 * W, team = W == 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
+    const int slot = blockIdx.x * ((int)blockDim.x / nt) + team;
+    if (slot >= nslots) return;
+    const int k = D.sub_list ? D.sub_list[slot] : D.gorder[slot], g = blockIdx.y, tid = (int)threadIdx.x - team * nt;
     if (sub_inactive(D, k)) return;
+    char *smraw = smem_all + (size_t)team * team_bytes;
+    auto team_sync = [] {
+        if constexpr (W == 1) wave_sync();
+        else __syncthreads();
+    };
     const int lane = tid & 63, m = lane & 15, q = lane >> 4;
     const int wv = W == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);
     const int pg0 = D.pg_ptr[k], p = D.pg_ptr[k + 1] - pg0;
@@ -1396,6 +1408,13 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
     T *y = xz + (size_t)pp * R;            // per wave: G Z^{-1} a from its blocks [W][R][ps], rows in yrow order
     T *scr = y;                            // before y: Z^{-1} a per port [np_k][R]
     T *ydummy = y + (size_t)W * ps * R;    // after y (over the scratch): 4 values per lane for the unused lanes
+    // With up to 4 RHS the twin and the vertex of each port wait in LDS (after the scratch) for the
+    // write-back, which loads the incoming wave again, instead of keeping them in registers through
+    // the stream: fewer registers, more waves per SIMD.
+    constexpr bool kPortsLds = R <= 4;
+    const int np_here = D.port_ptr[k + 1] - D.port_ptr[k];
+    int *twl = reinterpret_cast<int *>(y + (W * (ps * R + 256) > np_here * R ? W * (ps * R + 256) : np_here * R));
+    int *vin = twl + np_here;  // twl[np_k], vin[np_k]
     // With 8 RHS, the two halves of a row of xz swap places in every other group of 4 rows, so that
     // the 16-byte reads of 8 consecutive rows fall in distinct LDS banks.
     auto xzi = [](int r, int c) { return r * R + (R == 8 ? (c ^ (((r >> 2) & 1) << 2)) : c); };
@@ -1463,13 +1482,18 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
 #pragma unroll
             for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
     };
-    auto port_store = [&](int t0, const T (&iz)[U], const T (&a)[U][R]) {
+    auto port_store = [&](int t0, const T (&iz)[U], const T (&a)[U][R], const int (&tw)[U], const int (&vv)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + nt * u + tid;
-            if (t < np_k)
+            if (t < np_k) {
 #pragma unroll
                 for (int c = 0; c < R; ++c) scr[t * R + c] = a[u][c] * iz[u];
+                if constexpr (kPortsLds) {
+                    twl[t] = tw[u];
+                    vin[t] = vv[u];
+                }
+            }
         }
     };
     if (np_k > 0) port_loads(0, tw0, v0r, iz0, a0);
@@ -1483,14 +1507,14 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
         pre[f].load(Gl + next_load());
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (np_k > 0) port_store(0, iz0, a0);
+    if (np_k > 0) port_store(0, iz0, a0, tw0, v0r);
     for (int t0 = nt * U; t0 < np_k; t0 += nt * U) {
         int tw[U], vv[U];
         T iz[U], a[U][R];
         port_loads(t0, tw, vv, iz, a);
-        port_store(t0, iz, a);
+        port_store(t0, iz, a, tw, vv);
     }
-    __syncthreads();
+    team_sync();
     for (int v0 = 0; v0 < pp; v0 += nt * U) {
         int b0[U], cnt[U];
 #pragma unroll
@@ -1516,9 +1540,9 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
                 for (int c = 0; c < R; ++c) xz[xzi(v, c)] = s_[c];
         }
     }
-    __syncthreads();
+    team_sync();
     for (int i = tid; i < W * ps * R; i += nt) y[i] = 0;
-    __syncthreads();
+    team_sync();
     // B operand of y_I += B x_J: lane (m, q) gives x_J[4 q + kk][m] for m < R
     T xb[4], xbn[4];
     auto load_xb = [&](T (&d)[4], int J) {
@@ -1627,13 +1651,24 @@ __global__ __launch_bounds__(64 * W) void k_schur(DevSub D, int32_t npg, int64_t
             pre[f].load(Gl + next_load());
         }
     }
-    __syncthreads();
+    team_sync();
     // u = c + y at each port vertex; o_p = 2 u - a_p (loads of U ports per lane issued together; the
     // first U ports per lane from the registers kept by the gather)
     for (int t0 = 0; t0 < np_k; t0 += nt * U) {
         int tw[U], v[U];
         T a[U][R], cu[U][R];
-        if (t0 == 0) {
+        if constexpr (kPortsLds) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + nt * u + tid, tt = t < np_k ? t : 0;
+                tw[u] = twl[tt];
+                v[u] = vin[tt];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
+        } else if (t0 == 0) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 tw[u] = tw0[u];
@@ -2284,7 +2319,8 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
 // [R][pp + 4] and 4 values per lane for the unused lanes, which hold Z^{-1} a per port [np][R] before.
 static size_t schur_lds_w(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
     const size_t pp = (size_t)((max_p + 15) & ~15);
-    return tsize * (pp * (size_t)R + std::max((size_t)W * ((pp + 4) * (size_t)R + 256), (size_t)max_np * R));
+    const size_t ports = R <= 4 ? (size_t)max_np * 2 * sizeof(int) : 0;  // twins and vertices of the write-back (R <= 4)
+    return tsize * (pp * (size_t)R + std::max((size_t)W * ((pp + 4) * (size_t)R + 256), (size_t)max_np * R)) + ports;
 }
 
 // Two waves per subgraph when one wave's LDS would leave fewer than two waves per SIMD (W = 0).
@@ -2297,6 +2333,15 @@ size_t schur_lds_bytes(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, i
     return schur_lds_w(tsize, max_p, max_np, R, schur_waves(tsize, max_p, max_np, R, W));
 }
 
+// One-wave teams per workgroup of the streaming sweep: four when their LDS fits the CU (a CU holds a
+// limited number of workgroups, and one-wave workgroups would leave most of its wave slots empty),
+// else one; teams of two waves take a workgroup each.
+int schur_teams(int32_t W, size_t team_lds) {
+    if (W != 1) return 1;
+    const size_t tb = (team_lds + 15) & ~(size_t)15;
+    return tb * 4 <= kMaxLds ? 4 : tb * 2 <= kMaxLds ? 2 : 1;
+}
+
 template <typename T, int W>
 static const void *schur_fn(int32_t R) {
     return R == 1 ? (const void *)k_schur<T, 1, W> : R == 2 ? (const void *)k_schur<T, 2, W>
@@ -2306,21 +2351,26 @@ static const void *schur_fn(int32_t R) {
 template <typename T>
 hipError_t prepare_schur(int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
     const size_t shm = schur_lds_bytes(sizeof(T), max_p, max_np, R, W);
-    if (shm <= 64 * 1024) return hipSuccess;
-    const void *fn = schur_waves(sizeof(T), max_p, max_np, R, W) == 2 ? schur_fn<T, 2>(R) : schur_fn<T, 1>(R);
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    const int w = schur_waves(sizeof(T), max_p, max_np, R, W);
+    const size_t lds = ((shm + 15) & ~(size_t)15) * schur_teams(w, shm);
+    if (lds <= 64 * 1024) return hipSuccess;
+    const void *fn = w == 2 ? schur_fn<T, 2>(R) : schur_fn<T, 1>(R);
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename T, int W>
 static void launch_schur_w(const DevSub &D, int32_t nsub, int32_t ngroups, int32_t R, size_t shm, int32_t npg,
                            int64_t nports, const T *G, const int64_t *goff, const T *cport, const int32_t *twin,
                            const T *invz, const T *o_prev, T *o_next, hipStream_t st) {
-    const dim3 grid(nsub, ngroups), block(64 * W);
+    const int tb = (int)((shm + 15) & ~(size_t)15);
+    const int teams = schur_teams(W, shm);
+    const dim3 grid((nsub + teams - 1) / teams, ngroups), block(64 * W * teams);
+    const size_t lds = (size_t)tb * teams;
     switch (R) {
-        case 1: hipLaunchKernelGGL((k_schur<T, 1, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 2: hipLaunchKernelGGL((k_schur<T, 2, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        case 4: hipLaunchKernelGGL((k_schur<T, 4, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
-        default: hipLaunchKernelGGL((k_schur<T, 8, W>), grid, block, shm, st, D, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 1: hipLaunchKernelGGL((k_schur<T, 1, W>), grid, block, lds, st, D, nsub, tb, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 2: hipLaunchKernelGGL((k_schur<T, 2, W>), grid, block, lds, st, D, nsub, tb, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        case 4: hipLaunchKernelGGL((k_schur<T, 4, W>), grid, block, lds, st, D, nsub, tb, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
+        default: hipLaunchKernelGGL((k_schur<T, 8, W>), grid, block, lds, st, D, nsub, tb, npg, nports, G, goff, cport, twin, invz, o_prev, o_next); break;
     }
 }
 
