@@ -1,16 +1,20 @@
 """Train the learned impedance model and evaluate it against the diagonal rule.
 
     python -m paper_0807_1949_amd.train_zmodel [--k-probe 200] [--epochs 40]
-        [--budget-s 600] [--out zmodel_weights.json] [--report report.json]
+        [--budget-s 0] [--out zmodel_weights.json] [--report report.json]
 
 Training systems (all seeded, none from the evaluation seeds), at several scales so that the
 model sees how the best impedances grow with the number of subgraphs (its global-scale feature):
   grf    512^2 two-point-flux diffusion, k = exp(GRF sigma 1.5, l 16), 16x16 tiles (seeds 4000..)
   logn   m^2 lognormal(0,1) conductance Laplacian + 1e-3 I, m in {256, 384, 512, 768}, tiles of
          32 (64 to 576 subgraphs; seeds 100..)
-  pois3  m^3 Poisson, m in {32, 48, 64, 80, 96, 112}, seeded RCB into 64 to 4096 boxes of
-         340-512 unknowns (seeds 300..)
+  pois3  m^3 Poisson, m in {32, 48, 64, 80, 96, 112, 128}, seeded RCB into 64 to 4096 boxes of
+         340-512 unknowns (seeds 300..; the 3D workload's own seed is not among them)
   rgg    random geometric graph Laplacians + 1e-2 I, n 4k..200k, ~n/512 parts (seeds 7000..)
+  lap2   5-point Dirichlet Laplacian m^2, m in {81, 113, 145}, in 4x2 to 16x8 tiles (tiles of 6 x 11
+         to 37 x 73 vertices, the small subgraphs of Section 9's experiments, whose sizes it avoids;
+         seeds 8000..)
+Every listed seed is labelled (a fixed training set) unless --budget-s caps the time per family.
 Labels come from probe sweeps of the method itself (see zmodel.py).  The
 training target of a system's VTLs is its labels shifted so that their mean is
 ln alpha*: the per-interface refinement only redistributes impedance between
@@ -62,6 +66,11 @@ def family_system(fam: str, seed: int):
         A = GS.poisson3d_dirichlet(m)
         spec = dict(kind="rcb", dims=(m, m, m), levels=levels, seed=seed, min_size=0.0, max_size=1e30)
         return A, spec, GS.random_rhs(A.n, 1, seed), 1, None
+    if fam == "lap2":
+        combo = seed % (len(LAP2_SIZES) * len(LAP2_TILES))
+        m, (px, py) = LAP2_SIZES[combo % len(LAP2_SIZES)], LAP2_TILES[combo // len(LAP2_SIZES)]
+        A = GS.laplace2d_dirichlet(m)
+        return A, dict(kind="grid", dims=(m, m, 1), parts=(px, py, 1)), GS.random_rhs(A.n, 1, seed), 1, None
     if fam == "rgg":
         n = int(np.random.default_rng([seed, 3]).integers(4000, 200001))
         A = GS.random_geometric_graph(n, seed)
@@ -71,10 +80,14 @@ def family_system(fam: str, seed: int):
 
 
 LOGN_SIZES = (256, 384, 512, 768)
-POIS3_SCALES = ((32, 6), (48, 8), (64, 9), (80, 10), (96, 11), (112, 12))  # (m, RCB levels)
-TRAIN = dict(grf=range(4000, 4200), logn=range(100, 200), pois3=range(300, 400), rgg=range(7000, 7100))
-EVAL = dict(grf=range(4200, 4205), logn=range(200, 204), pois3=range(400, 406), rgg=range(7100, 7103))
-SHARE = dict(grf=0.25, logn=0.2, pois3=0.35, rgg=0.2)
+POIS3_SCALES = ((32, 6), (48, 8), (64, 9), (80, 10), (96, 11), (112, 12), (128, 12))  # (m, RCB levels)
+LAP2_SIZES = (81, 113, 145)
+LAP2_TILES = ((4, 2), (4, 4), (8, 4), (8, 8), (16, 8))  # tiles of at most 37 x 73 vertices
+TRAIN = dict(grf=range(4000, 4100), logn=range(100, 180), pois3=range(300, 349), rgg=range(7000, 7070),
+             lap2=range(8000, 8045))
+EVAL = dict(grf=range(4200, 4205), logn=range(200, 204), pois3=range(400, 407), rgg=range(7100, 7103),
+            lap2=(8101, 8107, 8113))
+SHARE = dict(grf=0.25, logn=0.2, pois3=0.35, rgg=0.2, lap2=0.1)
 
 
 def main(argv=None):
@@ -83,7 +96,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--budget-s", type=float, default=600.0, help="labelling time budget, split by family")
+    ap.add_argument("--budget-s", type=float, default=0.0, help="labelling time budget split by family (0: none)")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--report", default=None)
     ap.add_argument("--eval-c2", action="store_true", help="also evaluate on the 1024^2 workload")
@@ -95,7 +108,7 @@ def main(argv=None):
         used[fam] = []
         astar[fam] = []
         for seed in seeds:
-            if time.time() - t_fam > SHARE[fam] * args.budget_s:
+            if args.budget_s > 0 and time.time() - t_fam > SHARE[fam] * args.budget_s:
                 break
             A, spec, b, nsys, sptr = family_system(fam, seed)
             t0 = time.time()
