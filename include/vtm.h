@@ -225,7 +225,9 @@ vtm_status vtm_get_partition(vtm_handle h, int64_t *s_ptr, int32_t *s_idx, int64
  *                         and factor again; needs at most 2048 port vertices per subgraph
  *                         (else VTM_ERR_INVALID); setup_ms covers all three factorisations
  * Resets the waves to zero.  Errors: VTM_ERR_STATE (no partition),
- * VTM_ERR_INVALID (Z), VTM_ERR_NOT_SPD (first failing subgraph in the message).
+ * VTM_ERR_INVALID (Z; or a subgraph too large for a local solve: its vectors, 2 n_k + the largest
+ * update workspace values, must fit one CU's 160 KiB of LDS), VTM_ERR_NOT_SPD (first failing
+ * subgraph in the message).
  */
 vtm_status vtm_setup(vtm_handle h, int32_t z_rule, const double *z_vtl);
 

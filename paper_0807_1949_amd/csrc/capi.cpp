@@ -1529,6 +1529,14 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
                       const std::vector<double> *invz_port = nullptr) {
     const vtm::Partition &P = h->P;
     hipStream_t st = h->stream;
+    {  // every local solve (zero-wave solves, tests, plain sweeps) keeps a subgraph's vectors in LDS
+        const size_t need = vtm::sweep_lds_min(h->tsize(), h->max_nk, h->max_nu);
+        if (need > vtm::kMaxLds)
+            return fail(VTM_ERR_INVALID, "subgraphs too large: " + std::to_string(h->max_nk) +
+                                             " local unknowns need " + std::to_string(need / 1024) +
+                                             " KiB of LDS per local solve, more than the CU's " +
+                                             std::to_string(vtm::kMaxLds / 1024) + " KiB; use more subgraphs");
+    }
     if (z_rule == VTM_Z_LEARNED) {
         vtm_status rc = learned_z(h);
         if (rc) return rc;

@@ -2207,6 +2207,10 @@ size_t sweep_shm(int32_t max_nk, int32_t max_nu, int32_t, int32_t R) {
     return sizeof(T) * (size_t)(rs ? rs : 1) * (2 * (size_t)max_nk + (size_t)max_nu);
 }
 
+size_t sweep_lds_min(size_t tsize, int32_t max_nk, int32_t max_nu) {
+    return tsize * (2 * (size_t)max_nk + (size_t)max_nu);
+}
+
 template <typename T>
 hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_t R) {
     const int32_t rs = sweep_rs<T>(max_nk, max_nu, R);

@@ -139,6 +139,10 @@ template <typename T>
 void launch_restart(const DevSub &D, const DevMaps &M, int32_t nsub, int32_t nlist, int64_t nsplit, int64_t nports,
                     const double *b, int32_t nrhs, int32_t S, int32_t R, T *bsplit, T *o, hipStream_t st);
 
+// LDS bytes the substitution sweep needs for one right-hand side (largest local system and update
+// workspace); more than kMaxLds cannot run.
+size_t sweep_lds_min(size_t tsize, int32_t max_nk, int32_t max_nu);
+
 // One VTM sweep over all subgraphs and right-hand-side groups (grid = subgraphs x RHS groups).
 template <typename T>
 void launch_sweep(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_nk, int32_t max_nu, int32_t variant,

@@ -234,3 +234,20 @@ def test_portless_subgraph_in_a_batch(B):
     _close(xg[0], xo[0], 1e-10, "portless batch iterates")
     r = h.solve(b, 1e-10)
     assert r["status"] == 0 and int(r["iters"][0, 0]) == 1
+
+
+def test_oversized_subgraphs_are_refused_at_setup(B):
+    """A subgraph whose local solve cannot keep its vectors in one CU's LDS (here 73 x 73 tiles of a
+    145^2 Laplacian: 5329 local unknowns) is refused by vtm_setup with VTM_ERR_INVALID and a message
+    naming the limit; the handle stays usable for a partition with more subgraphs."""
+    A = gen.systems.laplace2d_dirichlet(145)
+    h = B.VTM(device=0)
+    h.evs_partition(A, dict(kind="grid", dims=(145, 145, 1), parts=(2, 2, 1)))
+    with pytest.raises(B.VTMError) as e:
+        h.setup(B.VTM_Z_DIAG)
+    assert e.value.code == B.VTM_ERR_INVALID and "subgraphs too large" in str(e.value)
+    h.evs_partition(A, dict(kind="grid", dims=(145, 145, 1), parts=(8, 8, 1)))
+    h.setup(B.VTM_Z_DIAG)
+    b = np.random.default_rng(1).uniform(-1, 1, A.n)
+    r = h.solve(b, 1e-8)
+    assert r["status"] == 0
