@@ -248,7 +248,10 @@ def roofline_of(st, workload):
     r = dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
              frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(kernel, summary),
              bytes_per_launch=st["sweep_bytes"] / max(st["sweeps"], 1), avg_launch_us=sweep_s * 1e6 / max(st["sweeps"], 1),
-             sweeps=int(st["sweeps"]))
+             sweeps=int(st["sweeps"]), bytes_per_full_launch=st["bytes_per_sweep"],
+             traffic_note="traffic: HBM bytes (copy-calibrated FETCH_SIZE + WRITE_SIZE) of the launches that cover "
+                          "every subgraph, to compare with bytes_per_full_launch (algorithmic bytes of such a "
+                          "launch); bytes_per_launch averages the solve's launches, fewer once systems converge")
     if st["persistent"]:
         r["bound"] = "latency"
         r["note"] = ("one persistent launch per batch of sweeps: G_k read once per launch; the time per sweep is "

@@ -1374,7 +1374,7 @@ __device__ inline void lds_put4(double *p, const double (&v)[4]) {
 }
 
 template <typename T, int R, int W>
-__global__ __launch_bounds__(W == 1 ? 256 : 64 * W, W == 1 && sizeof(T) == 4 && R <= 4 ? 6 : 1) void k_schur(DevSub D, int32_t nslots, int32_t team_bytes, int32_t npg,
+__global__ __launch_bounds__(W == 1 ? 256 : 64 * W) void k_schur(DevSub D, int32_t nslots, int32_t team_bytes, int32_t npg,
                                                               int64_t nports, const T *__restrict__ G,
                                                               const int64_t *__restrict__ goff, const T *__restrict__ cport,
                                                               const int32_t *__restrict__ twin, const T *__restrict__ invz,
@@ -1408,13 +1408,6 @@ __global__ __launch_bounds__(W == 1 ? 256 : 64 * W, W == 1 && sizeof(T) == 4 && 
     T *y = xz + (size_t)pp * R;            // per wave: G Z^{-1} a from its blocks [W][R][ps], rows in yrow order
     T *scr = y;                            // before y: Z^{-1} a per port [np_k][R]
     T *ydummy = y + (size_t)W * ps * R;    // after y (over the scratch): 4 values per lane for the unused lanes
-    // With up to 4 RHS the twin and the vertex of each port wait in LDS (after the scratch) for the
-    // write-back, which loads the incoming wave again, instead of keeping them in registers through
-    // the stream: fewer registers, more waves per SIMD.
-    constexpr bool kPortsLds = R <= 4;
-    const int np_here = D.port_ptr[k + 1] - D.port_ptr[k];
-    int *twl = reinterpret_cast<int *>(y + (W * (ps * R + 256) > np_here * R ? W * (ps * R + 256) : np_here * R));
-    int *vin = twl + np_here;  // twl[np_k], vin[np_k]
     // With 8 RHS, the two halves of a row of xz swap places in every other group of 4 rows, so that
     // the 16-byte reads of 8 consecutive rows fall in distinct LDS banks.
     auto xzi = [](int r, int c) { return r * R + (R == 8 ? (c ^ (((r >> 2) & 1) << 2)) : c); };
@@ -1482,18 +1475,13 @@ __global__ __launch_bounds__(W == 1 ? 256 : 64 * W, W == 1 && sizeof(T) == 4 && 
 #pragma unroll
             for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
     };
-    auto port_store = [&](int t0, const T (&iz)[U], const T (&a)[U][R], const int (&tw)[U], const int (&vv)[U]) {
+    auto port_store = [&](int t0, const T (&iz)[U], const T (&a)[U][R]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + nt * u + tid;
-            if (t < np_k) {
+            if (t < np_k)
 #pragma unroll
                 for (int c = 0; c < R; ++c) scr[t * R + c] = a[u][c] * iz[u];
-                if constexpr (kPortsLds) {
-                    twl[t] = tw[u];
-                    vin[t] = vv[u];
-                }
-            }
         }
     };
     if (np_k > 0) port_loads(0, tw0, v0r, iz0, a0);
@@ -1507,12 +1495,12 @@ __global__ __launch_bounds__(W == 1 ? 256 : 64 * W, W == 1 && sizeof(T) == 4 && 
         pre[f].load(Gl + next_load());
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (np_k > 0) port_store(0, iz0, a0, tw0, v0r);
+    if (np_k > 0) port_store(0, iz0, a0);
     for (int t0 = nt * U; t0 < np_k; t0 += nt * U) {
         int tw[U], vv[U];
         T iz[U], a[U][R];
         port_loads(t0, tw, vv, iz, a);
-        port_store(t0, iz, a, tw, vv);
+        port_store(t0, iz, a);
     }
     team_sync();
     for (int v0 = 0; v0 < pp; v0 += nt * U) {
@@ -1657,18 +1645,7 @@ __global__ __launch_bounds__(W == 1 ? 256 : 64 * W, W == 1 && sizeof(T) == 4 && 
     for (int t0 = 0; t0 < np_k; t0 += nt * U) {
         int tw[U], v[U];
         T a[U][R], cu[U][R];
-        if constexpr (kPortsLds) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = t0 + nt * u + tid, tt = t < np_k ? t : 0;
-                tw[u] = twl[tt];
-                v[u] = vin[tt];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int c = 0; c < R; ++c) a[u][c] = o_prev[wo + (int64_t)tw[u] * R + c];
-        } else if (t0 == 0) {
+        if (t0 == 0) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 tw[u] = tw0[u];
@@ -2323,8 +2300,7 @@ void launch_gather_ports(const DevSub &D, int32_t nsub, int32_t ngroups, int64_t
 // [R][pp + 4] and 4 values per lane for the unused lanes, which hold Z^{-1} a per port [np][R] before.
 static size_t schur_lds_w(size_t tsize, int32_t max_p, int32_t max_np, int32_t R, int32_t W) {
     const size_t pp = (size_t)((max_p + 15) & ~15);
-    const size_t ports = R <= 4 ? (size_t)max_np * 2 * sizeof(int) : 0;  // twins and vertices of the write-back (R <= 4)
-    return tsize * (pp * (size_t)R + std::max((size_t)W * ((pp + 4) * (size_t)R + 256), (size_t)max_np * R)) + ports;
+    return tsize * (pp * (size_t)R + std::max((size_t)W * ((pp + 4) * (size_t)R + 256), (size_t)max_np * R));
 }
 
 // Two waves per subgraph when one wave's LDS would leave fewer than two waves per SIMD (W = 0).
