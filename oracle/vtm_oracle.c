@@ -88,6 +88,11 @@ static int cmp_i32(const void *a, const void *b) {
     return (x > y) - (x < y);
 }
 
+static int cmp_i64(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
 /* splitmix64 (Steele, Lea & Flood 2014): state += golden gamma, then mix. */
 static uint64_t splitmix64(uint64_t *state) {
     uint64_t z = (*state += 0x9E3779B97F4A7C15ULL);
@@ -287,6 +292,87 @@ static void point_rcb(int64_t *vs, int64_t cnt, int32_t np, int32_t *next_id, in
     point_rcb(vs + cut, cnt - cut, np - nl, next_id, owner);
 }
 
+/* Connected parts: for part k = 0, 1, ... in turn, the vertices it owns at that moment fall into
+ * connected components (edges of A between two of them).  The largest component stays (equal sizes:
+ * the one holding the smallest vertex).  Each other component moves, whole, to the part owning the
+ * most far ends of its edges that leave part k (equal counts: the smallest part id); with no such
+ * edge (a component of A by itself) it stays.  Plain version: the members of part k (its first
+ * owners and the vertices moved into it) are sorted, and components are labelled by an
+ * explicit-stack depth-first search started at the smallest unlabelled member. */
+static void connect_parts(const or_part *p, int32_t *owner, int32_t nsub) {
+    const int64_t n = p->n;
+    int32_t *lab = malloc(sizeof(int32_t) * n);
+    int64_t *stack = malloc(sizeof(int64_t) * n);
+    int64_t *mem = malloc(sizeof(int64_t) * n);
+    int64_t *csize = malloc(sizeof(int64_t) * (n + 1));
+    int32_t *votes = calloc((size_t)nsub, sizeof(int32_t));
+    /* members by part: the initial owners in vertex order, then the vertices moved in (linked list) */
+    int64_t *first = calloc((size_t)nsub + 1, sizeof(int64_t));
+    int64_t *byp = malloc(sizeof(int64_t) * n);
+    int64_t *head = malloc(sizeof(int64_t) * nsub), *nxt = malloc(sizeof(int64_t) * n);
+    for (int64_t v = 0; v < n; v++) first[owner[v] + 1]++;
+    for (int32_t q = 0; q < nsub; q++) first[q + 1] += first[q];
+    {
+        int64_t *fill = malloc(sizeof(int64_t) * nsub);
+        for (int32_t q = 0; q < nsub; q++) { fill[q] = first[q]; head[q] = -1; }
+        for (int64_t v = 0; v < n; v++) byp[fill[owner[v]]++] = v;
+        free(fill);
+    }
+    for (int64_t v = 0; v < n; v++) lab[v] = -1;
+    for (int32_t k = 0; k < nsub; k++) {
+        int64_t m = 0;
+        for (int64_t i = first[k]; i < first[k + 1]; i++) mem[m++] = byp[i];
+        for (int64_t v = head[k]; v >= 0; v = nxt[v]) mem[m++] = v;
+        qsort(mem, (size_t)m, sizeof(int64_t), cmp_i64);
+        int32_t ncomp = 0;
+        for (int64_t i = 0; i < m; i++) {
+            if (lab[mem[i]] >= 0) continue;
+            int64_t top = 0, size = 0;
+            stack[top++] = mem[i];
+            lab[mem[i]] = ncomp;
+            while (top > 0) {
+                int64_t v = stack[--top];
+                size++;
+                for (int64_t e = p->rowptr[v]; e < p->rowptr[v + 1]; e++) {
+                    int32_t u = p->col[e];
+                    if (owner[u] == k && lab[u] < 0) { lab[u] = ncomp; stack[top++] = u; }
+                }
+            }
+            csize[ncomp++] = size;
+        }
+        int32_t keep = 0;
+        for (int32_t c = 1; c < ncomp; c++) if (csize[c] > csize[keep]) keep = c;
+        for (int32_t c = 0; c < ncomp; c++) {
+            if (c == keep) continue;
+            int32_t best = -1;
+            for (int64_t i = 0; i < m; i++) {
+                int64_t v = mem[i];
+                if (lab[v] != c) continue;
+                for (int64_t e = p->rowptr[v]; e < p->rowptr[v + 1]; e++) {
+                    int32_t q = owner[p->col[e]];
+                    if (q == k) continue;
+                    votes[q]++;
+                    if (best < 0 || votes[q] > votes[best] || (votes[q] == votes[best] && q < best)) best = q;
+                }
+            }
+            for (int64_t i = 0; i < m; i++) {  /* clear the votes */
+                int64_t v = mem[i];
+                if (lab[v] != c) continue;
+                for (int64_t e = p->rowptr[v]; e < p->rowptr[v + 1]; e++) votes[owner[p->col[e]]] = 0;
+            }
+            if (best < 0) continue;
+            for (int64_t i = 0; i < m; i++)
+                if (lab[mem[i]] == c) {
+                    owner[mem[i]] = best;
+                    nxt[mem[i]] = head[best];
+                    head[best] = mem[i];
+                }
+        }
+        for (int64_t i = 0; i < m; i++) lab[mem[i]] = -1;
+    }
+    free(lab); free(stack); free(mem); free(csize); free(votes); free(first); free(byp); free(head); free(nxt);
+}
+
 static int member_graph(or_part *p, const double *coords, int dim, int32_t nblocks, const int64_t *bstart,
                         const int64_t *bcount, const int32_t *bparts) {
     if (!coords || dim < 1 || dim > 3 || nblocks < 1) return OR_ERR_INVALID;
@@ -303,6 +389,7 @@ static int member_graph(or_part *p, const double *coords, int dim, int32_t nbloc
     }
     free(vs);
     for (int64_t v = 0; v < p->n; v++) if (owner[v] < 0) { free(owner); return OR_ERR_PARTITION; }
+    connect_parts(p, owner, next_id);
     p->nsub = next_id;
     p->s_ptr = calloc(p->n + 1, sizeof(int64_t));
     int64_t cap = p->n * 2 + 16, pos = 0;

@@ -140,6 +140,79 @@ int rcb_membership(const vtm_partition_spec &sp, Partition &P, std::string &err)
     return VTM_ERR_PARTITION;
 }
 
+// Parts whose owned vertices fall apart: a coordinate cut of a graph can leave a few vertices in a
+// part that they touch only through other parts.  Such a piece reaches the rest of its system only
+// through VTLs and holds a slowly decaying wave mode.  Parts in increasing id: the owned vertices of
+// part k are split into connected components (edges of A between vertices owned by k), the largest
+// stays (ties: the one with the smallest vertex), and every other component goes to the part it
+// shares the most edges with (ties: the smallest id); a component with no edge leaving the part (a
+// component of A) stays.  A moved component is connected to its new part, so a part processed
+// earlier stays connected.
+void connect_parts(const Csr &A, std::vector<int32_t> &owner, int32_t nsub) {
+    const int64_t n = A.n;
+    std::vector<std::vector<int64_t>> members(nsub);
+    for (int64_t v = 0; v < n; ++v) members[owner[v]].push_back(v);
+    std::vector<int32_t> comp(n, -1);
+    std::vector<int64_t> queue, start;  // vertices by component (BFS order), component starts
+    std::vector<std::pair<int32_t, int32_t>> cnt;
+    for (int32_t k = 0; k < nsub; ++k) {
+        std::vector<int64_t> &mv = members[k];
+        std::sort(mv.begin(), mv.end());
+        queue.clear();
+        start.clear();
+        int32_t nc = 0;
+        for (const int64_t s : mv) {
+            if (comp[s] >= 0) continue;
+            start.push_back((int64_t)queue.size());
+            comp[s] = nc;
+            queue.push_back(s);
+            for (size_t h = (size_t)start.back(); h < queue.size(); ++h) {
+                const int64_t v = queue[h];
+                for (int64_t e = A.rp[v]; e < A.rp[v + 1]; ++e) {
+                    const int32_t u = A.ci[e];
+                    if (owner[u] == k && comp[u] < 0) {
+                        comp[u] = nc;
+                        queue.push_back(u);
+                    }
+                }
+            }
+            ++nc;
+        }
+        start.push_back((int64_t)queue.size());
+        if (nc > 1) {
+            int32_t keep = 0;
+            for (int32_t c = 1; c < nc; ++c)
+                if (start[c + 1] - start[c] > start[keep + 1] - start[keep]) keep = c;
+            for (int32_t c = 0; c < nc; ++c) {
+                if (c == keep) continue;
+                cnt.clear();
+                for (int64_t i = start[c]; i < start[c + 1]; ++i) {
+                    const int64_t v = queue[i];
+                    for (int64_t e = A.rp[v]; e < A.rp[v + 1]; ++e) {
+                        const int32_t q = owner[A.ci[e]];
+                        if (q != k) cnt.push_back({q, 1});
+                    }
+                }
+                if (cnt.empty()) continue;
+                std::sort(cnt.begin(), cnt.end());
+                int32_t best = -1, best_n = 0;
+                for (size_t i = 0; i < cnt.size();) {
+                    size_t j = i;
+                    while (j < cnt.size() && cnt[j].first == cnt[i].first) ++j;
+                    if ((int32_t)(j - i) > best_n) { best_n = (int32_t)(j - i); best = cnt[i].first; }
+                    i = j;
+                }
+                for (int64_t i = start[c]; i < start[c + 1]; ++i) {
+                    owner[queue[i]] = best;
+                    members[best].push_back(queue[i]);
+                }
+            }
+        }
+        for (const int64_t v : queue) comp[v] = -1;
+        std::vector<int64_t>().swap(mv);
+    }
+}
+
 int graph_membership(const vtm_partition_spec &sp, const Csr &A, Partition &P, std::string &err) {
     if (!sp.coords || sp.dim < 1 || sp.dim > 3 || sp.nblocks < 1 || !sp.block_start || !sp.block_count ||
         !sp.block_parts) {
@@ -191,6 +264,7 @@ int graph_membership(const vtm_partition_spec &sp, const Csr &A, Partition &P, s
     }
     for (int64_t v = 0; v < P.n; ++v)
         if (owner[v] < 0) { err = "GRAPH blocks do not cover all vertices"; return VTM_ERR_PARTITION; }
+    connect_parts(A, owner, next);
     P.nsub = next;
     P.s_ptr.assign(P.n + 1, 0);
     P.s_idx.clear();

@@ -61,6 +61,25 @@ def test_partition_bit_exact_rules(split, topo):
     _assert_partition_equal(h.get_partition(), O.Partition(cfg["A"], cfg["spec"], split=split, topology=topo))
 
 
+def test_partition_bit_exact_graph_parts_made_connected():
+    """GRAPH parts that the coordinate cut leaves in pieces: the stray pieces move to the part they
+    share most edges with, in the library as in the oracle (hand-made graphs with a move and a tie)."""
+    from gen import systems as S
+    for edges, parts in (([(0, 1), (1, 3), (2, 4), (2, 5), (3, 4), (4, 5)], 2),
+                         ([(0, 1), (1, 2), (1, 3), (2, 4), (3, 4), (4, 5)], 3)):
+        u = np.array([a for a, b in edges], dtype=np.int64)
+        v = np.array([b for a, b in edges], dtype=np.int64)
+        diag = np.ones(6)
+        np.add.at(diag, u, 1.0)
+        np.add.at(diag, v, 1.0)
+        coords = np.stack([np.arange(6, dtype=np.float64), np.zeros(6)], axis=1)
+        A = S._assemble_weighted(6, u, v, np.ones(len(edges)), diag, coords=coords)
+        spec = dict(kind="graph", coords=coords, blocks=[(0, 6, parts)])
+        h = _host_handle()
+        h.evs_partition(A, spec)
+        _assert_partition_equal(h.get_partition(), O.Partition(A, spec))
+
+
 @pytest.mark.parametrize("name", ["c1", "c2", "c4", "c3", "c5"])
 def test_partition_bit_exact_full(name):
     """Every workload at full size, including the 3D RCB (4096 boxes) and the 64-system graph batch."""

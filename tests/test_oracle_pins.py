@@ -526,3 +526,60 @@ def test_tree_topology_is_a_spanning_tree_of_the_face_pairs():
     assert cycles > 0  # FACE had cycles here that the tree drops
     # ports and twins follow the VTLs: two ports per VTL, each the other's twin
     assert len(tree.port_v) == 2 * tree.nvtl and np.array_equal(tree.port_twin[tree.port_twin], np.arange(2 * tree.nvtl))
+
+
+def _hand_graph(n, edges, xs):
+    """Laplacian of the listed unit-weight edges plus I, with x coordinates xs (y = 0)."""
+    from gen import systems as S
+    u = np.array([a for a, b in edges], dtype=np.int64)
+    v = np.array([b for a, b in edges], dtype=np.int64)
+    w = np.ones(len(edges))
+    diag = np.ones(n)
+    np.add.at(diag, u, w)
+    np.add.at(diag, v, w)
+    coords = np.stack([np.asarray(xs, dtype=np.float64), np.zeros(n)], axis=1)
+    return S._assemble_weighted(n, u, v, w, diag, coords=coords)
+
+
+def test_graph_parts_are_made_connected_worked_example():
+    """A coordinate cut leaves vertex 2 in the left part although its edges all lead right; it moves
+    to the part it shares most edges with.  Worked by hand: left part {0, 1}, right {2, .., 5}; the
+    cut edge 1-3 makes vertex 1 the only split vertex (children in both parts).  Then a tie: vertex 3
+    of the middle part touches the left and the right part by one edge each and goes to the left
+    (smaller id)."""
+    from oracle import oracle as O
+    A = _hand_graph(6, [(0, 1), (1, 3), (2, 4), (2, 5), (3, 4), (4, 5)], [0, 1, 2, 3, 4, 5])
+    P = O.Partition(A, dict(kind="graph", coords=A.coords, blocks=[(0, 6, 2)]))
+    assert P.s_ptr.tolist() == [0, 1, 3, 4, 5, 6, 7]
+    assert P.s_idx.tolist() == [0, 0, 1, 1, 1, 1, 1]
+    # three parts of two vertices: {0, 1}, {2, 3}, {4, 5}; 2 - 3 is no edge, so the middle part falls
+    # into {2} (kept: smaller vertex at equal size) and {3}, which has one edge left (1 - 3) and one
+    # right (3 - 4): it goes left.  Vertex 1 (part 0) has a neighbour in part 1 (vertex 2): split.
+    B = _hand_graph(6, [(0, 1), (1, 2), (1, 3), (2, 4), (3, 4), (4, 5)], [0, 1, 2, 3, 4, 5])
+    Q = O.Partition(B, dict(kind="graph", coords=B.coords, blocks=[(0, 6, 3)]))
+    owner = Q.s_idx[Q.s_ptr[:-1]]
+    assert owner.tolist() == [0, 0, 1, 0, 2, 2]
+    assert Q.s_idx[Q.s_ptr[1]:Q.s_ptr[2]].tolist() == [0, 1]  # vertex 1: its own part and vertex 2's
+    assert Q.s_idx[Q.s_ptr[3]:Q.s_ptr[4]].tolist() == [0, 2]  # vertex 3: moved to 0, split into 2
+
+
+def test_graph_parts_are_connected():
+    """After the coordinate cut every part's owned vertices form one connected piece, up to
+    components of A lying wholly inside the part (which have no ports); every part keeps vertices."""
+    import scipy.sparse as sp
+    import gen
+    from oracle import oracle as O
+    cfg = gen.make_config("c5", small=True)
+    A = cfg["A"]
+    P = O.Partition(A, cfg["spec"])
+    M = A.to_scipy()
+    owner = P.s_idx[P.s_ptr[:-1]]
+    assert np.array_equal(np.unique(owner), np.arange(P.nsub))
+    for k in range(P.nsub):
+        vs = np.nonzero(owner == k)[0]
+        nc, lab = sp.csgraph.connected_components(M[vs][:, vs], directed=False)
+        keep = np.argmax(np.bincount(lab))
+        for c in range(nc):
+            if c != keep:
+                C = vs[lab == c]
+                assert (owner[M[C].indices] == k).all()  # a component of A, no edge leaves the part
