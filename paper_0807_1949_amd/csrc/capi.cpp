@@ -785,7 +785,7 @@ int32_t sweep_variant(vtm_ctx *h) {
 
 int32_t sweep_threads(vtm_ctx *h) {
     const int32_t t = h->opt.sweep_threads;
-    return t >= 64 && t <= 512 && t % 64 == 0 ? t : 256;
+    return t >= 64 && t <= 512 && t % 64 == 0 ? t : 512;
 }
 
 // Sweeps on the current waves; the last one stores the local solutions.  Batches of two or more
@@ -954,7 +954,7 @@ vtm_status test_solve(vtm_ctx *h) {
     const int32_t R = h->wave_R, ng = (h->wave_nrhs + R - 1) / R;
     if (h->have_y && h->yb_ok && vtm::prepare_ysolve<T>(h->max_nk, h->max_p, R) == hipSuccess) {
         vtm::launch_ysolve<T>(dev_sym(h), dev_sub(h), dev_green(h, true), yblocks_of<T>(h), nsub_launch(h), h->max_nk,
-                              h->max_p, ng, R, h->nsplit, h->nports, vals_of<T>(h), h->d_yb.as<T>(),
+                              h->max_p, ng, R, sweep_threads(h), h->nsplit, h->nports, vals_of<T>(h), h->d_yb.as<T>(),
                               h->d_twin.as<int32_t>(), invz_of<T>(h), h->d_o[h->cur ^ 1].as<T>(), h->d_xloc.as<T>(),
                               h->stream);
         return VTM_OK;

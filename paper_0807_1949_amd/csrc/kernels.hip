@@ -1106,7 +1106,7 @@ __global__ __launch_bounds__(512) void k_sweep(DevSym S, DevSub D, int64_t nspli
 // s (nc_s x w_s, row-major) live in its region of the Green workspace: after its port front in FP64,
 // column-major at y32_pos in the FP32 copy.
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_ysolve(DevSym S, DevSub D, DevGreen Gp, const T *__restrict__ Yw,
+__global__ __launch_bounds__(512) void k_ysolve(DevSym S, DevSub D, DevGreen Gp, const T *__restrict__ Yw,
                                                 int64_t nsplit, int64_t nports, const T *__restrict__ vals,
                                                 const T *__restrict__ yb, const int32_t *__restrict__ twin,
                                                 const T *__restrict__ invz, const T *__restrict__ o_in,
@@ -2232,10 +2232,11 @@ hipError_t prepare_ysolve(int32_t max_nk, int32_t max_p, int32_t R) {
 
 template <typename T>
 void launch_ysolve(const DevSym &S, const DevSub &D, const DevGreen &Gp, const T *Yw, int32_t nsub, int32_t max_nk,
-                   int32_t max_p, int32_t ngroups, int32_t R, int64_t nsplit, int64_t nports, const T *vals,
-                   const T *yb, const int32_t *twin, const T *invz, const T *o_in, T *xloc, hipStream_t st) {
+                   int32_t max_p, int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports,
+                   const T *vals, const T *yb, const int32_t *twin, const T *invz, const T *o_in, T *xloc,
+                   hipStream_t st) {
     const size_t shm = ysolve_shm<T>(max_nk, max_p, R);
-    const dim3 grid(nsub, ngroups), block(256);
+    const dim3 grid(nsub, ngroups), block(threads);
     switch (R) {
         case 1: hipLaunchKernelGGL((k_ysolve<T, 1>), grid, block, shm, st, S, D, Gp, Yw, nsplit, nports, vals, yb, twin, invz, o_in, xloc); break;
         case 2: hipLaunchKernelGGL((k_ysolve<T, 2>), grid, block, shm, st, S, D, Gp, Yw, nsplit, nports, vals, yb, twin, invz, o_in, xloc); break;
@@ -2450,10 +2451,10 @@ template void launch_sweep<float>(const DevSym &, const DevSub &, int32_t, int32
 template hipError_t prepare_ysolve<double>(int32_t, int32_t, int32_t);
 template hipError_t prepare_ysolve<float>(int32_t, int32_t, int32_t);
 template void launch_ysolve<double>(const DevSym &, const DevSub &, const DevGreen &, const double *, int32_t, int32_t,
-                                    int32_t, int32_t, int32_t, int64_t, int64_t, const double *, const double *,
+                                    int32_t, int32_t, int32_t, int32_t, int64_t, int64_t, const double *, const double *,
                                     const int32_t *, const double *, const double *, double *, hipStream_t);
 template void launch_ysolve<float>(const DevSym &, const DevSub &, const DevGreen &, const float *, int32_t, int32_t,
-                                   int32_t, int32_t, int32_t, int64_t, int64_t, const float *, const float *,
+                                   int32_t, int32_t, int32_t, int32_t, int64_t, int64_t, const float *, const float *,
                                    const int32_t *, const float *, const float *, float *, hipStream_t);
 template hipError_t prepare_sweep<double>(int32_t, int32_t, int32_t, int32_t);
 template void launch_gather_ports<double>(const DevSub &, int32_t, int32_t, int64_t, int32_t, int32_t, const double *,

@@ -155,13 +155,15 @@ hipError_t prepare_sweep(int32_t max_nk, int32_t max_nu, int32_t variant, int32_
 
 // Local solutions of a convergence test from the stored Y blocks (Yw: the Green workspace in T
 // precision) and y_b = L^{-1} b~ (yb, layout of the local solutions): one parallel product and the
-// backward substitution.  prepare_ysolve fails when the LDS need exceeds the CU's.
+// backward substitution, `threads` (64 .. 512) per subgraph.  prepare_ysolve fails when the LDS need
+// exceeds the CU's.
 template <typename T>
 hipError_t prepare_ysolve(int32_t max_nk, int32_t max_p, int32_t R);
 template <typename T>
 void launch_ysolve(const DevSym &S, const DevSub &D, const DevGreen &Gp, const T *Yw, int32_t nsub, int32_t max_nk,
-                   int32_t max_p, int32_t ngroups, int32_t R, int64_t nsplit, int64_t nports, const T *vals,
-                   const T *yb, const int32_t *twin, const T *invz, const T *o_in, T *xloc, hipStream_t st);
+                   int32_t max_p, int32_t ngroups, int32_t R, int32_t threads, int64_t nsplit, int64_t nports,
+                   const T *vals, const T *yb, const int32_t *twin, const T *invz, const T *o_in, T *xloc,
+                   hipStream_t st);
 
 // Port Green's functions G_k = R K_k^{-1} R^T by one substitution per group of four port columns
 // (FP64, packed like above); used when the column plan does not apply.
