@@ -74,7 +74,7 @@ typedef struct {
     int32_t rhs_per_block; /* right-hand sides one workgroup carries (0 = tuned: 1, 2, 4 or 8) */
     int32_t leaf_size;     /* nested-dissection leaf size of the local orderings (0 = 16) */
     int32_t sweep_threads; /* threads per substitution workgroup (sweeps and test solves), 64..512
-                              (0 = 512, or vtm_autotune's choice) */
+                              (0 = 256, or vtm_autotune's choice) */
     int32_t graph_mode;    /* 0: replay sweep batches as captured HIP graphs; 1: plain launches */
     int32_t sweep_variant; /* forward substitution: 1 = row dot products over descendant L21 rows,
                               2 = per-level update entries L21*y gathered by the ancestors, 0 = choose */

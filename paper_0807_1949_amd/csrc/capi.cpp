@@ -785,7 +785,7 @@ int32_t sweep_variant(vtm_ctx *h) {
 
 int32_t sweep_threads(vtm_ctx *h) {
     const int32_t t = h->opt.sweep_threads;
-    return t >= 64 && t <= 512 && t % 64 == 0 ? t : 512;
+    return t >= 64 && t <= 512 && t % 64 == 0 ? t : 256;
 }
 
 // Sweeps on the current waves; the last one stores the local solutions.  Batches of two or more
