@@ -100,6 +100,7 @@ struct vtm_ctx {
     int32_t persist_R = -1, persist_ng = -1;
     bool persist_fits = false;
     int64_t total_g = 0;   // stored entries of all packed G_k
+    bool plan_in_order = false;  // every subgraph's plan order is its port-vertex order (G_k by k_gram)
     double total_pp = 0;   // sum of p_k^2 (entries of the full G_k)
     bool have_green = false;
     bool have_y = false;  // the set-up kept the Y blocks (FP64 workspace, FP32 copy when sweeping in FP32)
@@ -336,6 +337,7 @@ vtm_status build_green_plan(vtm_ctx *h) {
     std::vector<int32_t> base(nsub + 1, 0), idoff(h->npg, 0);
     std::vector<uint16_t> perm(h->npg, 0);
     std::vector<int64_t> wso(nsub + 1, 0);
+    bool in_order = true;
     for (int32_t k = 0; k < nsub; ++k) {
         const int32_t c = S.sub_class[k];
         const vtm::ClassSym &C = S.classes[c];
@@ -370,6 +372,7 @@ vtm_status build_green_plan(vtm_ctx *h) {
         }
         for (int32_t a = 0; a < p; ++a) {
             const int32_t j = order[a], pos = h->h_pgpos[pg0 + j], s = C.col_sn[pos];
+            in_order = in_order && j == a;
             perm[pg0 + a] = (uint16_t)j;
             idoff[pg0 + a] = (int32_t)(fo[s] + (int64_t)(pos - C.sn_c0[s]) * w[s] + (a - lo[s]));
         }
@@ -384,6 +387,7 @@ vtm_status build_green_plan(vtm_ctx *h) {
     HIP_TRY(upload(h->d_gidoff, idoff, st));
     HIP_TRY(upload(h->d_gperm, perm, st));
     HIP_TRY(hipStreamSynchronize(st));
+    h->plan_in_order = in_order;
     h->plan_state = 1;
     return VTM_OK;
 }
@@ -1581,9 +1585,15 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
         HIP_TRY(ensure(h->d_gws32, sizeof(float) * (h->gws_total + 2)));
         h->have_y32 = true;
     }
+    // G_k from the stored Y blocks by k_gram (every entry written once) when the plan order is the
+    // port-vertex order; otherwise accumulated inside the factorisation into a cleared G
+    const bool gram_apart = fused && h->plan_in_order;
     if (want_green) {
         HIP_TRY(ensure(h->d_G64, sizeof(double) * (h->total_g + 256)));
-        HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 256), st));
+        if (gram_apart)  // only the spare block past the end, which k_gram does not write
+            HIP_TRY(hipMemsetAsync(h->d_G64.as<double>() + h->total_g, 0, sizeof(double) * 256, st));
+        else
+            HIP_TRY(hipMemsetAsync(h->d_G64.p, 0, sizeof(double) * (h->total_g + 256), st));
         // the port fronts start at zero; every factorisation leaves them zero (each supernode clears
         // the front it consumed), so the workspace is cleared only when new
         if (fused && !h->gws_clean) HIP_TRY(hipMemsetAsync(h->d_gws.p, 0, sizeof(double) * (h->gws_total + 2), st));
@@ -1597,7 +1607,10 @@ vtm_status setup_core(vtm_ctx *h, int32_t z_rule, const std::vector<double> &z, 
                        h->d_invz64.as<double>(), want64 ? h->d_vals64.as<double>() : nullptr,
                        h->fp32() ? h->d_vals32.as<float>() : nullptr, ws.as<double>(),
                        h->d_status.as<int32_t>(), dev_green(h, fused), h->d_goff.as<int64_t>(),
-                       want_green ? h->d_G64.as<double>() : nullptr, st);
+                       want_green && !gram_apart ? h->d_G64.as<double>() : nullptr, st);
+    if (gram_apart)
+        vtm::launch_gram(dev_sym(h), dev_sub(h), P.nsub, h->max_p, dev_green(h, true), h->d_goff.as<int64_t>(),
+                         h->d_G64.as<double>(), st);
     h->have_green = false;
     if (want_green) {
         if (!fused)

@@ -535,7 +535,7 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
             team_sync<BLK>();
             if (!staged)  // the port front is left zero for the next factorisation
                 for (int i = r; i < f * w; i += n) T[i] = 0.0;
-            if (!Yl && nc * w <= cap) {  // the front is consumed: Y_s over it, so the Gram products read LDS
+            if (X.Gk && !Yl && nc * w <= cap) {  // the front is consumed: Y_s over it, so the Gram products read LDS
                 for (int i0 = r; i0 < nc * w; i0 += 8 * n) {
                     double t[8];
 #pragma unroll
@@ -547,7 +547,7 @@ __device__ __forceinline__ void factor_front(const FactorArgs &X, int s, double 
                 Yl = F;
                 team_sync<BLK>();
             }
-            for (int it = wv; it < tcn * (tcn + 1) / 2; it += nw) {  // G += Y^T Y
+            for (int it = wv; X.Gk && it < tcn * (tcn + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
                 tri_tile(it, ta, tb);
                 const f64x4 acc = Yl ? gram_tile(ta, tb, nc, w, lane, [&](int t, int c) { return Yl[t * w + c]; })
@@ -700,7 +700,7 @@ __device__ __forceinline__ void factor_node(const FactorArgs &X, int s, double *
             __syncthreads();
             for (int i = r; i < f * w; i += n) T[i] = 0.0;  // the port front is left zero for the next factorisation
             const int tw = (w + 15) >> 4;
-            for (int it = wv; it < tw * (tw + 1) / 2; it += nw) {  // G += Y^T Y
+            for (int it = wv; X.Gk && it < tw * (tw + 1) / 2; it += nw) {  // G += Y^T Y
                 int ta, tb;
                 tri_tile(it, ta, tb);
                 const f64x4 acc = gram_tile(ta, tb, nc, w, lane, [&](int t, int a) { return Y[t * w + a]; });
@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, cons
         X.gws = Gp.ws + Gp.wso[k];
         X.gws32 = Gp.ws32 ? Gp.ws32 + Gp.wso[k] : nullptr;
         X.perm = Gp.perm + pg0;
-        X.Gk = G + goff[k];
+        X.Gk = G ? G + goff[k] : nullptr;  // nullptr: k_gram forms G_k from the stored Y blocks
         X.nb = (p + 15) >> 4;
         for (int a = tid; a < p; a += nt) X.gws[Gp.idoff[pg0 + a]] = 1.0;
     }
@@ -780,6 +780,60 @@ __global__ __launch_bounds__(kThreads, 4) void k_factor(DevSym S, DevSub D, cons
         __syncthreads();
     }
     if (tid == 0) status[k] = sbad == 0x7FFFFFFF ? 0 : sbad;
+}
+
+// G_k = sum over supernodes s of Y_s^T Y_s, one 16 x 16 block of the packed lower block triangle per
+// wave, written once (no atomics, no clearing).  The ports below s are the range [lo_s, lo_s + w_s)
+// of the plan order, which is also G_k's port order, so block (I, J) gathers the supernodes whose
+// range meets both ports 16 I .. 16 I + 15 and 16 J .. 16 J + 15 (the common ancestors of its ports),
+// in increasing order, on one chain of v_mfma_f64_16x16x4 (lane l: A[l % 16][l / 16] = Y_s[t][i - lo_s],
+// B[l / 16][l % 16] = Y_s[t][j - lo_s], D[4 q + l / 16][l % 16] in acc[q]).  Entries past the last
+// port are written as zeros (the padding of the last block).
+__global__ __launch_bounds__(256) void k_gram(DevSym S, DevSub D, DevGreen Gp, const int64_t *__restrict__ goff,
+                                              double *__restrict__ G) {
+    const int k = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p = D.pg_ptr[k + 1] - D.pg_ptr[k];
+    if (p == 0) return;
+    const ClassDev C = S.cls[D.cls[k]];
+    const int nb = (p + 15) >> 4, ntile = nb * (nb + 1) / 2;
+    const int4 *pl = Gp.sn + Gp.base[k];
+    const int32_t *sn_nc = S.sn_nc + C.o_sn, *sn_m = S.sn_m + C.o_sn;
+    const double *ws = Gp.ws + Gp.wso[k];
+    double *Gk = G + goff[k];
+    const int l16 = lane & 15, kr = lane >> 4;
+    for (int it = blockIdx.y * 4 + wv; it < ntile; it += gridDim.y * 4) {
+        int ti, tj;
+        tri_tile(it, ti, tj);
+        const int i0 = 16 * ti, j0 = 16 * tj;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < C.nsn; ++s) {
+            const int4 e = pl[s];
+            const int w = (int)((uint32_t)e.y >> 16), lo = e.y & 0xFFFF;
+            if (w == 0 || lo >= i0 + 16 || lo + w <= i0 || lo >= j0 + 16 || lo + w <= j0) continue;
+            const int nc = sn_nc[s], f = nc + sn_m[s];
+            const double *Y = ws + e.x + (int64_t)f * w;  // Y_s, nc x w row-major
+            const int ci = i0 + l16 - lo, cj = j0 + l16 - lo;
+            const bool vi = ci >= 0 && ci < w, vj = cj >= 0 && cj < w;
+            for (int t0 = 0; t0 < nc; t0 += 16) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = t0 + 4 * q + kr;
+                    av[q] = t < nc && vi ? Y[(int64_t)t * w + ci] : 0.0;
+                    bv[q] = t < nc && vj ? Y[(int64_t)t * w + cj] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (t0 + 4 * q < nc) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+            }
+        }
+        const int j = j0 + l16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + 4 * q + kr;
+            Gk[gpack_index(nb, i, j)] = i < p && j < p ? acc[q] : 0.0;
+        }
+    }
 }
 
 // ------------------------------------------------------------------------ split
@@ -2116,6 +2170,14 @@ void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_f
     if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void *)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(k_factor, dim3(nsub), dim3(kThreads), shm, st, S, D, aval, invz, vals, vals32, ws, lds_doubles,
                        status, Gp, goff, G);
+}
+
+void launch_gram(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_p, const DevGreen &Gp,
+                 const int64_t *goff, double *G, hipStream_t st) {
+    if (nsub <= 0 || max_p <= 0) return;
+    const int nb = (max_p + 15) / 16, ntile = nb * (nb + 1) / 2;
+    const int gy = std::min(32, (ntile + 3) / 4);  // four blocks per workgroup and pass
+    hipLaunchKernelGGL(k_gram, dim3(nsub, gy), dim3(256), 0, st, S, D, Gp, goff, G);
 }
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st) {

@@ -103,11 +103,18 @@ void launch_invz(const double *z_vtl, const int32_t *port_vtl, double *invz64, f
                  hipStream_t st);
 
 // FP64 multifrontal factorisation of every port-augmented local matrix; status[k] = 1 + supernode of the
-// first non-positive pivot (0 if fine).  With Gp.sn set it also accumulates the port Green's functions
-// G_k = R K_k^{-1} R^T (FP64, packed lower block triangle at goff[k], see k_schur; zero on entry).
+// first non-positive pivot (0 if fine).  With Gp.sn set it also computes the port Green's columns Y_s
+// and, when G is given, accumulates G_k = R K_k^{-1} R^T (FP64, packed lower block triangle at goff[k],
+// see k_schur; zero on entry); with G == nullptr launch_gram forms G_k afterwards.
 void launch_factor(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_front, const double *aval,
                    const double *invz, double *vals, float *vals32, double *ws, int32_t *status, const DevGreen &Gp,
                    const int64_t *goff, double *G, hipStream_t st);
+
+// G_k = sum_s Y_s^T Y_s from the Y blocks a factorisation left in Gp.ws (launched after launch_factor
+// with G == nullptr, which then skips these products); every stored entry of G is written.  Needs
+// G_k's port order to be the plan order (Gp.perm the identity).
+void launch_gram(const DevSym &S, const DevSub &D, int32_t nsub, int32_t max_p, const DevGreen &Gp,
+                 const int64_t *goff, double *G, hipStream_t st);
 
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 
