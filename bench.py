@@ -176,16 +176,17 @@ def measured_traffic(kernel, summary):
 
 
 def setup_mfma(workload):
-    """Matrix-core use of the factorisation kernel from its counters (FP64 MFMA FLOPs per launch over
-    the launch's duration), or None when the kernels have changed since."""
-    keys = ("k_factor-mfma-flops-per-launch", "k_factor-duration-us")
+    """Matrix-core use of the set-up kernels (factorisation and Gram) from their counters: FP64 MFMA
+    FLOPs of one set-up over the two launches' durations, or None when the kernels have changed since."""
+    keys = ("setup-mfma-flops-per-launch", "setup-duration-us")
     f = _profile_fields(f"setup_mfma_{workload.replace('^', '')}.md", keys)
     if f is None:
         return None
     flops, us = float(f[keys[0]]), float(f[keys[1]])
     achieved = flops / (us * 1e-6) / 1e12
-    return dict(kernel="k_factor", workload=workload, bound="latency", mfma_dtype="f64", flops_per_launch=flops,
-                avg_launch_us=us, achieved=achieved, peak=78.6, unit="TFLOP/s", frac=achieved / 78.6)
+    return dict(kernel="k_factor + k_gram", workload=workload, bound="latency", mfma_dtype="f64",
+                flops_per_launch=flops, avg_launch_us=us, achieved=achieved, peak=78.6, unit="TFLOP/s",
+                frac=achieved / 78.6)
 
 
 def host_cpu():
