@@ -985,15 +985,15 @@ __device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__res
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int j0 = 0; j0 < jn; j0 += 8) {  // eight loads in flight together
-                T v[8];
+            for (int j0 = 0; j0 < jn; j0 += 16) {  // sixteen loads in flight together
+                T v[16];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < 16; ++q) {
                     const int j = j0 + q < jn ? j0 + q : jn - 1;
                     v[q] = Vs[vcol(f, j) + (i - j)];
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
+                for (int q = 0; q < 16; ++q)
                     if (j0 + q < jn)
 #pragma unroll
                         for (int c = 0; c < R; ++c) acc[c] += v[q] * t[(j0 + q) * R + c];
@@ -1009,7 +1009,7 @@ __device__ void forward_subst(const ClassDev &C, const DevSym &S, const T *__res
 // Backward substitution of one subgraph, root level first: x_s = Linv^T y_s - W^T x_{R_s}, i.e. for
 // every column j of s, x_j = (column j of V_s) . [y_s; -x_{R_s}] over its rows j .. f - 1.  One
 // thread per column of the level; the column's entries are contiguous (V_s is stored by columns) and
-// read eight at a time.  In: vec = y.  Out: tmp = x.  Ends with a barrier.
+// read sixteen at a time.  In: vec = y.  Out: tmp = x.  Ends with a barrier.
 template <typename T, int R>
 __device__ void backward_subst(const ClassDev &C, const DevSym &S, const T *__restrict__ Vk, const T *vec, T *tmp) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -1026,27 +1026,27 @@ __device__ void backward_subst(const ClassDev &C, const DevSym &S, const T *__re
             T acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0;
-            for (int k0 = 0; k0 < nc - j; k0 += 8) {  // Linv^T y: eight loads in flight
-                T v[8];
+            for (int k0 = 0; k0 < nc - j; k0 += 16) {  // Linv^T y: sixteen loads in flight
+                T v[16];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = k0 + q < nc - j ? lcol[k0 + q] : (T)0;
+                for (int q = 0; q < 16; ++q) v[q] = k0 + q < nc - j ? lcol[k0 + q] : (T)0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < 16; ++q) {
                     const int row = k0 + q < nc - j ? c0 + j + k0 + q : c0 + j;
 #pragma unroll
                     for (int c = 0; c < R; ++c) acc[c] += v[q] * vec[row * R + c];
                 }
             }
-            for (int q0 = 0; q0 < m; q0 += 8) {  // - W^T x_R
-                T v[8];
-                int ri[8];
+            for (int q0 = 0; q0 < m; q0 += 16) {  // - W^T x_R
+                T v[16];
+                int ri[16];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {  // past m: a zero weight on a row that holds a finished x
+                for (int q = 0; q < 16; ++q) {  // past m: a zero weight on a row that holds a finished x
                     v[q] = q0 + q < m ? wcol[q0 + q] : (T)0;
                     ri[q] = rr[q0 + q < m ? q0 + q : m - 1];
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
+                for (int q = 0; q < 16; ++q)
 #pragma unroll
                     for (int c = 0; c < R; ++c) acc[c] -= v[q] * tmp[ri[q] * R + c];
             }
